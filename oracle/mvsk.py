@@ -1,0 +1,475 @@
+"""FP64 CPU oracle of YAND-MVSK (test infrastructure only; see package doc).
+
+Every function cites the passage of the paper it follows.  Section numbers
+follow the paper: Section 2 (problem setting), Section 4 (solver, with
+Algorithm 1 "YAND-MVSK algorithm"), Section 5 (Proposition "Exact operator
+representation", Proposition "Quartic exact line search from sample power
+sums", Proposition "Affine-subspace reduction"), Appendix B (Lemma
+"Interior-safe steplength cap", Proposition "A sufficient condition for the
+imported bounded-direction hypothesis"), Appendix D (Table "YAND-MVSK parameter
+settings").
+
+Readings of passages the paper leaves open are listed in the design notes of
+the repository (exact log-det correction, 1/(m+1) factor, relative
+regularisation, PCG preconditioner, stall rule, tie rule).  The parity status
+of each function:
+
+* centering, objective, moments, gradient, HVP, third-order action,
+  line-search coefficients, step selection, feasibility cap, reduced basis,
+  affine-normal direction, solve loop: pinned (tests/test_oracle_*.py).
+* PCG inner iterates: parity unpinned per iteration (the paper does not name
+  its preconditioner); pinned only at solve level through uniqueness of the
+  minimiser under the convexity certificate.
+"""
+
+from __future__ import annotations
+
+import math
+import time
+from dataclasses import dataclass, field
+
+import numpy as np
+import scipy.linalg as sla
+
+__all__ = [
+    "center", "psi", "dpsi", "d2psi", "d3psi", "objective", "moments",
+    "gradient", "hvp", "third", "constraints", "feasible_start",
+    "tangent_basis", "householder_frame", "Direction", "affine_normal",
+    "linesearch_coeffs", "alpha_max", "quartic_value", "select_step",
+    "Options", "SolveInfo", "solve", "certified_convex", "Unbounded",
+    "Indefinite",
+]
+
+
+class Unbounded(ArithmeticError):
+    """The quartic line model has no minimiser on [0, alpha_max)."""
+
+
+class Indefinite(ArithmeticError):
+    """The regularised tangent Hessian stayed indefinite after escalation."""
+
+
+# ---------------------------------------------------------------------------
+# Section 2: sample mean, centered returns, moments.
+# ---------------------------------------------------------------------------
+
+def center(R: np.ndarray):
+    """mu = T^-1 R^T 1 and A = R - 1 mu^T (Section 2; Algorithm 1, setup)."""
+    R = np.asarray(R, dtype=np.float64)
+    T = R.shape[0]
+    mu = R.sum(axis=0) / T
+    A = R - mu[None, :]
+    return mu, A
+
+
+def psi(c, s):
+    """psi(s) = c2 s^2 - c3 s^3 + c4 s^4 (Section 2, lifted form)."""
+    return c[1] * s**2 - c[2] * s**3 + c[3] * s**4
+
+
+def dpsi(c, s):
+    return 2.0 * c[1] * s - 3.0 * c[2] * s**2 + 4.0 * c[3] * s**3
+
+
+def d2psi(c, s):
+    """psi''(s) = 2c2 - 6c3 s + 12c4 s^2 (Proposition 'Lifted separability')."""
+    return 2.0 * c[1] - 6.0 * c[2] * s + 12.0 * c[3] * s**2
+
+
+def d3psi(c, s):
+    return -6.0 * c[2] + 24.0 * c[3] * s
+
+
+def moments(A, mu, x):
+    """m1 = mu^T x and m_p = T^-1 sum_t (a_t^T x)^p, p = 2,3,4 (Section 2)."""
+    z = A @ x
+    T = A.shape[0]
+    return np.array([mu @ x, np.sum(z**2) / T, np.sum(z**3) / T,
+                     np.sum(z**4) / T])
+
+
+def objective(A, mu, c, x):
+    """f(x) = -c1 mu^T x + (c2 |z|^2 - c3 sum z^3 + c4 sum z^4)/T, z = Ax.
+
+    Proposition 'Exact operator representation', equation (operator-f).
+    """
+    T = A.shape[0]
+    z = A @ x
+    return (-c[0] * (mu @ x) + c[1] / T * np.sum(z**2)
+            - c[2] / T * np.sum(z**3) + c[3] / T * np.sum(z**4))
+
+
+def gradient(A, mu, c, x):
+    """Equation (operator-grad): -c1 mu + A^T(2c2 z - 3c3 z^2 + 4c4 z^3)/T."""
+    T = A.shape[0]
+    z = A @ x
+    return (-c[0] * mu + 2.0 * c[1] / T * (A.T @ z)
+            - 3.0 * c[2] / T * (A.T @ z**2) + 4.0 * c[3] / T * (A.T @ z**3))
+
+
+def hvp(A, c, x, v):
+    """Equation (operator-hvp): Hessian of f at x applied to v."""
+    T = A.shape[0]
+    z = A @ x
+    Av = A @ v
+    return (2.0 * c[1] / T * (A.T @ Av) - 6.0 * c[2] / T * (A.T @ (z * Av))
+            + 12.0 * c[3] / T * (A.T @ (z**2 * Av)))
+
+
+def third(A, c, x, u, v):
+    """Equation (operator-third): D^3 f(x)[u, v, .]."""
+    T = A.shape[0]
+    z = A @ x
+    Au = A @ u
+    Av = A @ v
+    return (-6.0 * c[2] / T * (A.T @ (Au * Av))
+            + 24.0 * c[3] / T * (A.T @ (z * Au * Av)))
+
+
+def certified_convex(c) -> bool:
+    """Corollary 'coefficient-only convexity certificate': c4 > 0, 8c2c4 > 3c3^2."""
+    return bool(c[3] > 0.0 and 8.0 * c[1] * c[3] > 3.0 * c[2] ** 2)
+
+
+# ---------------------------------------------------------------------------
+# Section 4.2 / Proposition 'Affine-subspace reduction': reduced coordinates.
+# ---------------------------------------------------------------------------
+
+def constraints(mu, target=None):
+    """Equality constraints C^T x = b.
+
+    Budget only: C = [1], b = [1] (the simplex tangent space of Section 4.2).
+    With a return target r: C = [1, mu], b = [1, r]; the affine-subspace
+    reduction applies unchanged with the smaller tangent space null(C^T).
+    """
+    n = mu.shape[0]
+    if target is None:
+        return np.ones((n, 1)), np.array([1.0])
+    return np.stack([np.ones(n), mu], axis=1), np.array([1.0, float(target)])
+
+
+def feasible_start(C, b, x=None):
+    """Equal weights (Algorithm 1 input; Section 6.1), moved by the
+    minimum-norm correction onto C^T x = b when a target is present."""
+    n = C.shape[0]
+    x = np.full(n, 1.0 / n) if x is None else np.array(x, dtype=np.float64)
+    r = C.T @ x - b
+    return x - C @ np.linalg.solve(C.T @ C, r)
+
+
+def tangent_basis(C):
+    """Orthonormal U spanning null(C^T) (Section 4.2), from a complete QR."""
+    p = C.shape[1]
+    Qc, _ = np.linalg.qr(C, mode="complete")
+    return np.ascontiguousarray(Qc[:, p:])
+
+
+def householder_frame(nu):
+    """Householder frame Q with Q^T Q = I and Q^T nu = 0 (Section 4.2).
+
+    The reflector I - 2 v v^T / v^T v with v = nu + sign(nu_1) e_1 maps e_1 to
+    a multiple of nu; its remaining columns span the orthogonal complement.
+    """
+    m = nu.shape[0]
+    v = nu.copy()
+    s = 1.0 if nu[0] >= 0.0 else -1.0
+    v[0] += s * np.linalg.norm(nu)
+    Hh = np.eye(m) - 2.0 * np.outer(v, v) / (v @ v)
+    return np.ascontiguousarray(Hh[:, 1:])
+
+
+# ---------------------------------------------------------------------------
+# Section 4.2 / 4.4: the affine-normal direction with the exact trace.
+# ---------------------------------------------------------------------------
+
+@dataclass
+class Direction:
+    d: np.ndarray            # ambient direction d = U d_y
+    gnorm: float             # ||gbar||
+    lam: float               # regularisation used in H_{T,lambda}
+    a: np.ndarray            # log-det correction (reduced, length m-1)
+    u: np.ndarray            # tangential coefficients
+    cg_iters: int = 0
+
+
+def _pcg(Bmat, rhs, tol, maxit):
+    """Jacobi-preconditioned CG on the reduced tangent system, start 0.
+
+    Reading of the 'pcg reduced solve' of Table 'YAND-MVSK parameter
+    settings': stop when ||r_k|| <= tol ||r_0|| or after maxit iterations.
+    """
+    Minv = 1.0 / np.diag(Bmat)
+    u = np.zeros_like(rhs)
+    r = rhs.copy()
+    r0 = np.linalg.norm(r)
+    if r0 == 0.0:
+        return u, 0
+    zv = Minv * r
+    p = zv.copy()
+    rz = r @ zv
+    it = 0
+    while it < maxit:
+        Bp = Bmat @ p
+        alpha = rz / (p @ Bp)
+        u += alpha * p
+        r -= alpha * Bp
+        it += 1
+        if np.linalg.norm(r) <= tol * r0:
+            break
+        zv = Minv * r
+        rz_new = r @ zv
+        p = zv + (rz_new / rz) * p
+        rz = rz_new
+    return u, it
+
+
+def affine_normal(A, mu, c, x, U, *, solver="direct", reg=0.0,
+                  krylov_tol=1e-3, krylov_maxit=15, max_escalations=8):
+    """Exact-trace affine-normal direction in reduced coordinates.
+
+    Section 4.2 and Section 4.4: with gbar = U^T g, nu = gbar/|gbar|, the
+    Householder frame Q, H_red = U^T H U,
+        h = Q^T H_red nu,   H_{T,lam} = Q^T H_red Q + lam I,
+        u = H_{T,lam}^{-1} (h - |gbar|/(m+1) a),   d_y = Q u - nu,  d = U d_y,
+    with m = dim of the reduced space (the form of Appendix B, Proposition
+    'A sufficient condition for the imported bounded-direction hypothesis').
+
+    The exact log-det correction is
+        a_l = sum_ij (H_{T,lam}^{-1})_ij D^3 phi[Q e_i, Q e_j, Q e_l],
+    the derivative of log det Q^T H_red(y + Q eta) Q at eta = 0; with P = A U Q
+    and q_t = p_t^T H_{T,lam}^{-1} p_t it equals P^T (psi'''(z) * q) / T.
+
+    ``reg`` is relative: lam = reg * trace(Q^T H_red Q) / (m - 1).  The direct
+    solver starts at reg (0 by default) and escalates lam on a failed Cholesky
+    factorisation; the PCG solver keeps the factorisation only for the exact
+    trace and solves for u by ``_pcg``.
+    """
+    T = A.shape[0]
+    m = U.shape[1]
+    z = A @ x
+    g = gradient(A, mu, c, x)
+    gbar = U.T @ g
+    gn = float(np.linalg.norm(gbar))
+    nu = gbar / gn
+    if m == 1:
+        d = U @ (-nu)
+        return Direction(d=d, gnorm=gn, lam=0.0, a=np.zeros(0), u=np.zeros(0))
+    Q = householder_frame(nu)
+    V = U @ Q
+    P = A @ V
+    D2 = d2psi(c, z)
+    B0 = P.T @ (D2[:, None] * P) / T
+    scale = np.trace(B0) / (m - 1)
+    lam = reg * scale
+    for _ in range(max_escalations + 1):
+        Bm = B0 + lam * np.eye(m - 1)
+        try:
+            L = np.linalg.cholesky(Bm)
+            break
+        except np.linalg.LinAlgError:
+            lam = max(10.0 * lam, 1e-12 * scale)
+    else:
+        raise Indefinite("tangent Hessian indefinite after escalation")
+    h = V.T @ hvp(A, c, x, U @ nu)
+    Y = sla.solve_triangular(L, P.T, lower=True)       # (m-1) x T
+    q = np.sum(Y * Y, axis=0)
+    a = P.T @ (d3psi(c, z) * q) / T
+    rhs = h - gn / (m + 1) * a
+    cg_iters = 0
+    if solver == "direct":
+        u = sla.cho_solve((L, True), rhs)
+    elif solver == "pcg":
+        u, cg_iters = _pcg(Bm, rhs, krylov_tol, krylov_maxit)
+    else:
+        raise ValueError(solver)
+    dy = Q @ u - nu
+    return Direction(d=U @ dy, gnorm=gn, lam=lam, a=a, u=u, cg_iters=cg_iters)
+
+
+# ---------------------------------------------------------------------------
+# Proposition 'Quartic exact line search from sample power sums'.
+# ---------------------------------------------------------------------------
+
+def linesearch_coeffs(A, mu, c, x, d):
+    """A0..A4 of f(x + alpha d) from s_rs = T^-1 sum_t z_t^r w_t^s."""
+    T = A.shape[0]
+    z = A @ x
+    w = A @ d
+
+    def s(r, k):
+        return np.sum(z**r * w**k) / T
+
+    A0 = objective(A, mu, c, x)
+    A1 = (-c[0] * (mu @ d) + 2.0 * c[1] * s(1, 1) - 3.0 * c[2] * s(2, 1)
+          + 4.0 * c[3] * s(3, 1))
+    A2 = c[1] * s(0, 2) - 3.0 * c[2] * s(1, 2) + 6.0 * c[3] * s(2, 2)
+    A3 = -c[2] * s(0, 3) + 4.0 * c[3] * s(1, 3)
+    A4 = c[3] * s(0, 4)
+    return np.array([A0, A1, A2, A3, A4])
+
+
+def alpha_max(x, d, tau):
+    """Lemma 'Interior-safe steplength cap': min over d_i < 0 of (x_i-tau)/(-d_i)."""
+    neg = d < 0.0
+    if not np.any(neg):
+        return math.inf
+    return float(np.min((x[neg] - tau) / (-d[neg])))
+
+
+def quartic_value(coef, alpha):
+    return (coef[0] + coef[1] * alpha + coef[2] * alpha**2
+            + coef[3] * alpha**3 + coef[4] * alpha**4)
+
+
+def select_step(coef, amax=math.inf):
+    """Exact step: argmin of the quartic over {0, amax} and the real roots of
+    its derivative inside (0, amax) (Proposition 'Quartic exact line search').
+
+    Roots come from the companion-matrix eigenvalues (numpy.roots).  The
+    candidates are compared on phi(alpha) - A0 = A1 a + A2 a^2 + A3 a^3 + A4 a^4
+    so that decreases far below the rounding of A0 still count.  Ties are
+    broken toward the smallest step among candidates within
+    1e-15 * sum_{i>=1} |A_i| alpha^i of the minimum.  On an unbounded interval
+    the quartic must grow at infinity (leading nonzero coefficient positive),
+    otherwise ``Unbounded`` is raised.
+    """
+    coef = np.asarray(coef, dtype=np.float64)
+    if not math.isfinite(amax):
+        lead = next((coef[i] for i in (4, 3, 2, 1) if coef[i] != 0.0), 0.0)
+        if lead <= 0.0:
+            raise Unbounded("line model unbounded below on [0, inf)")
+    dcoef = [4.0 * coef[4], 3.0 * coef[3], 2.0 * coef[2], coef[1]]
+    cands = [0.0]
+    if math.isfinite(amax):
+        cands.append(float(amax))
+    nz = np.trim_zeros(np.array(dcoef), "f")
+    if nz.size > 1:
+        for r in np.roots(nz):
+            if abs(r.imag) <= 1e-8 * max(1.0, abs(r.real)):
+                a = float(r.real)
+                if 0.0 < a < amax:
+                    cands.append(a)
+    cands = np.array(sorted(set(cands)))
+    pw = cands[:, None] ** np.arange(1, 5)[None, :]
+    vals = pw @ coef[1:]
+    scale = pw @ np.abs(coef[1:])
+    ok = vals <= vals.min() + 1e-15 * scale
+    return float(cands[np.argmax(ok)])
+
+
+# ---------------------------------------------------------------------------
+# Algorithm 1: the outer loop.
+# ---------------------------------------------------------------------------
+
+@dataclass
+class Options:
+    """Parameters of Table 'YAND-MVSK parameter settings' plus readings.
+
+    solver: 'direct' (YAND-MVSK small) or 'pcg' (YAND-MVSK large).
+    feasible_set: 'budget' (affine hull, no cap) or 'simplex' (cap on
+    Delta(tau), Lemma 'Interior-safe steplength cap').
+    """
+    solver: str = "direct"
+    feasible_set: str = "budget"
+    eps: float = 1e-8
+    max_iter: int = 300
+    max_elapsed: float = math.inf
+    reg: float = 0.0
+    krylov_tol: float = 1e-3
+    krylov_maxit: int = 15
+    tau: float = 1e-8
+    stall_recovery: bool = True
+    restart_max_iter: int = 120
+
+    @staticmethod
+    def large():
+        """YAND-MVSK (large): PCG, 40 iterations, 60 s, reg 1e-4."""
+        return Options(solver="pcg", max_iter=40, max_elapsed=60.0, reg=1e-4)
+
+
+@dataclass
+class SolveInfo:
+    iterations: int = 0
+    restarts: int = 0
+    f: float = math.nan
+    gnorm: float = math.nan
+    status: int = 0
+    cg_iters: int = 0
+    oracle_passes: int = 0
+    ls_passes: int = 0
+    history: list = field(default_factory=list)
+
+
+def _iterate(A, mu, c, x, U, opts: Options, solver, krylov_maxit, max_iter,
+             info: SolveInfo, t0):
+    """Run outer iterations from x; return (x, converged, stalled)."""
+    small = 0
+    f_prev = objective(A, mu, c, x)
+    for _ in range(max_iter):
+        g = gradient(A, mu, c, x)
+        info.oracle_passes += 1
+        gn = float(np.linalg.norm(U.T @ g))
+        info.gnorm = gn
+        if gn <= opts.eps:
+            return x, True, False
+        if time.perf_counter() - t0 > opts.max_elapsed:
+            return x, False, True
+        reg = opts.reg if solver == "pcg" else 0.0
+        dr = affine_normal(A, mu, c, x, U, solver=solver, reg=reg,
+                           krylov_tol=opts.krylov_tol,
+                           krylov_maxit=krylov_maxit)
+        info.cg_iters += dr.cg_iters
+        coef = linesearch_coeffs(A, mu, c, x, dr.d)
+        info.ls_passes += 1
+        amax = (alpha_max(x, dr.d, opts.tau)
+                if opts.feasible_set == "simplex" else math.inf)
+        alpha = select_step(coef, amax)
+        x = x + alpha * dr.d
+        info.iterations += 1
+        f_new = quartic_value(coef, alpha)
+        info.history.append((gn, alpha, f_new))
+        if f_prev - f_new < 1e-14 * abs(f_prev):
+            small += 1
+            if small >= 3:
+                return x, False, True
+        else:
+            small = 0
+        f_prev = f_new
+    g = gradient(A, mu, c, x)
+    info.gnorm = float(np.linalg.norm(U.T @ g))
+    return x, info.gnorm <= opts.eps, True
+
+
+def solve(R, c, target=None, x0=None, opts: Options | None = None):
+    """Algorithm 1 (YAND-MVSK) in FP64 with explicit reduced bases.
+
+    Stall recovery (reading of the 'stall-recovery restarts' of Table
+    'YAND-MVSK parameter settings' for the affine budget set): when the
+    baseline budget ends above eps, or the objective stops decreasing for 3
+    iterations, restart from the current iterate with restart_max_iter
+    iterations, first with twice the Krylov budget, then with the direct
+    solve.  Status: 0 converged, 1 iteration budget exhausted.
+    """
+    opts = opts or Options()
+    c = np.asarray(c, dtype=np.float64)
+    mu, A = center(R)
+    C, b = constraints(mu, target)
+    x = feasible_start(C, b, x0)
+    if opts.feasible_set == "simplex" and np.any(x < opts.tau):
+        raise ValueError("start outside the interior slice")
+    U = tangent_basis(C)
+    info = SolveInfo()
+    t0 = time.perf_counter()
+    x, conv, stalled = _iterate(A, mu, c, x, U, opts, opts.solver,
+                                opts.krylov_maxit, opts.max_iter, info, t0)
+    if not conv and opts.stall_recovery and opts.solver == "pcg":
+        for solver, kmax in (("pcg", 2 * opts.krylov_maxit), ("direct", 0)):
+            info.restarts += 1
+            t0 = time.perf_counter()
+            x, conv, stalled = _iterate(A, mu, c, x, U, opts, solver, kmax,
+                                        opts.restart_max_iter, info, t0)
+            if conv:
+                break
+    info.f = objective(A, mu, c, x)
+    info.status = 0 if conv else 1
+    return x, info
