@@ -1,0 +1,174 @@
+/*
+ * libyand -- MI355X-native hot path of YAND-MVSK (Yau's affine-normal descent
+ * for unrestricted mean-variance-skewness-kurtosis portfolios).
+ *
+ * Problem (Section 2, equation (mvsk)): minimise over portfolio weights w
+ *     f(w) = -c1 m1(w) + c2 m2(w) - c3 m3(w) + c4 m4(w),
+ * with m1 = mu^T w and m_p = T^-1 sum_t ((R w)_t - mu^T w)^p, where R (T x n)
+ * holds one row of asset returns per bar, mu = T^-1 R^T 1 and A = R - 1 mu^T.
+ * Weights satisfy the budget 1^T w = 1 (BUDGET set: its affine hull, the
+ * reduced parametrisation of Section 4.2) and optionally a return target
+ * mu^T w = r; the SIMPLEX set additionally keeps w_i >= tau through the
+ * feasibility cap of Section 4.3.
+ *
+ * Conventions for every entry point:
+ *  - Scalars and small fixed-size arrays (c[4], coef[5], mom[4], f, target)
+ *    are HOST memory.  Vectors of length n or T (w, v, d, grad, hv, w_out)
+ *    are DEVICE memory on the context's device, FP64, contiguous.
+ *  - The caller owns every buffer it passes in; the library never frees or
+ *    retains them.  The context owns its copy of A (centered, at the chosen
+ *    storage precision), mu and all workspaces.
+ *  - Work is enqueued on the context's HIP stream.  Every call returns after
+ *    the stream has finished the call's work (host outputs are valid).
+ *  - Return value: 0 success, > 0 warning, < 0 error (YAND_* codes below).
+ *    Nothing is thrown across the ABI.  A context is not thread-safe: calls
+ *    on one context must be serialised by the caller.
+ *  - c must satisfy c_i >= 0 (Section 2) or YAND_ERR_ARG is returned.
+ */
+#ifndef YAND_H
+#define YAND_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+  YAND_OK = 0,
+  YAND_WARN_MAXITER = 1,     /* iteration / time budget ended above eps      */
+  YAND_WARN_STALL = 2,       /* still above eps after the stall restarts     */
+  YAND_ERR_ARG = -1,         /* bad size, negative c, infeasible start/target */
+  YAND_ERR_NONFINITE = -2,   /* NaN or Inf in R or in an iterate             */
+  YAND_ERR_HIP = -3,         /* a HIP runtime call failed                    */
+  YAND_ERR_OOM = -4,         /* device allocation failed                     */
+  YAND_ERR_INDEFINITE = -5,  /* tangent Hessian indefinite after escalation  */
+  YAND_ERR_UNBOUNDED = -6    /* quartic line model unbounded below           */
+};
+
+/* Storage precision of the centered matrix A inside the context. */
+enum { YAND_FP64 = 0, YAND_FP32 = 1, YAND_BF16 = 2 };
+/* Reduced tangent solve: dense Cholesky ("small") or projected PCG ("large"),
+ * Appendix D, Table "YAND-MVSK parameter settings". */
+enum { YAND_SOLVER_DIRECT = 0, YAND_SOLVER_PCG = 1 };
+/* Feasible set: affine budget hull (no cap) or the slice Delta(tau). */
+enum { YAND_SET_BUDGET = 0, YAND_SET_SIMPLEX = 1 };
+
+typedef struct yand_ctx yand_ctx;
+
+/* Solver parameters (Appendix D, Table "YAND-MVSK parameter settings").
+ * regularization is relative: lambda = regularization * (mean diagonal of the
+ * tangent Hessian).  yand_default_opts fills the direct configuration. */
+typedef struct yand_opts {
+  int solver;             /* YAND_SOLVER_*                                    */
+  int feasible_set;       /* YAND_SET_*                                       */
+  double eps;             /* stop when ||reduced gradient||_2 <= eps (1e-8)   */
+  int max_iter;           /* outer budget (direct 300, PCG 40)                */
+  double max_elapsed;     /* seconds (PCG 60; <= 0 means unlimited)           */
+  double regularization;  /* relative lambda (direct 0, PCG 1e-4)             */
+  double krylov_tol;      /* relative PCG residual (1e-3)                     */
+  int krylov_maxit;       /* PCG iterations (15)                              */
+  double tau;             /* interior margin of Delta(tau) (1e-8)             */
+  int stall_recovery;     /* PCG: restart twice when stalled                  */
+  int restart_max_iter;   /* outer budget of each restart (120)               */
+} yand_opts;
+
+/* Per-solve report: counters follow the oracle-query accounting of the
+ * implementation appendix (value/gradient, Hessian-vector, third-order,
+ * line-search passes, Krylov iterations). */
+typedef struct yand_info {
+  int status;             /* return code of the solve                         */
+  int iterations;         /* outer iterations performed                       */
+  int restarts;           /* stall-recovery restarts                          */
+  int cg_iters;           /* total PCG iterations                             */
+  double f;               /* objective at w_out                               */
+  double gnorm;           /* ||reduced gradient||_2 at w_out (own precision)  */
+  double elapsed;         /* seconds                                          */
+  double lambda_used;     /* absolute regularisation of the last direction    */
+  int64_t oracle_passes;  /* value/gradient passes over A                     */
+  int64_t hvp_passes;     /* Hessian-vector passes over A                     */
+  int64_t third_passes;   /* third-order back-projection passes over A        */
+  int64_t ls_passes;      /* line-search passes over A                        */
+  int64_t dense_traces;   /* exact-trace factorisations                       */
+} yand_info;
+
+/* Fill *opts with the direct configuration (YAND-MVSK small). */
+void yand_default_opts(yand_opts* opts);
+/* Fill *opts with the PCG configuration with stall recovery (YAND-MVSK large). */
+void yand_large_opts(yand_opts* opts);
+
+/* Create a context from device returns R (T x n, FP64, row stride ldr >= n).
+ * Computes mu = T^-1 R^T 1 and A = R - 1 mu^T (Section 2; Algorithm 1 setup),
+ * rounds A to `precision` and keeps it; R is not retained.
+ * hip_stream: a hipStream_t (NULL = default stream).  Requires n >= 2, T >= 2.
+ * Errors: YAND_ERR_ARG, YAND_ERR_NONFINITE (R has NaN/Inf), YAND_ERR_OOM,
+ * YAND_ERR_HIP.  On error *out is set to NULL. */
+int yand_create(const double* R, int64_t T, int64_t n, int64_t ldr,
+                int precision, void* hip_stream, yand_ctx** out);
+int yand_destroy(yand_ctx* ctx);
+
+/* Copy mu (n, FP64) to a device buffer. */
+int yand_get_mu(yand_ctx* ctx, double* mu_out);
+
+/* Exact sample oracle (Proposition "Exact operator representation"):
+ * f(w) (host), grad = -c1 mu + A^T psi'(Aw)/T (device, nullable) and the
+ * moments m1..m4 (host, nullable).  One pass over A. */
+int yand_eval(yand_ctx* ctx, const double c[4], const double* w, double* f,
+              double* grad, double mom[4]);
+
+/* Hessian-vector product hv = A^T (psi''(Aw) * Av) / T (equation
+ * (operator-hvp)); w, v, hv device.  One fused pass over A after the pass that
+ * caches z = Aw (skipped when w is the point of the previous call). */
+int yand_hvp(yand_ctx* ctx, const double c[4], const double* w,
+             const double* v, double* hv);
+
+/* Quartic line-search coefficients coef[0..4] = A0..A4 of f(w + alpha d)
+ * (Proposition "Quartic exact line search from sample power sums"), built
+ * from the FP64 power sums s_rs = T^-1 sum z^r (Ad)^s.  w, d device. */
+int yand_linesearch_coeffs(yand_ctx* ctx, const double c[4], const double* w,
+                           const double* d, double coef[5]);
+
+/* Exact step (same proposition): the argmin of the quartic over 0, alpha_max
+ * (if finite; pass INFINITY for the budget set) and the real roots of its
+ * derivative in (0, alpha_max), computed on the device.  Ties go to the
+ * smallest step within 1e-15 * sum_{i>=1} |A_i| alpha^i.  Returns
+ * YAND_ERR_UNBOUNDED when alpha_max is infinite and the quartic does not grow
+ * at infinity. */
+int yand_select_step(yand_ctx* ctx, const double coef[5], double alpha_max,
+                     double* alpha);
+
+/* Affine-normal direction with the exact log-det trace at the feasible point
+ * w (Section 4.2 and Section 4.4; factor 1/(m+1) of Appendix B, Proposition
+ * "A sufficient condition for the imported bounded-direction hypothesis"),
+ * written to d_out (device, n).  target: NULL for the budget constraint only,
+ * else a host pointer to r in mu^T w = r.  gnorm (host, nullable) receives
+ * the reduced-gradient norm.  opts selects direct or PCG solve (NULL: direct,
+ * no regularisation). */
+int yand_affine_normal(yand_ctx* ctx, const double c[4], const double* target,
+                       const double* w, const yand_opts* opts, double* d_out,
+                       double* gnorm);
+
+/* Algorithm 1: solve from w0 (device, n; NULL = equal weights moved onto the
+ * target constraint) and write w_out (device, n).  info (host) is nullable. */
+int yand_mvsk_solve(yand_ctx* ctx, const double c[4], const double* target,
+                    const double* w0, const yand_opts* opts, double* w_out,
+                    yand_info* info);
+
+/* Stateless wrapper: returns R (device, T x n contiguous) -> w_out (device),
+ * FP64 storage, direct solver, budget set. */
+int yand_mvsk_solve_R(const double* R, int64_t T, int64_t n, double c1,
+                      double c2, double c3, double c4, const double* target,
+                      double* w_out);
+
+/* Corollary "coefficient-only convexity certificate": 1 if c4 > 0 and
+ * 8 c2 c4 > 3 c3^2, else 0. */
+int yand_is_certified_convex(const double c[4]);
+
+/* Storage precision, T, n of a context (host outputs, nullable). */
+int yand_shape(yand_ctx* ctx, int64_t* T, int64_t* n, int* precision);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* YAND_H */

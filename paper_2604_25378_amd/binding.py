@@ -1,0 +1,309 @@
+"""ctypes binding of libyand (argument marshalling only).
+
+PyTorch supplies device memory and the current stream; every step of the
+method runs in the library's HIP kernels.  The binding raises if libyand.so is
+missing or no GPU is visible: there is no CPU fallback.
+"""
+
+from __future__ import annotations
+
+import ctypes as C
+import math
+import os
+from dataclasses import dataclass
+
+import numpy as np
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "libyand.so")
+
+YAND_OK = 0
+YAND_WARN_MAXITER = 1
+YAND_WARN_STALL = 2
+ERRORS = {
+    -1: "YAND_ERR_ARG", -2: "YAND_ERR_NONFINITE", -3: "YAND_ERR_HIP",
+    -4: "YAND_ERR_OOM", -5: "YAND_ERR_INDEFINITE", -6: "YAND_ERR_UNBOUNDED",
+}
+PRECISIONS = {"fp64": 0, "fp32": 1, "bf16": 2}
+SOLVERS = {"direct": 0, "pcg": 1}
+SETS = {"budget": 0, "simplex": 1}
+
+
+class YandError(RuntimeError):
+    def __init__(self, code: int, where: str):
+        super().__init__(f"{where}: {ERRORS.get(code, code)}")
+        self.code = code
+
+
+class yand_opts(C.Structure):
+    _fields_ = [("solver", C.c_int), ("feasible_set", C.c_int),
+                ("eps", C.c_double), ("max_iter", C.c_int),
+                ("max_elapsed", C.c_double), ("regularization", C.c_double),
+                ("krylov_tol", C.c_double), ("krylov_maxit", C.c_int),
+                ("tau", C.c_double), ("stall_recovery", C.c_int),
+                ("restart_max_iter", C.c_int)]
+
+
+class yand_info(C.Structure):
+    _fields_ = [("status", C.c_int), ("iterations", C.c_int),
+                ("restarts", C.c_int), ("cg_iters", C.c_int),
+                ("f", C.c_double), ("gnorm", C.c_double),
+                ("elapsed", C.c_double), ("lambda_used", C.c_double),
+                ("oracle_passes", C.c_int64), ("hvp_passes", C.c_int64),
+                ("third_passes", C.c_int64), ("ls_passes", C.c_int64),
+                ("dense_traces", C.c_int64)]
+
+
+_D = C.POINTER(C.c_double)
+_lib = None
+
+
+def load(path: str = LIB_PATH):
+    """Load libyand.so and declare its signatures (no GPU needed to load)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError(
+            f"libyand.so not found at {path}; build it with "
+            "`python -m paper_2604_25378_amd.build`")
+    lib = C.CDLL(path)
+    vp = C.c_void_p
+    sig = {
+        "yand_default_opts": (None, [C.POINTER(yand_opts)]),
+        "yand_large_opts": (None, [C.POINTER(yand_opts)]),
+        "yand_create": (C.c_int, [vp, C.c_int64, C.c_int64, C.c_int64, C.c_int,
+                                  vp, C.POINTER(vp)]),
+        "yand_destroy": (C.c_int, [vp]),
+        "yand_get_mu": (C.c_int, [vp, vp]),
+        "yand_eval": (C.c_int, [vp, _D, vp, _D, vp, _D]),
+        "yand_hvp": (C.c_int, [vp, _D, vp, vp, vp]),
+        "yand_linesearch_coeffs": (C.c_int, [vp, _D, vp, vp, _D]),
+        "yand_select_step": (C.c_int, [vp, _D, C.c_double, _D]),
+        "yand_affine_normal": (C.c_int, [vp, _D, _D, vp, C.POINTER(yand_opts),
+                                         vp, _D]),
+        "yand_mvsk_solve": (C.c_int, [vp, _D, _D, vp, C.POINTER(yand_opts),
+                                      vp, C.POINTER(yand_info)]),
+        "yand_mvsk_solve_R": (C.c_int, [vp, C.c_int64, C.c_int64, C.c_double,
+                                        C.c_double, C.c_double, C.c_double,
+                                        _D, vp]),
+        "yand_is_certified_convex": (C.c_int, [_D]),
+        "yand_shape": (C.c_int, [vp, C.POINTER(C.c_int64),
+                                 C.POINTER(C.c_int64), C.POINTER(C.c_int)]),
+        "yand_profile_enable": (C.c_int, [vp, C.c_int]),
+        "yand_profile_read": (C.c_int, [vp, C.c_int, C.c_char_p, C.c_int, _D,
+                                        C.POINTER(C.c_int64)]),
+    }
+    for name, (res, args) in sig.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    _lib = lib
+    return lib
+
+
+def _c4(c):
+    arr = (C.c_double * 4)(*[float(v) for v in c])
+    return arr
+
+
+def _check(rc: int, where: str, warn_ok: bool = False):
+    if rc < 0 or (rc > 0 and not warn_ok):
+        raise YandError(rc, where)
+    return rc
+
+
+def _torch():
+    import torch
+    if not torch.cuda.is_available():
+        raise RuntimeError("libyand needs a visible GPU (no CPU fallback)")
+    return torch
+
+
+def _dev(t, n=None):
+    torch = _torch()
+    if not isinstance(t, torch.Tensor):
+        t = torch.as_tensor(np.asarray(t, dtype=np.float64))
+    t = t.to(device="cuda", dtype=torch.float64).contiguous()
+    if n is not None and t.numel() != n:
+        raise ValueError(f"expected {n} elements, got {t.numel()}")
+    return t
+
+
+def default_opts(**kw) -> yand_opts:
+    o = yand_opts()
+    lib = load()
+    if kw.pop("large", False):
+        lib.yand_large_opts(C.byref(o))
+    else:
+        lib.yand_default_opts(C.byref(o))
+    for k, v in kw.items():
+        if k == "solver":
+            v = SOLVERS[v] if isinstance(v, str) else v
+        if k == "feasible_set":
+            v = SETS[v] if isinstance(v, str) else v
+        setattr(o, k, v)
+    return o
+
+
+def is_certified_convex(c) -> bool:
+    return bool(load().yand_is_certified_convex(_c4(c)))
+
+
+@dataclass
+class SolveInfo:
+    status: int
+    iterations: int
+    restarts: int
+    cg_iters: int
+    f: float
+    gnorm: float
+    elapsed: float
+    lambda_used: float
+    oracle_passes: int
+    hvp_passes: int
+    third_passes: int
+    ls_passes: int
+    dense_traces: int
+
+
+class Context:
+    """A libyand context owning the centered matrix A at one precision."""
+
+    def __init__(self, R, precision: str = "fp64", stream=None):
+        torch = _torch()
+        lib = load()
+        R = _dev(R)
+        if R.dim() != 2:
+            raise ValueError("R must be T x n")
+        self.T, self.n = R.shape
+        self.precision = precision
+        self._stream = stream if stream is not None else torch.cuda.current_stream()
+        h = C.c_void_p()
+        rc = lib.yand_create(C.c_void_p(R.data_ptr()), self.T, self.n, self.n,
+                             PRECISIONS[precision],
+                             C.c_void_p(self._stream.cuda_stream), C.byref(h))
+        _check(rc, "yand_create")
+        self._h = h
+        self._lib = lib
+
+    def close(self):
+        if getattr(self, "_h", None):
+            self._lib.yand_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    def mu(self):
+        torch = _torch()
+        out = torch.empty(self.n, dtype=torch.float64, device="cuda")
+        _check(self._lib.yand_get_mu(self._h, C.c_void_p(out.data_ptr())),
+               "yand_get_mu")
+        return out
+
+    def eval(self, c, w, grad: bool = True):
+        torch = _torch()
+        w = _dev(w, self.n)
+        f = C.c_double()
+        mom = (C.c_double * 4)()
+        g = torch.empty(self.n, dtype=torch.float64, device="cuda") if grad else None
+        rc = self._lib.yand_eval(self._h, _c4(c), C.c_void_p(w.data_ptr()),
+                                 C.byref(f),
+                                 C.c_void_p(g.data_ptr()) if grad else None, mom)
+        _check(rc, "yand_eval")
+        return f.value, g, np.array(mom[:])
+
+    def hvp(self, c, w, v):
+        torch = _torch()
+        w, v = _dev(w, self.n), _dev(v, self.n)
+        out = torch.empty(self.n, dtype=torch.float64, device="cuda")
+        rc = self._lib.yand_hvp(self._h, _c4(c), C.c_void_p(w.data_ptr()),
+                                C.c_void_p(v.data_ptr()),
+                                C.c_void_p(out.data_ptr()))
+        _check(rc, "yand_hvp")
+        return out
+
+    def linesearch_coeffs(self, c, w, d):
+        w, d = _dev(w, self.n), _dev(d, self.n)
+        coef = (C.c_double * 5)()
+        rc = self._lib.yand_linesearch_coeffs(self._h, _c4(c),
+                                              C.c_void_p(w.data_ptr()),
+                                              C.c_void_p(d.data_ptr()), coef)
+        _check(rc, "yand_linesearch_coeffs")
+        return np.array(coef[:])
+
+    def select_step(self, coef, alpha_max=math.inf):
+        arr = (C.c_double * 5)(*[float(v) for v in coef])
+        al = C.c_double()
+        rc = self._lib.yand_select_step(self._h, arr, float(alpha_max),
+                                        C.byref(al))
+        _check(rc, "yand_select_step")
+        return al.value
+
+    def affine_normal(self, c, w, target=None, opts: yand_opts | None = None):
+        torch = _torch()
+        w = _dev(w, self.n)
+        d = torch.empty(self.n, dtype=torch.float64, device="cuda")
+        gn = C.c_double()
+        tg = C.byref(C.c_double(float(target))) if target is not None else None
+        rc = self._lib.yand_affine_normal(self._h, _c4(c), tg,
+                                          C.c_void_p(w.data_ptr()),
+                                          C.byref(opts) if opts else None,
+                                          C.c_void_p(d.data_ptr()), C.byref(gn))
+        _check(rc, "yand_affine_normal")
+        return d, gn.value
+
+    def solve(self, c, target=None, w0=None, opts: yand_opts | None = None,
+              raise_on_warning: bool = False):
+        torch = _torch()
+        out = torch.empty(self.n, dtype=torch.float64, device="cuda")
+        w0d = _dev(w0, self.n) if w0 is not None else None
+        info = yand_info()
+        tg = C.byref(C.c_double(float(target))) if target is not None else None
+        rc = self._lib.yand_mvsk_solve(
+            self._h, _c4(c), tg,
+            C.c_void_p(w0d.data_ptr()) if w0d is not None else None,
+            C.byref(opts) if opts else None, C.c_void_p(out.data_ptr()),
+            C.byref(info))
+        _check(rc, "yand_mvsk_solve", warn_ok=not raise_on_warning)
+        return out, SolveInfo(**{k: getattr(info, k) for k, _ in yand_info._fields_})
+
+    def profile(self, enable: bool = True):
+        _check(self._lib.yand_profile_enable(self._h, int(enable)),
+               "yand_profile_enable")
+
+    def profile_read(self):
+        k = self._lib.yand_profile_read(self._h, -1, None, 0, None, None)
+        out = {}
+        for i in range(k):
+            name = C.create_string_buffer(64)
+            ms = C.c_double()
+            cnt = C.c_int64()
+            self._lib.yand_profile_read(self._h, i, name, 64, C.byref(ms),
+                                        C.byref(cnt))
+            out[name.value.decode()] = (ms.value, cnt.value)
+        return out
+
+
+def solve_R(R, c, target=None):
+    """Stateless solve (FP64 storage, direct solver, budget set)."""
+    torch = _torch()
+    lib = load()
+    R = _dev(R)
+    T, n = R.shape
+    out = torch.empty(n, dtype=torch.float64, device="cuda")
+    tg = C.byref(C.c_double(float(target))) if target is not None else None
+    rc = lib.yand_mvsk_solve_R(C.c_void_p(R.data_ptr()), T, n, *map(float, c),
+                               tg, C.c_void_p(out.data_ptr()))
+    _check(rc, "yand_mvsk_solve_R", warn_ok=True)
+    return out

@@ -1,0 +1,106 @@
+// Kernel launchers of libyand (internal).
+#pragma once
+
+#include "common.h"
+
+namespace yand {
+
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+typedef double f64x4 __attribute__((ext_vector_type(4)));
+
+template <typename S> struct Vec16;
+template <> struct Vec16<double> { static constexpr int N = 2; };
+template <> struct Vec16<float> { static constexpr int N = 4; };
+template <> struct Vec16<bf16_t> { static constexpr int N = 8; };
+
+template <typename S>
+__device__ __forceinline__ void unpack16(const u32x4& raw,
+                                         double (&out)[Vec16<S>::N]);
+template <>
+__device__ __forceinline__ void unpack16<double>(const u32x4& raw,
+                                                 double (&out)[2]) {
+  out[0] = __hiloint2double((int)raw.y, (int)raw.x);
+  out[1] = __hiloint2double((int)raw.w, (int)raw.z);
+}
+template <>
+__device__ __forceinline__ void unpack16<float>(const u32x4& raw,
+                                                double (&out)[4]) {
+  out[0] = (double)__uint_as_float(raw.x);
+  out[1] = (double)__uint_as_float(raw.y);
+  out[2] = (double)__uint_as_float(raw.z);
+  out[3] = (double)__uint_as_float(raw.w);
+}
+template <>
+__device__ __forceinline__ void unpack16<bf16_t>(const u32x4& raw,
+                                                 double (&out)[8]) {
+  const uint32_t w[4] = {raw.x, raw.y, raw.z, raw.w};
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    out[2 * i] = (double)__uint_as_float(w[i] << 16);
+    out[2 * i + 1] = (double)__uint_as_float(w[i] & 0xffff0000u);
+  }
+}
+
+constexpr int kMaxSums = 16;       // scalar partial sums per pass workgroup
+constexpr int kMaxPassChunks = 8;  // 16-byte chunks per thread per row
+
+enum class PassKind { Oracle, Value, Hvp, Line, Dot, Third };
+
+struct PassArgs {
+  const void* A;        // Tp x lda, storage precision
+  int64_t lda;
+  int64_t Tp;
+  int64_t n;
+  int64_t rows_per_wg;  // set by the launcher
+  const double* v;      // dot operand (n)
+  const double* zc;     // cached z = Ax (Tp)
+  const double* q;      // per-row input (Tp)
+  double* tout;         // per-row output (Tp), may be null for Hvp/Line
+  double* part;         // [nwg][lda] back-projection partials
+  double* psums;        // [nwg][kMaxSums] scalar partials
+  Coef c;
+  double invT;
+};
+
+int pass_groups(int64_t Tp, int R, int64_t* rows_per_wg);
+int64_t max_pass_columns(int precision);
+hipError_t launch_pass(int precision, PassKind kind, const PassArgs& a,
+                       hipStream_t st, int* nwg);
+hipError_t launch_reduce_partials(const double* part, int nwg, int64_t lda,
+                                  int64_t n, double alpha, double beta,
+                                  const double* y, double* out,
+                                  hipStream_t st);
+hipError_t launch_reduce_sums(const double* psums, int nwg, int nsum,
+                              double* out, hipStream_t st);
+hipError_t launch_center(const double* R, int64_t T, int64_t n, int64_t ldr,
+                         int precision, void* A, int64_t Tp, int64_t lda,
+                         double* mu, double* scratch, int* nonfinite,
+                         hipStream_t st);
+
+// ---- dense FP64 MFMA kernels (dense.hip) ----------------------------------
+constexpr int kTile = 128;  // output tile and Cholesky block size
+
+// B = A^T diag(s) A / 1 (full symmetric n x n, ldb = lda), s length Tp.
+hipError_t launch_syrk(int precision, const void* A, int64_t lda, int64_t Tp,
+                       const double* s, double* B, hipStream_t st);
+// In-place Cholesky of the lower triangle of M (np x np, np multiple of
+// kTile) and X = L^-1 (lower; X must be zero on entry).  *fail != 0 on exit
+// when a pivot was not positive.
+hipError_t launch_potrf_trtri(double* M, double* X, int64_t np, int* fail,
+                              hipStream_t st);
+// rn[J][t] = sum_{j in tile J} (sum_k A[t][k] X[j][k])^2  (X lower)
+hipError_t launch_trace_gemm(int precision, const void* A, int64_t lda,
+                             int64_t Tp, const double* X, int64_t np,
+                             double* rn, hipStream_t st);
+// y = X v (lower), y = X^T v (transposed); X is np x np.  part holds
+// ceil(n/64) * n doubles of partial sums for the transposed product.
+hipError_t launch_trmv(const double* X, int64_t np, int64_t n,
+                       const double* v, double* y, double* part, bool trans,
+                       hipStream_t st);
+// W[:, a] = B E[:, a] for a < p (E is n x p column-major with ld n).
+hipError_t launch_symm_multi(const double* B, int64_t ldb, int64_t n,
+                             const double* E, int p, double* W,
+                             hipStream_t st);
+
+
+}  // namespace yand

@@ -1,0 +1,412 @@
+// Streaming passes over the centered return matrix A (HBM-bound kernels).
+//
+// Every oracle quantity of the exact sample oracle (Proposition "Exact
+// operator representation", equations (operator-f) to (operator-third)) and
+// every line-search power sum (Proposition "Quartic exact line search from
+// sample power sums") is one read of A: a row dot a_t^T v, a scalar function
+// of the row results, and a weighted back-projection sum_t omega_t a_t.
+//
+// Layout: A is row-major, Tp x lda (Tp = T rounded up to kRowPad, lda = n
+// rounded up to kColPad), zero in the padding.  A 1024-thread workgroup owns a
+// contiguous band of rows; each thread owns NCH 16-byte column chunks of every
+// row, keeps the dot operand for those chunks in registers, and accumulates its
+// columns of the back-projection in FP64 registers.  The row dot is reduced
+// across the workgroup in a fixed order (wave butterfly, then the 16 wave
+// results in order), so results are bit-reproducible.  Each workgroup writes
+// one FP64 partial row; reduce_partials sums them in workgroup order.
+#include "common.h"
+#include "kernels.h"
+
+namespace yand {
+
+// ------------------------------------------------------------- centering --
+
+// Column partial sums of R over a chunk of rows (a1: mu = T^-1 R^T 1).
+__global__ void colsum_kernel(const double* __restrict__ R, int64_t T,
+                              int64_t n, int64_t ldr, int64_t chunk,
+                              double* __restrict__ part) {
+  int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  int64_t t0 = (int64_t)blockIdx.y * chunk;
+  if (j >= n) return;
+  int64_t t1 = t0 + chunk < T ? t0 + chunk : T;
+  double s = 0.0;
+  for (int64_t t = t0; t < t1; ++t) s += R[t * ldr + j];
+  part[(int64_t)blockIdx.y * n + j] = s;
+}
+
+__global__ void colsum_finish_kernel(const double* __restrict__ part,
+                                     int64_t nchunks, int64_t n, int64_t T,
+                                     double* __restrict__ mu,
+                                     int* __restrict__ nonfinite) {
+  int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= n) return;
+  double s = 0.0;
+  for (int64_t b = 0; b < nchunks; ++b) s += part[b * n + j];
+  double m = s / (double)T;
+  mu[j] = m;
+  if (!isfinite(m)) atomicOr(nonfinite, 1);
+}
+
+// A = R - 1 mu^T rounded to the storage type; zero padding.
+template <typename S>
+__global__ void center_convert_kernel(const double* __restrict__ R, int64_t T,
+                                      int64_t n, int64_t ldr,
+                                      const double* __restrict__ mu,
+                                      S* __restrict__ A, int64_t lda,
+                                      int64_t Tp) {
+  for (int64_t t = blockIdx.y; t < Tp; t += gridDim.y) {
+    for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < lda;
+         j += (int64_t)gridDim.x * blockDim.x) {
+      double v = (t < T && j < n) ? R[t * ldr + j] - mu[j] : 0.0;
+      A[t * lda + j] = StoreConv<S>::from(v);
+    }
+  }
+}
+
+// -------------------------------------------------------------- the pass --
+
+// Per-row scalar work of each pass.  s is the finished row dot (if any),
+// t the row index; the op returns the back-projection weight and updates its
+// running scalar sums (kept by thread 0 only).
+struct OpOracle {   // a2: z = Ax, psi'(z)/T, sum z^2, z^3, z^4
+  static constexpr bool kDot = true, kBack = true;
+  static constexpr int kSums = 3;
+  __device__ static double row(const PassArgs& a, int64_t t, double s,
+                               double* sums, bool lead) {
+    if (lead) {
+      a.tout[t] = s;
+      double s2 = s * s;
+      sums[0] += s2;
+      sums[1] += s2 * s;
+      sums[2] += s2 * s2;
+    }
+    return dpsi(a.c, s) * a.invT;
+  }
+};
+struct OpValue {    // z = Ax and sum z^2, z^3, z^4 only
+  static constexpr bool kDot = true, kBack = false;
+  static constexpr int kSums = 3;
+  __device__ static double row(const PassArgs& a, int64_t t, double s,
+                               double* sums, bool lead) {
+    return OpOracle::row(a, t, s, sums, lead);
+  }
+};
+struct OpHvp {      // a4: psi''(z_t) (Av)_t / T; (Av)_t optionally stored
+  static constexpr bool kDot = true, kBack = true;
+  static constexpr int kSums = 0;
+  __device__ static double row(const PassArgs& a, int64_t t, double s,
+                               double*, bool lead) {
+    if (lead && a.tout) a.tout[t] = s;
+    return d2psi(a.c, a.zc[t]) * s * a.invT;
+  }
+};
+struct OpLine {     // a8: w = Ad and the nine mixed power sums with z
+  static constexpr bool kDot = true, kBack = false;
+  static constexpr int kSums = 9;
+  __device__ static double row(const PassArgs& a, int64_t t, double w,
+                               double* sums, bool lead) {
+    if (lead) {
+      if (a.tout) a.tout[t] = w;
+      double z = a.zc[t];
+      double z2 = z * z, w2 = w * w;
+      sums[0] += z * w;        // s11
+      sums[1] += z2 * w;       // s21
+      sums[2] += z2 * z * w;   // s31
+      sums[3] += w2;           // s02
+      sums[4] += z * w2;       // s12
+      sums[5] += z2 * w2;      // s22
+      sums[6] += w2 * w;       // s03
+      sums[7] += z * w2 * w;   // s13
+      sums[8] += w2 * w2;      // s04
+    }
+    return 0.0;
+  }
+};
+struct OpDot {      // plain row dot (Av)_t, stored
+  static constexpr bool kDot = true, kBack = false;
+  static constexpr int kSums = 0;
+  __device__ static double row(const PassArgs& a, int64_t t, double s,
+                               double*, bool lead) {
+    if (lead) a.tout[t] = s;
+    return 0.0;
+  }
+};
+struct OpThird {    // a6: psi'''(z_t) q_t / T (third-order back-projection)
+  static constexpr bool kDot = false, kBack = true;
+  static constexpr int kSums = 0;
+  __device__ static double row(const PassArgs& a, int64_t t, double,
+                               double*, bool) {
+    return d3psi(a.c, a.zc[t]) * a.q[t] * a.invT;
+  }
+};
+
+template <typename S, int NCH, int R, class Op>
+__global__ void __launch_bounds__(kPassThreads)
+pass_kernel(PassArgs a) {
+  constexpr int VEC = Vec16<S>::N;
+  __shared__ double red[2][R][kPassWaves];
+  const int tid = threadIdx.x;
+  const int wave = tid >> 6, lane = tid & 63;
+  const int64_t nvec = a.lda / VEC;   // 16-byte chunks per row
+  const int64_t row0 = (int64_t)blockIdx.x * a.rows_per_wg;
+  int64_t row1 = row0 + a.rows_per_wg;
+  if (row1 > a.Tp) row1 = a.Tp;
+  const char* base = (const char*)a.A;
+  const int64_t row_bytes = a.lda * (int64_t)sizeof(S);
+
+  bool valid[NCH];
+  double v[NCH][VEC];
+  double acc[NCH][VEC];
+#pragma unroll
+  for (int k = 0; k < NCH; ++k) {
+    int64_t c = tid + (int64_t)k * kPassThreads;
+    valid[k] = c < nvec;
+#pragma unroll
+    for (int e = 0; e < VEC; ++e) {
+      int64_t j = c * VEC + e;
+      v[k][e] = (Op::kDot && valid[k] && j < a.n) ? a.v[j] : 0.0;
+      acc[k][e] = 0.0;
+    }
+  }
+  double sums[Op::kSums > 0 ? Op::kSums : 1];
+#pragma unroll
+  for (int i = 0; i < (Op::kSums > 0 ? Op::kSums : 1); ++i) sums[i] = 0.0;
+
+  u32x4 cur[R][NCH], nxt[R][NCH];
+  auto load_block = [&](int64_t r0, u32x4 (&dst)[R][NCH]) {
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      const u32x4* rowp = (const u32x4*)(base + (r0 + r) * row_bytes);
+#pragma unroll
+      for (int k = 0; k < NCH; ++k) {
+        int64_t c = tid + (int64_t)k * kPassThreads;
+        dst[r][k] = valid[k] ? __builtin_nontemporal_load(rowp + c)
+                             : u32x4{0u, 0u, 0u, 0u};
+      }
+    }
+  };
+
+  if (row0 < row1) load_block(row0, cur);
+  int parity = 0;
+  for (int64_t r0 = row0; r0 < row1; r0 += R) {
+    if (r0 + R < row1) load_block(r0 + R, nxt);
+    double s[R];
+    if constexpr (Op::kDot) {
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+        double p = 0.0;
+#pragma unroll
+        for (int k = 0; k < NCH; ++k) {
+          double x[VEC];
+          unpack16<S>(cur[r][k], x);
+#pragma unroll
+          for (int e = 0; e < VEC; ++e) p = fma(x[e], v[k][e], p);
+        }
+        p = wave_sum(p);
+        if (lane == 0) red[parity][r][wave] = p;
+      }
+      __syncthreads();
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+        double p = 0.0;
+#pragma unroll
+        for (int w = 0; w < kPassWaves; ++w) p += red[parity][r][w];
+        s[r] = p;
+      }
+      parity ^= 1;
+    } else {
+#pragma unroll
+      for (int r = 0; r < R; ++r) s[r] = 0.0;
+    }
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      double om = Op::row(a, r0 + r, s[r], sums, tid == 0);
+      if constexpr (Op::kBack) {
+#pragma unroll
+        for (int k = 0; k < NCH; ++k) {
+          double x[VEC];
+          unpack16<S>(cur[r][k], x);
+#pragma unroll
+          for (int e = 0; e < VEC; ++e) acc[k][e] = fma(om, x[e], acc[k][e]);
+        }
+      }
+    }
+#pragma unroll
+    for (int r = 0; r < R; ++r)
+#pragma unroll
+      for (int k = 0; k < NCH; ++k) cur[r][k] = nxt[r][k];
+  }
+
+  if constexpr (Op::kBack) {
+    double* prow = a.part + (int64_t)blockIdx.x * a.lda;
+#pragma unroll
+    for (int k = 0; k < NCH; ++k) {
+      if (!valid[k]) continue;
+      int64_t c = tid + (int64_t)k * kPassThreads;
+#pragma unroll
+      for (int e = 0; e < VEC; ++e) prow[c * VEC + e] = acc[k][e];
+    }
+  }
+  if constexpr (Op::kSums > 0) {
+    if (tid == 0) {
+#pragma unroll
+      for (int i = 0; i < Op::kSums; ++i)
+        a.psums[(int64_t)blockIdx.x * kMaxSums + i] = sums[i];
+    }
+  }
+}
+
+// out[j] = alpha * sum_b part[b][j] + beta * y[j]   (j < n, fixed order)
+__global__ void reduce_partials_kernel(const double* __restrict__ part,
+                                       int nwg, int64_t lda, int64_t n,
+                                       double alpha, double beta,
+                                       const double* __restrict__ y,
+                                       double* __restrict__ out) {
+  int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= n) return;
+  double s = 0.0;
+  for (int b = 0; b < nwg; ++b) s += part[(int64_t)b * lda + j];
+  double r = alpha * s;
+  if (y) r += beta * y[j];
+  out[j] = r;
+}
+
+// sums[i] = sum_b psums[b][i] for i < nsum (one wave per sum, fixed order).
+__global__ void reduce_sums_kernel(const double* __restrict__ psums, int nwg,
+                                   int nsum, double* __restrict__ out) {
+  int i = blockIdx.x;
+  if (i >= nsum) return;
+  int lane = threadIdx.x;
+  double s = 0.0;
+  for (int b = lane; b < nwg; b += 64) s += psums[(int64_t)b * kMaxSums + i];
+  s = wave_sum(s);
+  if (lane == 0) out[i] = s;
+}
+
+// ------------------------------------------------------------ launchers --
+
+int pass_groups(int64_t Tp, int R, int64_t* rows_per_wg) {
+  int64_t blocks = Tp / R;
+  int64_t nwg = blocks < kMaxPassGroups ? blocks : kMaxPassGroups;
+  int64_t bpw = (blocks + nwg - 1) / nwg;
+  *rows_per_wg = bpw * R;
+  return (int)((Tp + *rows_per_wg - 1) / *rows_per_wg);
+}
+
+template <typename S, class Op, int R>
+static hipError_t launch_nch(int nch, PassArgs a, int nwg, hipStream_t st) {
+  dim3 g(nwg), b(kPassThreads);
+  switch (nch) {
+#define YAND_NCH_CASE(K)                                                  \
+  case K:                                                               \
+    hipLaunchKernelGGL((pass_kernel<S, K, R, Op>), g, b, 0, st, a);     \
+    break;
+    YAND_NCH_CASE(1)
+    YAND_NCH_CASE(2)
+    YAND_NCH_CASE(3)
+    YAND_NCH_CASE(4)
+    YAND_NCH_CASE(5)
+    YAND_NCH_CASE(6)
+    YAND_NCH_CASE(7)
+    YAND_NCH_CASE(8)
+#undef YAND_NCH_CASE
+    default:
+      return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+template <typename S> constexpr int rows_per_block() {
+  return sizeof(S) == 8 ? 2 : 4;
+}
+
+template <typename S>
+static hipError_t launch_pass_t(PassKind kind, PassArgs a, hipStream_t st,
+                                int* nwg_out) {
+  constexpr int R = rows_per_block<S>();
+  constexpr int VEC = Vec16<S>::N;
+  int64_t nvec = a.lda / VEC;
+  int nch = (int)((nvec + kPassThreads - 1) / kPassThreads);
+  if (nch < 1) nch = 1;
+  if (nch > kMaxPassChunks) return hipErrorInvalidValue;
+  int nwg = pass_groups(a.Tp, R, &a.rows_per_wg);
+  *nwg_out = nwg;
+  switch (kind) {
+    case PassKind::Oracle: return launch_nch<S, OpOracle, R>(nch, a, nwg, st);
+    case PassKind::Value: return launch_nch<S, OpValue, R>(nch, a, nwg, st);
+    case PassKind::Hvp: return launch_nch<S, OpHvp, R>(nch, a, nwg, st);
+    case PassKind::Line: return launch_nch<S, OpLine, R>(nch, a, nwg, st);
+    case PassKind::Dot: return launch_nch<S, OpDot, R>(nch, a, nwg, st);
+    case PassKind::Third: return launch_nch<S, OpThird, R>(nch, a, nwg, st);
+  }
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_pass(int precision, PassKind kind, const PassArgs& a,
+                       hipStream_t st, int* nwg) {
+  switch (precision) {
+    case 0: return launch_pass_t<double>(kind, a, st, nwg);
+    case 1: return launch_pass_t<float>(kind, a, st, nwg);
+    case 2: return launch_pass_t<bf16_t>(kind, a, st, nwg);
+  }
+  return hipErrorInvalidValue;
+}
+
+int64_t max_pass_columns(int precision) {
+  int vec = precision == 0 ? 2 : precision == 1 ? 4 : 8;
+  return (int64_t)kMaxPassChunks * kPassThreads * vec;
+}
+
+hipError_t launch_reduce_partials(const double* part, int nwg, int64_t lda,
+                                  int64_t n, double alpha, double beta,
+                                  const double* y, double* out,
+                                  hipStream_t st) {
+  dim3 b(256), g((unsigned)((n + 255) / 256));
+  hipLaunchKernelGGL(reduce_partials_kernel, g, b, 0, st, part, nwg, lda, n,
+                     alpha, beta, y, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_reduce_sums(const double* psums, int nwg, int nsum,
+                              double* out, hipStream_t st) {
+  hipLaunchKernelGGL(reduce_sums_kernel, dim3(nsum), dim3(64), 0, st, psums,
+                     nwg, nsum, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_center(const double* R, int64_t T, int64_t n, int64_t ldr,
+                         int precision, void* A, int64_t Tp, int64_t lda,
+                         double* mu, double* scratch, int* nonfinite,
+                         hipStream_t st) {
+  const int64_t chunk = 256;
+  int64_t nchunks = (T + chunk - 1) / chunk;
+  dim3 b(256);
+  dim3 g1((unsigned)((n + 255) / 256), (unsigned)nchunks);
+  hipLaunchKernelGGL(colsum_kernel, g1, b, 0, st, R, T, n, ldr, chunk,
+                     scratch);
+  dim3 g2((unsigned)((n + 255) / 256));
+  hipLaunchKernelGGL(colsum_finish_kernel, g2, b, 0, st, scratch, nchunks, n,
+                     T, mu, nonfinite);
+  int64_t gx = (lda + 255) / 256;
+  if (gx > 64) gx = 64;
+  dim3 g3((unsigned)gx, (unsigned)(Tp < 16384 ? Tp : 16384));
+  switch (precision) {
+    case 0:
+      hipLaunchKernelGGL(center_convert_kernel<double>, g3, b, 0, st, R, T, n,
+                         ldr, mu, (double*)A, lda, Tp);
+      break;
+    case 1:
+      hipLaunchKernelGGL(center_convert_kernel<float>, g3, b, 0, st, R, T, n,
+                         ldr, mu, (float*)A, lda, Tp);
+      break;
+    case 2:
+      hipLaunchKernelGGL(center_convert_kernel<bf16_t>, g3, b, 0, st, R, T,
+                         n, ldr, mu, (bf16_t*)A, lda, Tp);
+      break;
+    default:
+      return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+}  // namespace yand

@@ -1,0 +1,58 @@
+// Device-resident scalars and the small-kernel launchers (internal).
+#pragma once
+
+#include "common.h"
+
+namespace yand {
+
+// Scalars of one solve, kept on the device and read back once per iteration.
+struct DevScalars {
+  double f;          // objective at the current point
+  double gn;         // |projected gradient|
+  double mux;        // mu^T x
+  double mom[4];     // m1..m4
+  double tr;         // trace of B
+  double gamma;      // scale of the (I - P_S) block of M
+  double tang_scale; // mean diagonal of the tangent Hessian
+  double lambda;     // absolute regularisation
+  double GE[9];      // E^T B E
+  double mud;        // mu^T d
+  double coef[5];    // A0..A4
+  double amax;       // feasibility cap
+  double alpha;      // chosen step
+  double aux[4];     // PCG dots
+  int status;        // quartic step status (0 or -6)
+  int fail;          // Cholesky pivot failure
+  int nonfinite;     // NaN/Inf seen
+  int pad;
+};
+
+hipError_t launch_grad_project(const double* g, double* E, int p0, int64_t n,
+                               DevScalars* sc, hipStream_t st);
+hipError_t launch_trace_scale(const double* B, int64_t ld, int64_t n,
+                              const double* E, const double* W, int p,
+                              double reg, DevScalars* sc, hipStream_t st);
+hipError_t launch_project(const double* B, double* M, int64_t ld, int64_t n,
+                          int64_t np, const double* E, const double* W, int p,
+                          const DevScalars* sc, hipStream_t st);
+hipError_t launch_trace_weight(const double* rn, int nt, int64_t Tp,
+                               const double* AE, int p, const DevScalars* sc,
+                               double* q, hipStream_t st);
+hipError_t launch_rhs(const double* Bnu, const double* t3, const double* E,
+                      int p, int64_t n, double mp1, const DevScalars* sc,
+                      double* r, hipStream_t st);
+hipError_t launch_direction(const double* y, const double* E, int p,
+                            int64_t n, const double* x, const double* mu,
+                            double tau, int simplex, double* d,
+                            DevScalars* sc, hipStream_t st);
+hipError_t launch_coef_step(const double* sums, double invT, Coef c,
+                            int select, DevScalars* sc, hipStream_t st);
+hipError_t launch_select_step(DevScalars* sc, hipStream_t st);
+hipError_t launch_objective(const double* sums, double invT, Coef c,
+                            DevScalars* sc, hipStream_t st);
+hipError_t launch_dot(const double* u, const double* v, int64_t n, double* out,
+                      hipStream_t st);
+hipError_t launch_axpy(double* x, const double* d, int64_t n,
+                       const DevScalars* sc, hipStream_t st);
+
+}  // namespace yand

@@ -1,0 +1,65 @@
+"""CPU-side checks of the C-ABI library: it loads, exports every entry point
+the header declares, and its host-only helpers agree with the paper."""
+
+import ctypes as C
+import os
+import re
+
+import numpy as np
+import pytest
+
+import oracle as O
+import synth
+from paper_2604_25378_amd import binding
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "yand.h")
+
+
+def _declared():
+    text = open(HEADER).read()
+    return sorted(set(re.findall(r"\b(yand_[a-z0-9_]+)\s*\(", text)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(binding.LIB_PATH):
+        pytest.fail("libyand.so is not built (run __graft_entry__.build())")
+    return binding.load()
+
+
+def test_header_symbols_exported(lib):
+    names = _declared()
+    assert "yand_mvsk_solve" in names and "yand_hvp" in names
+    for name in names:
+        assert hasattr(lib, name), name
+
+
+def test_certified_convex_matches_paper(lib, golden_dir):
+    rows = np.atleast_2d(np.loadtxt(f"{golden_dir}/crra_calibration.txt"))
+    for g, *cv in rows:
+        assert binding.is_certified_convex(cv)
+    for g in (0.5, 2.0, 4.0, 10.0):
+        c = synth.crra_coefficients(g)
+        assert binding.is_certified_convex(c) == O.certified_convex(c)
+    assert not binding.is_certified_convex([10, 1, 10, 1])
+    assert not binding.is_certified_convex([1, 1, 1, 0])
+
+
+def test_default_opts_follow_parameter_table(lib):
+    o = binding.default_opts()
+    assert (o.solver, o.max_iter, o.eps, o.tau) == (0, 300, 1e-8, 1e-8)
+    lg = binding.default_opts(large=True)
+    assert (lg.solver, lg.max_iter, lg.max_elapsed) == (1, 40, 60.0)
+    assert (lg.krylov_tol, lg.krylov_maxit, lg.regularization) == (1e-3, 15, 1e-4)
+    assert lg.restart_max_iter == 120 and lg.stall_recovery == 1
+
+
+def test_create_rejects_bad_arguments_without_device(lib):
+    h = C.c_void_p()
+    # null returns / bad sizes are rejected before any device work
+    assert lib.yand_create(None, 10, 4, 4, 0, None, C.byref(h)) == -1
+    assert lib.yand_create(C.c_void_p(8), 1, 4, 4, 0, None, C.byref(h)) == -1
+    assert lib.yand_create(C.c_void_p(8), 10, 4, 3, 0, None, C.byref(h)) == -1
+    assert lib.yand_create(C.c_void_p(8), 10, 4, 4, 7, None, C.byref(h)) == -1
+    assert h.value is None
