@@ -214,81 +214,182 @@ trace_gemm_kernel(const S* __restrict__ A, int64_t lda, int64_t Tp,
 }
 
 // ------------------------------------------------------ blocked Cholesky --
-// Diagonal block k: unblocked Cholesky in LDS, then its triangular inverse.
-// L_kk is written to M (lower), L_kk^-1 to the diagonal block of X.
-__global__ void __launch_bounds__(1024) diag_block_kernel(double* M, double* X,
-                                                          int64_t ld, int k,
-                                                          int* fail) {
-  extern __shared__ double L[];          // BM * BM
-  __shared__ double dg[BM], xcol[BM];
-  const int tid = threadIdx.x;
+// Diagonal block k: Cholesky of the 128 x 128 block in LDS and its inverse,
+// blocked in 32-column sub-panels.  Wave 0 factors and inverts each 32 x 32
+// diagonal sub-block in registers (lane r owns row r; column values move by
+// lane shuffles); the panel below is L21 = A21 X11^T and the trailing update
+// A22 -= L21 L21^T, both spread over all threads.  The inverse is assembled
+// from the last sub-panel: X21 = -(X22 L21) X11.  X11 blocks are parked
+// transposed in the free upper triangle.  L_kk goes to M (lower) and L_kk^-1
+// to the diagonal block of X.  LDS rows are padded to 129 doubles.
+constexpr int DT = 512;      // threads of the diagonal-block kernel
+constexpr int SB = 32;       // sub-panel width
+constexpr int LDD = BM + 1;  // padded LDS row
+
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
+  __builtin_amdgcn_wave_barrier();
+}
+
+__global__ void __launch_bounds__(DT) diag_block_kernel(double* M, double* X,
+                                                        int64_t ld, int k,
+                                                        int* fail) {
+  extern __shared__ double L[];  // BM x LDD
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   double* Mk = M + (int64_t)k * BM * ld + (int64_t)k * BM;
   double* Xk = X + (int64_t)k * BM * ld + (int64_t)k * BM;
-  for (int idx = tid; idx < BM * BM; idx += 1024)
-    L[idx] = Mk[(int64_t)(idx / BM) * ld + idx % BM];
-  __syncthreads();
-  // Right-looking: step j reads column j (rows > j, unscaled) and the pivot,
-  // updates the trailing lower triangle, and parks the scaled column in the
-  // (unused) upper triangle L[j][i].
-  for (int j = 0; j < BM; ++j) {
-    double p = L[j * BM + j];
-    bool bad = !(p > 0.0) || !isfinite(p);
-    if (bad) p = 1.0;
-    const double piv = sqrt(p), inv_p = 1.0 / p, inv_piv = 1.0 / piv;
-    if (tid == 0) {
-      dg[j] = piv;
-      if (bad) atomicOr(fail, 1);
+  constexpr int PER = BM * BM / DT;   // 32 elements per thread
+  {
+    double v[PER];
+#pragma unroll
+    for (int q = 0; q < PER; ++q) {
+      const int idx = tid + q * DT, i = idx / BM, c = idx % BM;
+      v[q] = c <= i ? Mk[(int64_t)i * ld + c] : 0.0;
     }
-    const int rem = BM - j - 1;
-    for (int idx = tid; idx < rem * rem; idx += 1024) {
-      int i = idx / rem, c = idx % rem;
+#pragma unroll
+    for (int q = 0; q < PER; ++q) {
+      const int idx = tid + q * DT, i = idx / BM, c = idx % BM;
+      L[i * LDD + c] = v[q];
+    }
+  }
+  __syncthreads();
+  for (int c0 = 0; c0 < BM; c0 += SB) {
+    if (wave == 0) {
+      const int r = lane & (SB - 1);
+      double a[SB];
+#pragma unroll
+      for (int j = 0; j < SB; ++j) a[j] = L[(c0 + r) * LDD + c0 + j];
+      bool bad = false;
+#pragma unroll
+      for (int j = 0; j < SB; ++j) {
+        double p = __shfl(a[j], j, 64);
+        if (!(p > 0.0) || !isfinite(p)) {
+          bad = true;
+          p = 1.0;
+        }
+        const double piv = sqrt(p);
+        if (r == j) a[j] = piv;
+        if (r > j) a[j] /= piv;
+#pragma unroll
+        for (int c = j + 1; c < SB; ++c) {
+          const double lcj = __shfl(a[j], c, 64);
+          if (c <= r) a[c] -= a[j] * lcj;
+        }
+      }
+      if (bad && lane == 0) atomicOr(fail, 1);
+      if (lane < SB) {
+#pragma unroll
+        for (int j = 0; j < SB; ++j)
+          if (j <= r) L[(c0 + r) * LDD + c0 + j] = a[j];
+      }
+      wave_sync();
+      // column r of X11 = L11^-1 by forward substitution (lane r -> column
+      // r): X11[i][r] for i > r is parked at (c0 + r, c0 + i), in the free
+      // upper part of row r, and read back from there.
+      if (lane < SB) {
+        double* pr = L + (c0 + r) * LDD + c0;
+        const double xr = 1.0 / pr[r];
+        for (int i = r + 1; i < SB; ++i) {
+          const double* li = L + (c0 + i) * LDD + c0;
+          double v = li[r] * xr;
+#pragma unroll 4
+          for (int m = r + 1; m < i; ++m) v += li[m] * pr[m];
+          pr[i] = -v / li[i];
+        }
+      }
+    }
+    __syncthreads();
+    const int r0 = c0 + SB, rem = BM - r0;
+    if (rem == 0) break;
+    // L21[i][j] = sum_{m<=j} A21[i][m] X11[j][m]; results staged in registers
+    {
+      constexpr int MAXO = (BM - SB) * SB / DT;   // 6
+      double o[MAXO];
+#pragma unroll
+      for (int q = 0; q < MAXO; ++q) {
+        const int idx = tid + q * DT, i = idx / SB, j = idx % SB;
+        double v = 0.0;
+        if (i < rem) {
+          const double* ai = L + (r0 + i) * LDD + c0;
+          for (int m = 0; m < j; ++m)
+            v += ai[m] * L[(c0 + m) * LDD + c0 + j];   // X11[j][m], m < j
+          v += ai[j] / L[(c0 + j) * LDD + c0 + j];     // X11[j][j]
+        }
+        o[q] = v;
+      }
+      __syncthreads();
+#pragma unroll
+      for (int q = 0; q < MAXO; ++q) {
+        const int idx = tid + q * DT, i = idx / SB, j = idx % SB;
+        if (i < rem) L[(r0 + i) * LDD + c0 + j] = o[q];
+      }
+    }
+    __syncthreads();
+    // trailing update A22 -= L21 L21^T (lower part)
+    for (int idx = tid; idx < rem * rem; idx += DT) {
+      const int i = r0 + idx / rem, c = r0 + idx % rem;
       if (c > i) continue;
-      int gi = j + 1 + i, gc = j + 1 + c;
-      L[gi * BM + gc] -= L[gi * BM + j] * L[gc * BM + j] * inv_p;
+      const double* li = L + i * LDD + c0;
+      const double* lc = L + c * LDD + c0;
+      double v = 0.0;
+#pragma unroll 8
+      for (int m = 0; m < SB; ++m) v += li[m] * lc[m];
+      L[i * LDD + c] -= v;
     }
-    for (int i = j + 1 + tid; i < BM; i += 1024)
-      L[j * BM + i] = L[i * BM + j] * inv_piv;
     __syncthreads();
   }
-  // Assemble L (lower) from the parked columns: gather into registers, then
-  // (after every thread has read) write back in place and to M.
-  constexpr int kPer = BM * BM / 1024;
-  double lv[kPer];
-#pragma unroll
-  for (int q = 0; q < kPer; ++q) {
-    int idx = tid + q * 1024, i = idx / BM, c = idx % BM;
-    lv[q] = c < i ? L[c * BM + i] : (c == i ? dg[i] : 0.0);
+  // write L_kk (lower)
+  for (int idx = tid; idx < BM * BM; idx += DT) {
+    const int i = idx / BM, c = idx % BM;
+    Mk[(int64_t)i * ld + c] = c <= i ? L[i * LDD + c] : 0.0;
   }
   __syncthreads();
+  // ---- assemble the inverse, sub-panels from the last ---------------------
+  for (int c0 = BM - SB; c0 >= 0; c0 -= SB) {
+    const int r0 = c0 + SB, rem = BM - r0;
+    // T[i][c] = sum_{m<=i} X[r0+i][r0+m] L[r0+m][c0+c], parked at (c0+c, r0+i)
+    if (rem > 0) {
+      for (int idx = tid; idx < rem * SB; idx += DT) {
+        const int i = idx / SB, c = idx % SB;
+        const double* xi = L + (r0 + i) * LDD + r0;
+        double v = 0.0;
+        for (int m = 0; m <= i; ++m) v += xi[m] * L[(r0 + m) * LDD + c0 + c];
+        L[(c0 + c) * LDD + r0 + i] = v;
+      }
+    }
+    __syncthreads();
+    // move X11 into the lower part of the sub-block
+    {
+      double v[2];
 #pragma unroll
-  for (int q = 0; q < kPer; ++q) {
-    int idx = tid + q * 1024, i = idx / BM, c = idx % BM;
-    L[idx] = lv[q];
-    Mk[(int64_t)i * ld + c] = lv[q];
+      for (int q = 0; q < 2; ++q) {
+        const int idx = tid + q * DT, i = idx / SB, c = idx % SB;
+        v[q] = i > c ? L[(c0 + c) * LDD + c0 + i]
+                     : (i == c ? 1.0 / L[(c0 + i) * LDD + c0 + i] : 0.0);
+      }
+      __syncthreads();
+#pragma unroll
+      for (int q = 0; q < 2; ++q) {
+        const int idx = tid + q * DT, i = idx / SB, c = idx % SB;
+        if (i >= c) L[(c0 + i) * LDD + c0 + c] = v[q];
+      }
+    }
+    __syncthreads();
+    // X[r0+i][c0+c] = -sum_{m>=c} T[i][m] X11[m][c]
+    if (rem > 0) {
+      for (int idx = tid; idx < rem * SB; idx += DT) {
+        const int i = idx / SB, c = idx % SB;
+        double v = 0.0;
+        for (int m = c; m < SB; ++m)
+          v += L[(c0 + m) * LDD + r0 + i] * L[(c0 + m) * LDD + c0 + c];
+        L[(r0 + i) * LDD + c0 + c] = -v;
+      }
+    }
+    __syncthreads();
   }
-  __syncthreads();
-  // In-place inverse, columns from the last: Linv[j][j] = 1/L[j][j],
-  // Linv[j+1:, j] = -Linv[j][j] * Linv[j+1:, j+1:] L[j+1:, j].
-  for (int j = BM - 1; j >= 0; --j) {
-    if (tid < BM) xcol[tid] = tid > j ? L[tid * BM + j] : 0.0;
-    __syncthreads();
-    const double ajj = 1.0 / L[j * BM + j];
-    // 8 threads per row i > j, each a strided share of c in (j, i].
-    const int i = j + 1 + (tid >> 3), sub = tid & 7;
-    double s = 0.0;
-    if (i < BM)
-      for (int c = j + 1 + sub; c <= i; c += 8) s += L[i * BM + c] * xcol[c];
-    s += __shfl_xor(s, 1, 64);
-    s += __shfl_xor(s, 2, 64);
-    s += __shfl_xor(s, 4, 64);
-    __syncthreads();
-    if (i < BM && sub == 0) L[i * BM + j] = -ajj * s;
-    if (tid == 0) L[j * BM + j] = ajj;
-    __syncthreads();
-  }
-  for (int idx = tid; idx < BM * BM; idx += 1024) {
-    int i = idx / BM, c = idx % BM;
-    Xk[(int64_t)i * ld + c] = c <= i ? L[idx] : 0.0;
+  for (int idx = tid; idx < BM * BM; idx += DT) {
+    const int i = idx / BM, c = idx % BM;
+    Xk[(int64_t)i * ld + c] = c <= i ? L[i * LDD + c] : 0.0;
   }
 }
 
@@ -428,7 +529,7 @@ hipError_t launch_syrk(int precision, const void* A, int64_t lda, int64_t Tp,
 hipError_t launch_potrf_trtri(double* M, double* X, int64_t np, int* fail,
                               hipStream_t st) {
   const int nt = (int)(np / BM);
-  const size_t lds = (size_t)BM * BM * sizeof(double);
+  const size_t lds = (size_t)BM * LDD * sizeof(double);
   static bool attr_set = false;
   if (!attr_set) {
     hipError_t e = hipFuncSetAttribute(
@@ -438,7 +539,7 @@ hipError_t launch_potrf_trtri(double* M, double* X, int64_t np, int* fail,
     attr_set = true;
   }
   for (int k = 0; k < nt; ++k) {
-    hipLaunchKernelGGL(diag_block_kernel, dim3(1), dim3(1024), lds, st, M, X,
+    hipLaunchKernelGGL(diag_block_kernel, dim3(1), dim3(DT), lds, st, M, X,
                        np, k, fail);
     const int rem = nt - k - 1;
     if (rem > 0)

@@ -256,19 +256,28 @@ pass_kernel(PassArgs a) {
   }
 }
 
-// out[j] = alpha * sum_b part[b][j] + beta * y[j]   (j < n, fixed order)
-__global__ void reduce_partials_kernel(const double* __restrict__ part,
-                                       int nwg, int64_t lda, int64_t n,
-                                       double alpha, double beta,
-                                       const double* __restrict__ y,
-                                       double* __restrict__ out) {
-  int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (j >= n) return;
+// out[j] = alpha * sum_b part[b][j] + beta * y[j]   (j < n, fixed order):
+// 64 columns per workgroup, 16 row groups each summing a strided subset of the
+// partial rows, combined in group order.
+__global__ void __launch_bounds__(1024)
+reduce_partials_kernel(const double* __restrict__ part, int nwg, int64_t lda,
+                       int64_t n, double alpha, double beta,
+                       const double* __restrict__ y, double* __restrict__ out) {
+  __shared__ double sh[16][64];
+  const int x = threadIdx.x & 63, g = threadIdx.x >> 6;
+  const int64_t j = (int64_t)blockIdx.x * 64 + x;
   double s = 0.0;
-  for (int b = 0; b < nwg; ++b) s += part[(int64_t)b * lda + j];
-  double r = alpha * s;
-  if (y) r += beta * y[j];
-  out[j] = r;
+  if (j < n)
+    for (int b = g; b < nwg; b += 16) s += part[(int64_t)b * lda + j];
+  sh[g][x] = s;
+  __syncthreads();
+  if (g == 0 && j < n) {
+    double t = 0.0;
+    for (int i = 0; i < 16; ++i) t += sh[i][x];
+    double r = alpha * t;
+    if (y) r += beta * y[j];
+    out[j] = r;
+  }
 }
 
 // sums[i] = sum_b psums[b][i] for i < nsum (one wave per sum, fixed order).
@@ -361,7 +370,7 @@ hipError_t launch_reduce_partials(const double* part, int nwg, int64_t lda,
                                   int64_t n, double alpha, double beta,
                                   const double* y, double* out,
                                   hipStream_t st) {
-  dim3 b(256), g((unsigned)((n + 255) / 256));
+  dim3 b(1024), g((unsigned)((n + 63) / 64));
   hipLaunchKernelGGL(reduce_partials_kernel, g, b, 0, st, part, nwg, lda, n,
                      alpha, beta, y, out);
   return hipGetLastError();
