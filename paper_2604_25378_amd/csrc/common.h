@@ -15,8 +15,8 @@ namespace yand {
 constexpr int kRowPad = 128;
 constexpr int kColPad = 128;
 
-// Pass kernels: one 1024-thread workgroup per compute unit.
-constexpr int kPassThreads = 1024;
+// Pass kernels: one 512-thread workgroup per compute unit.
+constexpr int kPassThreads = 512;
 constexpr int kPassWaves = kPassThreads / 64;
 constexpr int kMaxPassGroups = 256;
 

@@ -7,11 +7,11 @@
 // of the row results, and a weighted back-projection sum_t omega_t a_t.
 //
 // Layout: A is row-major, Tp x lda (Tp = T rounded up to kRowPad, lda = n
-// rounded up to kColPad), zero in the padding.  A 1024-thread workgroup owns a
+// rounded up to kColPad), zero in the padding.  A 512-thread workgroup owns a
 // contiguous band of rows; each thread owns NCH 16-byte column chunks of every
 // row, keeps the dot operand for those chunks in registers, and accumulates its
 // columns of the back-projection in FP64 registers.  The row dot is reduced
-// across the workgroup in a fixed order (wave butterfly, then the 16 wave
+// across the workgroup in a fixed order (wave butterfly, then the 8 wave
 // results in order), so results are bit-reproducible.  Each workgroup writes
 // one FP64 partial row; reduce_partials sums them in workgroup order.
 #include "common.h"
