@@ -117,8 +117,8 @@ int yand_eval(yand_ctx* ctx, const double c[4], const double* w, double* f,
               double* grad, double mom[4]);
 
 /* Hessian-vector product hv = A^T (psi''(Aw) * Av) / T (equation
- * (operator-hvp)); w, v, hv device.  One fused pass over A after the pass that
- * caches z = Aw (skipped when w is the point of the previous call). */
+ * (operator-hvp)); w, v, hv device.  A value pass caches z = Aw, then one
+ * fused pass over A forms the product. */
 int yand_hvp(yand_ctx* ctx, const double c[4], const double* w,
              const double* v, double* hv);
 
@@ -153,6 +153,37 @@ int yand_affine_normal(yand_ctx* ctx, const double c[4], const double* target,
 int yand_mvsk_solve(yand_ctx* ctx, const double c[4], const double* target,
                     const double* w0, const yand_opts* opts, double* w_out,
                     yand_info* info);
+
+/* Batched efficient-frontier solve on one context (shared A): instance b
+ * minimises with preference vector C4[4b..4b+3] (host) and, when targets
+ * (host, length B) is not NULL, the return target targets[b].  Weights go to
+ * row b of W_out (device, B x n row-major); infos (host, length B) is
+ * nullable.  Instances advance together in lanes of up to 64 solves; after
+ * the first iteration one outer iteration of all lanes is replayed from a
+ * captured HIP graph, with one host synchronisation per iteration.  Direct
+ * configuration only (opts->solver must be YAND_SOLVER_DIRECT).  Returns the
+ * first error; per-instance status is in infos[b].status. */
+int yand_frontier_solve(yand_ctx* ctx, int64_t B, const double* C4,
+                        const double* targets, const yand_opts* opts,
+                        double* W_out, yand_info* infos);
+
+/* Batched solve over contexts that may differ (universes of uneven n):
+ * instance b runs on ctxs[b] (host array of B contexts on one device) and
+ * writes W_out[b] (host array of B device pointers, each n_b long).
+ * max_lanes bounds the solves advancing together (<= 0: 64); use_graph != 0
+ * replays captured iterations. */
+int yand_batch_solve(int64_t B, yand_ctx* const* ctxs, const double* C4,
+                     const double* targets, const yand_opts* opts,
+                     double* const* W_out, yand_info* infos, int max_lanes,
+                     int use_graph);
+
+/* Kernel timing on the context stream (instrumentation): enable != 0 starts
+ * recording HIP events around the main kernels; yand_profile_read(ctx, -1,
+ * ...) returns the number of recorded kernel names, and index i >= 0 fills
+ * the name, the total milliseconds and the launch count. */
+int yand_profile_enable(yand_ctx* ctx, int enable);
+int yand_profile_read(yand_ctx* ctx, int index, char* name, int name_len,
+                      double* total_ms, int64_t* count);
 
 /* Stateless wrapper: returns R (device, T x n contiguous) -> w_out (device),
  * FP64 storage, direct solver, budget set. */

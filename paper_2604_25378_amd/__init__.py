@@ -10,6 +10,7 @@ from .binding import (  # noqa: F401
     Context,
     SolveInfo,
     YandError,
+    batch_solve,
     default_opts,
     is_certified_convex,
     load,

@@ -90,6 +90,13 @@ def load(path: str = LIB_PATH):
         "yand_is_certified_convex": (C.c_int, [_D]),
         "yand_shape": (C.c_int, [vp, C.POINTER(C.c_int64),
                                  C.POINTER(C.c_int64), C.POINTER(C.c_int)]),
+        "yand_frontier_solve": (C.c_int, [vp, C.c_int64, _D, _D,
+                                          C.POINTER(yand_opts), vp,
+                                          C.POINTER(yand_info)]),
+        "yand_batch_solve": (C.c_int, [C.c_int64, C.POINTER(vp), _D, _D,
+                                       C.POINTER(yand_opts), C.POINTER(vp),
+                                       C.POINTER(yand_info), C.c_int,
+                                       C.c_int]),
         "yand_profile_enable": (C.c_int, [vp, C.c_int]),
         "yand_profile_read": (C.c_int, [vp, C.c_int, C.c_char_p, C.c_int, _D,
                                         C.POINTER(C.c_int64)]),
@@ -278,6 +285,29 @@ class Context:
         _check(rc, "yand_mvsk_solve", warn_ok=not raise_on_warning)
         return out, SolveInfo(**{k: getattr(info, k) for k, _ in yand_info._fields_})
 
+    def frontier(self, C4, targets=None, opts: yand_opts | None = None):
+        """Batched solve of B instances on this context's A (direct solver).
+
+        C4: B x 4 preference vectors; targets: B return targets or None.
+        Returns (W (B x n device tensor), [SolveInfo])."""
+        torch = _torch()
+        C4 = np.ascontiguousarray(np.asarray(C4, dtype=np.float64).reshape(-1, 4))
+        B = C4.shape[0]
+        W = torch.empty((B, self.n), dtype=torch.float64, device="cuda")
+        infos = (yand_info * B)()
+        tg = None
+        if targets is not None:
+            tga = np.ascontiguousarray(np.asarray(targets, dtype=np.float64))
+            if tga.shape[0] != B:
+                raise ValueError("targets must have one entry per instance")
+            tg = tga.ctypes.data_as(_D)
+        rc = self._lib.yand_frontier_solve(
+            self._h, B, C4.ctypes.data_as(_D), tg,
+            C.byref(opts) if opts else None, C.c_void_p(W.data_ptr()), infos)
+        _check(rc, "yand_frontier_solve", warn_ok=True)
+        return W, [SolveInfo(**{k: getattr(i, k) for k, _ in yand_info._fields_})
+                   for i in infos]
+
     def profile(self, enable: bool = True):
         _check(self._lib.yand_profile_enable(self._h, int(enable)),
                "yand_profile_enable")
@@ -293,6 +323,34 @@ class Context:
                                         C.byref(cnt))
             out[name.value.decode()] = (ms.value, cnt.value)
         return out
+
+
+def batch_solve(contexts, C4, targets=None, opts: yand_opts | None = None,
+                max_lanes: int = 64, use_graph: bool = True):
+    """Batched solve where instance b runs on contexts[b] (uneven universes).
+
+    Returns ([w_b device tensors], [SolveInfo])."""
+    torch = _torch()
+    lib = load()
+    C4 = np.ascontiguousarray(np.asarray(C4, dtype=np.float64).reshape(-1, 4))
+    B = C4.shape[0]
+    if len(contexts) != B:
+        raise ValueError("one context per instance")
+    outs = [torch.empty(cx.n, dtype=torch.float64, device="cuda")
+            for cx in contexts]
+    ctx_arr = (C.c_void_p * B)(*[cx._h.value for cx in contexts])
+    out_arr = (C.c_void_p * B)(*[o.data_ptr() for o in outs])
+    infos = (yand_info * B)()
+    tg = None
+    if targets is not None:
+        tga = np.ascontiguousarray(np.asarray(targets, dtype=np.float64))
+        tg = tga.ctypes.data_as(_D)
+    rc = lib.yand_batch_solve(B, ctx_arr, C4.ctypes.data_as(_D), tg,
+                              C.byref(opts) if opts else None, out_arr, infos,
+                              int(max_lanes), int(use_graph))
+    _check(rc, "yand_batch_solve", warn_ok=True)
+    return outs, [SolveInfo(**{k: getattr(i, k) for k, _ in yand_info._fields_})
+                  for i in infos]
 
 
 def solve_R(R, c, target=None):

@@ -1,6 +1,18 @@
-// libyand C-ABI: context, sample-oracle entry points and the YAND-MVSK solve
-// loop (Algorithm 1), driving the HIP kernels of pass.hip, dense.hip and
-// vec.hip on the caller's stream.
+// libyand C-ABI: contexts, sample-oracle entry points, the YAND-MVSK outer
+// loop (Algorithm 1) and the batched frontier solve, driving the HIP kernels
+// of pass.hip, dense.hip and vec.hip.
+//
+// State is split in two.  Data (per context, immutable after creation) holds
+// the centered matrix A at its storage precision, mu and the constraint frame.
+// A Work (per solve lane) holds every per-iterate buffer, the device-resident
+// scalars and a stream.  One outer iteration is enqueued as a fixed sequence
+// of kernels with no host synchronisation: the stationarity test sets a device
+// flag that makes the rest of the iteration return at once, and a failed
+// factorisation forces a zero step.  The host reads the scalars of all lanes
+// once per iteration and only then decides (stop, escalate the
+// regularisation, freeze a lane).  The batched frontier captures one
+// iteration of all lanes into a hipGraph and replays it.
+#include <algorithm>
 #include <chrono>
 #include <cstdlib>
 #include <cstring>
@@ -21,11 +33,14 @@ struct TimedLaunch {
   hipEvent_t a, b;
 };
 
-}  // namespace
+struct Prof {
+  bool on = false;
+  std::vector<TimedLaunch> timed;
+  std::vector<std::pair<std::string, std::pair<double, int64_t>>> acc;
+};
 
-struct yand_ctx {
+struct Data {
   int device = 0;
-  hipStream_t stream = nullptr;
   int precision = 0;
   int64_t T = 0, n = 0, Tp = 0, lda = 0, nt = 0;
   size_t esize = 8;
@@ -34,22 +49,33 @@ struct yand_ctx {
   double* Efix = nullptr;   // 2 x n: e1 = 1/sqrt(n), e2 = unit centred mu
   double* AEfix = nullptr;  // 2 x Tp: A e1, A e2
   bool have_e2 = false;
-  // per-iteration vectors
-  double *x = nullptr, *g = nullptr, *d = nullptr, *z = nullptr, *wv = nullptr,
-         *q = nullptr, *AE = nullptr, *E = nullptr, *W = nullptr,
-         *t3 = nullptr, *r = nullptr, *y = nullptr, *y2 = nullptr,
-         *hv = nullptr, *s_t = nullptr;
+  double mbar = 0.0, mnorm = 0.0;  // mean of mu and |mu - mbar|
+};
+
+struct Work {
+  hipStream_t st = nullptr;
+  bool own_stream = false;
+  double *x = nullptr, *g = nullptr, *d = nullptr, *z = nullptr,
+         *wv = nullptr, *q = nullptr, *AE = nullptr, *E = nullptr,
+         *W = nullptr, *t3 = nullptr, *r = nullptr, *y = nullptr,
+         *y2 = nullptr, *hv = nullptr, *s_t = nullptr;
   double *pcg_s = nullptr, *pcg_res = nullptr, *pcg_p = nullptr,
          *pcg_u = nullptr;
   double *part = nullptr, *psums = nullptr, *sums = nullptr,
          *trpart = nullptr;
   double *B = nullptr, *M = nullptr, *X = nullptr, *rn = nullptr;
   DevScalars* sc = nullptr;
+  bool own_sc = true;
   DevScalars hs{};
-  // profiling
-  bool profiling = false;
-  std::vector<TimedLaunch> timed;
-  std::vector<std::pair<std::string, std::pair<double, int64_t>>> prof;
+  Prof* prof = nullptr;
+};
+
+}  // namespace
+
+struct yand_ctx {
+  Data d;
+  Work w;
+  Prof prof;
 };
 
 namespace {
@@ -88,162 +114,299 @@ int check_c(const double* c) {
   return YAND_OK;
 }
 
-// Timed launch wrapper: records events around `fn` when profiling is on.
+// ------------------------------------------------------------ profiling --
+
 template <class F>
-hipError_t timed(yand_ctx* ctx, const char* name, F fn) {
-  if (!ctx->profiling) return fn();
+hipError_t timed(Work& w, const char* name, F fn) {
+  if (!w.prof || !w.prof->on) return fn();
   TimedLaunch t{name, nullptr, nullptr};
   if (hipEventCreate(&t.a) != hipSuccess || hipEventCreate(&t.b) != hipSuccess)
     return hipErrorOutOfMemory;
-  hipEventRecord(t.a, ctx->stream);
+  hipEventRecord(t.a, w.st);
   hipError_t e = fn();
-  hipEventRecord(t.b, ctx->stream);
-  ctx->timed.push_back(t);
+  hipEventRecord(t.b, w.st);
+  w.prof->timed.push_back(t);
   return e;
 }
 
-void flush_timed(yand_ctx* ctx) {
-  if (ctx->timed.empty()) return;
-  hipStreamSynchronize(ctx->stream);
-  for (auto& t : ctx->timed) {
+void flush_timed(Prof& p, hipStream_t st) {
+  if (p.timed.empty()) return;
+  (void)hipStreamSynchronize(st);
+  for (auto& t : p.timed) {
     float ms = 0.f;
-    hipEventElapsedTime(&ms, t.a, t.b);
+    (void)hipEventElapsedTime(&ms, t.a, t.b);
     bool found = false;
-    for (auto& p : ctx->prof)
-      if (p.first == t.name) {
-        p.second.first += ms;
-        p.second.second += 1;
+    for (auto& a : p.acc)
+      if (a.first == t.name) {
+        a.second.first += ms;
+        a.second.second += 1;
         found = true;
         break;
       }
-    if (!found) ctx->prof.push_back({t.name, {(double)ms, 1}});
-    hipEventDestroy(t.a);
-    hipEventDestroy(t.b);
+    if (!found) p.acc.push_back({t.name, {(double)ms, 1}});
+    (void)hipEventDestroy(t.a);
+    (void)hipEventDestroy(t.b);
   }
-  ctx->timed.clear();
+  p.timed.clear();
 }
 
-PassArgs pass_args(yand_ctx* ctx, const double c[4]) {
+// ------------------------------------------------------------ workspaces --
+
+void free_work(Work& w) {
+  double* ptrs[] = {w.x,     w.g,      w.d,     w.z,      w.wv,   w.q,
+                    w.AE,    w.E,      w.W,     w.t3,     w.r,    w.y,
+                    w.y2,    w.hv,     w.s_t,   w.pcg_s,  w.pcg_res,
+                    w.pcg_p, w.pcg_u,  w.part,  w.psums,  w.sums, w.trpart,
+                    w.B,     w.M,      w.X,     w.rn};
+  for (double* p : ptrs)
+    if (p) (void)hipFree(p);
+  if (w.sc && w.own_sc) (void)hipFree(w.sc);
+  if (w.st && w.own_stream) (void)hipStreamDestroy(w.st);
+  w = Work{};
+}
+
+int alloc_work(Work& w, const Data& D, DevScalars* sc_external) {
+  const int64_t n = D.n, lda = D.lda, Tp = D.Tp;
+  const size_t nb = (size_t)lda * sizeof(double), tb = (size_t)Tp * sizeof(double);
+  int rc;
+  if ((rc = alloc((void**)&w.x, nb)) || (rc = alloc((void**)&w.g, nb)) ||
+      (rc = alloc((void**)&w.d, nb)) || (rc = alloc((void**)&w.z, tb)) ||
+      (rc = alloc((void**)&w.wv, tb)) || (rc = alloc((void**)&w.q, tb)) ||
+      (rc = alloc((void**)&w.AE, 3 * tb)) ||
+      (rc = alloc((void**)&w.E, 3 * nb)) ||
+      (rc = alloc((void**)&w.W, 3 * nb)) ||
+      (rc = alloc((void**)&w.t3, nb)) || (rc = alloc((void**)&w.r, nb)) ||
+      (rc = alloc((void**)&w.y, nb)) || (rc = alloc((void**)&w.y2, nb)) ||
+      (rc = alloc((void**)&w.hv, nb)) || (rc = alloc((void**)&w.s_t, tb)) ||
+      (rc = alloc((void**)&w.pcg_s, nb)) ||
+      (rc = alloc((void**)&w.pcg_res, nb)) ||
+      (rc = alloc((void**)&w.pcg_p, nb)) ||
+      (rc = alloc((void**)&w.pcg_u, nb)) ||
+      (rc = alloc((void**)&w.part,
+                  (size_t)kMaxPassGroups * lda * sizeof(double))) ||
+      (rc = alloc((void**)&w.psums,
+                  (size_t)kMaxPassGroups * kMaxSums * sizeof(double))) ||
+      (rc = alloc((void**)&w.sums, kMaxSums * sizeof(double))) ||
+      (rc = alloc((void**)&w.trpart,
+                  (size_t)((n + 63) / 64) * n * sizeof(double))))
+    return rc;
+  if (sc_external) {
+    w.sc = sc_external;
+    w.own_sc = false;
+  } else {
+    if ((rc = alloc((void**)&w.sc, sizeof(DevScalars)))) return rc;
+    w.own_sc = true;
+    HIPTRY(hipMemsetAsync(w.sc, 0, sizeof(DevScalars), w.st));
+  }
+  HIPTRY(launch_fill(w.z, Tp, 0.0, w.st));
+  HIPTRY(launch_fill(w.q, Tp, 0.0, w.st));
+  HIPTRY(launch_fill(w.AE, 3 * Tp, 0.0, w.st));
+  HIPTRY(launch_fill(w.s_t, Tp, 0.0, w.st));
+  return YAND_OK;
+}
+
+int ensure_dense(Work& w, const Data& D) {
+  if (w.B) return YAND_OK;
+  const size_t nn = (size_t)D.lda * D.lda * sizeof(double);
+  TRY(alloc((void**)&w.B, nn));
+  TRY(alloc((void**)&w.M, nn));
+  TRY(alloc((void**)&w.X, nn));
+  TRY(alloc((void**)&w.rn, (size_t)D.nt * D.Tp * sizeof(double)));
+  return YAND_OK;
+}
+
+int sync_scalars(Work& w) {
+  HIPTRY(hipMemcpyAsync(&w.hs, w.sc, sizeof(DevScalars), hipMemcpyDeviceToHost,
+                        w.st));
+  HIPTRY(hipStreamSynchronize(w.st));
+  return YAND_OK;
+}
+
+// ----------------------------------------------------------- pipeline ----
+
+PassArgs pass_args(const Data& D, const Work& w, const double c[4]) {
   PassArgs a{};
-  a.A = ctx->A;
-  a.lda = ctx->lda;
-  a.Tp = ctx->Tp;
-  a.n = ctx->n;
-  a.part = ctx->part;
-  a.psums = ctx->psums;
+  a.A = D.A;
+  a.lda = D.lda;
+  a.Tp = D.Tp;
+  a.n = D.n;
+  a.part = w.part;
+  a.psums = w.psums;
   a.c = c ? to_coef(c) : Coef{0, 0, 0, 0};
-  a.invT = 1.0 / (double)ctx->T;
+  a.invT = 1.0 / (double)D.T;
+  a.skip = nullptr;
   return a;
 }
 
-int run_pass(yand_ctx* ctx, PassKind kind, const PassArgs& a, int* nwg,
-             const char* name) {
-  HIPTRY(timed(ctx, name, [&] {
-    return launch_pass(ctx->precision, kind, a, ctx->stream, nwg);
+int run_pass(const Data& D, Work& w, PassKind kind, const PassArgs& a,
+             int* nwg, const char* name) {
+  HIPTRY(timed(w, name, [&] {
+    return launch_pass(D.precision, kind, a, w.st, nwg);
   }));
   return YAND_OK;
 }
 
-int sync_scalars(yand_ctx* ctx) {
-  HIPTRY(hipMemcpyAsync(&ctx->hs, ctx->sc, sizeof(DevScalars),
-                        hipMemcpyDeviceToHost, ctx->stream));
-  HIPTRY(hipStreamSynchronize(ctx->stream));
-  return YAND_OK;
-}
-
-// Oracle pass at x: z (ctx->z), g (ctx->g), f and moments in ctx->sc.
-int oracle_at(yand_ctx* ctx, const double c[4], const double* x,
-              bool with_grad) {
-  PassArgs a = pass_args(ctx, c);
+// Oracle pass at x: z, g, f and the moments (device scalars).
+int oracle_at(const Data& D, Work& w, const double c[4], const double* x,
+              bool with_grad, const int* skip = nullptr) {
+  PassArgs a = pass_args(D, w, c);
   a.v = x;
-  a.tout = ctx->z;
+  a.tout = w.z;
+  a.skip = skip;
   int nwg = 0;
-  TRY(run_pass(ctx, with_grad ? PassKind::Oracle : PassKind::Value, a, &nwg,
+  TRY(run_pass(D, w, with_grad ? PassKind::Oracle : PassKind::Value, a, &nwg,
                "oracle_pass"));
-  HIPTRY(launch_reduce_sums(ctx->psums, nwg, 3, ctx->sums, ctx->stream));
-  HIPTRY(launch_dot(ctx->mu, x, ctx->n, &ctx->sc->mux, ctx->stream));
-  HIPTRY(launch_objective(ctx->sums, a.invT, to_coef(c), ctx->sc,
-                          ctx->stream));
+  HIPTRY(launch_reduce_sums(w.psums, nwg, 3, w.sums, w.st, skip));
+  HIPTRY(launch_dot(D.mu, x, D.n, &w.sc->mux, w.st));
+  HIPTRY(launch_objective(w.sums, a.invT, to_coef(c), w.sc, w.st));
   if (with_grad)
-    HIPTRY(launch_reduce_partials(ctx->part, nwg, ctx->lda, ctx->n, 1.0,
-                                  -c[0], ctx->mu, ctx->g, ctx->stream));
+    HIPTRY(launch_reduce_partials(w.part, nwg, D.lda, D.n, 1.0, -c[0], D.mu,
+                                  w.g, w.st, skip));
   return YAND_OK;
 }
 
-// hv = A^T (psi''(z) * Av) / T at the cached z; (Av)_t to tout if given.
-int hvp_cached(yand_ctx* ctx, const double c[4], const double* v, double* hv,
-               double* tout) {
-  PassArgs a = pass_args(ctx, c);
+int hvp_cached(const Data& D, Work& w, const double c[4], const double* v,
+               double* hv, double* tout) {
+  PassArgs a = pass_args(D, w, c);
   a.v = v;
-  a.zc = ctx->z;
+  a.zc = w.z;
   a.tout = tout;
   int nwg = 0;
-  TRY(run_pass(ctx, PassKind::Hvp, a, &nwg, "hvp_pass"));
-  HIPTRY(launch_reduce_partials(ctx->part, nwg, ctx->lda, ctx->n, 1.0, 0.0,
-                                nullptr, hv, ctx->stream));
+  TRY(run_pass(D, w, PassKind::Hvp, a, &nwg, "hvp_pass"));
+  HIPTRY(launch_reduce_partials(w.part, nwg, D.lda, D.n, 1.0, 0.0, nullptr, hv,
+                                w.st));
   return YAND_OK;
 }
 
-// Line-search sums along d at the cached z; coefficients (and optionally the
-// step) in ctx->sc.  mu^T d must already be in sc->mud.
-int line_at(yand_ctx* ctx, const double c[4], const double* d, int select) {
-  PassArgs a = pass_args(ctx, c);
+// Line-search sums along d at the cached z; coefficients (and the step when
+// select) in the device scalars.  mu^T d must already be in sc->mud.
+int line_at(const Data& D, Work& w, const double c[4], const double* d,
+            int select, const int* skip) {
+  PassArgs a = pass_args(D, w, c);
   a.v = d;
-  a.zc = ctx->z;
-  a.tout = ctx->wv;
+  a.zc = w.z;
+  a.tout = w.wv;
+  a.skip = skip;
   int nwg = 0;
-  TRY(run_pass(ctx, PassKind::Line, a, &nwg, "line_pass"));
-  HIPTRY(launch_reduce_sums(ctx->psums, nwg, 9, ctx->sums, ctx->stream));
-  HIPTRY(launch_coef_step(ctx->sums, a.invT, to_coef(c), select, ctx->sc,
-                          ctx->stream));
-  return YAND_OK;
-}
-
-int ensure_dense(yand_ctx* ctx) {
-  if (ctx->B) return YAND_OK;
-  const size_t nn = (size_t)ctx->lda * ctx->lda * sizeof(double);
-  TRY(alloc((void**)&ctx->B, nn));
-  TRY(alloc((void**)&ctx->M, nn));
-  TRY(alloc((void**)&ctx->X, nn));
-  TRY(alloc((void**)&ctx->rn, (size_t)ctx->nt * ctx->Tp * sizeof(double)));
+  TRY(run_pass(D, w, PassKind::Line, a, &nwg, "line_pass"));
+  HIPTRY(launch_reduce_sums(w.psums, nwg, 9, w.sums, w.st, skip));
+  HIPTRY(launch_coef_step(w.sums, a.invT, to_coef(c), select, w.sc, w.st));
   return YAND_OK;
 }
 
 __global__ void psi2_weight_kernel(const double* __restrict__ z, int64_t Tp,
-                                   Coef c, double invT, double* __restrict__ s) {
+                                   Coef c, double invT, double* __restrict__ s,
+                                   const int* skip) {
+  if (skip && *skip) return;
   int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (t < Tp) s[t] = d2psi(c, z[t]) * invT;
 }
 
-__global__ void fill_kernel(double* p, int64_t count, double v) {
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count;
-       i += (int64_t)gridDim.x * blockDim.x)
-    p[i] = v;
-}
-
-hipError_t fill(double* p, int64_t count, double v, hipStream_t st) {
-  int64_t blocks = (count + 255) / 256;
-  if (blocks > 4096) blocks = 4096;
-  if (blocks < 1) blocks = 1;
-  hipLaunchKernelGGL(fill_kernel, dim3((unsigned)blocks), dim3(256), 0, st, p,
-                     count, v);
-  return hipGetLastError();
-}
-
 __global__ void set_lambda_kernel(DevScalars* sc, double lam) {
-  if (threadIdx.x == 0) sc->lambda = lam;
+  if (threadIdx.x == 0) {
+    sc->lambda = lam;
+    sc->fail = 0;
+  }
 }
 
-// Projected PCG on P_S (H + lambda) P_S s = r (s in S) with the Jacobi
-// preconditioner P_S diag(B + lambda)^-1 P_S; r already in S.
+struct DirOpts {
+  int solver = YAND_SOLVER_DIRECT;
+  double reg = 0.0;
+  double krylov_tol = 1e-3;
+  int krylov_maxit = 15;
+  double tau = 1e-8;
+  int simplex = 0;
+};
+
+struct DirStats {
+  int cg = 0;
+  int escalations = 0;
+};
+
+// Direction, first part: nu-projection (Aν), B = A^T diag(psi''/T) A,
+// W_E = B E and the scales gamma, lambda.  Needs z, g and E[p0] = nu.
+int dir_front(const Data& D, Work& w, const double c[4], int p0,
+              const DirOpts& o, const int* skip) {
+  TRY(ensure_dense(w, D));
+  const int64_t n = D.n, np = D.lda, Tp = D.Tp;
+  const int p = p0 + 1;
+  {
+    PassArgs a = pass_args(D, w, c);
+    a.v = w.E + (int64_t)p0 * n;
+    a.tout = w.AE + (int64_t)p0 * Tp;
+    a.skip = skip;
+    int nwg;
+    TRY(run_pass(D, w, PassKind::Dot, a, &nwg, "dot_pass"));
+  }
+  hipLaunchKernelGGL(psi2_weight_kernel, dim3((unsigned)((Tp + 255) / 256)),
+                     dim3(256), 0, w.st, w.z, Tp, to_coef(c),
+                     1.0 / (double)D.T, w.s_t, skip);
+  HIPTRY(timed(w, "syrk", [&] {
+    return launch_syrk(D.precision, D.A, D.lda, Tp, w.s_t, w.B, w.st, skip);
+  }));
+  HIPTRY(launch_symm_multi(w.B, np, n, w.E, p, w.W, w.st, skip));
+  HIPTRY(launch_trace_scale(w.B, np, n, w.E, w.W, p, o.reg, w.sc, w.st));
+  return YAND_OK;
+}
+
+// Projection of B into M and the factorisation M = L L^T, X = L^-1.
+int dir_factor(const Data& D, Work& w, int p0, const int* skip) {
+  const int64_t n = D.n, np = D.lda;
+  HIPTRY(launch_project(w.B, w.M, np, n, np, w.E, w.W, p0 + 1, w.sc, w.st));
+  HIPTRY(launch_fill(w.X, np * np, 0.0, w.st, skip));
+  HIPTRY(timed(w, "potrf_trtri", [&] {
+    return launch_potrf_trtri(w.M, w.X, np, &w.sc->fail, w.st, skip);
+  }));
+  return YAND_OK;
+}
+
+// Exact trace q, third-order back-projection t3 and r = P_S(B nu - |G|/(m+1) t3).
+int dir_trace(const Data& D, Work& w, const double c[4], int p0,
+              const int* skip) {
+  const int64_t n = D.n, np = D.lda, Tp = D.Tp;
+  const int p = p0 + 1;
+  HIPTRY(timed(w, "trace_gemm", [&] {
+    return launch_trace_gemm(D.precision, D.A, D.lda, Tp, w.X, np, w.rn, w.st,
+                             skip);
+  }));
+  HIPTRY(launch_copy(w.AE, D.AEfix, (int64_t)p0 * Tp, w.st, skip));
+  HIPTRY(launch_trace_weight(w.rn, (int)D.nt, Tp, w.AE, p, w.sc, w.q, w.st));
+  {
+    PassArgs a = pass_args(D, w, c);
+    a.zc = w.z;
+    a.q = w.q;
+    a.skip = skip;
+    int nwg;
+    TRY(run_pass(D, w, PassKind::Third, a, &nwg, "third_pass"));
+    HIPTRY(launch_reduce_partials(w.part, nwg, D.lda, n, 1.0, 0.0, nullptr,
+                                  w.t3, w.st, skip));
+  }
+  const double mp1 = (double)(n - p0 + 1);
+  HIPTRY(launch_rhs(w.W + (int64_t)p0 * n, w.t3, w.E, p, n, mp1, w.sc, w.r,
+                    w.st));
+  return YAND_OK;
+}
+
+// d = K r - nu with K = P_S M^-1 P_S = P_S X^T X P_S (direct solve).
+int dir_direct_solve(const Data& D, Work& w, int p0, const double* x,
+                     const DirOpts& o, double* d, const int* skip) {
+  const int64_t n = D.n, np = D.lda;
+  HIPTRY(launch_trmv(w.X, np, n, w.r, w.y, w.trpart, false, w.st, skip));
+  HIPTRY(launch_trmv(w.X, np, n, w.y, w.y2, w.trpart, true, w.st, skip));
+  HIPTRY(launch_direction(w.y2, w.E, p0 + 1, n, x, D.mu, o.tau, o.simplex, d,
+                          w.sc, w.st));
+  return YAND_OK;
+}
+
+// ------------------------------------------------------ projected PCG ----
 constexpr int PT = 1024;
 template <int K>
 __device__ void bsum(double (&v)[K], double* sh) {
-  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
 #pragma unroll
   for (int k = 0; k < K; ++k) {
     double s = wave_sum(v[k]);
-    if (lane == 0) sh[k * 16 + w] = s;
+    if (lane == 0) sh[k * 16 + wv] = s;
   }
   __syncthreads();
 #pragma unroll
@@ -261,6 +424,8 @@ __device__ double precond_diag(const double* B, int64_t ld, int64_t j,
   return dj > 0.0 ? dj : 1.0;
 }
 
+// Projected PCG on P_S (H + lambda) P_S s = r (s in S) with the Jacobi
+// preconditioner P_S diag(B + lambda)^-1 P_S; r already in S.
 __global__ void __launch_bounds__(PT)
 pcg_init_kernel(const double* __restrict__ r, const double* __restrict__ B,
                 int64_t ld, const double* __restrict__ E, int p, int64_t n,
@@ -292,6 +457,7 @@ pcg_init_kernel(const double* __restrict__ r, const double* __restrict__ B,
     sc->aux[0] = rz[0];
     sc->aux[1] = dots[3];
     sc->aux[2] = dots[3];
+    sc->aux[3] = 0.0;
   }
 }
 
@@ -348,133 +514,79 @@ pcg_update_kernel(const double* __restrict__ Hp, const double* __restrict__ B,
   }
 }
 
-struct DirOpts {
-  int solver = YAND_SOLVER_DIRECT;
-  double reg = 0.0;
-  double krylov_tol = 1e-3;
-  int krylov_maxit = 15;
-  double tau = 1e-8;
-  int simplex = 0;
-};
-
-struct DirStats {
-  int cg = 0;
-  int escalations = 0;
-};
-
-// Affine-normal direction at x (oracle pass already done at x: z, g valid).
-// p0 = number of equality constraints (1 budget, 2 budget + target).
-int direction_at(yand_ctx* ctx, const double c[4], int p0, const double* x,
-                 const DirOpts& o, double* d, DirStats* stats) {
-  TRY(ensure_dense(ctx));
-  hipStream_t st = ctx->stream;
-  const int64_t n = ctx->n, np = ctx->lda, Tp = ctx->Tp;
+int dir_pcg_solve(const Data& D, Work& w, const double c[4], int p0,
+                  const double* x, const DirOpts& o, double* d,
+                  DirStats* stats) {
+  const int64_t n = D.n, np = D.lda;
   const int p = p0 + 1;
-  const double invT = 1.0 / (double)ctx->T;
-  // nu and |G|
-  HIPTRY(launch_grad_project(ctx->g, ctx->E, p0, n, ctx->sc, st));
-  // (A nu)_t -> AE[p0]
-  {
-    PassArgs a = pass_args(ctx, c);
-    a.v = ctx->E + (int64_t)p0 * n;
-    a.tout = ctx->AE + (int64_t)p0 * Tp;
-    int nwg;
-    TRY(run_pass(ctx, PassKind::Dot, a, &nwg, "dot_pass"));
+  hipLaunchKernelGGL(pcg_init_kernel, dim3(1), dim3(PT), 0, w.st, w.r, w.B, np,
+                     w.E, p, n, w.pcg_s, w.pcg_res, w.pcg_p, w.pcg_u, w.sc);
+  TRY(sync_scalars(w));
+  const double r0 = std::sqrt(w.hs.aux[2]);
+  int it = 0;
+  while (it < o.krylov_maxit && r0 > 0.0) {
+    TRY(hvp_cached(D, w, c, w.pcg_p, w.hv, nullptr));
+    hipLaunchKernelGGL(pcg_update_kernel, dim3(1), dim3(PT), 0, w.st, w.hv,
+                       w.B, np, w.E, p, n, w.pcg_s, w.pcg_res, w.pcg_p,
+                       w.pcg_u, w.y, w.sc);
+    ++it;
+    TRY(sync_scalars(w));
+    if (std::sqrt(w.hs.aux[1]) <= o.krylov_tol * r0) break;
+    if (w.hs.aux[3] != 0.0) break;
   }
-  // B = A^T diag(psi''(z)/T) A
-  hipLaunchKernelGGL(psi2_weight_kernel, dim3((unsigned)((Tp + 255) / 256)),
-                     dim3(256), 0, st, ctx->z, Tp, to_coef(c), invT, ctx->s_t);
-  HIPTRY(timed(ctx, "syrk", [&] {
-    return launch_syrk(ctx->precision, ctx->A, ctx->lda, Tp, ctx->s_t, ctx->B,
-                       st);
-  }));
-  HIPTRY(launch_symm_multi(ctx->B, np, n, ctx->E, p, ctx->W, st));
-  HIPTRY(launch_trace_scale(ctx->B, np, n, ctx->E, ctx->W, p, o.reg, ctx->sc,
-                            st));
-  // project, factor, invert (with regularisation escalation)
-  double lam = -1.0;
+  if (stats) stats->cg += it;
+  HIPTRY(launch_direction(w.pcg_s, w.E, p, n, x, D.mu, o.tau, o.simplex, d,
+                          w.sc, w.st));
+  return YAND_OK;
+}
+
+// Eager direction with regularisation escalation (host reads the Cholesky
+// flag) and either solver.  The oracle pass and the gradient projection must
+// already have run at x with the done flag clear.
+int direction_eager(const Data& D, Work& w, const double c[4], int p0,
+                    const double* x, const DirOpts& o, double* d,
+                    DirStats* stats) {
+  TRY(dir_front(D, w, c, p0, o, nullptr));
   for (int attempt = 0;; ++attempt) {
-    if (lam >= 0.0)
-      hipLaunchKernelGGL(set_lambda_kernel, dim3(1), dim3(64), 0, st, ctx->sc,
-                         lam);
-    HIPTRY(launch_project(ctx->B, ctx->M, np, n, np, ctx->E, ctx->W, p,
-                          ctx->sc, st));
-    HIPTRY(fill(ctx->X, np * np, 0.0, st));
-    HIPTRY(hipMemsetAsync(&ctx->sc->fail, 0, sizeof(int), st));
-    HIPTRY(timed(ctx, "potrf_trtri", [&] {
-      return launch_potrf_trtri(ctx->M, ctx->X, np, &ctx->sc->fail, st);
-    }));
-    TRY(sync_scalars(ctx));
-    if (!ctx->hs.fail) break;
+    TRY(dir_factor(D, w, p0, nullptr));
+    TRY(sync_scalars(w));
+    if (!w.hs.fail) break;
     if (attempt >= 8) return YAND_ERR_INDEFINITE;
-    lam = std::max(10.0 * ctx->hs.lambda, 1e-12 * ctx->hs.tang_scale);
+    const double lam = std::max(10.0 * w.hs.lambda, 1e-12 * w.hs.tang_scale);
+    hipLaunchKernelGGL(set_lambda_kernel, dim3(1), dim3(64), 0, w.st, w.sc,
+                       lam);
     if (stats) stats->escalations++;
   }
-  // q_t and the third-order back-projection t3 = A^T(psi'''(z) q)/T
-  HIPTRY(timed(ctx, "trace_gemm", [&] {
-    return launch_trace_gemm(ctx->precision, ctx->A, ctx->lda, Tp, ctx->X, np,
-                             ctx->rn, st);
-  }));
-  hipMemcpyAsync(ctx->AE, ctx->AEfix, (size_t)p0 * Tp * sizeof(double),
-                 hipMemcpyDeviceToDevice, st);
-  HIPTRY(launch_trace_weight(ctx->rn, (int)ctx->nt, Tp, ctx->AE, p, ctx->sc,
-                             ctx->q, st));
-  {
-    PassArgs a = pass_args(ctx, c);
-    a.zc = ctx->z;
-    a.q = ctx->q;
-    int nwg;
-    TRY(run_pass(ctx, PassKind::Third, a, &nwg, "third_pass"));
-    HIPTRY(launch_reduce_partials(ctx->part, nwg, ctx->lda, n, 1.0, 0.0,
-                                  nullptr, ctx->t3, st));
-  }
-  // r = P_S (B nu - |G|/(m+1) t3), m = n - p0
-  const double mp1 = (double)(n - p0 + 1);
-  HIPTRY(launch_rhs(ctx->W + (int64_t)p0 * n, ctx->t3, ctx->E, p, n, mp1,
-                    ctx->sc, ctx->r, st));
-  if (o.solver == YAND_SOLVER_DIRECT) {
-    HIPTRY(launch_trmv(ctx->X, np, n, ctx->r, ctx->y, ctx->trpart, false, st));
-    HIPTRY(launch_trmv(ctx->X, np, n, ctx->y, ctx->y2, ctx->trpart, true, st));
-    HIPTRY(launch_direction(ctx->y2, ctx->E, p, n, x, ctx->mu, o.tau,
-                            o.simplex, d, ctx->sc, st));
-  } else {
-    hipLaunchKernelGGL(pcg_init_kernel, dim3(1), dim3(PT), 0, st, ctx->r,
-                       ctx->B, np, ctx->E, p, n, ctx->pcg_s, ctx->pcg_res,
-                       ctx->pcg_p, ctx->pcg_u, ctx->sc);
-    TRY(sync_scalars(ctx));
-    const double r0 = std::sqrt(ctx->hs.aux[2]);
-    int it = 0;
-    while (it < o.krylov_maxit && r0 > 0.0) {
-      TRY(hvp_cached(ctx, c, ctx->pcg_p, ctx->hv, nullptr));
-      hipLaunchKernelGGL(pcg_update_kernel, dim3(1), dim3(PT), 0, st, ctx->hv,
-                         ctx->B, np, ctx->E, p, n, ctx->pcg_s, ctx->pcg_res,
-                         ctx->pcg_p, ctx->pcg_u, ctx->y, ctx->sc);
-      ++it;
-      TRY(sync_scalars(ctx));
-      if (std::sqrt(ctx->hs.aux[1]) <= o.krylov_tol * r0) break;
-      if (ctx->hs.aux[3] != 0.0) break;
-    }
-    if (stats) stats->cg += it;
-    HIPTRY(launch_direction(ctx->pcg_s, ctx->E, p, n, x, ctx->mu, o.tau,
-                            o.simplex, d, ctx->sc, st));
-  }
+  TRY(dir_trace(D, w, c, p0, nullptr));
+  if (o.solver == YAND_SOLVER_DIRECT)
+    return dir_direct_solve(D, w, p0, x, o, d, nullptr);
+  return dir_pcg_solve(D, w, c, p0, x, o, d, stats);
+}
+
+// One outer iteration of the direct configuration, enqueued with no host
+// synchronisation: oracle, stationarity (sets done when |G| <= eps), exact-
+// trace direction, line search, step, update.
+int enqueue_iteration(const Data& D, Work& w, const double c[4], int p0,
+                      const DirOpts& o, double eps) {
+  const int* skip = &w.sc->done;
+  TRY(oracle_at(D, w, c, w.x, true, &w.sc->frozen));
+  HIPTRY(launch_grad_project(w.g, w.E, p0, D.n, w.sc, w.st, eps));
+  TRY(dir_front(D, w, c, p0, o, skip));
+  TRY(dir_factor(D, w, p0, skip));
+  TRY(dir_trace(D, w, c, p0, skip));
+  TRY(dir_direct_solve(D, w, p0, w.x, o, w.d, skip));
+  TRY(line_at(D, w, c, w.d, 1, skip));
+  HIPTRY(launch_axpy(w.x, w.d, D.n, w.sc, w.st));
   return YAND_OK;
 }
 
-int setup_constraints(yand_ctx* ctx, const double* target, int* p0) {
-  *p0 = target ? 2 : 1;
-  if (target && !ctx->have_e2) return YAND_ERR_ARG;
-  HIPTRY(hipMemcpyAsync(ctx->E, ctx->Efix, (size_t)(*p0) * ctx->n *
-                        sizeof(double), hipMemcpyDeviceToDevice, ctx->stream));
-  return YAND_OK;
-}
+// ------------------------------------------------- constraints and start --
 
-// Minimum-norm correction of x onto 1^T x = 1 (and mu^T x = r): with the
-// orthonormal e1, e2 of span{1, mu}, x <- x + sum_a e_a (b_a' - e_a^T x),
-// where b' are the right-hand sides in the e-basis.
+// x <- x + sum_a e_a (b_a - e_a^T x): minimum-norm move onto the budget (and
+// target) constraint, expressed in the orthonormal frame e1, e2.
 __global__ void __launch_bounds__(PT)
-feasible_kernel(double* x, const double* E, int p0, int64_t n,
-                double b1, double b2) {
+feasible_kernel(double* x, const double* E, int p0, int64_t n, double b1,
+                double b2) {
   __shared__ double sh[4 * 16];
   const int tid = threadIdx.x;
   double dots[2] = {0, 0};
@@ -491,7 +603,7 @@ feasible_kernel(double* x, const double* E, int p0, int64_t n,
 
 __global__ void __launch_bounds__(PT)
 efix_kernel(const double* __restrict__ mu, int64_t n, double* Efix,
-            int* has_e2) {
+            double* stats) {
   __shared__ double sh[4 * 16];
   const int tid = threadIdx.x;
   const double e1 = 1.0 / sqrt((double)n);
@@ -511,7 +623,237 @@ efix_kernel(const double* __restrict__ mu, int64_t n, double* Efix,
   const double nrm = sqrt(ss[0]);
   for (int64_t j = tid; j < n; j += PT)
     Efix[n + j] = nrm > 0.0 ? (mu[j] - mbar) / nrm : 0.0;
-  if (tid == 0) *has_e2 = nrm > 1e-300 ? 1 : 0;
+  if (tid == 0) {
+    stats[0] = mbar;
+    stats[1] = nrm;
+  }
+}
+
+__global__ void set_frozen_kernel(DevScalars* sc, int v) {
+  if (threadIdx.x == 0) {
+    sc->frozen = v;
+    if (v) sc->done = 1;
+  }
+}
+// Load the constraint frame into w.E and set w.x to the feasible start.
+int setup_lane(const Data& D, Work& w, const double* target,
+               const double* w0, int* p0) {
+  *p0 = target ? 2 : 1;
+  if (target && (!D.have_e2 || !std::isfinite(*target))) return YAND_ERR_ARG;
+  hipLaunchKernelGGL(set_frozen_kernel, dim3(1), dim3(64), 0, w.st, w.sc, 0);
+  HIPTRY(launch_copy(w.E, D.Efix, (int64_t)(*p0) * D.n, w.st));
+  if (w0)
+    HIPTRY(launch_copy(w.x, w0, D.n, w.st));
+  else
+    HIPTRY(launch_fill(w.x, D.n, 1.0 / (double)D.n, w.st));
+  const double b1 = 1.0 / std::sqrt((double)D.n);
+  const double b2 = target ? (*target - D.mbar) / D.mnorm : 0.0;
+  hipLaunchKernelGGL(feasible_kernel, dim3(1), dim3(PT), 0, w.st, w.x, w.E,
+                     *p0, D.n, b1, b2);
+  return YAND_OK;
+}
+
+int check_simplex_start(const Data& D, Work& w, double tau) {
+  std::vector<double> xh(D.n);
+  HIPTRY(hipMemcpyAsync(xh.data(), w.x, D.n * sizeof(double),
+                        hipMemcpyDeviceToHost, w.st));
+  HIPTRY(hipStreamSynchronize(w.st));
+  for (int64_t j = 0; j < D.n; ++j)
+    if (!(xh[j] >= tau)) return YAND_ERR_ARG;
+  return YAND_OK;
+}
+
+// ---------------------------------------------------- lanes (batch loop) --
+
+struct Lane {
+  const Data* D = nullptr;
+  Work* w = nullptr;
+  double c[4] = {0, 0, 0, 0};
+  bool has_target = false;
+  double target = 0.0;
+  const double* w0 = nullptr;
+  double* w_out = nullptr;
+  int p0 = 1;
+  // host state
+  bool active = true, converged = false, frozen_set = false;
+  int rc = YAND_OK;
+  int small = 0;
+  double f_prev = NAN;
+  yand_info info{};
+};
+
+
+
+// Apply the host decisions after reading a lane's scalars for one iteration
+// (direct configuration).  Returns YAND_OK or a HIP error.
+int after_iteration(Lane& L, const yand_opts& opts, const DirOpts& o) {
+  Work& w = *L.w;
+  const DevScalars& s = w.hs;
+  L.info.oracle_passes++;
+  L.info.f = s.f;
+  L.info.gnorm = s.gn;
+  if (s.nonfinite) {
+    L.rc = YAND_ERR_NONFINITE;
+    L.active = false;
+    return YAND_OK;
+  }
+  if (s.done) {
+    L.converged = true;
+    L.active = false;
+    return YAND_OK;
+  }
+  if (s.fail) {
+    // redo this iteration's direction with regularisation escalation; x did
+    // not move, and z, g, nu of the iteration are still valid
+    DirStats ds;
+    int rc = direction_eager(*L.D, w, L.c, L.p0, w.x, o, w.d, &ds);
+    if (rc != YAND_OK) {
+      L.rc = rc;
+      L.active = false;
+      return YAND_OK;
+    }
+    TRY(line_at(*L.D, w, L.c, w.d, 1, nullptr));
+    HIPTRY(launch_axpy(w.x, w.d, L.D->n, w.sc, w.st));
+    TRY(sync_scalars(w));
+  }
+  L.info.dense_traces++;
+  L.info.third_passes++;
+  L.info.ls_passes++;
+  L.info.lambda_used = w.hs.lambda;
+  if (w.hs.status != 0) {
+    L.rc = YAND_ERR_UNBOUNDED;
+    L.active = false;
+    return YAND_OK;
+  }
+  L.info.iterations++;
+  const double a = w.hs.alpha, *A = w.hs.coef;
+  const double dec = -(a * (A[1] + a * (A[2] + a * (A[3] + a * A[4]))));
+  if (std::isnan(L.f_prev)) L.f_prev = A[0];
+  if (dec < 1e-14 * std::fabs(L.f_prev)) {
+    if (++L.small >= 3) L.active = false;
+  } else {
+    L.small = 0;
+  }
+  L.f_prev = A[0] - dec;
+  if (L.info.iterations >= opts.max_iter) L.active = false;
+  return YAND_OK;
+}
+
+// Final stationarity check of a lane that stopped without converging.
+int final_check(Lane& L, const yand_opts& opts) {
+  Work& w = *L.w;
+  hipLaunchKernelGGL(set_frozen_kernel, dim3(1), dim3(64), 0, w.st, w.sc, 0);
+  TRY(oracle_at(*L.D, w, L.c, w.x, true));
+  HIPTRY(launch_grad_project(w.g, w.E, L.p0, L.D->n, w.sc, w.st, opts.eps));
+  TRY(sync_scalars(w));
+  L.info.f = w.hs.f;
+  L.info.gnorm = w.hs.gn;
+  L.info.oracle_passes++;
+  if (w.hs.done) L.converged = true;
+  return YAND_OK;
+}
+
+// Run the direct configuration on a set of lanes until each converges or
+// stops.  Iteration 0 is enqueued eagerly; with use_graph, later iterations
+// replay one captured graph of all lanes.  cs: control stream.
+int run_lanes(std::vector<Lane>& lanes, const yand_opts& opts,
+              const DirOpts& o, hipStream_t cs, bool use_graph,
+              DevScalars* host_sc, DevScalars* dev_sc) {
+  const size_t nl = lanes.size();
+  HIPTRY(prepare_dense_kernels());
+  hipEvent_t ev_fork = nullptr;
+  std::vector<hipEvent_t> ev_join(nl, nullptr);
+  HIPTRY(hipEventCreateWithFlags(&ev_fork, hipEventDisableTiming));
+  for (auto& e : ev_join)
+    HIPTRY(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+  auto cleanup = [&]() {
+    (void)hipEventDestroy(ev_fork);
+    for (auto& e : ev_join) (void)hipEventDestroy(e);
+  };
+  auto enqueue_all = [&]() -> int {
+    HIPTRY(hipEventRecord(ev_fork, cs));
+    for (size_t i = 0; i < nl; ++i) {
+      Lane& L = lanes[i];
+      HIPTRY(hipStreamWaitEvent(L.w->st, ev_fork, 0));
+      TRY(enqueue_iteration(*L.D, *L.w, L.c, L.p0, o, opts.eps));
+      HIPTRY(hipEventRecord(ev_join[i], L.w->st));
+      HIPTRY(hipStreamWaitEvent(cs, ev_join[i], 0));
+    }
+    return YAND_OK;
+  };
+  auto read_all = [&]() -> int {
+    if (dev_sc) {
+      HIPTRY(hipMemcpyAsync(host_sc, dev_sc, nl * sizeof(DevScalars),
+                            hipMemcpyDeviceToHost, cs));
+      HIPTRY(hipStreamSynchronize(cs));
+      for (size_t i = 0; i < nl; ++i) lanes[i].w->hs = host_sc[i];
+    } else {
+      for (auto& L : lanes) TRY(sync_scalars(*L.w));
+      HIPTRY(hipStreamSynchronize(cs));
+    }
+    return YAND_OK;
+  };
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  int rc = YAND_OK;
+  for (int it = 0;; ++it) {
+    bool any = false;
+    for (auto& L : lanes) any |= L.active;
+    if (!any) break;
+    // lanes that stopped must skip their work in replays
+    for (auto& L : lanes)
+      if (!L.active && !L.frozen_set) {
+        hipLaunchKernelGGL(set_frozen_kernel, dim3(1), dim3(64), 0, cs,
+                           L.w->sc, 1);
+        L.frozen_set = true;
+      }
+    if (use_graph && it >= 1) {
+      if (!exec) {
+        // the frozen lanes' done flags were set on cs; make lane streams see it
+        if (hipStreamBeginCapture(cs, hipStreamCaptureModeGlobal) !=
+            hipSuccess) {
+          use_graph = false;
+        } else {
+          rc = enqueue_all();
+          hipError_t e = hipStreamEndCapture(cs, &graph);
+          if (rc != YAND_OK || e != hipSuccess) {
+            cleanup();
+            return rc != YAND_OK ? rc : YAND_ERR_HIP;
+          }
+          if (hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0) !=
+              hipSuccess) {
+            (void)hipGetLastError();
+            (void)hipGraphDestroy(graph);
+            graph = nullptr;
+            exec = nullptr;
+            use_graph = false;
+          }
+        }
+      }
+    }
+    if (exec) {
+      if (hipGraphLaunch(exec, cs) != hipSuccess) {
+        rc = YAND_ERR_HIP;
+        break;
+      }
+    } else {
+      rc = enqueue_all();
+      if (rc) break;
+    }
+    if ((rc = read_all())) break;
+    for (auto& L : lanes) {
+      if (!L.active) continue;
+      if ((rc = after_iteration(L, opts, o))) break;
+    }
+    if (rc) break;
+  }
+  if (exec) (void)hipGraphExecDestroy(exec);
+  if (graph) (void)hipGraphDestroy(graph);
+  cleanup();
+  if (rc) return rc;
+  for (auto& L : lanes)
+    if (L.rc == YAND_OK && !L.converged) TRY(final_check(L, opts));
+  return YAND_OK;
 }
 
 }  // namespace
@@ -551,15 +893,11 @@ int yand_is_certified_convex(const double c[4]) {
 
 int yand_destroy(yand_ctx* ctx) {
   if (!ctx) return YAND_OK;
-  flush_timed(ctx);
-  void* ptrs[] = {ctx->A, ctx->mu, ctx->Efix, ctx->AEfix, ctx->x, ctx->g,
-                  ctx->d, ctx->z, ctx->wv, ctx->q, ctx->AE, ctx->E, ctx->W,
-                  ctx->t3, ctx->r, ctx->y, ctx->y2, ctx->hv, ctx->s_t,
-                  ctx->pcg_s, ctx->pcg_res, ctx->pcg_p, ctx->pcg_u, ctx->part,
-                  ctx->psums, ctx->sums, ctx->trpart, ctx->B, ctx->M, ctx->X,
-                  ctx->rn, ctx->sc};
+  flush_timed(ctx->prof, ctx->w.st);
+  free_work(ctx->w);
+  void* ptrs[] = {ctx->d.A, ctx->d.mu, ctx->d.Efix, ctx->d.AEfix};
   for (void* p : ptrs)
-    if (p) hipFree(p);
+    if (p) (void)hipFree(p);
   delete ctx;
   return YAND_OK;
 }
@@ -572,102 +910,81 @@ int yand_create(const double* R, int64_t T, int64_t n, int64_t ldr,
   if (precision < 0 || precision > 2) return YAND_ERR_ARG;
   if (n > max_pass_columns(precision)) return YAND_ERR_ARG;
   yand_ctx* ctx = new yand_ctx();
-  ctx->stream = (hipStream_t)hip_stream;
-  hipGetDevice(&ctx->device);
-  ctx->precision = precision;
-  ctx->T = T;
-  ctx->n = n;
-  ctx->Tp = round_up(T, kRowPad);
-  ctx->lda = round_up(n, kColPad);
-  ctx->nt = ctx->lda / kTile;
-  ctx->esize = precision == 0 ? 8 : precision == 1 ? 4 : 2;
-  const int64_t Tp = ctx->Tp, lda = ctx->lda;
+  Data& D = ctx->d;
+  Work& w = ctx->w;
+  w.st = (hipStream_t)hip_stream;
+  w.own_stream = false;
+  w.prof = &ctx->prof;
+  (void)hipGetDevice(&D.device);
+  D.precision = precision;
+  D.T = T;
+  D.n = n;
+  D.Tp = round_up(T, kRowPad);
+  D.lda = round_up(n, kColPad);
+  D.nt = D.lda / kTile;
+  D.esize = precision == 0 ? 8 : precision == 1 ? 4 : 2;
   auto fail = [&](int rc) {
     yand_destroy(ctx);
     return rc;
   };
-  int rc = YAND_OK;
-  const size_t nb = (size_t)lda * sizeof(double), tb = (size_t)Tp * sizeof(double);
-  if ((rc = alloc(&ctx->A, (size_t)Tp * lda * ctx->esize)) ||
-      (rc = alloc((void**)&ctx->mu, nb)) ||
-      (rc = alloc((void**)&ctx->Efix, 2 * nb)) ||
-      (rc = alloc((void**)&ctx->AEfix, 2 * tb)) ||
-      (rc = alloc((void**)&ctx->x, nb)) || (rc = alloc((void**)&ctx->g, nb)) ||
-      (rc = alloc((void**)&ctx->d, nb)) || (rc = alloc((void**)&ctx->z, tb)) ||
-      (rc = alloc((void**)&ctx->wv, tb)) || (rc = alloc((void**)&ctx->q, tb)) ||
-      (rc = alloc((void**)&ctx->AE, 3 * tb)) ||
-      (rc = alloc((void**)&ctx->E, 3 * nb)) ||
-      (rc = alloc((void**)&ctx->W, 3 * nb)) ||
-      (rc = alloc((void**)&ctx->t3, nb)) || (rc = alloc((void**)&ctx->r, nb)) ||
-      (rc = alloc((void**)&ctx->y, nb)) || (rc = alloc((void**)&ctx->y2, nb)) ||
-      (rc = alloc((void**)&ctx->hv, nb)) || (rc = alloc((void**)&ctx->s_t, tb)) ||
-      (rc = alloc((void**)&ctx->pcg_s, nb)) ||
-      (rc = alloc((void**)&ctx->pcg_res, nb)) ||
-      (rc = alloc((void**)&ctx->pcg_p, nb)) ||
-      (rc = alloc((void**)&ctx->pcg_u, nb)) ||
-      (rc = alloc((void**)&ctx->part,
-                  (size_t)kMaxPassGroups * lda * sizeof(double))) ||
-      (rc = alloc((void**)&ctx->psums,
-                  (size_t)kMaxPassGroups * kMaxSums * sizeof(double))) ||
-      (rc = alloc((void**)&ctx->sums, kMaxSums * sizeof(double))) ||
-      (rc = alloc((void**)&ctx->trpart,
-                  (size_t)((n + 63) / 64) * n * sizeof(double))) ||
-      (rc = alloc((void**)&ctx->sc, sizeof(DevScalars))))
+  int rc;
+  const size_t nb = (size_t)D.lda * sizeof(double),
+               tb = (size_t)D.Tp * sizeof(double);
+  if ((rc = alloc(&D.A, (size_t)D.Tp * D.lda * D.esize)) ||
+      (rc = alloc((void**)&D.mu, nb)) ||
+      (rc = alloc((void**)&D.Efix, 2 * nb)) ||
+      (rc = alloc((void**)&D.AEfix, 2 * tb)))
     return fail(rc);
-  hipStream_t st = ctx->stream;
-  if (hipMemsetAsync(ctx->sc, 0, sizeof(DevScalars), st) != hipSuccess ||
-      fill(ctx->z, Tp, 0.0, st) != hipSuccess ||
-      fill(ctx->q, Tp, 0.0, st) != hipSuccess ||
-      fill(ctx->AE, 3 * Tp, 0.0, st) != hipSuccess)
-    return fail(YAND_ERR_HIP);
+  if ((rc = alloc_work(w, D, nullptr))) return fail(rc);
+  hipStream_t st = w.st;
   double* colpart = nullptr;
   const int64_t nchunks = (T + 255) / 256;
   if ((rc = alloc((void**)&colpart, (size_t)nchunks * n * sizeof(double))))
     return fail(rc);
-  hipError_t e = launch_center(R, T, n, ldr, precision, ctx->A, Tp, lda,
-                               ctx->mu, colpart, &ctx->sc->nonfinite, st);
-  if (e != hipSuccess) {
-    hipFree(colpart);
-    return fail(YAND_ERR_HIP);
-  }
-  // constraint frame and the fixed projections A e1, A e2
-  int* has_e2 = (int*)&ctx->sc->pad;
-  hipLaunchKernelGGL(efix_kernel, dim3(1), dim3(PT), 0, st, ctx->mu, n,
-                     ctx->Efix, has_e2);
-  for (int a = 0; a < 2; ++a) {
-    PassArgs pa = pass_args(ctx, nullptr);
-    pa.v = ctx->Efix + (int64_t)a * n;
-    pa.tout = ctx->AEfix + (int64_t)a * Tp;
-    int nwg;
-    if (launch_pass(precision, PassKind::Dot, pa, st, &nwg) != hipSuccess) {
-      hipFree(colpart);
-      return fail(YAND_ERR_HIP);
+  hipError_t e = launch_center(R, T, n, ldr, precision, D.A, D.Tp, D.lda,
+                               D.mu, colpart, &w.sc->nonfinite, st);
+  if (e == hipSuccess) {
+    hipLaunchKernelGGL(efix_kernel, dim3(1), dim3(PT), 0, st, D.mu, n, D.Efix,
+                       w.sums);
+    for (int a = 0; a < 2 && e == hipSuccess; ++a) {
+      PassArgs pa = pass_args(D, w, nullptr);
+      pa.v = D.Efix + (int64_t)a * n;
+      pa.tout = D.AEfix + (int64_t)a * D.Tp;
+      int nwg;
+      e = launch_pass(precision, PassKind::Dot, pa, st, &nwg);
     }
   }
-  if (sync_scalars(ctx) != YAND_OK) {
-    hipFree(colpart);
-    return fail(YAND_ERR_HIP);
-  }
-  hipFree(colpart);
-  if (ctx->hs.nonfinite) return fail(YAND_ERR_NONFINITE);
-  ctx->have_e2 = ctx->hs.pad != 0;
+  double stats[2] = {0.0, 0.0};
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(stats, w.sums, 2 * sizeof(double),
+                       hipMemcpyDeviceToHost, st);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(&w.hs, w.sc, sizeof(DevScalars), hipMemcpyDeviceToHost,
+                       st);
+  if (e == hipSuccess) e = hipStreamSynchronize(st);
+  (void)hipFree(colpart);
+  if (e != hipSuccess) return fail(YAND_ERR_HIP);
+  if (w.hs.nonfinite) return fail(YAND_ERR_NONFINITE);
+  D.mbar = stats[0];
+  D.mnorm = stats[1];
+  D.have_e2 = stats[1] > 1e-300;
   *out = ctx;
   return YAND_OK;
 }
 
 int yand_shape(yand_ctx* ctx, int64_t* T, int64_t* n, int* precision) {
   if (!ctx) return YAND_ERR_ARG;
-  if (T) *T = ctx->T;
-  if (n) *n = ctx->n;
-  if (precision) *precision = ctx->precision;
+  if (T) *T = ctx->d.T;
+  if (n) *n = ctx->d.n;
+  if (precision) *precision = ctx->d.precision;
   return YAND_OK;
 }
 
 int yand_get_mu(yand_ctx* ctx, double* mu_out) {
   if (!ctx || !mu_out) return YAND_ERR_ARG;
-  HIPTRY(hipMemcpyAsync(mu_out, ctx->mu, ctx->n * sizeof(double),
-                        hipMemcpyDeviceToDevice, ctx->stream));
-  HIPTRY(hipStreamSynchronize(ctx->stream));
+  HIPTRY(hipMemcpyAsync(mu_out, ctx->d.mu, ctx->d.n * sizeof(double),
+                        hipMemcpyDeviceToDevice, ctx->w.st));
+  HIPTRY(hipStreamSynchronize(ctx->w.st));
   return YAND_OK;
 }
 
@@ -675,26 +992,27 @@ int yand_eval(yand_ctx* ctx, const double c[4], const double* w, double* f,
               double* grad, double mom[4]) {
   if (!ctx || !w) return YAND_ERR_ARG;
   TRY(check_c(c));
-  TRY(oracle_at(ctx, c, w, grad != nullptr));
+  Work& W = ctx->w;
+  TRY(oracle_at(ctx->d, W, c, w, grad != nullptr));
   if (grad)
-    HIPTRY(hipMemcpyAsync(grad, ctx->g, ctx->n * sizeof(double),
-                          hipMemcpyDeviceToDevice, ctx->stream));
-  TRY(sync_scalars(ctx));
-  if (f) *f = ctx->hs.f;
+    HIPTRY(hipMemcpyAsync(grad, W.g, ctx->d.n * sizeof(double),
+                          hipMemcpyDeviceToDevice, W.st));
+  TRY(sync_scalars(W));
+  if (f) *f = W.hs.f;
   if (mom)
-    for (int i = 0; i < 4; ++i) mom[i] = ctx->hs.mom[i];
-  flush_timed(ctx);
-  return ctx->hs.nonfinite ? YAND_ERR_NONFINITE : YAND_OK;
+    for (int i = 0; i < 4; ++i) mom[i] = W.hs.mom[i];
+  flush_timed(ctx->prof, W.st);
+  return W.hs.nonfinite ? YAND_ERR_NONFINITE : YAND_OK;
 }
 
 int yand_hvp(yand_ctx* ctx, const double c[4], const double* w,
              const double* v, double* hv) {
   if (!ctx || !w || !v || !hv) return YAND_ERR_ARG;
   TRY(check_c(c));
-  TRY(oracle_at(ctx, c, w, false));
-  TRY(hvp_cached(ctx, c, v, hv, nullptr));
-  HIPTRY(hipStreamSynchronize(ctx->stream));
-  flush_timed(ctx);
+  TRY(oracle_at(ctx->d, ctx->w, c, w, false));
+  TRY(hvp_cached(ctx->d, ctx->w, c, v, hv, nullptr));
+  HIPTRY(hipStreamSynchronize(ctx->w.st));
+  flush_timed(ctx->prof, ctx->w.st);
   return YAND_OK;
 }
 
@@ -702,12 +1020,13 @@ int yand_linesearch_coeffs(yand_ctx* ctx, const double c[4], const double* w,
                            const double* d, double coef[5]) {
   if (!ctx || !w || !d || !coef) return YAND_ERR_ARG;
   TRY(check_c(c));
-  TRY(oracle_at(ctx, c, w, false));
-  HIPTRY(launch_dot(ctx->mu, d, ctx->n, &ctx->sc->mud, ctx->stream));
-  TRY(line_at(ctx, c, d, 0));
-  TRY(sync_scalars(ctx));
-  for (int i = 0; i < 5; ++i) coef[i] = ctx->hs.coef[i];
-  flush_timed(ctx);
+  Work& W = ctx->w;
+  TRY(oracle_at(ctx->d, W, c, w, false));
+  HIPTRY(launch_dot(ctx->d.mu, d, ctx->d.n, &W.sc->mud, W.st));
+  TRY(line_at(ctx->d, W, c, d, 0, nullptr));
+  TRY(sync_scalars(W));
+  for (int i = 0; i < 5; ++i) coef[i] = W.hs.coef[i];
+  flush_timed(ctx->prof, W.st);
   return YAND_OK;
 }
 
@@ -715,15 +1034,17 @@ int yand_select_step(yand_ctx* ctx, const double coef[5], double alpha_max,
                      double* alpha) {
   if (!ctx || !coef || !alpha) return YAND_ERR_ARG;
   if (std::isnan(alpha_max) || alpha_max < 0.0) return YAND_ERR_ARG;
-  DevScalars hs = ctx->hs;
+  Work& W = ctx->w;
+  TRY(sync_scalars(W));
+  DevScalars hs = W.hs;
   for (int i = 0; i < 5; ++i) hs.coef[i] = coef[i];
   hs.amax = alpha_max;
-  HIPTRY(hipMemcpyAsync(ctx->sc, &hs, sizeof(DevScalars),
-                        hipMemcpyHostToDevice, ctx->stream));
-  HIPTRY(launch_select_step(ctx->sc, ctx->stream));
-  TRY(sync_scalars(ctx));
-  *alpha = ctx->hs.alpha;
-  return ctx->hs.status == 0 ? YAND_OK : YAND_ERR_UNBOUNDED;
+  HIPTRY(hipMemcpyAsync(W.sc, &hs, sizeof(DevScalars), hipMemcpyHostToDevice,
+                        W.st));
+  HIPTRY(launch_select_step(W.sc, W.st));
+  TRY(sync_scalars(W));
+  *alpha = W.hs.alpha;
+  return W.hs.status == 0 ? YAND_OK : YAND_ERR_UNBOUNDED;
 }
 
 int yand_affine_normal(yand_ctx* ctx, const double c[4], const double* target,
@@ -731,8 +1052,10 @@ int yand_affine_normal(yand_ctx* ctx, const double c[4], const double* target,
                        double* gnorm) {
   if (!ctx || !w || !d_out) return YAND_ERR_ARG;
   TRY(check_c(c));
-  int p0;
-  TRY(setup_constraints(ctx, target, &p0));
+  Work& W = ctx->w;
+  int p0 = target ? 2 : 1;
+  if (target && (!ctx->d.have_e2 || !std::isfinite(*target))) return YAND_ERR_ARG;
+  HIPTRY(launch_copy(W.E, ctx->d.Efix, (int64_t)p0 * ctx->d.n, W.st));
   DirOpts o;
   if (opts) {
     o.solver = opts->solver;
@@ -741,12 +1064,94 @@ int yand_affine_normal(yand_ctx* ctx, const double c[4], const double* target,
     o.krylov_maxit = opts->krylov_maxit;
     o.tau = opts->tau;
   }
-  TRY(oracle_at(ctx, c, w, true));
-  TRY(direction_at(ctx, c, p0, w, o, d_out, nullptr));
-  TRY(sync_scalars(ctx));
-  if (gnorm) *gnorm = ctx->hs.gn;
-  flush_timed(ctx);
-  return ctx->hs.nonfinite ? YAND_ERR_NONFINITE : YAND_OK;
+  TRY(oracle_at(ctx->d, W, c, w, true));
+  HIPTRY(launch_grad_project(W.g, W.E, p0, ctx->d.n, W.sc, W.st));
+  TRY(direction_eager(ctx->d, W, c, p0, w, o, d_out, nullptr));
+  TRY(sync_scalars(W));
+  if (gnorm) *gnorm = W.hs.gn;
+  flush_timed(ctx->prof, W.st);
+  return W.hs.nonfinite ? YAND_ERR_NONFINITE : YAND_OK;
+}
+
+// PCG configuration with stall recovery (eager; the Krylov test is on the host).
+static int solve_pcg(yand_ctx* ctx, const double c[4], int p0,
+                     const yand_opts& opts, yand_info& inf, bool* converged) {
+  const Data& D = ctx->d;
+  Work& w = ctx->w;
+  DirOpts o;
+  o.tau = opts.tau;
+  o.simplex = opts.feasible_set == YAND_SET_SIMPLEX;
+  struct Phase {
+    int solver, kmax, max_iter;
+    double reg;
+  };
+  std::vector<Phase> phases;
+  phases.push_back({YAND_SOLVER_PCG, opts.krylov_maxit, opts.max_iter,
+                    opts.regularization});
+  if (opts.stall_recovery) {
+    phases.push_back({YAND_SOLVER_PCG, 2 * opts.krylov_maxit,
+                      opts.restart_max_iter, opts.regularization});
+    phases.push_back({YAND_SOLVER_DIRECT, 0, opts.restart_max_iter, 0.0});
+  }
+  *converged = false;
+  for (size_t ph = 0; ph < phases.size() && !*converged; ++ph) {
+    if (ph > 0) inf.restarts++;
+    o.solver = phases[ph].solver;
+    o.krylov_maxit = phases[ph].kmax;
+    o.reg = phases[ph].reg;
+    const auto t_phase = std::chrono::steady_clock::now();
+    int small = 0;
+    double f_prev = NAN;
+    for (int it = 0;; ++it) {
+      TRY(oracle_at(D, w, c, w.x, true));
+      inf.oracle_passes++;
+      HIPTRY(launch_grad_project(w.g, w.E, p0, D.n, w.sc, w.st));
+      TRY(sync_scalars(w));
+      inf.f = w.hs.f;
+      inf.gnorm = w.hs.gn;
+      if (w.hs.nonfinite) return YAND_ERR_NONFINITE;
+      if (std::isnan(f_prev)) f_prev = w.hs.f;
+      if (w.hs.gn <= opts.eps) {
+        *converged = true;
+        break;
+      }
+      if (it >= phases[ph].max_iter) break;
+      const double el = std::chrono::duration<double>(
+                            std::chrono::steady_clock::now() - t_phase)
+                            .count();
+      if (opts.max_elapsed > 0.0 && el > opts.max_elapsed) break;
+      DirStats ds;
+      TRY(direction_eager(D, w, c, p0, w.x, o, w.d, &ds));
+      inf.dense_traces++;
+      inf.third_passes++;
+      inf.cg_iters += ds.cg;
+      inf.hvp_passes += ds.cg;
+      TRY(line_at(D, w, c, w.d, 1, nullptr));
+      inf.ls_passes++;
+      TRY(sync_scalars(w));
+      inf.lambda_used = w.hs.lambda;
+      if (w.hs.status != 0) return YAND_ERR_UNBOUNDED;
+      HIPTRY(launch_axpy(w.x, w.d, D.n, w.sc, w.st));
+      inf.iterations++;
+      const double a = w.hs.alpha, *A = w.hs.coef;
+      const double dec = -(a * (A[1] + a * (A[2] + a * (A[3] + a * A[4]))));
+      if (dec < 1e-14 * std::fabs(f_prev)) {
+        if (++small >= 3) break;
+      } else {
+        small = 0;
+      }
+      f_prev = A[0] - dec;
+    }
+  }
+  return YAND_OK;
+}
+
+static bool valid_opts(const yand_opts& o) {
+  return o.eps >= 0.0 && o.max_iter >= 0 && o.tau >= 0.0 &&
+         (o.solver == YAND_SOLVER_DIRECT || o.solver == YAND_SOLVER_PCG) &&
+         (o.feasible_set == YAND_SET_BUDGET ||
+          o.feasible_set == YAND_SET_SIMPLEX) &&
+         o.krylov_maxit >= 0 && o.restart_max_iter >= 0;
 }
 
 int yand_mvsk_solve(yand_ctx* ctx, const double c[4], const double* target,
@@ -759,140 +1164,44 @@ int yand_mvsk_solve(yand_ctx* ctx, const double c[4], const double* target,
     opts = *opts_in;
   else
     yand_default_opts(&opts);
-  if (opts.eps < 0.0 || opts.max_iter < 0 || opts.tau < 0.0)
-    return YAND_ERR_ARG;
-  if (target && !std::isfinite(*target)) return YAND_ERR_ARG;
+  if (!valid_opts(opts)) return YAND_ERR_ARG;
   const auto t_start = std::chrono::steady_clock::now();
-  hipStream_t st = ctx->stream;
-  const int64_t n = ctx->n;
+  const Data& D = ctx->d;
+  Work& w = ctx->w;
   int p0;
-  TRY(setup_constraints(ctx, target, &p0));
-  // starting point: w0 or equal weights, moved onto the constraints
-  if (w0)
-    HIPTRY(hipMemcpyAsync(ctx->x, w0, n * sizeof(double),
-                          hipMemcpyDeviceToDevice, st));
-  else
-    HIPTRY(fill(ctx->x, n, 1.0 / (double)n, st));
-  {
-    // right-hand sides in the orthonormal e-basis: e1^T x = 1/sqrt(n);
-    // e2^T x = (r - mbar) / |mu - mbar| where mbar = mean(mu).
-    std::vector<double> mu_h(n);
-    HIPTRY(hipMemcpyAsync(mu_h.data(), ctx->mu, n * sizeof(double),
-                          hipMemcpyDeviceToHost, st));
-    HIPTRY(hipStreamSynchronize(st));
-    double mbar = 0.0, ss = 0.0;
-    for (int64_t j = 0; j < n; ++j) mbar += mu_h[j];
-    mbar /= (double)n;
-    for (int64_t j = 0; j < n; ++j) ss += (mu_h[j] - mbar) * (mu_h[j] - mbar);
-    const double b1 = 1.0 / std::sqrt((double)n);
-    const double b2 = target ? (*target - mbar) / std::sqrt(ss) : 0.0;
-    hipLaunchKernelGGL(feasible_kernel, dim3(1), dim3(PT), 0, st, ctx->x,
-                       ctx->E, p0, n, b1, b2);
-  }
-  DirOpts o;
-  o.reg = opts.regularization;
-  o.krylov_tol = opts.krylov_tol;
-  o.krylov_maxit = opts.krylov_maxit;
-  o.tau = opts.tau;
-  o.simplex = opts.feasible_set == YAND_SET_SIMPLEX;
-  if (o.simplex) {
-    // the start must lie in Delta(tau)
-    std::vector<double> xh(n);
-    HIPTRY(hipMemcpyAsync(xh.data(), ctx->x, n * sizeof(double),
-                          hipMemcpyDeviceToHost, st));
-    HIPTRY(hipStreamSynchronize(st));
-    for (int64_t j = 0; j < n; ++j)
-      if (!(xh[j] >= opts.tau)) return YAND_ERR_ARG;
-  }
+  TRY(setup_lane(D, w, target, w0, &p0));
+  if (opts.feasible_set == YAND_SET_SIMPLEX)
+    TRY(check_simplex_start(D, w, opts.tau));
   yand_info inf{};
-  int status = YAND_WARN_MAXITER;
   int rc = YAND_OK;
-  // phases: baseline, then (PCG with stall recovery) mild and aggressive
-  struct Phase {
-    int solver, kmax, max_iter;
-    double reg;
-  };
-  std::vector<Phase> phases;
-  phases.push_back({opts.solver, opts.krylov_maxit, opts.max_iter,
-                    opts.solver == YAND_SOLVER_PCG ? opts.regularization
-                                                   : 0.0});
-  if (opts.solver == YAND_SOLVER_PCG && opts.stall_recovery) {
-    phases.push_back({YAND_SOLVER_PCG, 2 * opts.krylov_maxit,
-                      opts.restart_max_iter, opts.regularization});
-    phases.push_back({YAND_SOLVER_DIRECT, 0, opts.restart_max_iter, 0.0});
-  }
   bool converged = false;
-  for (size_t ph = 0; ph < phases.size() && !converged && rc == YAND_OK;
-       ++ph) {
-    if (ph > 0) inf.restarts++;
-    o.solver = phases[ph].solver;
-    o.krylov_maxit = phases[ph].kmax;
-    o.reg = phases[ph].reg;
-    const auto t_phase = std::chrono::steady_clock::now();
-    int small = 0;
-    double f_prev = NAN;
-    for (int it = 0;; ++it) {
-      rc = oracle_at(ctx, c, ctx->x, true);
-      if (rc) break;
-      inf.oracle_passes++;
-      rc = launch_grad_project(ctx->g, ctx->E, p0, n, ctx->sc, st) == hipSuccess
-               ? YAND_OK
-               : YAND_ERR_HIP;
-      if (rc) break;
-      if ((rc = sync_scalars(ctx))) break;
-      inf.f = ctx->hs.f;
-      inf.gnorm = ctx->hs.gn;
-      if (ctx->hs.nonfinite) {
-        rc = YAND_ERR_NONFINITE;
-        break;
-      }
-      if (std::isnan(f_prev)) f_prev = ctx->hs.f;
-      if (ctx->hs.gn <= opts.eps) {
-        converged = true;
-        break;
-      }
-      if (it >= phases[ph].max_iter) break;
-      const double el = std::chrono::duration<double>(
-                            std::chrono::steady_clock::now() - t_phase)
-                            .count();
-      if (opts.max_elapsed > 0.0 && el > opts.max_elapsed) break;
-      DirStats ds;
-      rc = direction_at(ctx, c, p0, ctx->x, o, ctx->d, &ds);
-      if (rc) break;
-      inf.dense_traces++;
-      inf.third_passes++;
-      inf.cg_iters += ds.cg;
-      inf.hvp_passes += ds.cg;
-      rc = line_at(ctx, c, ctx->d, 1);
-      if (rc) break;
-      inf.ls_passes++;
-      if ((rc = sync_scalars(ctx))) break;
-      inf.lambda_used = ctx->hs.lambda;
-      if (ctx->hs.status != 0) {
-        rc = YAND_ERR_UNBOUNDED;
-        break;
-      }
-      HIPTRY(launch_axpy(ctx->x, ctx->d, n, ctx->sc, st));
-      inf.iterations++;
-      // stall: objective decrease below 1e-14 relative three times running
-      const double a = ctx->hs.alpha, *A = ctx->hs.coef;
-      const double dec = -(a * (A[1] + a * (A[2] + a * (A[3] + a * A[4]))));
-      if (dec < 1e-14 * std::fabs(f_prev)) {
-        if (++small >= 3) break;
-      } else {
-        small = 0;
-      }
-      f_prev = A[0] - dec;
+  if (opts.solver == YAND_SOLVER_PCG) {
+    rc = solve_pcg(ctx, c, p0, opts, inf, &converged);
+  } else {
+    DirOpts o;
+    o.tau = opts.tau;
+    o.simplex = opts.feasible_set == YAND_SET_SIMPLEX;
+    std::vector<Lane> lanes(1);
+    Lane& L = lanes[0];
+    L.D = &D;
+    L.w = &w;
+    for (int i = 0; i < 4; ++i) L.c[i] = c[i];
+    L.p0 = p0;
+    L.active = opts.max_iter > 0;
+    rc = run_lanes(lanes, opts, o, w.st, false, nullptr, nullptr);
+    if (rc == YAND_OK) {
+      inf = L.info;
+      converged = L.converged;
+      if (L.rc != YAND_OK) rc = L.rc;
     }
   }
+  int status;
   if (rc == YAND_OK) {
-    if (converged)
-      status = YAND_OK;
-    else
-      status = inf.restarts > 0 ? YAND_WARN_STALL : YAND_WARN_MAXITER;
-    HIPTRY(hipMemcpyAsync(w_out, ctx->x, n * sizeof(double),
-                          hipMemcpyDeviceToDevice, st));
-    HIPTRY(hipStreamSynchronize(st));
+    status = converged ? YAND_OK
+                       : (inf.restarts > 0 ? YAND_WARN_STALL : YAND_WARN_MAXITER);
+    HIPTRY(hipMemcpyAsync(w_out, w.x, D.n * sizeof(double),
+                          hipMemcpyDeviceToDevice, w.st));
+    HIPTRY(hipStreamSynchronize(w.st));
   } else {
     status = rc;
   }
@@ -901,8 +1210,163 @@ int yand_mvsk_solve(yand_ctx* ctx, const double c[4], const double* target,
                     std::chrono::steady_clock::now() - t_start)
                     .count();
   if (info) *info = inf;
-  flush_timed(ctx);
+  flush_timed(ctx->prof, w.st);
   return status;
+}
+
+// Batched solve: each instance b runs on contexts[b] (one shared context for
+// a frontier, or different ones for universes of different n).  Instances are
+// processed in waves of at most `lanes` solves that advance together.
+static int batch_solve(int64_t B, yand_ctx* const* ctxs, const double* C4,
+                       const double* targets, const yand_opts* opts_in,
+                       double* const* W_out, yand_info* infos, int max_lanes,
+                       int use_graph) {
+  if (B <= 0 || !ctxs || !C4 || !W_out) return YAND_ERR_ARG;
+  yand_opts opts;
+  if (opts_in)
+    opts = *opts_in;
+  else
+    yand_default_opts(&opts);
+  if (!valid_opts(opts)) return YAND_ERR_ARG;
+  if (opts.solver != YAND_SOLVER_DIRECT) return YAND_ERR_ARG;
+  for (int64_t b = 0; b < B; ++b) {
+    if (!ctxs[b] || !W_out[b]) return YAND_ERR_ARG;
+    TRY(check_c(C4 + 4 * b));
+    if (ctxs[b]->d.device != ctxs[0]->d.device) return YAND_ERR_ARG;
+  }
+  const auto t_start = std::chrono::steady_clock::now();
+  // Own control stream (graph capture is not allowed on the legacy default
+  // stream), ordered after the caller's stream and joined back at the end.
+  hipStream_t caller = ctxs[0]->w.st;
+  hipStream_t cs = nullptr;
+  hipEvent_t ev_in = nullptr, ev_out = nullptr;
+  HIPTRY(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
+  HIPTRY(hipEventCreateWithFlags(&ev_in, hipEventDisableTiming));
+  HIPTRY(hipEventCreateWithFlags(&ev_out, hipEventDisableTiming));
+  HIPTRY(hipEventRecord(ev_in, caller));
+  HIPTRY(hipStreamWaitEvent(cs, ev_in, 0));
+  DirOpts o;
+  o.tau = opts.tau;
+  o.simplex = opts.feasible_set == YAND_SET_SIMPLEX;
+  // lane count: bounded by max_lanes and by free device memory
+  size_t freeb = 0, totalb = 0;
+  (void)hipMemGetInfo(&freeb, &totalb);
+  size_t per_lane = 0;
+  for (int64_t b = 0; b < B; ++b) {
+    const Data& D = ctxs[b]->d;
+    size_t need = 3 * (size_t)D.lda * D.lda * 8 + (size_t)D.nt * D.Tp * 8 +
+                  (size_t)kMaxPassGroups * D.lda * 8 + 12 * (size_t)D.Tp * 8 +
+                  24 * (size_t)D.lda * 8 + (size_t)((D.n + 63) / 64) * D.n * 8;
+    per_lane = std::max(per_lane, need);
+  }
+  int64_t nl = std::min<int64_t>(B, max_lanes > 0 ? max_lanes : 64);
+  const int64_t mem_lanes = (int64_t)((freeb / 2) / std::max<size_t>(per_lane, 1));
+  nl = std::max<int64_t>(1, std::min(nl, mem_lanes));
+  // workspaces with their own streams and one contiguous scalar block
+  DevScalars* dev_sc = nullptr;
+  if (alloc((void**)&dev_sc, (size_t)nl * sizeof(DevScalars)) != YAND_OK) {
+    (void)hipStreamDestroy(cs);
+    (void)hipEventDestroy(ev_in);
+    (void)hipEventDestroy(ev_out);
+    return YAND_ERR_OOM;
+  }
+  HIPTRY(hipMemsetAsync(dev_sc, 0, (size_t)nl * sizeof(DevScalars), cs));
+  std::vector<DevScalars> host_sc(nl);
+  std::vector<Work> works(nl);
+  // every workspace is sized for the largest instance it may serve
+  Data big = ctxs[0]->d;
+  for (int64_t b = 0; b < B; ++b) {
+    const Data& D = ctxs[b]->d;
+    big.n = std::max(big.n, D.n);
+    big.lda = std::max(big.lda, D.lda);
+    big.Tp = std::max(big.Tp, D.Tp);
+    big.nt = std::max(big.nt, D.nt);
+  }
+  int rc = YAND_OK;
+  for (int64_t i = 0; i < nl && rc == YAND_OK; ++i) {
+    Work& w = works[i];
+    if (hipStreamCreateWithFlags(&w.st, hipStreamNonBlocking) != hipSuccess) {
+      rc = YAND_ERR_HIP;
+      break;
+    }
+    w.own_stream = true;
+    if (hipStreamWaitEvent(w.st, ev_in, 0) != hipSuccess) {
+      rc = YAND_ERR_HIP;
+      break;
+    }
+    rc = alloc_work(w, big, dev_sc + i);
+    if (rc == YAND_OK) rc = ensure_dense(w, big);
+  }
+  for (int64_t start = 0; start < B && rc == YAND_OK; start += nl) {
+    const int64_t cnt = std::min(nl, B - start);
+    std::vector<Lane> lanes(cnt);
+    for (int64_t i = 0; i < cnt && rc == YAND_OK; ++i) {
+      const int64_t b = start + i;
+      Lane& L = lanes[i];
+      L.D = &ctxs[b]->d;
+      L.w = &works[i];
+      for (int k = 0; k < 4; ++k) L.c[k] = C4[4 * b + k];
+      L.has_target = targets != nullptr;
+      if (targets) L.target = targets[b];
+      L.w_out = W_out[b];
+      L.active = opts.max_iter > 0;
+      rc = setup_lane(*L.D, *L.w, targets ? &L.target : nullptr, nullptr,
+                      &L.p0);
+      if (rc == YAND_OK && o.simplex)
+        rc = check_simplex_start(*L.D, *L.w, opts.tau);
+    }
+    for (auto& w : works) {
+      if (rc != YAND_OK) break;
+      if (hipStreamSynchronize(w.st) != hipSuccess) rc = YAND_ERR_HIP;
+    }
+    if (rc != YAND_OK) break;
+    rc = run_lanes(lanes, opts, o, cs, use_graph != 0, host_sc.data(),
+                   dev_sc);
+    for (int64_t i = 0; i < cnt && rc == YAND_OK; ++i) {
+      Lane& L = lanes[i];
+      const int64_t b = start + i;
+      int st = L.rc != YAND_OK ? L.rc
+                               : (L.converged ? YAND_OK : YAND_WARN_MAXITER);
+      L.info.status = st;
+      if (hipMemcpyAsync(L.w_out, L.w->x, L.D->n * sizeof(double),
+                         hipMemcpyDeviceToDevice, cs) != hipSuccess)
+        rc = YAND_ERR_HIP;
+      L.info.elapsed = std::chrono::duration<double>(
+                           std::chrono::steady_clock::now() - t_start)
+                           .count();
+      if (infos) infos[b] = L.info;
+    }
+  }
+  if (hipStreamSynchronize(cs) != hipSuccess && rc == YAND_OK)
+    rc = YAND_ERR_HIP;
+  for (auto& w : works) free_work(w);
+  (void)hipFree(dev_sc);
+  (void)hipEventRecord(ev_out, cs);
+  (void)hipStreamWaitEvent(caller, ev_out, 0);
+  (void)hipStreamSynchronize(caller);
+  (void)hipEventDestroy(ev_in);
+  (void)hipEventDestroy(ev_out);
+  (void)hipStreamDestroy(cs);
+  return rc;
+}
+
+int yand_frontier_solve(yand_ctx* ctx, int64_t B, const double* C4,
+                        const double* targets, const yand_opts* opts,
+                        double* W_out, yand_info* infos) {
+  if (!ctx || !W_out || B <= 0) return YAND_ERR_ARG;
+  std::vector<yand_ctx*> ctxs(B, ctx);
+  std::vector<double*> outs(B);
+  for (int64_t b = 0; b < B; ++b) outs[b] = W_out + b * ctx->d.n;
+  return batch_solve(B, ctxs.data(), C4, targets, opts, outs.data(), infos, 64,
+                     1);
+}
+
+int yand_batch_solve(int64_t B, yand_ctx* const* ctxs, const double* C4,
+                     const double* targets, const yand_opts* opts,
+                     double* const* W_out, yand_info* infos, int max_lanes,
+                     int use_graph) {
+  return batch_solve(B, ctxs, C4, targets, opts, W_out, infos, max_lanes,
+                     use_graph);
 }
 
 int yand_mvsk_solve_R(const double* R, int64_t T, int64_t n, double c1,
@@ -917,22 +1381,21 @@ int yand_mvsk_solve_R(const double* R, int64_t T, int64_t n, double c1,
   return rc;
 }
 
-// Per-kernel timing (instrumentation, not part of the method).
 int yand_profile_enable(yand_ctx* ctx, int enable) {
   if (!ctx) return YAND_ERR_ARG;
-  flush_timed(ctx);
-  ctx->profiling = enable != 0;
-  if (enable) ctx->prof.clear();
+  flush_timed(ctx->prof, ctx->w.st);
+  ctx->prof.on = enable != 0;
+  if (enable) ctx->prof.acc.clear();
   return YAND_OK;
 }
 
 int yand_profile_read(yand_ctx* ctx, int index, char* name, int name_len,
                       double* total_ms, int64_t* count) {
   if (!ctx) return YAND_ERR_ARG;
-  flush_timed(ctx);
-  if (index < 0) return (int)ctx->prof.size();
-  if (index >= (int)ctx->prof.size()) return YAND_ERR_ARG;
-  const auto& p = ctx->prof[index];
+  flush_timed(ctx->prof, ctx->w.st);
+  if (index < 0) return (int)ctx->prof.acc.size();
+  if (index >= (int)ctx->prof.acc.size()) return YAND_ERR_ARG;
+  const auto& p = ctx->prof.acc[index];
   if (name && name_len > 0) {
     std::strncpy(name, p.first.c_str(), name_len - 1);
     name[name_len - 1] = 0;

@@ -163,7 +163,9 @@ template <typename S>
 __global__ void __launch_bounds__(NT) syrk_kernel(const S* __restrict__ A,
                                                   int64_t lda, int64_t Tp,
                                                   const double* __restrict__ s,
-                                                  double* __restrict__ B) {
+                                                  double* __restrict__ B,
+                                                  const int* skip) {
+  if (skip && *skip) return;
   __shared__ double sA[BKK * LDP], sB[BKK * LDP];
   int I, J;
   lower_tile(blockIdx.x, &I, &J);
@@ -185,7 +187,8 @@ template <typename S>
 __global__ void __launch_bounds__(NT)
 trace_gemm_kernel(const S* __restrict__ A, int64_t lda, int64_t Tp,
                   const double* __restrict__ X, int64_t ldx,
-                  double* __restrict__ rn) {
+                  double* __restrict__ rn, const int* skip) {
+  if (skip && *skip) return;
   __shared__ double sA[BKK * LDP], sB[BKK * LDP];
   __shared__ double rows[2][BM];
   const int J = blockIdx.x;
@@ -233,7 +236,9 @@ __device__ __forceinline__ void wave_sync() {
 
 __global__ void __launch_bounds__(DT) diag_block_kernel(double* M, double* X,
                                                         int64_t ld, int k,
-                                                        int* fail) {
+                                                        int* fail,
+                                                        const int* skip) {
+  if (skip && *skip) return;
   extern __shared__ double L[];  // BM x LDD
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   double* Mk = M + (int64_t)k * BM * ld + (int64_t)k * BM;
@@ -396,7 +401,9 @@ __global__ void __launch_bounds__(DT) diag_block_kernel(double* M, double* X,
 // L[I, k] = M[I, k] L_kk^-T for I > k (in place).
 __global__ void __launch_bounds__(NT) panel_kernel(double* M,
                                                    const double* X,
-                                                   int64_t ld, int k) {
+                                                   int64_t ld, int k,
+                                                   const int* skip) {
+  if (skip && *skip) return;
   __shared__ double sA[BKK * LDP], sB[BKK * LDP];
   const int I = k + 1 + blockIdx.x;
   double* Mik = M + (int64_t)I * BM * ld + (int64_t)k * BM;
@@ -409,7 +416,8 @@ __global__ void __launch_bounds__(NT) panel_kernel(double* M,
 
 // M[I, J] -= L[I, k] L[J, k]^T for k < J <= I.
 __global__ void __launch_bounds__(NT) update_kernel(double* M, int64_t ld,
-                                                    int k) {
+                                                    int k, const int* skip) {
+  if (skip && *skip) return;
   __shared__ double sA[BKK * LDP], sB[BKK * LDP];
   int I, J;
   lower_tile(blockIdx.x, &I, &J);
@@ -426,7 +434,9 @@ __global__ void __launch_bounds__(NT) update_kernel(double* M, int64_t ld,
 
 // X[k, j] = -L_kk^-1 S[k, j] for j < k (S accumulated in place in X).
 __global__ void __launch_bounds__(NT) inv_finalize_kernel(double* X,
-                                                          int64_t ld, int k) {
+                                                          int64_t ld, int k,
+                                                          const int* skip) {
+  if (skip && *skip) return;
   __shared__ double sA[BKK * LDP], sB[BKK * LDP];
   const int j = blockIdx.x;
   const double* Xkk = X + (int64_t)k * BM * ld + (int64_t)k * BM;
@@ -440,7 +450,9 @@ __global__ void __launch_bounds__(NT) inv_finalize_kernel(double* X,
 // S[i, j] += L[i, k] X[k, j] for i > k, j <= k.
 __global__ void __launch_bounds__(NT) inv_update_kernel(double* X,
                                                         const double* M,
-                                                        int64_t ld, int k) {
+                                                        int64_t ld, int k,
+                                                        const int* skip) {
+  if (skip && *skip) return;
   __shared__ double sA[BKK * LDP], sB[BKK * LDP];
   const int i = k + 1 + blockIdx.x / (k + 1);
   const int j = blockIdx.x % (k + 1);
@@ -457,7 +469,8 @@ __global__ void __launch_bounds__(NT) inv_update_kernel(double* X,
 // y = X v, X lower (np x np); one wave per row, rows < n.
 __global__ void trmv_n_kernel(const double* __restrict__ X, int64_t ld,
                               int64_t n, const double* __restrict__ v,
-                              double* __restrict__ y) {
+                              double* __restrict__ y, const int* skip) {
+  if (skip && *skip) return;
   const int64_t i = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
   const int lane = threadIdx.x & 63;
   if (i >= n) return;
@@ -471,7 +484,8 @@ __global__ void trmv_n_kernel(const double* __restrict__ X, int64_t ld,
 constexpr int kTrmvRows = 64;
 __global__ void trmv_t_kernel(const double* __restrict__ X, int64_t ld,
                               int64_t n, const double* __restrict__ v,
-                              double* __restrict__ part) {
+                              double* __restrict__ part, const int* skip) {
+  if (skip && *skip) return;
   const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int64_t i0 = (int64_t)blockIdx.y * kTrmvRows;
   if (j >= n) return;
@@ -484,7 +498,9 @@ __global__ void trmv_t_kernel(const double* __restrict__ X, int64_t ld,
 // W[a*n + i] = sum_j B[i][j] E[a*n + j], a < p (B full symmetric).
 __global__ void symm_multi_kernel(const double* __restrict__ B, int64_t ld,
                                   int64_t n, const double* __restrict__ E,
-                                  int p, double* __restrict__ W) {
+                                  int p, double* __restrict__ W,
+                                  const int* skip) {
+  if (skip && *skip) return;
   const int64_t i = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
   const int lane = threadIdx.x & 63;
   if (i >= n) return;
@@ -504,21 +520,22 @@ __global__ void symm_multi_kernel(const double* __restrict__ B, int64_t ld,
 // ------------------------------------------------------------ launchers --
 
 hipError_t launch_syrk(int precision, const void* A, int64_t lda, int64_t Tp,
-                       const double* s, double* B, hipStream_t st) {
+                       const double* s, double* B, hipStream_t st,
+                       const int* skip) {
   const int64_t nt = lda / BM;
   dim3 g((unsigned)(nt * (nt + 1) / 2)), b(NT);
   switch (precision) {
     case 0:
       hipLaunchKernelGGL(syrk_kernel<double>, g, b, 0, st, (const double*)A,
-                         lda, Tp, s, B);
+                         lda, Tp, s, B, skip);
       break;
     case 1:
       hipLaunchKernelGGL(syrk_kernel<float>, g, b, 0, st, (const float*)A, lda,
-                         Tp, s, B);
+                         Tp, s, B, skip);
       break;
     case 2:
       hipLaunchKernelGGL(syrk_kernel<bf16_t>, g, b, 0, st, (const bf16_t*)A,
-                         lda, Tp, s, B);
+                         lda, Tp, s, B, skip);
       break;
     default:
       return hipErrorInvalidValue;
@@ -526,33 +543,40 @@ hipError_t launch_syrk(int precision, const void* A, int64_t lda, int64_t Tp,
   return hipGetLastError();
 }
 
-hipError_t launch_potrf_trtri(double* M, double* X, int64_t np, int* fail,
-                              hipStream_t st) {
-  const int nt = (int)(np / BM);
-  const size_t lds = (size_t)BM * LDD * sizeof(double);
+hipError_t prepare_dense_kernels() {
   static bool attr_set = false;
   if (!attr_set) {
+    const size_t lds = (size_t)BM * LDD * sizeof(double);
     hipError_t e = hipFuncSetAttribute(
         (const void*)diag_block_kernel,
         hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;
     attr_set = true;
   }
+  return hipSuccess;
+}
+
+hipError_t launch_potrf_trtri(double* M, double* X, int64_t np, int* fail,
+                              hipStream_t st, const int* skip) {
+  const int nt = (int)(np / BM);
+  const size_t lds = (size_t)BM * LDD * sizeof(double);
+  hipError_t pe = prepare_dense_kernels();
+  if (pe != hipSuccess) return pe;
   for (int k = 0; k < nt; ++k) {
     hipLaunchKernelGGL(diag_block_kernel, dim3(1), dim3(DT), lds, st, M, X,
-                       np, k, fail);
+                       np, k, fail, skip);
     const int rem = nt - k - 1;
     if (rem > 0)
       hipLaunchKernelGGL(panel_kernel, dim3(rem), dim3(NT), 0, st, M,
-                         (const double*)X, np, k);
+                         (const double*)X, np, k, skip);
     if (k > 0)
       hipLaunchKernelGGL(inv_finalize_kernel, dim3(k), dim3(NT), 0, st, X, np,
-                         k);
+                         k, skip);
     if (rem > 0) {
       hipLaunchKernelGGL(update_kernel, dim3(rem * (rem + 1) / 2), dim3(NT), 0,
-                         st, M, np, k);
+                         st, M, np, k, skip);
       hipLaunchKernelGGL(inv_update_kernel, dim3(rem * (k + 1)), dim3(NT), 0,
-                         st, X, (const double*)M, np, k);
+                         st, X, (const double*)M, np, k, skip);
     }
   }
   return hipGetLastError();
@@ -560,20 +584,20 @@ hipError_t launch_potrf_trtri(double* M, double* X, int64_t np, int* fail,
 
 hipError_t launch_trace_gemm(int precision, const void* A, int64_t lda,
                              int64_t Tp, const double* X, int64_t np,
-                             double* rn, hipStream_t st) {
+                             double* rn, hipStream_t st, const int* skip) {
   dim3 g((unsigned)(np / BM), (unsigned)(Tp / BM)), b(NT);
   switch (precision) {
     case 0:
       hipLaunchKernelGGL(trace_gemm_kernel<double>, g, b, 0, st,
-                         (const double*)A, lda, Tp, X, np, rn);
+                         (const double*)A, lda, Tp, X, np, rn, skip);
       break;
     case 1:
       hipLaunchKernelGGL(trace_gemm_kernel<float>, g, b, 0, st,
-                         (const float*)A, lda, Tp, X, np, rn);
+                         (const float*)A, lda, Tp, X, np, rn, skip);
       break;
     case 2:
       hipLaunchKernelGGL(trace_gemm_kernel<bf16_t>, g, b, 0, st,
-                         (const bf16_t*)A, lda, Tp, X, np, rn);
+                         (const bf16_t*)A, lda, Tp, X, np, rn, skip);
       break;
     default:
       return hipErrorInvalidValue;
@@ -583,25 +607,25 @@ hipError_t launch_trace_gemm(int precision, const void* A, int64_t lda,
 
 hipError_t launch_trmv(const double* X, int64_t np, int64_t n,
                        const double* v, double* y, double* part, bool trans,
-                       hipStream_t st) {
+                       hipStream_t st, const int* skip) {
   if (!trans) {
     hipLaunchKernelGGL(trmv_n_kernel, dim3((unsigned)((n + 3) / 4)),
-                       dim3(256), 0, st, X, np, n, v, y);
+                       dim3(256), 0, st, X, np, n, v, y, skip);
     return hipGetLastError();
   }
   const int64_t nb = (n + kTrmvRows - 1) / kTrmvRows;
   hipLaunchKernelGGL(trmv_t_kernel,
                      dim3((unsigned)((n + 255) / 256), (unsigned)nb),
-                     dim3(256), 0, st, X, np, n, v, part);
+                     dim3(256), 0, st, X, np, n, v, part, skip);
   return launch_reduce_partials(part, (int)nb, n, n, 1.0, 0.0, nullptr, y,
-                                st);
+                                st, skip);
 }
 
 hipError_t launch_symm_multi(const double* B, int64_t ldb, int64_t n,
                              const double* E, int p, double* W,
-                             hipStream_t st) {
+                             hipStream_t st, const int* skip) {
   hipLaunchKernelGGL(symm_multi_kernel, dim3((unsigned)((n + 3) / 4)),
-                     dim3(256), 0, st, B, ldb, n, E, p, W);
+                     dim3(256), 0, st, B, ldb, n, E, p, W, skip);
   return hipGetLastError();
 }
 

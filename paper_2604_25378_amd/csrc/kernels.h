@@ -60,6 +60,7 @@ struct PassArgs {
   double* psums;        // [nwg][kMaxSums] scalar partials
   Coef c;
   double invT;
+  const int* skip;      // nonzero: every workgroup returns at once
 };
 
 int pass_groups(int64_t Tp, int R, int64_t* rows_per_wg);
@@ -69,9 +70,10 @@ hipError_t launch_pass(int precision, PassKind kind, const PassArgs& a,
 hipError_t launch_reduce_partials(const double* part, int nwg, int64_t lda,
                                   int64_t n, double alpha, double beta,
                                   const double* y, double* out,
-                                  hipStream_t st);
+                                  hipStream_t st, const int* skip = nullptr);
 hipError_t launch_reduce_sums(const double* psums, int nwg, int nsum,
-                              double* out, hipStream_t st);
+                              double* out, hipStream_t st,
+                              const int* skip = nullptr);
 hipError_t launch_center(const double* R, int64_t T, int64_t n, int64_t ldr,
                          int precision, void* A, int64_t Tp, int64_t lda,
                          double* mu, double* scratch, int* nonfinite,
@@ -82,25 +84,29 @@ constexpr int kTile = 128;  // output tile and Cholesky block size
 
 // B = A^T diag(s) A / 1 (full symmetric n x n, ldb = lda), s length Tp.
 hipError_t launch_syrk(int precision, const void* A, int64_t lda, int64_t Tp,
-                       const double* s, double* B, hipStream_t st);
+                       const double* s, double* B, hipStream_t st,
+                       const int* skip = nullptr);
 // In-place Cholesky of the lower triangle of M (np x np, np multiple of
 // kTile) and X = L^-1 (lower; X must be zero on entry).  *fail != 0 on exit
 // when a pivot was not positive.
 hipError_t launch_potrf_trtri(double* M, double* X, int64_t np, int* fail,
-                              hipStream_t st);
+                              hipStream_t st, const int* skip = nullptr);
+// Sets the LDS attribute of the diagonal-block kernel (call before capture).
+hipError_t prepare_dense_kernels();
 // rn[J][t] = sum_{j in tile J} (sum_k A[t][k] X[j][k])^2  (X lower)
 hipError_t launch_trace_gemm(int precision, const void* A, int64_t lda,
                              int64_t Tp, const double* X, int64_t np,
-                             double* rn, hipStream_t st);
+                             double* rn, hipStream_t st,
+                             const int* skip = nullptr);
 // y = X v (lower), y = X^T v (transposed); X is np x np.  part holds
 // ceil(n/64) * n doubles of partial sums for the transposed product.
 hipError_t launch_trmv(const double* X, int64_t np, int64_t n,
                        const double* v, double* y, double* part, bool trans,
-                       hipStream_t st);
+                       hipStream_t st, const int* skip = nullptr);
 // W[:, a] = B E[:, a] for a < p (E is n x p column-major with ld n).
 hipError_t launch_symm_multi(const double* B, int64_t ldb, int64_t n,
                              const double* E, int p, double* W,
-                             hipStream_t st);
+                             hipStream_t st, const int* skip = nullptr);
 
 
 }  // namespace yand

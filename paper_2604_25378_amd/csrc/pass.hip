@@ -143,6 +143,7 @@ struct OpThird {    // a6: psi'''(z_t) q_t / T (third-order back-projection)
 template <typename S, int NCH, int R, class Op>
 __global__ void __launch_bounds__(kPassThreads)
 pass_kernel(PassArgs a) {
+  if (a.skip && *a.skip) return;
   constexpr int VEC = Vec16<S>::N;
   __shared__ double red[2][R][kPassWaves];
   const int tid = threadIdx.x;
@@ -262,7 +263,9 @@ pass_kernel(PassArgs a) {
 __global__ void __launch_bounds__(1024)
 reduce_partials_kernel(const double* __restrict__ part, int nwg, int64_t lda,
                        int64_t n, double alpha, double beta,
-                       const double* __restrict__ y, double* __restrict__ out) {
+                       const double* __restrict__ y, double* __restrict__ out,
+                       const int* skip) {
+  if (skip && *skip) return;
   __shared__ double sh[16][64];
   const int x = threadIdx.x & 63, g = threadIdx.x >> 6;
   const int64_t j = (int64_t)blockIdx.x * 64 + x;
@@ -282,7 +285,9 @@ reduce_partials_kernel(const double* __restrict__ part, int nwg, int64_t lda,
 
 // sums[i] = sum_b psums[b][i] for i < nsum (one wave per sum, fixed order).
 __global__ void reduce_sums_kernel(const double* __restrict__ psums, int nwg,
-                                   int nsum, double* __restrict__ out) {
+                                   int nsum, double* __restrict__ out,
+                                   const int* skip) {
+  if (skip && *skip) return;
   int i = blockIdx.x;
   if (i >= nsum) return;
   int lane = threadIdx.x;
@@ -369,17 +374,17 @@ int64_t max_pass_columns(int precision) {
 hipError_t launch_reduce_partials(const double* part, int nwg, int64_t lda,
                                   int64_t n, double alpha, double beta,
                                   const double* y, double* out,
-                                  hipStream_t st) {
+                                  hipStream_t st, const int* skip) {
   dim3 b(1024), g((unsigned)((n + 63) / 64));
   hipLaunchKernelGGL(reduce_partials_kernel, g, b, 0, st, part, nwg, lda, n,
-                     alpha, beta, y, out);
+                     alpha, beta, y, out, skip);
   return hipGetLastError();
 }
 
 hipError_t launch_reduce_sums(const double* psums, int nwg, int nsum,
-                              double* out, hipStream_t st) {
+                              double* out, hipStream_t st, const int* skip) {
   hipLaunchKernelGGL(reduce_sums_kernel, dim3(nsum), dim3(64), 0, st, psums,
-                     nwg, nsum, out);
+                     nwg, nsum, out, skip);
   return hipGetLastError();
 }
 

@@ -25,10 +25,14 @@ struct DevScalars {
   int fail;          // Cholesky pivot failure
   int nonfinite;     // NaN/Inf seen
   int pad;
+  int done;          // |G| <= eps at this iteration: the rest is skipped
+  int frozen;        // lane stopped by the host: every pass is skipped
 };
 
+// eps < 0: never mark done.  Also clears fail and status for the iteration.
 hipError_t launch_grad_project(const double* g, double* E, int p0, int64_t n,
-                               DevScalars* sc, hipStream_t st);
+                               DevScalars* sc, hipStream_t st,
+                               double eps = -1.0);
 hipError_t launch_trace_scale(const double* B, int64_t ld, int64_t n,
                               const double* E, const double* W, int p,
                               double reg, DevScalars* sc, hipStream_t st);
@@ -45,6 +49,11 @@ hipError_t launch_direction(const double* y, const double* E, int p,
                             int64_t n, const double* x, const double* mu,
                             double tau, int simplex, double* d,
                             DevScalars* sc, hipStream_t st);
+// dst[i] = src[i] unless *skip; fill dst with v unless *skip.
+hipError_t launch_copy(double* dst, const double* src, int64_t count,
+                       hipStream_t st, const int* skip = nullptr);
+hipError_t launch_fill(double* dst, int64_t count, double v, hipStream_t st,
+                       const int* skip = nullptr);
 hipError_t launch_coef_step(const double* sums, double invT, Coef c,
                             int select, DevScalars* sc, hipStream_t st);
 hipError_t launch_select_step(DevScalars* sc, hipStream_t st);

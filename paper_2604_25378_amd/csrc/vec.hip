@@ -35,7 +35,7 @@ __device__ void block_sum(double (&v)[K], double* sh) {
 // reduction": |gbar| = |P_T g|.)
 __global__ void __launch_bounds__(VT)
 grad_project_kernel(const double* __restrict__ g, double* __restrict__ E,
-                    int p0, int64_t n, DevScalars* sc) {
+                    int p0, int64_t n, DevScalars* sc, double eps) {
   __shared__ double sh[4 * VW];
   const int tid = threadIdx.x;
   double dots[2] = {0.0, 0.0};
@@ -59,6 +59,12 @@ grad_project_kernel(const double* __restrict__ g, double* __restrict__ E,
   if (tid == 0) {
     sc->gn = gn;
     if (!isfinite(gn)) sc->nonfinite = 1;
+    sc->done = (eps >= 0.0 && (sc->frozen || gn <= eps)) || !isfinite(gn)
+                   ? 1
+                   : 0;
+    sc->fail = 0;
+    sc->status = 0;
+    sc->alpha = 0.0;
   }
 }
 
@@ -68,6 +74,7 @@ __global__ void __launch_bounds__(VT)
 trace_scale_kernel(const double* __restrict__ B, int64_t ld, int64_t n,
                    const double* __restrict__ E, const double* __restrict__ W,
                    int p, double reg, DevScalars* sc) {
+  if (sc->done) return;
   __shared__ double sh[4 * VW];
   const int tid = threadIdx.x;
   double t[1] = {0.0};
@@ -105,6 +112,7 @@ __global__ void project_kernel(const double* __restrict__ B, double* M,
                                const double* __restrict__ E,
                                const double* __restrict__ W, int p,
                                const DevScalars* __restrict__ sc) {
+  if (sc->done) return;
   const int64_t i = blockIdx.y;
   const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (j > i || i >= np) return;
@@ -138,6 +146,7 @@ __global__ void trace_weight_kernel(const double* __restrict__ rn, int nt,
                                     int64_t Tp, const double* __restrict__ AE,
                                     int p, const DevScalars* __restrict__ sc,
                                     double* __restrict__ q) {
+  if (sc->done) return;
   const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= Tp) return;
   double s = 0.0;
@@ -156,6 +165,7 @@ __global__ void __launch_bounds__(VT)
 rhs_kernel(const double* __restrict__ Bnu, const double* __restrict__ t3,
            const double* __restrict__ E, int p, int64_t n, double mp1,
            const DevScalars* __restrict__ sc, double* __restrict__ r) {
+  if (sc->done) return;
   __shared__ double sh[4 * VW];
   const int tid = threadIdx.x;
   const double coef = sc->gn / mp1;
@@ -179,6 +189,7 @@ direction_kernel(const double* __restrict__ y, const double* __restrict__ E,
                  int p, int64_t n, const double* __restrict__ x,
                  const double* __restrict__ mu, double tau, int simplex,
                  double* __restrict__ d, DevScalars* sc) {
+  if (sc->done) return;
   __shared__ double sh[4 * VW];
   const int tid = threadIdx.x;
   double dots[3] = {0.0, 0.0, 0.0};
@@ -344,6 +355,10 @@ __device__ int quartic_step(const double* A, double amax, double* alpha) {
 __global__ void coef_step_kernel(const double* __restrict__ sums, double invT,
                                  Coef c, int select, DevScalars* sc) {
   if (threadIdx.x != 0) return;
+  if (select && (sc->done || sc->fail)) {
+    sc->alpha = 0.0;
+    return;
+  }
   const double s11 = sums[0] * invT, s21 = sums[1] * invT,
                s31 = sums[2] * invT, s02 = sums[3] * invT,
                s12 = sums[4] * invT, s22 = sums[5] * invT,
@@ -392,16 +407,34 @@ dot_kernel(const double* __restrict__ u, const double* __restrict__ v,
 __global__ void axpy_kernel(double* __restrict__ x,
                             const double* __restrict__ d, int64_t n,
                             const DevScalars* __restrict__ sc) {
+  if (sc->done || sc->fail || sc->status != 0) return;
   const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (j < n) x[j] += sc->alpha * d[j];
+}
+
+__global__ void copy_kernel(double* __restrict__ dst,
+                            const double* __restrict__ src, int64_t count,
+                            const int* skip) {
+  if (skip && *skip) return;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count;
+       i += (int64_t)gridDim.x * blockDim.x)
+    dst[i] = src[i];
+}
+
+__global__ void fill_kernel(double* __restrict__ dst, int64_t count, double v,
+                            const int* skip) {
+  if (skip && *skip) return;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count;
+       i += (int64_t)gridDim.x * blockDim.x)
+    dst[i] = v;
 }
 
 // ------------------------------------------------------------ launchers --
 
 hipError_t launch_grad_project(const double* g, double* E, int p0, int64_t n,
-                               DevScalars* sc, hipStream_t st) {
+                               DevScalars* sc, hipStream_t st, double eps) {
   hipLaunchKernelGGL(grad_project_kernel, dim3(1), dim3(VT), 0, st, g, E, p0,
-                     n, sc);
+                     n, sc, eps);
   return hipGetLastError();
 }
 hipError_t launch_trace_scale(const double* B, int64_t ld, int64_t n,
@@ -466,6 +499,25 @@ hipError_t launch_axpy(double* x, const double* d, int64_t n,
                        const DevScalars* sc, hipStream_t st) {
   hipLaunchKernelGGL(axpy_kernel, dim3((unsigned)((n + 255) / 256)),
                      dim3(256), 0, st, x, d, n, sc);
+  return hipGetLastError();
+}
+
+static unsigned grid_for(int64_t count) {
+  int64_t b = (count + 255) / 256;
+  if (b > 4096) b = 4096;
+  if (b < 1) b = 1;
+  return (unsigned)b;
+}
+hipError_t launch_copy(double* dst, const double* src, int64_t count,
+                       hipStream_t st, const int* skip) {
+  hipLaunchKernelGGL(copy_kernel, dim3(grid_for(count)), dim3(256), 0, st, dst,
+                     src, count, skip);
+  return hipGetLastError();
+}
+hipError_t launch_fill(double* dst, int64_t count, double v, hipStream_t st,
+                       const int* skip) {
+  hipLaunchKernelGGL(fill_kernel, dim3(grid_for(count)), dim3(256), 0, st, dst,
+                     count, v, skip);
   return hipGetLastError();
 }
 
