@@ -69,6 +69,49 @@ def cpu_baseline(R, c):
                       f"{el:.1f} s"}
 
 
+def frontier_bench(workload, n_targets, n_plain, precision="fp64"):
+    """Frontier solves/s: batched (one call, lanes advancing together with
+    graph-replayed iterations) vs plain single-instance solves of the same
+    instances, at ||reduced gradient|| <= 1e-8."""
+    import torch
+
+    import synth
+    from paper_2604_25378_amd import binding as yb
+
+    R = synth.workload_returns(workload)
+    T, n = R.shape
+    targets = synth.frontier_targets(R, n_targets)
+    C4 = np.array([synth.crra_coefficients(g) for g in (2.0, 4.0, 6.0, 10.0)
+                   for _ in targets])
+    tg = np.tile(targets, 4)
+    ctx = yb.Context(torch.from_numpy(R).cuda(), precision)
+    ctx.frontier(C4[:2], tg[:2])            # warm-up (graph path, allocations)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    W, infos = ctx.frontier(C4, tg)
+    torch.cuda.synchronize()
+    el_b = time.perf_counter() - t0
+    ok = sum(1 for i in infos if i.status == 0 and i.gnorm <= 1e-8)
+    its = [i.iterations for i in infos]
+    t0 = time.perf_counter()
+    plain_its = []
+    for b in range(n_plain):
+        _, inf = ctx.solve(C4[b], target=tg[b])
+        plain_its.append(inf.iterations)
+    torch.cuda.synchronize()
+    el_p = time.perf_counter() - t0
+    ctx.close()
+    return {"workload": f"{workload}: n={n} T={T}, {len(tg)} instances "
+                        f"({n_targets} targets x 4 CRRA gamma)",
+            "batched_solves_per_s": len(tg) / el_b,
+            "plain_solves_per_s": n_plain / el_p,
+            "speedup": (len(tg) / el_b) / (n_plain / el_p),
+            "converged": f"{ok}/{len(tg)}",
+            "iterations_mean": float(np.mean(its)),
+            "plain_sample": n_plain,
+            "plain_iterations_mean": float(np.mean(plain_its))}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -77,6 +120,7 @@ def main():
     ap.add_argument("--precision", default="fp64", choices=list(ESIZE))
     ap.add_argument("--workload", default="n5440_T12000")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-frontier", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build measures one GPU; --gpus {args.gpus} is "
@@ -193,6 +237,14 @@ def main():
         "gnorm_after": gn,
     }
     ctx.close()
+    del ctx
+    if not args.no_frontier:
+        fr = {"n1000_T12000": frontier_bench("n1000_T12000_frontier", 16, 8,
+                                             args.precision),
+              "n5440_T12000": frontier_bench(args.workload, 4, 2,
+                                             args.precision)}
+        out["frontier"] = fr
+        out["frontier_solves_per_s"] = fr["n5440_T12000"]["batched_solves_per_s"]
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(R, c)
     print(json.dumps(out), flush=True)

@@ -156,7 +156,9 @@ int yand_mvsk_solve(yand_ctx* ctx, const double c[4], const double* target,
 
 /* Batched efficient-frontier solve on one context (shared A): instance b
  * minimises with preference vector C4[4b..4b+3] (host) and, when targets
- * (host, length B) is not NULL, the return target targets[b].  Weights go to
+ * (host, length B) is not NULL, the return target targets[b].  W0 (device,
+ * B x n, nullable) holds the starting weights, each moved onto the
+ * instance's constraints (NULL: equal weights moved there).  Weights go to
  * row b of W_out (device, B x n row-major); infos (host, length B) is
  * nullable.  Instances advance together in lanes of up to 64 solves; after
  * the first iteration one outer iteration of all lanes is replayed from a
@@ -164,18 +166,20 @@ int yand_mvsk_solve(yand_ctx* ctx, const double c[4], const double* target,
  * configuration only (opts->solver must be YAND_SOLVER_DIRECT).  Returns the
  * first error; per-instance status is in infos[b].status. */
 int yand_frontier_solve(yand_ctx* ctx, int64_t B, const double* C4,
-                        const double* targets, const yand_opts* opts,
-                        double* W_out, yand_info* infos);
+                        const double* targets, const double* W0,
+                        const yand_opts* opts, double* W_out,
+                        yand_info* infos);
 
 /* Batched solve over contexts that may differ (universes of uneven n):
  * instance b runs on ctxs[b] (host array of B contexts on one device) and
- * writes W_out[b] (host array of B device pointers, each n_b long).
+ * writes W_out[b] (host array of B device pointers, each n_b long); W0
+ * (nullable host array of B device pointers, entries nullable) gives starts.
  * max_lanes bounds the solves advancing together (<= 0: 64); use_graph != 0
  * replays captured iterations. */
 int yand_batch_solve(int64_t B, yand_ctx* const* ctxs, const double* C4,
-                     const double* targets, const yand_opts* opts,
-                     double* const* W_out, yand_info* infos, int max_lanes,
-                     int use_graph);
+                     const double* targets, const double* const* W0,
+                     const yand_opts* opts, double* const* W_out,
+                     yand_info* infos, int max_lanes, int use_graph);
 
 /* Kernel timing on the context stream (instrumentation): enable != 0 starts
  * recording HIP events around the main kernels; yand_profile_read(ctx, -1,
@@ -197,6 +201,92 @@ int yand_is_certified_convex(const double c[4]);
 
 /* Storage precision, T, n of a context (host outputs, nullable). */
 int yand_shape(yand_ctx* ctx, int64_t* T, int64_t* n, int* precision);
+
+/* ------------------------------------------------------------------------
+ * Learned warm start (an extension; the paper trains no model).  A small
+ * fully connected network maps instance features (preferences c, return
+ * target, moment summaries of the equal-weight portfolio) to the solution in
+ * reduced coordinates of the fixed Householder basis U of {1^T x = 0}:
+ * H = I - 2 v v^T / v^T v with v = e_n - 1/sqrt(n) 1; U = first n-1 columns
+ * of H, and w = 1/n + U y.  The plain iteration always finishes the solve;
+ * the first-order stationarity residual ||reduced gradient|| decides whether
+ * the proposal or the plain start is used.
+ * FP32 network buffers are DEVICE memory; the handle owns its weights, Adam
+ * moments and activations.  Calls on one handle must be serialised.
+ * ---------------------------------------------------------------------- */
+typedef struct yand_mlp yand_mlp;
+
+/* Features per instance built by the warm start (see yand_warmstart_features). */
+#define YAND_WS_FEATURES 11
+
+typedef struct yand_mlp_opts {
+  int hidden;      /* width of every hidden layer (512)                       */
+  int layers;      /* weight layers: hidden layers + 1 (4)                    */
+  int epochs;      /* full-batch Adam steps (2000)                            */
+  double lr;       /* Adam step size (1e-3)                                   */
+  uint64_t seed;   /* initial weights N(0, 1/fan_in), counter-based           */
+} yand_mlp_opts;
+
+void yand_default_mlp_opts(yand_mlp_opts* opts);
+
+/* Network in_dim -> hidden (tanh) x (layers-1) -> out_dim (linear), FP32,
+ * weights initialised from seed, Adam moments zero.  Work runs on hip_stream
+ * (NULL = default).  Errors: YAND_ERR_ARG, YAND_ERR_OOM, YAND_ERR_HIP. */
+int yand_mlp_create(int64_t in_dim, int64_t out_dim, int hidden, int layers,
+                    uint64_t seed, void* hip_stream, yand_mlp** out);
+int yand_mlp_destroy(yand_mlp* mlp);
+/* Number of FP32 parameters: for each layer l, W_l (fan_in x fan_out,
+ * row-major, x W convention) followed by b_l (fan_out). -1 for NULL. */
+int64_t yand_mlp_num_params(const yand_mlp* mlp);
+/* Copy the parameter vector to / from a device buffer of num_params floats. */
+int yand_mlp_get_params(const yand_mlp* mlp, float* dst);
+int yand_mlp_set_params(yand_mlp* mlp, const float* src);
+/* out (N x out_dim) = network(X (N x in_dim)); device, row-major. */
+int yand_mlp_forward(yand_mlp* mlp, int64_t N, const float* X, float* out);
+/* Gradient of (1/2N) sum_i |out_i - Y_i|^2 with respect to the parameters by
+ * backpropagation; grad (device, num_params) and loss (host) are nullable.
+ * The gradient is also kept in the handle for yand_mlp_adam_step. */
+int yand_mlp_loss_grad(yand_mlp* mlp, int64_t N, const float* X,
+                       const float* Y, float* grad, double* loss);
+/* One bias-corrected Adam step (beta1 0.9, beta2 0.999, eps 1e-8) with the
+ * handle's step counter; grad NULL uses the last yand_mlp_loss_grad result. */
+int yand_mlp_adam_step(yand_mlp* mlp, const float* grad, double lr);
+
+/* Reduced coordinates, FP64 device rows: Y[b] = U^T (W[b] - 1/n)
+ * (N x n -> N x (n-1)) and its inverse W[b] = 1/n + U Y[b]. */
+int yand_reduced_coords(int64_t N, int64_t n, const double* W, double* Y,
+                        void* hip_stream);
+int yand_from_reduced(int64_t N, int64_t n, const double* Y, double* W,
+                      void* hip_stream);
+
+/* Features of N instances (C4 host N x 4, targets host N or NULL) on ctx,
+ * into F (host, N x YAND_WS_FEATURES): log1p(c1..c4), has_target,
+ * (r - mean(mu)) / |mu - mean(mu)|, and from the equal-weight portfolio
+ * z = A 1/n: log m2, m3 / m2^1.5, log(m4 / m2^2), mean(mu) / sqrt(m2),
+ * |mu - mean(mu)| / sqrt(n m2).  One value pass over A. */
+int yand_warmstart_features(yand_ctx* ctx, int64_t N, const double* C4,
+                            const double* targets, double* F);
+
+/* Train a warm-start network on N solved instances of ctx: W_solved (device,
+ * N x n) holds their weights.  Features are standardised per column and the
+ * reduced coordinates per column mean and one global scale; training is
+ * full-batch Adam for opts->epochs steps on the context's stream.  final_loss
+ * (host, nullable) receives the last loss.  *out is NULL on error. */
+int yand_warmstart_train(yand_ctx* ctx, int64_t N, const double* C4,
+                         const double* targets, const double* W_solved,
+                         const yand_mlp_opts* opts, yand_mlp** out,
+                         double* final_loss);
+
+/* Warm starts for B instances on ctx (same n as in training): each proposal
+ * w = 1/n + U y is moved onto the budget (and target) constraint, then its
+ * reduced-gradient norm is compared with that of the plain start (equal
+ * weights moved onto the constraints); the smaller wins and goes to row b of
+ * W0_out (device, B x n).  used_mlp (host, B, nullable) is 1 where the
+ * proposal won; gnorms (host, B x 2, nullable) receives both norms.  For the
+ * BUDGET set (the proposal may hold negative weights). */
+int yand_warmstart_predict(yand_ctx* ctx, yand_mlp* mlp, int64_t B,
+                           const double* C4, const double* targets,
+                           double* W0_out, int* used_mlp, double* gnorms);
 
 #ifdef __cplusplus
 }

@@ -8,12 +8,19 @@ the first call loads the library and fails loudly if it or the GPU is absent.
 
 from .binding import (  # noqa: F401
     Context,
+    Mlp,
     SolveInfo,
     YandError,
     batch_solve,
+    default_mlp_opts,
     default_opts,
+    from_reduced,
     is_certified_convex,
     load,
+    reduced_coords,
     solve_R,
+    warmstart_features,
+    warmstart_predict,
+    warmstart_train,
     LIB_PATH,
 )

@@ -54,6 +54,13 @@ class yand_info(C.Structure):
                 ("dense_traces", C.c_int64)]
 
 
+class yand_mlp_opts(C.Structure):
+    _fields_ = [("hidden", C.c_int), ("layers", C.c_int), ("epochs", C.c_int),
+                ("lr", C.c_double), ("seed", C.c_uint64)]
+
+
+WS_FEATURES = 11
+
 _D = C.POINTER(C.c_double)
 _lib = None
 
@@ -90,13 +97,31 @@ def load(path: str = LIB_PATH):
         "yand_is_certified_convex": (C.c_int, [_D]),
         "yand_shape": (C.c_int, [vp, C.POINTER(C.c_int64),
                                  C.POINTER(C.c_int64), C.POINTER(C.c_int)]),
-        "yand_frontier_solve": (C.c_int, [vp, C.c_int64, _D, _D,
+        "yand_frontier_solve": (C.c_int, [vp, C.c_int64, _D, _D, vp,
                                           C.POINTER(yand_opts), vp,
                                           C.POINTER(yand_info)]),
         "yand_batch_solve": (C.c_int, [C.c_int64, C.POINTER(vp), _D, _D,
-                                       C.POINTER(yand_opts), C.POINTER(vp),
-                                       C.POINTER(yand_info), C.c_int,
-                                       C.c_int]),
+                                       C.POINTER(vp), C.POINTER(yand_opts),
+                                       C.POINTER(vp), C.POINTER(yand_info),
+                                       C.c_int, C.c_int]),
+        "yand_default_mlp_opts": (None, [C.POINTER(yand_mlp_opts)]),
+        "yand_mlp_create": (C.c_int, [C.c_int64, C.c_int64, C.c_int, C.c_int,
+                                      C.c_uint64, vp, C.POINTER(vp)]),
+        "yand_mlp_destroy": (C.c_int, [vp]),
+        "yand_mlp_num_params": (C.c_int64, [vp]),
+        "yand_mlp_get_params": (C.c_int, [vp, vp]),
+        "yand_mlp_set_params": (C.c_int, [vp, vp]),
+        "yand_mlp_forward": (C.c_int, [vp, C.c_int64, vp, vp]),
+        "yand_mlp_loss_grad": (C.c_int, [vp, C.c_int64, vp, vp, vp, _D]),
+        "yand_mlp_adam_step": (C.c_int, [vp, vp, C.c_double]),
+        "yand_reduced_coords": (C.c_int, [C.c_int64, C.c_int64, vp, vp, vp]),
+        "yand_from_reduced": (C.c_int, [C.c_int64, C.c_int64, vp, vp, vp]),
+        "yand_warmstart_features": (C.c_int, [vp, C.c_int64, _D, _D, _D]),
+        "yand_warmstart_train": (C.c_int, [vp, C.c_int64, _D, _D, vp,
+                                           C.POINTER(yand_mlp_opts),
+                                           C.POINTER(vp), _D]),
+        "yand_warmstart_predict": (C.c_int, [vp, vp, C.c_int64, _D, _D, vp,
+                                             C.POINTER(C.c_int), _D]),
         "yand_profile_enable": (C.c_int, [vp, C.c_int]),
         "yand_profile_read": (C.c_int, [vp, C.c_int, C.c_char_p, C.c_int, _D,
                                         C.POINTER(C.c_int64)]),
@@ -285,15 +310,18 @@ class Context:
         _check(rc, "yand_mvsk_solve", warn_ok=not raise_on_warning)
         return out, SolveInfo(**{k: getattr(info, k) for k, _ in yand_info._fields_})
 
-    def frontier(self, C4, targets=None, opts: yand_opts | None = None):
+    def frontier(self, C4, targets=None, opts: yand_opts | None = None,
+                 W0=None):
         """Batched solve of B instances on this context's A (direct solver).
 
-        C4: B x 4 preference vectors; targets: B return targets or None.
+        C4: B x 4 preference vectors; targets: B return targets or None;
+        W0: B x n starting weights (device) or None.
         Returns (W (B x n device tensor), [SolveInfo])."""
         torch = _torch()
         C4 = np.ascontiguousarray(np.asarray(C4, dtype=np.float64).reshape(-1, 4))
         B = C4.shape[0]
         W = torch.empty((B, self.n), dtype=torch.float64, device="cuda")
+        W0d = _dev(W0, B * self.n) if W0 is not None else None
         infos = (yand_info * B)()
         tg = None
         if targets is not None:
@@ -303,6 +331,7 @@ class Context:
             tg = tga.ctypes.data_as(_D)
         rc = self._lib.yand_frontier_solve(
             self._h, B, C4.ctypes.data_as(_D), tg,
+            C.c_void_p(W0d.data_ptr()) if W0d is not None else None,
             C.byref(opts) if opts else None, C.c_void_p(W.data_ptr()), infos)
         _check(rc, "yand_frontier_solve", warn_ok=True)
         return W, [SolveInfo(**{k: getattr(i, k) for k, _ in yand_info._fields_})
@@ -326,7 +355,7 @@ class Context:
 
 
 def batch_solve(contexts, C4, targets=None, opts: yand_opts | None = None,
-                max_lanes: int = 64, use_graph: bool = True):
+                max_lanes: int = 64, use_graph: bool = True, W0=None):
     """Batched solve where instance b runs on contexts[b] (uneven universes).
 
     Returns ([w_b device tensors], [SolveInfo])."""
@@ -345,7 +374,13 @@ def batch_solve(contexts, C4, targets=None, opts: yand_opts | None = None,
     if targets is not None:
         tga = np.ascontiguousarray(np.asarray(targets, dtype=np.float64))
         tg = tga.ctypes.data_as(_D)
-    rc = lib.yand_batch_solve(B, ctx_arr, C4.ctypes.data_as(_D), tg,
+    w0_arr = None
+    if W0 is not None:
+        starts = [_dev(w, cx.n) if w is not None else None
+                  for w, cx in zip(W0, contexts)]
+        w0_arr = (C.c_void_p * B)(*[w.data_ptr() if w is not None else None
+                                    for w in starts])
+    rc = lib.yand_batch_solve(B, ctx_arr, C4.ctypes.data_as(_D), tg, w0_arr,
                               C.byref(opts) if opts else None, out_arr, infos,
                               int(max_lanes), int(use_graph))
     _check(rc, "yand_batch_solve", warn_ok=True)
@@ -365,3 +400,181 @@ def solve_R(R, c, target=None):
                                tg, C.c_void_p(out.data_ptr()))
     _check(rc, "yand_mvsk_solve_R", warn_ok=True)
     return out
+
+
+# ------------------------------------------------------------ warm start --
+
+def default_mlp_opts(**kw) -> yand_mlp_opts:
+    o = yand_mlp_opts()
+    load().yand_default_mlp_opts(C.byref(o))
+    for k, v in kw.items():
+        setattr(o, k, v)
+    return o
+
+
+def _f32(t, n=None):
+    torch = _torch()
+    if not isinstance(t, torch.Tensor):
+        t = torch.as_tensor(np.asarray(t, dtype=np.float32))
+    t = t.to(device="cuda", dtype=torch.float32).contiguous()
+    if n is not None and t.numel() != n:
+        raise ValueError(f"expected {n} elements, got {t.numel()}")
+    return t
+
+
+class Mlp:
+    """Handle of a libyand FP32 network (weights, Adam state, activations)."""
+
+    def __init__(self, handle=None, in_dim=None, out_dim=None, hidden=512,
+                 layers=4, seed=0, stream=None):
+        torch = _torch()
+        self._lib = load()
+        if handle is None:
+            st = stream if stream is not None else torch.cuda.current_stream()
+            handle = C.c_void_p()
+            _check(self._lib.yand_mlp_create(int(in_dim), int(out_dim),
+                                             int(hidden), int(layers),
+                                             int(seed), C.c_void_p(st.cuda_stream),
+                                             C.byref(handle)),
+                   "yand_mlp_create")
+        self._h = handle
+        self.in_dim, self.out_dim = in_dim, out_dim
+        self.hidden, self.layers = hidden, layers
+
+    def close(self):
+        if getattr(self, "_h", None):
+            self._lib.yand_mlp_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @property
+    def num_params(self) -> int:
+        return int(self._lib.yand_mlp_num_params(self._h))
+
+    def get_params(self):
+        torch = _torch()
+        out = torch.empty(self.num_params, dtype=torch.float32, device="cuda")
+        _check(self._lib.yand_mlp_get_params(self._h, C.c_void_p(out.data_ptr())),
+               "yand_mlp_get_params")
+        return out
+
+    def set_params(self, p):
+        p = _f32(p, self.num_params)
+        _check(self._lib.yand_mlp_set_params(self._h, C.c_void_p(p.data_ptr())),
+               "yand_mlp_set_params")
+
+    def forward(self, X):
+        torch = _torch()
+        X = _f32(X)
+        N = X.shape[0]
+        out = torch.empty((N, self.out_dim), dtype=torch.float32, device="cuda")
+        _check(self._lib.yand_mlp_forward(self._h, N, C.c_void_p(X.data_ptr()),
+                                          C.c_void_p(out.data_ptr())),
+               "yand_mlp_forward")
+        return out
+
+    def loss_grad(self, X, Y):
+        torch = _torch()
+        X, Y = _f32(X), _f32(Y)
+        g = torch.empty(self.num_params, dtype=torch.float32, device="cuda")
+        loss = C.c_double()
+        _check(self._lib.yand_mlp_loss_grad(self._h, X.shape[0],
+                                            C.c_void_p(X.data_ptr()),
+                                            C.c_void_p(Y.data_ptr()),
+                                            C.c_void_p(g.data_ptr()),
+                                            C.byref(loss)),
+               "yand_mlp_loss_grad")
+        return loss.value, g
+
+    def adam_step(self, lr, grad=None):
+        gp = None
+        if grad is not None:
+            grad = _f32(grad, self.num_params)
+            gp = C.c_void_p(grad.data_ptr())
+        _check(self._lib.yand_mlp_adam_step(self._h, gp, float(lr)),
+               "yand_mlp_adam_step")
+
+
+def reduced_coords(W, n):
+    """Y = U^T (W - 1/n) row by row (device FP64, N x (n-1))."""
+    torch = _torch()
+    W = _dev(W).reshape(-1, n)
+    Y = torch.empty((W.shape[0], n - 1), dtype=torch.float64, device="cuda")
+    st = torch.cuda.current_stream().cuda_stream
+    _check(load().yand_reduced_coords(W.shape[0], n, C.c_void_p(W.data_ptr()),
+                                      C.c_void_p(Y.data_ptr()), C.c_void_p(st)),
+           "yand_reduced_coords")
+    return Y
+
+
+def from_reduced(Y, n):
+    """W = 1/n + U Y row by row (device FP64, N x n)."""
+    torch = _torch()
+    Y = _dev(Y).reshape(-1, n - 1)
+    W = torch.empty((Y.shape[0], n), dtype=torch.float64, device="cuda")
+    st = torch.cuda.current_stream().cuda_stream
+    _check(load().yand_from_reduced(Y.shape[0], n, C.c_void_p(Y.data_ptr()),
+                                    C.c_void_p(W.data_ptr()), C.c_void_p(st)),
+           "yand_from_reduced")
+    return W
+
+
+def _c4_targets(C4, targets):
+    C4 = np.ascontiguousarray(np.asarray(C4, dtype=np.float64).reshape(-1, 4))
+    tg = None
+    tga = None
+    if targets is not None:
+        tga = np.ascontiguousarray(np.asarray(targets, dtype=np.float64))
+        if tga.shape[0] != C4.shape[0]:
+            raise ValueError("targets must have one entry per instance")
+        tg = tga.ctypes.data_as(_D)
+    return C4, tga, tg
+
+
+def warmstart_features(ctx: Context, C4, targets=None):
+    C4, tga, tg = _c4_targets(C4, targets)
+    F = np.zeros((C4.shape[0], WS_FEATURES))
+    _check(ctx._lib.yand_warmstart_features(ctx._h, C4.shape[0],
+                                            C4.ctypes.data_as(_D), tg,
+                                            F.ctypes.data_as(_D)),
+           "yand_warmstart_features")
+    return F
+
+
+def warmstart_train(ctx: Context, C4, targets, W_solved,
+                    opts: yand_mlp_opts | None = None):
+    """Train the warm-start network on solved instances; returns (Mlp, loss)."""
+    C4, tga, tg = _c4_targets(C4, targets)
+    W = _dev(W_solved, C4.shape[0] * ctx.n)
+    h = C.c_void_p()
+    loss = C.c_double()
+    _check(ctx._lib.yand_warmstart_train(ctx._h, C4.shape[0],
+                                         C4.ctypes.data_as(_D), tg,
+                                         C.c_void_p(W.data_ptr()),
+                                         C.byref(opts) if opts else None,
+                                         C.byref(h), C.byref(loss)),
+           "yand_warmstart_train")
+    o = opts or default_mlp_opts()
+    return Mlp(handle=h, in_dim=WS_FEATURES, out_dim=ctx.n - 1,
+               hidden=o.hidden, layers=o.layers), loss.value
+
+
+def warmstart_predict(ctx: Context, mlp: Mlp, C4, targets=None):
+    """Warm starts (B x n device), used_mlp (B bool), gnorms (B x 2)."""
+    torch = _torch()
+    C4, tga, tg = _c4_targets(C4, targets)
+    B = C4.shape[0]
+    W0 = torch.empty((B, ctx.n), dtype=torch.float64, device="cuda")
+    used = (C.c_int * B)()
+    gn = np.zeros((B, 2))
+    _check(ctx._lib.yand_warmstart_predict(ctx._h, mlp._h, B,
+                                           C4.ctypes.data_as(_D), tg,
+                                           C.c_void_p(W0.data_ptr()), used,
+                                           gn.ctypes.data_as(_D)),
+           "yand_warmstart_predict")
+    return W0, np.array(used[:], dtype=bool), gn

@@ -16,12 +16,14 @@
 #include <chrono>
 #include <cstdlib>
 #include <cstring>
+#include <memory>
 #include <string>
 #include <vector>
 
 #include "../../include/yand.h"
 #include "common.h"
 #include "kernels.h"
+#include "mlp.h"
 #include "vec.h"
 
 using namespace yand;
@@ -860,6 +862,102 @@ int run_lanes(std::vector<Lane>& lanes, const yand_opts& opts,
 
 // ===================================================================== ABI ==
 
+// ------------------------------------------------------- warm start --
+
+namespace {
+
+constexpr int kWsF = YAND_WS_FEATURES;
+
+// Moments m1..m4 of the equal-weight portfolio (one value pass).
+int equal_weight_moments(yand_ctx* ctx, double mom[4]) {
+  const Data& D = ctx->d;
+  Work& w = ctx->w;
+  const double c1[4] = {1.0, 1.0, 1.0, 1.0};
+  HIPTRY(launch_fill(w.x, D.n, 1.0 / (double)D.n, w.st));
+  TRY(oracle_at(D, w, c1, w.x, false));
+  TRY(sync_scalars(w));
+  if (w.hs.nonfinite) return YAND_ERR_NONFINITE;
+  for (int i = 0; i < 4; ++i) mom[i] = w.hs.mom[i];
+  return YAND_OK;
+}
+
+void instance_features(const Data& D, const double mom[4], const double c[4],
+                       const double* target, double* F) {
+  const double tiny = 1e-300;
+  const double m2 = std::max(mom[1], tiny);
+  for (int k = 0; k < 4; ++k) F[k] = std::log1p(c[k]);
+  F[4] = target ? 1.0 : 0.0;
+  F[5] = (target && D.mnorm > 0.0) ? (*target - D.mbar) / D.mnorm : 0.0;
+  F[6] = std::log(m2);
+  F[7] = mom[2] / std::pow(m2, 1.5);
+  F[8] = std::log(std::max(mom[3], tiny) / (m2 * m2));
+  F[9] = D.mbar / std::sqrt(m2);
+  F[10] = D.mnorm / std::sqrt((double)D.n * m2);
+}
+
+int all_features(yand_ctx* ctx, int64_t N, const double* C4,
+                 const double* targets, std::vector<double>& F) {
+  if (!ctx || N < 1 || !C4) return YAND_ERR_ARG;
+  for (int64_t b = 0; b < N; ++b) {
+    TRY(check_c(C4 + 4 * b));
+    if (targets && (!std::isfinite(targets[b]) || !ctx->d.have_e2))
+      return YAND_ERR_ARG;
+  }
+  double mom[4];
+  TRY(equal_weight_moments(ctx, mom));
+  F.assign((size_t)N * kWsF, 0.0);
+  for (int64_t b = 0; b < N; ++b)
+    instance_features(ctx->d, mom, C4 + 4 * b, targets ? targets + b : nullptr,
+                      F.data() + b * kWsF);
+  return YAND_OK;
+}
+
+// Standardised FP32 features on the device (caller frees *Xd).
+int upload_features(const yand_mlp& h, const std::vector<double>& F,
+                    int64_t N, hipStream_t st, float** Xd) {
+  std::vector<float> xf((size_t)N * kWsF);
+  for (int64_t b = 0; b < N; ++b)
+    for (int k = 0; k < kWsF; ++k)
+      xf[b * kWsF + k] =
+          (float)((F[b * kWsF + k] - h.fmean[k]) / h.fscale[k]);
+  TRY(alloc((void**)Xd, xf.size() * sizeof(float)));
+  HIPTRY(hipMemcpyAsync(*Xd, xf.data(), xf.size() * sizeof(float),
+                        hipMemcpyHostToDevice, st));
+  HIPTRY(hipStreamSynchronize(st));
+  return YAND_OK;
+}
+
+// Reduced-gradient norm at the start setup_lane builds from w0 (nullable);
+// the start itself stays in w.x.
+int start_gnorm(const Data& D, Work& w, const double c[4],
+                const double* target, const double* w0, double* gn) {
+  int p0 = 1;
+  TRY(setup_lane(D, w, target, w0, &p0));
+  TRY(oracle_at(D, w, c, w.x, true));
+  HIPTRY(launch_grad_project(w.g, w.E, p0, D.n, w.sc, w.st, -1.0));
+  TRY(sync_scalars(w));
+  *gn = w.hs.nonfinite ? NAN : w.hs.gn;
+  return YAND_OK;
+}
+
+struct DevBufs {
+  std::vector<void*> p;
+  ~DevBufs() {
+    for (void* q : p)
+      if (q) (void)hipFree(q);
+  }
+  template <class T>
+  int get(T** out, size_t bytes) {
+    void* q = nullptr;
+    TRY(alloc(&q, bytes));
+    p.push_back(q);
+    *out = (T*)q;
+    return YAND_OK;
+  }
+};
+
+}  // namespace
+
 extern "C" {
 
 void yand_default_opts(yand_opts* o) {
@@ -1218,9 +1316,9 @@ int yand_mvsk_solve(yand_ctx* ctx, const double c[4], const double* target,
 // a frontier, or different ones for universes of different n).  Instances are
 // processed in waves of at most `lanes` solves that advance together.
 static int batch_solve(int64_t B, yand_ctx* const* ctxs, const double* C4,
-                       const double* targets, const yand_opts* opts_in,
-                       double* const* W_out, yand_info* infos, int max_lanes,
-                       int use_graph) {
+                       const double* targets, const double* const* W0,
+                       const yand_opts* opts_in, double* const* W_out,
+                       yand_info* infos, int max_lanes, int use_graph) {
   if (B <= 0 || !ctxs || !C4 || !W_out) return YAND_ERR_ARG;
   yand_opts opts;
   if (opts_in)
@@ -1309,8 +1407,9 @@ static int batch_solve(int64_t B, yand_ctx* const* ctxs, const double* C4,
       L.has_target = targets != nullptr;
       if (targets) L.target = targets[b];
       L.w_out = W_out[b];
+      L.w0 = W0 ? W0[b] : nullptr;
       L.active = opts.max_iter > 0;
-      rc = setup_lane(*L.D, *L.w, targets ? &L.target : nullptr, nullptr,
+      rc = setup_lane(*L.D, *L.w, targets ? &L.target : nullptr, L.w0,
                       &L.p0);
       if (rc == YAND_OK && o.simplex)
         rc = check_simplex_start(*L.D, *L.w, opts.tau);
@@ -1351,22 +1450,154 @@ static int batch_solve(int64_t B, yand_ctx* const* ctxs, const double* C4,
 }
 
 int yand_frontier_solve(yand_ctx* ctx, int64_t B, const double* C4,
-                        const double* targets, const yand_opts* opts,
-                        double* W_out, yand_info* infos) {
+                        const double* targets, const double* W0,
+                        const yand_opts* opts, double* W_out,
+                        yand_info* infos) {
   if (!ctx || !W_out || B <= 0) return YAND_ERR_ARG;
   std::vector<yand_ctx*> ctxs(B, ctx);
   std::vector<double*> outs(B);
-  for (int64_t b = 0; b < B; ++b) outs[b] = W_out + b * ctx->d.n;
-  return batch_solve(B, ctxs.data(), C4, targets, opts, outs.data(), infos, 64,
-                     1);
+  std::vector<const double*> starts(B);
+  for (int64_t b = 0; b < B; ++b) {
+    outs[b] = W_out + b * ctx->d.n;
+    starts[b] = W0 ? W0 + b * ctx->d.n : nullptr;
+  }
+  return batch_solve(B, ctxs.data(), C4, targets, W0 ? starts.data() : nullptr,
+                     opts, outs.data(), infos, 64, 1);
 }
 
 int yand_batch_solve(int64_t B, yand_ctx* const* ctxs, const double* C4,
-                     const double* targets, const yand_opts* opts,
-                     double* const* W_out, yand_info* infos, int max_lanes,
-                     int use_graph) {
-  return batch_solve(B, ctxs, C4, targets, opts, W_out, infos, max_lanes,
+                     const double* targets, const double* const* W0,
+                     const yand_opts* opts, double* const* W_out,
+                     yand_info* infos, int max_lanes, int use_graph) {
+  return batch_solve(B, ctxs, C4, targets, W0, opts, W_out, infos, max_lanes,
                      use_graph);
+}
+
+int yand_warmstart_features(yand_ctx* ctx, int64_t N, const double* C4,
+                            const double* targets, double* F) {
+  if (!F) return YAND_ERR_ARG;
+  std::vector<double> f;
+  TRY(all_features(ctx, N, C4, targets, f));
+  std::memcpy(F, f.data(), f.size() * sizeof(double));
+  return YAND_OK;
+}
+
+int yand_warmstart_train(yand_ctx* ctx, int64_t N, const double* C4,
+                         const double* targets, const double* W_solved,
+                         const yand_mlp_opts* opts_in, yand_mlp** out,
+                         double* final_loss) {
+  if (!out) return YAND_ERR_ARG;
+  *out = nullptr;
+  if (!ctx || !W_solved || N < 1 || N > (1 << 20)) return YAND_ERR_ARG;
+  yand_mlp_opts o;
+  if (opts_in)
+    o = *opts_in;
+  else
+    yand_default_mlp_opts(&o);
+  if (o.epochs < 0 || !(o.lr > 0.0) || o.hidden < 1 || o.layers < 2)
+    return YAND_ERR_ARG;
+  std::vector<double> F;
+  TRY(all_features(ctx, N, C4, targets, F));
+  const Data& D = ctx->d;
+  hipStream_t st = ctx->w.st;
+  const int64_t m = D.n - 1;
+  yand_mlp* h = nullptr;
+  TRY(yand_mlp_create(kWsF, m, o.hidden, o.layers, o.seed, st, &h));
+  std::unique_ptr<yand_mlp, int (*)(yand_mlp*)> guard(h, yand_mlp_destroy);
+  // feature standardisation (per column; constant columns map to zero)
+  h->fmean.assign(kWsF, 0.0);
+  h->fscale.assign(kWsF, 1.0);
+  for (int k = 0; k < kWsF; ++k) {
+    double s = 0.0, q = 0.0;
+    for (int64_t b = 0; b < N; ++b) s += F[b * kWsF + k];
+    const double mean = s / (double)N;
+    for (int64_t b = 0; b < N; ++b) {
+      const double d = F[b * kWsF + k] - mean;
+      q += d * d;
+    }
+    const double sd = std::sqrt(q / (double)N);
+    h->fmean[k] = mean;
+    h->fscale[k] = sd > 1e-12 * std::max(1.0, std::fabs(mean)) ? sd : 1.0;
+  }
+  DevBufs bufs;
+  float* Xd = nullptr;
+  TRY(upload_features(*h, F, N, st, &Xd));
+  bufs.p.push_back(Xd);
+  // targets: reduced coordinates, centred per column, one global scale
+  double *Y = nullptr, *ss = nullptr;
+  float* Z = nullptr;
+  TRY(bufs.get(&Y, (size_t)N * m * sizeof(double)));
+  TRY(bufs.get(&ss, (size_t)m * sizeof(double)));
+  TRY(bufs.get(&Z, (size_t)N * m * sizeof(float)));
+  TRY(alloc((void**)&h->ybar, (size_t)m * sizeof(double)));
+  HIPTRY(launch_to_reduced(W_solved, N, D.n, Y, st));
+  HIPTRY(launch_col_stats(Y, N, m, h->ybar, ss, st));
+  std::vector<double> hs(m);
+  HIPTRY(hipMemcpyAsync(hs.data(), ss, m * sizeof(double),
+                        hipMemcpyDeviceToHost, st));
+  HIPTRY(hipStreamSynchronize(st));
+  double tot = 0.0;
+  for (double x : hs) tot += x;
+  if (!std::isfinite(tot)) return YAND_ERR_NONFINITE;
+  const double scale = std::sqrt(tot / ((double)N * (double)m));
+  h->yscale = scale > 0.0 ? scale : 1.0;
+  HIPTRY(launch_standardize(Y, h->ybar, h->yscale, N, m, Z, st));
+  h->n = D.n;
+  double loss = NAN;
+  for (int e = 0; e < o.epochs; ++e) {
+    TRY(h->net.loss_grad(N, Xd, Z, e + 1 == o.epochs ? &loss : nullptr));
+    h->t += 1;
+    TRY(h->net.adam(h->net.grads, o.lr, h->t));
+  }
+  HIPTRY(hipStreamSynchronize(st));
+  if (final_loss) *final_loss = loss;
+  *out = guard.release();
+  return YAND_OK;
+}
+
+int yand_warmstart_predict(yand_ctx* ctx, yand_mlp* mlp, int64_t B,
+                           const double* C4, const double* targets,
+                           double* W0_out, int* used_mlp, double* gnorms) {
+  if (!ctx || !mlp || !W0_out || B < 1 || B > (1 << 20)) return YAND_ERR_ARG;
+  const Data& D = ctx->d;
+  if (mlp->n != D.n || !mlp->ybar || (int64_t)mlp->fmean.size() != kWsF)
+    return YAND_ERR_ARG;
+  std::vector<double> F;
+  TRY(all_features(ctx, B, C4, targets, F));
+  Work& w = ctx->w;
+  hipStream_t st = w.st;
+  // the network runs on this context's stream
+  HIPTRY(hipStreamSynchronize(mlp->stream));
+  mlp->net.stream = st;
+  mlp->stream = st;
+  DevBufs bufs;
+  float* Xd = nullptr;
+  TRY(upload_features(*mlp, F, B, st, &Xd));
+  bufs.p.push_back(Xd);
+  float* O = nullptr;
+  TRY(bufs.get(&O, (size_t)B * (D.n - 1) * sizeof(float)));
+  TRY(mlp->net.forward(B, Xd, O));
+  HIPTRY(launch_from_reduced_f32(O, mlp->ybar, mlp->yscale, B, D.n, W0_out,
+                                 st));
+  for (int64_t b = 0; b < B; ++b) {
+    const double* c = C4 + 4 * b;
+    const double* tg = targets ? targets + b : nullptr;
+    double* row = W0_out + b * D.n;
+    double g_mlp = NAN, g_plain = NAN;
+    TRY(start_gnorm(D, w, c, tg, row, &g_mlp));
+    HIPTRY(launch_copy(row, w.x, D.n, st));
+    TRY(start_gnorm(D, w, c, tg, nullptr, &g_plain));
+    const bool use = g_mlp < g_plain;  // false when the proposal is NaN
+    if (!use) HIPTRY(launch_copy(row, w.x, D.n, st));
+    if (used_mlp) used_mlp[b] = use ? 1 : 0;
+    if (gnorms) {
+      gnorms[2 * b] = g_mlp;
+      gnorms[2 * b + 1] = g_plain;
+    }
+  }
+  HIPTRY(hipStreamSynchronize(st));
+  flush_timed(ctx->prof, st);
+  return YAND_OK;
 }
 
 int yand_mvsk_solve_R(const double* R, int64_t T, int64_t n, double c1,

@@ -18,7 +18,7 @@ HEADER = os.path.join(ROOT, "include", "yand.h")
 
 def _declared():
     text = open(HEADER).read()
-    return sorted(set(re.findall(r"\b(yand_[a-z0-9_]+)\s*\(", text)))
+    return sorted(set(re.findall(r"\b(yand_[A-Za-z0-9_]+)\s*\(", text)))
 
 
 @pytest.fixture(scope="module")
@@ -31,6 +31,7 @@ def lib():
 def test_header_symbols_exported(lib):
     names = _declared()
     assert "yand_mvsk_solve" in names and "yand_hvp" in names
+    assert "yand_mvsk_solve_R" in names and "yand_warmstart_train" in names
     for name in names:
         assert hasattr(lib, name), name
 
@@ -63,3 +64,26 @@ def test_create_rejects_bad_arguments_without_device(lib):
     assert lib.yand_create(C.c_void_p(8), 10, 4, 3, 0, None, C.byref(h)) == -1
     assert lib.yand_create(C.c_void_p(8), 10, 4, 4, 7, None, C.byref(h)) == -1
     assert h.value is None
+
+
+def test_mlp_entry_points_reject_bad_arguments_without_device(lib):
+    o = binding.default_mlp_opts()
+    assert (o.hidden, o.layers, o.epochs, o.lr) == (512, 4, 2000, 1e-3)
+    h = C.c_void_p()
+    assert lib.yand_mlp_create(0, 5, 8, 2, 0, None, C.byref(h)) == -1
+    assert lib.yand_mlp_create(4, 5, 0, 2, 0, None, C.byref(h)) == -1
+    assert lib.yand_mlp_create(4, 5, 8, 0, 0, None, C.byref(h)) == -1
+    assert lib.yand_mlp_create(4, 5, 8, 2, 0, None, None) == -1
+    assert h.value is None
+    assert lib.yand_mlp_num_params(None) == -1
+    assert lib.yand_mlp_forward(None, 1, C.c_void_p(8), C.c_void_p(8)) == -1
+    assert lib.yand_mlp_adam_step(None, None, 1e-3) == -1
+    assert lib.yand_mlp_destroy(None) == 0
+    assert lib.yand_reduced_coords(0, 5, C.c_void_p(8), C.c_void_p(8), None) == -1
+    assert lib.yand_from_reduced(3, 1, C.c_void_p(8), C.c_void_p(8), None) == -1
+    out = C.c_void_p()
+    assert lib.yand_warmstart_train(None, 4, None, None, None, None,
+                                    C.byref(out), None) == -1
+    assert out.value is None
+    assert lib.yand_warmstart_predict(None, None, 1, None, None, None, None,
+                                      None) == -1

@@ -92,3 +92,27 @@ def test_ragged_universes_batch():
         assert np.abs(w - xr).max() <= _kappa_w(R, C4[i], xr, None)
     for cx in ctxs:
         cx.close()
+
+
+def test_frontier_from_given_starts():
+    R = synth.factor_returns(60, 500, 3, 0, 5.0, 0.0, 21)
+    mu, _ = O.center(R)
+    C4 = np.array([synth.crra_coefficients(g) for g in (2.0, 4.0, 8.0)])
+    tg = np.quantile(mu, [0.4, 0.6, 0.8])
+    ctx = yb.Context(torch.from_numpy(R).cuda())
+    W, infos = ctx.frontier(C4, tg)
+    # restarting from the solutions stops at the first stationarity test
+    W2, infos2 = ctx.frontier(C4, tg, W0=W)
+    for b in range(3):
+        assert infos2[b].status == 0 and infos2[b].iterations == 0, infos2[b]
+        assert np.abs(W2[b].cpu().numpy() - W[b].cpu().numpy()).max() <= 1e-14
+    # an infeasible start is moved onto the constraints first
+    rng = np.random.default_rng(0)
+    Wr = torch.from_numpy(rng.standard_normal((3, 60)) * 0.01 + 1.0 / 60).cuda()
+    W3, infos3 = ctx.frontier(C4, tg, W0=Wr)
+    for b in range(3):
+        assert infos3[b].status == 0
+        xr, _ = O.solve(R, C4[b], target=tg[b])
+        assert np.abs(W3[b].cpu().numpy() - xr).max() <= _kappa_w(R, C4[b], xr, tg[b])
+        assert abs(mu @ W3[b].cpu().numpy() - tg[b]) <= 1e-14
+    ctx.close()
