@@ -69,6 +69,15 @@ def cpu_baseline(R, c):
                       f"{el:.1f} s"}
 
 
+def log(msg):
+    """Progress line on stderr (stdout carries only the JSON result)."""
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def _conv(infos):
+    return sum(1 for i in infos if i.status == 0 and i.gnorm <= 1e-8)
+
+
 def frontier_bench(workload, n_targets, n_plain, precision="fp64"):
     """Frontier solves/s: batched (one call, lanes advancing together with
     graph-replayed iterations) vs plain single-instance solves of the same
@@ -78,6 +87,7 @@ def frontier_bench(workload, n_targets, n_plain, precision="fp64"):
     import synth
     from paper_2604_25378_amd import binding as yb
 
+    log(f"frontier {workload}")
     R = synth.workload_returns(workload)
     T, n = R.shape
     targets = synth.frontier_targets(R, n_targets)
@@ -91,7 +101,6 @@ def frontier_bench(workload, n_targets, n_plain, precision="fp64"):
     W, infos = ctx.frontier(C4, tg)
     torch.cuda.synchronize()
     el_b = time.perf_counter() - t0
-    ok = sum(1 for i in infos if i.status == 0 and i.gnorm <= 1e-8)
     its = [i.iterations for i in infos]
     t0 = time.perf_counter()
     plain_its = []
@@ -106,10 +115,139 @@ def frontier_bench(workload, n_targets, n_plain, precision="fp64"):
             "batched_solves_per_s": len(tg) / el_b,
             "plain_solves_per_s": n_plain / el_p,
             "speedup": (len(tg) / el_b) / (n_plain / el_p),
-            "converged": f"{ok}/{len(tg)}",
+            "converged": f"{_conv(infos)}/{len(tg)}",
             "iterations_mean": float(np.mean(its)),
             "plain_sample": n_plain,
             "plain_iterations_mean": float(np.mean(plain_its))}
+
+
+def ragged_bench(count=32, T=6000, precision="fp64"):
+    """32 independent universes with n uniform in [100, 1500]: one batched
+    call over all contexts vs plain single solves, budget set."""
+    import torch
+
+    import synth
+    from paper_2604_25378_amd import binding as yb
+
+    log(f"ragged universes: {count} contexts")
+    sizes = synth.ragged_universe_sizes(count)
+    ctxs = [yb.Context(torch.from_numpy(
+        synth.factor_returns(int(m), T, 10, 0, 4.0, 0.0, 2000 + i)).cuda(),
+        precision) for i, m in enumerate(sizes)]
+    C4 = np.tile(np.array([1.0, 5.0, 2.0, 10.0]), (count, 1))
+    yb.batch_solve(ctxs[:2], C4[:2])        # warm-up
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    W, infos = yb.batch_solve(ctxs, C4)
+    torch.cuda.synchronize()
+    el_b = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    dev = 0.0
+    for b in range(count):
+        w, _ = ctxs[b].solve(C4[b])
+        dev = max(dev, float((w - W[b]).abs().max()))
+    torch.cuda.synchronize()
+    el_p = time.perf_counter() - t0
+    for cx in ctxs:
+        cx.close()
+    return {"workload": f"{count} universes, n in [{sizes.min()}, "
+                        f"{sizes.max()}] (sum {int(sizes.sum())}), T={T}",
+            "batched_solves_per_s": count / el_b,
+            "plain_solves_per_s": count / el_p,
+            "speedup": el_p / el_b,
+            "converged": f"{_conv(infos)}/{count}",
+            "iterations_mean": float(np.mean([i.iterations for i in infos])),
+            "max_abs_w_diff_vs_plain": dev}
+
+
+def warmstart_bench(workload, n_train_targets=16, n_points=256, n_plain=16,
+                    precision="fp64"):
+    """Frontier sweep at full scale: batched + MLP-warm-started solves vs
+    batched plain-start solves vs plain single-instance solves of the same
+    n_points instances, all to ||reduced gradient|| <= 1e-8.
+
+    The network is trained on plain solutions of a disjoint grid (16 targets
+    x gamma in {2, 4, 6, 10}); the sweep uses gamma in {2.5, 3.5, 5, 8} and
+    n_points / 4 targets from the minimum-variance mean to the largest mean.
+    Warm-started timings include the prediction (features, forward pass,
+    residual test against the plain start)."""
+    import torch
+
+    import synth
+    from paper_2604_25378_amd import binding as yb
+
+    R = synth.workload_returns(workload)
+    T, n = R.shape
+    ctx = yb.Context(torch.from_numpy(R).cuda(), precision)
+
+    def grid(gammas, k):
+        tt = synth.frontier_targets(R, k)
+        return (np.array([synth.crra_coefficients(g) for g in gammas for _ in tt]),
+                np.tile(tt, len(gammas)))
+
+    log(f"warm-start sweep {workload}: training solves")
+    Ctr, ttr = grid((2.0, 4.0, 6.0, 10.0), n_train_targets)
+    Cev, tev = grid((2.5, 3.5, 5.0, 8.0), n_points // 4)
+    ctx.frontier(Ctr[:2], ttr[:2])          # warm-up (graph path, allocations)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    Wtr, itr = ctx.frontier(Ctr, ttr)
+    torch.cuda.synchronize()
+    el_trsolve = time.perf_counter() - t0
+    log(f"training set solved in {el_trsolve:.1f} s; training the network")
+    t0 = time.perf_counter()
+    net, loss = yb.warmstart_train(ctx, Ctr, ttr, Wtr)
+    torch.cuda.synchronize()
+    el_train = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    W0, used, gns = yb.warmstart_predict(ctx, net, Cev, tev)
+    torch.cuda.synchronize()
+    el_pred = time.perf_counter() - t0
+    Ww, iw = ctx.frontier(Cev, tev, W0=W0)
+    torch.cuda.synchronize()
+    el_warm = time.perf_counter() - t0
+    log(f"trained in {el_train:.1f} s; warm sweep {el_warm:.1f} s; plain batched")
+    t0 = time.perf_counter()
+    Wp, ip = ctx.frontier(Cev, tev)
+    torch.cuda.synchronize()
+    el_batch = time.perf_counter() - t0
+    log(f"plain batched sweep {el_batch:.1f} s; plain single solves")
+    idx = np.linspace(0, len(tev) - 1, n_plain).astype(int)
+    t0 = time.perf_counter()
+    plain_its = []
+    for b in idx:
+        _, inf = ctx.solve(Cev[b], target=tev[b])
+        plain_its.append(inf.iterations)
+    torch.cuda.synchronize()
+    el_plain = time.perf_counter() - t0
+    dev = float((Ww - Wp).abs().max())
+    net.close()
+    ctx.close()
+    P = len(tev)
+    warm = P / el_warm
+    return {"workload": f"{workload}: n={n} T={T}, {P}-point sweep "
+                        f"({P // 4} targets x gamma 2.5/3.5/5/8)",
+            "warm_batched_solves_per_s": warm,
+            "batched_solves_per_s": P / el_batch,
+            "plain_solves_per_s": n_plain / el_plain,
+            "speedup_warm_vs_plain": warm / (n_plain / el_plain),
+            "speedup_warm_vs_batched": warm / (P / el_batch),
+            "converged_warm": f"{_conv(iw)}/{P}",
+            "converged_batched": f"{_conv(ip)}/{P}",
+            "iterations_mean_warm": float(np.mean([i.iterations for i in iw])),
+            "iterations_mean_batched": float(np.mean([i.iterations for i in ip])),
+            "plain_sample": n_plain,
+            "plain_iterations_mean": float(np.mean(plain_its)),
+            "mlp_used_frac": float(used.mean()),
+            "gnorm_start_median": {"mlp": float(np.median(gns[:, 0])),
+                                   "plain": float(np.median(gns[:, 1]))},
+            "predict_s": el_pred,
+            "max_abs_w_diff_warm_vs_batched": dev,
+            "training": {"instances": len(ttr), "solve_s": el_trsolve,
+                         "train_s": el_train, "final_loss": loss,
+                         "network": f"{yb.WS_FEATURES}-512-512-512-{n - 1}, "
+                                    "FP32, full-batch Adam, 2000 epochs"},
+            "warm_solves_per_s_incl_training": P / (el_warm + el_trsolve + el_train)}
 
 
 def main():
@@ -121,6 +259,7 @@ def main():
     ap.add_argument("--workload", default="n5440_T12000")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-frontier", action="store_true")
+    ap.add_argument("--frontier-points", type=int, default=256)
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build measures one GPU; --gpus {args.gpus} is "
@@ -241,10 +380,12 @@ def main():
     if not args.no_frontier:
         fr = {"n1000_T12000": frontier_bench("n1000_T12000_frontier", 16, 8,
                                              args.precision),
-              "n5440_T12000": frontier_bench(args.workload, 4, 2,
-                                             args.precision)}
+              "ragged_T6000": ragged_bench(32, 6000, args.precision),
+              "n5440_T12000": warmstart_bench(args.workload, 16,
+                                              args.frontier_points, 16,
+                                              args.precision)}
         out["frontier"] = fr
-        out["frontier_solves_per_s"] = fr["n5440_T12000"]["batched_solves_per_s"]
+        out["frontier_solves_per_s"] = fr["n5440_T12000"]["warm_batched_solves_per_s"]
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(R, c)
     print(json.dumps(out), flush=True)
