@@ -18,11 +18,27 @@ namespace {
 constexpr int BM = kTile;
 constexpr int BKK = 16;
 constexpr int NT = 256;
-constexpr int LDP = BM + 1;   // padded LDS row (k-major tiles)
+// LDS row pitch of the k-major tiles: with 144 doubles (1152 bytes) the four
+// k-rows one MFMA operand read touches start 32 banks apart, so each
+// half-wave reads 64 distinct banks.
+constexpr int LDP = BM + 16;
+constexpr int kStage = BKK * LDP;   // one k-slice of one operand
 
-// Loads one BKK-deep slice of a 128-wide operand into registers and writes it
-// to LDS as s[k][m] (FP64).  KC: element (m, k) at base[m * ld + k] (contiguous
-// in k); otherwise element (m, k) at base[k * ld + m] (contiguous in m).
+// LDS layouts of one BKK-deep slice of a 128-wide operand:
+//  - operand contiguous in m in memory (KC = false): k-major, s[k * LDP + m];
+//  - operand contiguous in k (KC = true): m-major, s[m * LDK + k] with
+//    LDK = BKK + 1, which keeps both the 16-byte row stores and the MFMA
+//    operand reads (16 rows x 4 k per instruction) spread over the banks.
+constexpr int LDK = BKK + 1;
+static_assert(BM * LDK <= kStage, "m-major slice must fit the stage buffer");
+
+template <bool KC>
+__device__ __forceinline__ int lds_at(int m, int k) {
+  return KC ? m * LDK + k : k * LDP + m;
+}
+
+// Loads one BKK-deep slice into registers and writes it to LDS (FP64).  KC:
+// element (m, k) at base[m * ld + k]; otherwise at base[k * ld + m].
 template <typename T, bool KC>
 struct Stage {
   static constexpr int VEC = Vec16<T>::N;
@@ -61,19 +77,20 @@ struct Stage {
 #pragma unroll
         for (int e = 0; e < VEC; ++e) {
           double sc = scale ? scale[k0 + k + e] : 1.0;
-          s[(k + e) * LDP + m] = x[e] * sc;
+          s[lds_at<true>(m, k + e)] = x[e] * sc;
         }
       } else {
         constexpr int CPR = BM / VEC;
         int k = idx / CPR, m = (idx % CPR) * VEC;
         double sc = scale ? scale[k0 + k] : 1.0;
 #pragma unroll
-        for (int e = 0; e < VEC; ++e) s[k * LDP + m + e] = x[e] * sc;
+        for (int e = 0; e < VEC; ++e) s[lds_at<false>(m + e, k)] = x[e] * sc;
       }
     }
   }
 };
 
+template <bool AKC, bool BKC>
 __device__ __forceinline__ void mma_slice(const double* sA, const double* sB,
                                           f64x4 (&acc)[4][4], int wm, int wn,
                                           int lane) {
@@ -83,8 +100,8 @@ __device__ __forceinline__ void mma_slice(const double* sA, const double* sB,
     double a[4], b[4];
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
-      a[i] = sA[kr * LDP + wm + i * 16 + c];
-      b[i] = sB[kr * LDP + wn + i * 16 + c];
+      a[i] = sA[lds_at<AKC>(wm + i * 16 + c, kr)];
+      b[i] = sB[lds_at<BKC>(wn + i * 16 + c, kr)];
     }
 #pragma unroll
     for (int i = 0; i < 4; ++i)
@@ -97,6 +114,9 @@ __device__ __forceinline__ void mma_slice(const double* sA, const double* sB,
 
 // acc (this wave's 64 x 64 block) = sum_{k in [kbeg, kend)} opA(m,k) opB(k,n),
 // opB optionally scaled by bscale[k].  kend - kbeg must be a multiple of BKK.
+// sA, sB hold two k-slices each (double buffer): slice s is computed from
+// buffer s % 2 while slice s + 1 waits in registers and slice s + 2 is in
+// flight from memory; one barrier per slice.
 template <typename TA, bool AKC, typename TB, bool BKC>
 __device__ void gemm_core(const TA* Ab, int64_t lda, const TB* Bb,
                           int64_t ldb, const double* bscale, int64_t kbeg,
@@ -115,20 +135,25 @@ __device__ void gemm_core(const TA* Ab, int64_t lda, const TB* Bb,
   sb.load(Bb, ldb, kbeg, tid);
   sa.store(sA, tid, nullptr, kbeg);
   sb.store(sB, tid, bscale, kbeg);
+  if (kbeg + BKK < kend) {
+    sa.load(Ab, lda, kbeg + BKK, tid);
+    sb.load(Bb, ldb, kbeg + BKK, tid);
+  }
   __syncthreads();
+  int buf = 0;
   for (int64_t k0 = kbeg; k0 < kend; k0 += BKK) {
-    const bool more = k0 + BKK < kend;
-    if (more) {
-      sa.load(Ab, lda, k0 + BKK, tid);
-      sb.load(Bb, ldb, k0 + BKK, tid);
+    mma_slice<AKC, BKC>(sA + buf * kStage, sB + buf * kStage, acc, wm, wn,
+                        lane);
+    if (k0 + BKK < kend) {
+      sa.store(sA + (buf ^ 1) * kStage, tid, nullptr, k0 + BKK);
+      sb.store(sB + (buf ^ 1) * kStage, tid, bscale, k0 + BKK);
+      if (k0 + 2 * BKK < kend) {
+        sa.load(Ab, lda, k0 + 2 * BKK, tid);
+        sb.load(Bb, ldb, k0 + 2 * BKK, tid);
+      }
     }
-    mma_slice(sA, sB, acc, wm, wn, lane);
     __syncthreads();
-    if (more) {
-      sa.store(sA, tid, nullptr, k0 + BKK);
-      sb.store(sB, tid, bscale, k0 + BKK);
-      __syncthreads();
-    }
+    buf ^= 1;
   }
 }
 
@@ -166,7 +191,7 @@ __global__ void __launch_bounds__(NT) syrk_kernel(const S* __restrict__ A,
                                                   double* __restrict__ B,
                                                   const int* skip) {
   if (skip && *skip) return;
-  __shared__ double sA[BKK * LDP], sB[BKK * LDP];
+  __shared__ double sA[2 * kStage], sB[2 * kStage];
   int I, J;
   lower_tile(blockIdx.x, &I, &J);
   f64x4 acc[4][4];
@@ -189,10 +214,12 @@ trace_gemm_kernel(const S* __restrict__ A, int64_t lda, int64_t Tp,
                   const double* __restrict__ X, int64_t ldx,
                   double* __restrict__ rn, const int* skip) {
   if (skip && *skip) return;
-  __shared__ double sA[BKK * LDP], sB[BKK * LDP];
+  __shared__ double sA[2 * kStage], sB[2 * kStage];
   __shared__ double rows[2][BM];
-  const int J = blockIdx.x;
-  const int64_t t0 = (int64_t)blockIdx.y * BM;
+  // longest reductions first (J descending), so the short ones fill the tail
+  const int ntt = (int)(Tp / BM), nJ = gridDim.x / ntt;
+  const int J = nJ - 1 - (int)blockIdx.x / ntt;
+  const int64_t t0 = (int64_t)(blockIdx.x % ntt) * BM;
   f64x4 acc[4][4];
   gemm_core<S, true, double, true>(A + t0 * lda, lda,
                                    X + (int64_t)J * BM * ldx, ldx, nullptr, 0,
@@ -217,21 +244,120 @@ trace_gemm_kernel(const S* __restrict__ A, int64_t lda, int64_t Tp,
 }
 
 // ------------------------------------------------------ blocked Cholesky --
-// Diagonal block k: Cholesky of the 128 x 128 block in LDS and its inverse,
-// blocked in 32-column sub-panels.  Wave 0 factors and inverts each 32 x 32
-// diagonal sub-block in registers (lane r owns row r; column values move by
-// lane shuffles); the panel below is L21 = A21 X11^T and the trailing update
-// A22 -= L21 L21^T, both spread over all threads.  The inverse is assembled
-// from the last sub-panel: X21 = -(X22 L21) X11.  X11 blocks are parked
-// transposed in the free upper triangle.  L_kk goes to M (lower) and L_kk^-1
-// to the diagonal block of X.  LDS rows are padded to 129 doubles.
+// Diagonal block k: Cholesky factor L_kk of the 128 x 128 block and its
+// inverse X_kk = L_kk^-1, computed in LDS by one workgroup of 8 waves.
+//
+// LDS layout (128 rows of LDD doubles): L in the lower triangle (diagonal
+// included); the strictly lower part of X stored transposed in the strict
+// upper triangle (X[i][j], i > j, at row j, column i); 1/L_ii in rdiag.
+//
+// Factorisation: right-looking in 32-column steps.  Wave 0 factors the
+// 32 x 32 diagonal sub-block in registers (lane r holds row r; column values
+// move by lane shuffles) and inverts it by forward substitution (lane c
+// solves for column c).  The sub-panel below, L21 = A21 X11^T, and the
+// trailing update A22 -= L21 L21^T run on the FP64 matrix cores.
+// Inverse: recursive doubling, X21 = -X22 (L21 X11), first for the two
+// 64 x 64 halves (32-row blocks), then for the whole block (64-row blocks),
+// again on the matrix cores.
 constexpr int DT = 512;      // threads of the diagonal-block kernel
-constexpr int SB = 32;       // sub-panel width
+constexpr int SB = 16;       // leaf width
 constexpr int LDD = BM + 1;  // padded LDS row
+constexpr size_t kDiagLds = ((size_t)BM * LDD + BM) * sizeof(double);
 
 __device__ __forceinline__ void wave_sync() {
   __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
   __builtin_amdgcn_wave_barrier();
+}
+
+// One 16 x 16 output block: sum_{k in [kb, ke)} fa(r0 + i, k) fb(k, c0 + j),
+// ke - kb a multiple of 4.  Lane l holds (r0 + l/16 + 4 r, c0 + l%16) in
+// component r of the result.
+template <class FA, class FB>
+__device__ __forceinline__ f64x4 mfma_block(FA fa, FB fb, int r0, int c0,
+                                            int kb, int ke, int lane) {
+  f64x4 acc = {0.0, 0.0, 0.0, 0.0};
+  const int lr = lane & 15, lk = lane >> 4;
+  for (int k = kb; k < ke; k += 4)
+    acc = __builtin_amdgcn_mfma_f64_16x16x4f64(fa(r0 + lr, k + lk),
+                                               fb(k + lk, c0 + lr), acc, 0, 0,
+                                               0);
+  return acc;
+}
+
+// Value of v in lane l (l uniform), read through the scalar unit.
+__device__ __forceinline__ double bcast(double v, int l) {
+  const long long b = __double_as_longlong(v);
+  const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)b, l);
+  const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(b >> 32), l);
+  return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
+
+// 1 / sqrt(p) for p > 0: hardware estimate refined by one Newton-Raphson
+// step y <- y + y (1 - p y^2) / 2 (relative error of the estimate squares).
+__device__ __forceinline__ double rsqrt_nr(double p) {
+  const double y = __builtin_amdgcn_rsq(p);
+  const double r = fma(-p * y, y, 1.0);
+  return fma(0.5 * y, r, y);
+}
+
+// Wave 0: Cholesky and inverse of the SB x SB diagonal sub-block at (c0, c0).
+// Lane r holds row r of the block.  Factor: column j is scaled by its pivot
+// and applied to the rows below; the reciprocal pivots 1 / L_jj are kept.
+// Inverse, row by row: X[m] = (e_m - sum_{m'<m} L[m][m'] X[m']) / L[m][m];
+// row m is broadcast once its sum is complete and applied to the rows below.
+__device__ __forceinline__ void leaf_chol_inv(double* S, double* rd, int c0,
+                                              int lane, int* fail) {
+  const int r = lane & (SB - 1);  // lanes >= SB mirror lanes < SB, never store
+  double a[SB], rp[SB];
+#pragma unroll
+  for (int j = 0; j < SB; ++j) a[j] = S[(c0 + r) * LDD + c0 + j];
+  bool bad = false;
+  // Branch-free: every lane runs every step.  Entries right of the diagonal
+  // of a lane's row are never read by other lanes nor stored, so the
+  // column update needs no mask.
+#pragma unroll
+  for (int j = 0; j < SB; ++j) {
+    double p = bcast(a[j], j);
+    if (!(p > 0.0) || !isfinite(p)) {
+      bad = true;
+      p = 1.0;
+    }
+    const double y = rsqrt_nr(p);
+    rp[j] = y;
+    const double scaled = a[j] * y;
+    a[j] = r == j ? p * y : (r > j ? scaled : a[j]);
+#pragma unroll
+    for (int c = j + 1; c < SB; ++c) a[c] = fma(-a[j], bcast(a[j], c), a[c]);
+  }
+  if (bad && lane == 0) atomicOr(fail, 1);
+  // x (lane r) accumulates sum_{m<r} L[r][m] X[m][:]; row m of X is formed
+  // from lane m's accumulator as it is broadcast.
+  double x[SB];
+#pragma unroll
+  for (int c = 0; c < SB; ++c) x[c] = 0.0;
+#pragma unroll
+  for (int m = 0; m + 1 < SB; ++m) {
+    const double am = r > m ? a[m] : 0.0;
+#pragma unroll
+    for (int c = 0; c <= m; ++c) {
+      const double xmc = ((c == m ? 1.0 : 0.0) - bcast(x[c], m)) * rp[m];
+      x[c] = fma(am, xmc, x[c]);
+    }
+  }
+  double rpr = 0.0;
+#pragma unroll
+  for (int j = 0; j < SB; ++j) rpr = j == r ? rp[j] : rpr;
+#pragma unroll
+  for (int c = 0; c < SB; ++c) x[c] = ((c == r ? 1.0 : 0.0) - x[c]) * rpr;
+  if (lane < SB) {
+#pragma unroll
+    for (int j = 0; j < SB; ++j) {
+      if (j <= r) S[(c0 + r) * LDD + c0 + j] = a[j];
+      // X[r][j] for j < r, parked at (c0 + j, c0 + r)
+      if (j < r) S[(c0 + j) * LDD + c0 + r] = x[j];
+    }
+    rd[c0 + r] = rpr;
+  }
 }
 
 __global__ void __launch_bounds__(DT) diag_block_kernel(double* M, double* X,
@@ -239,12 +365,19 @@ __global__ void __launch_bounds__(DT) diag_block_kernel(double* M, double* X,
                                                         int* fail,
                                                         const int* skip) {
   if (skip && *skip) return;
-  extern __shared__ double L[];  // BM x LDD
+  extern __shared__ double S[];  // BM x LDD, then rdiag (BM)
+  double* rd = S + BM * LDD;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  constexpr int NW = DT / 64;
   double* Mk = M + (int64_t)k * BM * ld + (int64_t)k * BM;
   double* Xk = X + (int64_t)k * BM * ld + (int64_t)k * BM;
-  constexpr int PER = BM * BM / DT;   // 32 elements per thread
+  auto Lv = [&](int i, int j) { return S[i * LDD + j]; };  // i >= j only
+  auto Xv = [&](int i, int j) {
+    return i > j ? S[j * LDD + i] : (i == j ? rd[i] : 0.0);
+  };
+  auto Xt = [&](int m, int c) { return Xv(c, m); };  // X^T
   {
+    constexpr int PER = BM * BM / DT;
     double v[PER];
 #pragma unroll
     for (int q = 0; q < PER; ++q) {
@@ -254,215 +387,169 @@ __global__ void __launch_bounds__(DT) diag_block_kernel(double* M, double* X,
 #pragma unroll
     for (int q = 0; q < PER; ++q) {
       const int idx = tid + q * DT, i = idx / BM, c = idx % BM;
-      L[i * LDD + c] = v[q];
+      S[i * LDD + c] = v[q];
     }
   }
   __syncthreads();
+  // ---- factorisation --------------------------------------------------------
   for (int c0 = 0; c0 < BM; c0 += SB) {
-    if (wave == 0) {
-      const int r = lane & (SB - 1);
-      double a[SB];
-#pragma unroll
-      for (int j = 0; j < SB; ++j) a[j] = L[(c0 + r) * LDD + c0 + j];
-      bool bad = false;
-#pragma unroll
-      for (int j = 0; j < SB; ++j) {
-        double p = __shfl(a[j], j, 64);
-        if (!(p > 0.0) || !isfinite(p)) {
-          bad = true;
-          p = 1.0;
-        }
-        const double piv = sqrt(p);
-        if (r == j) a[j] = piv;
-        if (r > j) a[j] /= piv;
-#pragma unroll
-        for (int c = j + 1; c < SB; ++c) {
-          const double lcj = __shfl(a[j], c, 64);
-          if (c <= r) a[c] -= a[j] * lcj;
-        }
-      }
-      if (bad && lane == 0) atomicOr(fail, 1);
-      if (lane < SB) {
-#pragma unroll
-        for (int j = 0; j < SB; ++j)
-          if (j <= r) L[(c0 + r) * LDD + c0 + j] = a[j];
-      }
-      wave_sync();
-      // column r of X11 = L11^-1 by forward substitution (lane r -> column
-      // r): X11[i][r] for i > r is parked at (c0 + r, c0 + i), in the free
-      // upper part of row r, and read back from there.
-      if (lane < SB) {
-        double* pr = L + (c0 + r) * LDD + c0;
-        const double xr = 1.0 / pr[r];
-        for (int i = r + 1; i < SB; ++i) {
-          const double* li = L + (c0 + i) * LDD + c0;
-          double v = li[r] * xr;
-#pragma unroll 4
-          for (int m = r + 1; m < i; ++m) v += li[m] * pr[m];
-          pr[i] = -v / li[i];
-        }
-      }
-    }
+    if (wave == 0) leaf_chol_inv(S, rd, c0, lane, fail);
     __syncthreads();
     const int r0 = c0 + SB, rem = BM - r0;
     if (rem == 0) break;
-    // L21[i][j] = sum_{m<=j} A21[i][m] X11[j][m]; results staged in registers
+    const int nb = rem / 16;
+    // L21 = A21 X11^T: nb x (SB / 16) blocks, at most 2 per wave, stored
+    // after all waves have read A21
     {
-      constexpr int MAXO = (BM - SB) * SB / DT;   // 6
-      double o[MAXO];
+      constexpr int CB = SB / 16;
+      f64x4 res[2];
 #pragma unroll
-      for (int q = 0; q < MAXO; ++q) {
-        const int idx = tid + q * DT, i = idx / SB, j = idx % SB;
-        double v = 0.0;
-        if (i < rem) {
-          const double* ai = L + (r0 + i) * LDD + c0;
-          for (int m = 0; m < j; ++m)
-            v += ai[m] * L[(c0 + m) * LDD + c0 + j];   // X11[j][m], m < j
-          v += ai[j] / L[(c0 + j) * LDD + c0 + j];     // X11[j][j]
+      for (int sl = 0; sl < 2; ++sl) {
+        const int b = wave + sl * NW, bi = b / CB, bj = b % CB;
+        if (b < nb * CB)
+          res[sl] = mfma_block(Lv, Xt, r0 + 16 * bi, c0 + 16 * bj, c0,
+                               c0 + 16 * bj + 16, lane);
+      }
+      __syncthreads();
+#pragma unroll
+      for (int sl = 0; sl < 2; ++sl) {
+        const int b = wave + sl * NW, bi = b / CB, bj = b % CB;
+        if (b < nb * CB) {
+#pragma unroll
+          for (int q = 0; q < 4; ++q)
+            S[(r0 + 16 * bi + (lane >> 4) + 4 * q) * LDD + c0 + 16 * bj +
+              (lane & 15)] = res[sl][q];
         }
-        o[q] = v;
-      }
-      __syncthreads();
-#pragma unroll
-      for (int q = 0; q < MAXO; ++q) {
-        const int idx = tid + q * DT, i = idx / SB, j = idx % SB;
-        if (i < rem) L[(r0 + i) * LDD + c0 + j] = o[q];
       }
     }
     __syncthreads();
-    // trailing update A22 -= L21 L21^T (lower part)
-    for (int idx = tid; idx < rem * rem; idx += DT) {
-      const int i = r0 + idx / rem, c = r0 + idx % rem;
-      if (c > i) continue;
-      const double* li = L + i * LDD + c0;
-      const double* lc = L + c * LDD + c0;
-      double v = 0.0;
-#pragma unroll 8
-      for (int m = 0; m < SB; ++m) v += li[m] * lc[m];
-      L[i * LDD + c] -= v;
-    }
-    __syncthreads();
-  }
-  // write L_kk (lower)
-  for (int idx = tid; idx < BM * BM; idx += DT) {
-    const int i = idx / BM, c = idx % BM;
-    Mk[(int64_t)i * ld + c] = c <= i ? L[i * LDD + c] : 0.0;
-  }
-  __syncthreads();
-  // ---- assemble the inverse, sub-panels from the last ---------------------
-  for (int c0 = BM - SB; c0 >= 0; c0 -= SB) {
-    const int r0 = c0 + SB, rem = BM - r0;
-    // T[i][c] = sum_{m<=i} X[r0+i][r0+m] L[r0+m][c0+c], parked at (c0+c, r0+i)
-    if (rem > 0) {
-      for (int idx = tid; idx < rem * SB; idx += DT) {
-        const int i = idx / SB, c = idx % SB;
-        const double* xi = L + (r0 + i) * LDD + r0;
-        double v = 0.0;
-        for (int m = 0; m <= i; ++m) v += xi[m] * L[(r0 + m) * LDD + c0 + c];
-        L[(c0 + c) * LDD + r0 + i] = v;
-      }
-    }
-    __syncthreads();
-    // move X11 into the lower part of the sub-block
+    // A22 -= L21 L21^T on the lower blocks
     {
-      double v[2];
+      auto Lt = [&](int m, int c) { return S[c * LDD + m]; };  // L21^T
+      for (int b = wave; b < nb * (nb + 1) / 2; b += NW) {
+        int bi = 0;
+        while ((bi + 1) * (bi + 2) / 2 <= b) ++bi;
+        const int bj = b - bi * (bi + 1) / 2;
+        const f64x4 v =
+            mfma_block(Lv, Lt, r0 + 16 * bi, r0 + 16 * bj, c0, c0 + SB, lane);
 #pragma unroll
-      for (int q = 0; q < 2; ++q) {
-        const int idx = tid + q * DT, i = idx / SB, c = idx % SB;
-        v[q] = i > c ? L[(c0 + c) * LDD + c0 + i]
-                     : (i == c ? 1.0 / L[(c0 + i) * LDD + c0 + i] : 0.0);
-      }
-      __syncthreads();
-#pragma unroll
-      for (int q = 0; q < 2; ++q) {
-        const int idx = tid + q * DT, i = idx / SB, c = idx % SB;
-        if (i >= c) L[(c0 + i) * LDD + c0 + c] = v[q];
+        for (int q = 0; q < 4; ++q)
+          S[(r0 + 16 * bi + (lane >> 4) + 4 * q) * LDD + r0 + 16 * bj +
+            (lane & 15)] -= v[q];
       }
     }
     __syncthreads();
-    // X[r0+i][c0+c] = -sum_{m>=c} T[i][m] X11[m][c]
-    if (rem > 0) {
-      for (int idx = tid; idx < rem * SB; idx += DT) {
-        const int i = idx / SB, c = idx % SB;
-        double v = 0.0;
-        for (int m = c; m < SB; ++m)
-          v += L[(c0 + m) * LDD + r0 + i] * L[(c0 + m) * LDD + c0 + c];
-        L[(r0 + i) * LDD + c0 + c] = -v;
+  }
+  // ---- inverse: X21 = -X22 (L21 X11) at half sizes 32, then 64 ---------------
+  auto Tv = [&](int m, int c) { return S[c * LDD + m]; };  // parked T / X21
+  for (int h = SB; h < BM; h *= 2) {
+    const int nh = BM / (2 * h);         // independent problems
+    const int hb = h / 16;               // 16-blocks per side
+    const int nblk = nh * hb * hb;       // <= 16: at most 2 per wave
+    // T = L21 X11, parked where X21 goes
+    for (int b = wave; b < nblk; b += NW) {
+      const int p = b / (hb * hb), bi = (b / hb) % hb, bj = b % hb;
+      const int b0 = p * 2 * h;
+      const int row = b0 + h + 16 * bi, col = b0 + 16 * bj;
+      const f64x4 v = mfma_block(Lv, Xv, row, col, col, b0 + h, lane);
+#pragma unroll
+      for (int q = 0; q < 4; ++q)
+        S[(col + (lane & 15)) * LDD + row + (lane >> 4) + 4 * q] = v[q];
+    }
+    __syncthreads();
+    // X21 = -X22 T, stored over T after all waves have read it
+    f64x4 res[2];
+#pragma unroll
+    for (int sl = 0; sl < 2; ++sl) {
+      const int b = wave + sl * NW;
+      const int p = b / (hb * hb), bi = (b / hb) % hb, bj = b % hb;
+      const int b0 = p * 2 * h;
+      const int row = b0 + h + 16 * bi, col = b0 + 16 * bj;
+      if (b < nblk) res[sl] = mfma_block(Xv, Tv, row, col, b0 + h, row + 16, lane);
+    }
+    __syncthreads();
+#pragma unroll
+    for (int sl = 0; sl < 2; ++sl) {
+      const int b = wave + sl * NW;
+      const int p = b / (hb * hb), bi = (b / hb) % hb, bj = b % hb;
+      const int b0 = p * 2 * h;
+      const int row = b0 + h + 16 * bi, col = b0 + 16 * bj;
+      if (b < nblk) {
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+          S[(col + (lane & 15)) * LDD + row + (lane >> 4) + 4 * q] = -res[sl][q];
       }
     }
     __syncthreads();
   }
   for (int idx = tid; idx < BM * BM; idx += DT) {
     const int i = idx / BM, c = idx % BM;
-    Xk[(int64_t)i * ld + c] = c <= i ? L[i * LDD + c] : 0.0;
+    Mk[(int64_t)i * ld + c] = c <= i ? S[i * LDD + c] : 0.0;
+    Xk[(int64_t)i * ld + c] = c <= i ? Xv(i, c) : 0.0;
   }
 }
 
-// L[I, k] = M[I, k] L_kk^-T for I > k (in place).
-__global__ void __launch_bounds__(NT) panel_kernel(double* M,
-                                                   const double* X,
-                                                   int64_t ld, int k,
-                                                   const int* skip) {
+// Step k after the diagonal block, first launch (both need only L_kk^-1):
+//   blocks [0, rem):        L[I, k] = M[I, k] L_kk^-T, I = k + 1 + b (in place)
+//   blocks [rem, rem + k):  X[k, j] = -L_kk^-1 S[k, j], j = b - rem, where S
+//                           accumulated sum_{m<k} L[k, m] X[m, j] in place.
+__global__ void __launch_bounds__(NT) panel_finalize_kernel(double* M,
+                                                            double* X,
+                                                            int64_t ld, int k,
+                                                            int rem,
+                                                            const int* skip) {
   if (skip && *skip) return;
-  __shared__ double sA[BKK * LDP], sB[BKK * LDP];
-  const int I = k + 1 + blockIdx.x;
-  double* Mik = M + (int64_t)I * BM * ld + (int64_t)k * BM;
+  __shared__ double sA[2 * kStage], sB[2 * kStage];
   const double* Xkk = X + (int64_t)k * BM * ld + (int64_t)k * BM;
   f64x4 acc[4][4];
-  gemm_core<double, true, double, true>(Mik, ld, Xkk, ld, nullptr, 0, BM, acc,
-                                        sA, sB);
-  for_each_acc(acc, [&](int r, int c, double v) { Mik[(int64_t)r * ld + c] = v; });
+  if ((int)blockIdx.x < rem) {
+    const int I = k + 1 + blockIdx.x;
+    double* Mik = M + (int64_t)I * BM * ld + (int64_t)k * BM;
+    gemm_core<double, true, double, true>(Mik, ld, Xkk, ld, nullptr, 0, BM,
+                                          acc, sA, sB);
+    for_each_acc(acc, [&](int r, int c, double v) { Mik[(int64_t)r * ld + c] = v; });
+  } else {
+    const int j = blockIdx.x - rem;
+    double* Skj = X + (int64_t)k * BM * ld + (int64_t)j * BM;
+    gemm_core<double, true, double, false>(Xkk, ld, Skj, ld, nullptr, 0, BM,
+                                           acc, sA, sB);
+    for_each_acc(acc, [&](int r, int c, double v) { Skj[(int64_t)r * ld + c] = -v; });
+  }
 }
 
-// M[I, J] -= L[I, k] L[J, k]^T for k < J <= I.
-__global__ void __launch_bounds__(NT) update_kernel(double* M, int64_t ld,
-                                                    int k, const int* skip) {
+// Step k, second launch (needs the panel L[:, k] and the row X[k, :]):
+//   blocks [0, nu):       M[I, J] -= L[I, k] L[J, k]^T, k < J <= I
+//   blocks [nu, nu + ni): S[i, j] += L[i, k] X[k, j],   i > k, j <= k
+// with nu = rem (rem + 1) / 2 and ni = rem (k + 1).  The two sets touch
+// disjoint tiles (J > k versus j <= k).
+__global__ void __launch_bounds__(NT) update_kernel(double* M, double* X,
+                                                    int64_t ld, int k, int nu,
+                                                    const int* skip) {
   if (skip && *skip) return;
-  __shared__ double sA[BKK * LDP], sB[BKK * LDP];
-  int I, J;
-  lower_tile(blockIdx.x, &I, &J);
-  I += k + 1;
-  J += k + 1;
-  const double* Lik = M + (int64_t)I * BM * ld + (int64_t)k * BM;
-  const double* Ljk = M + (int64_t)J * BM * ld + (int64_t)k * BM;
+  __shared__ double sA[2 * kStage], sB[2 * kStage];
   f64x4 acc[4][4];
-  gemm_core<double, true, double, true>(Lik, ld, Ljk, ld, nullptr, 0, BM, acc,
-                                        sA, sB);
-  double* Mij = M + (int64_t)I * BM * ld + (int64_t)J * BM;
-  for_each_acc(acc, [&](int r, int c, double v) { Mij[(int64_t)r * ld + c] -= v; });
-}
-
-// X[k, j] = -L_kk^-1 S[k, j] for j < k (S accumulated in place in X).
-__global__ void __launch_bounds__(NT) inv_finalize_kernel(double* X,
-                                                          int64_t ld, int k,
-                                                          const int* skip) {
-  if (skip && *skip) return;
-  __shared__ double sA[BKK * LDP], sB[BKK * LDP];
-  const int j = blockIdx.x;
-  const double* Xkk = X + (int64_t)k * BM * ld + (int64_t)k * BM;
-  double* Skj = X + (int64_t)k * BM * ld + (int64_t)j * BM;
-  f64x4 acc[4][4];
-  gemm_core<double, true, double, false>(Xkk, ld, Skj, ld, nullptr, 0, BM, acc,
-                                         sA, sB);
-  for_each_acc(acc, [&](int r, int c, double v) { Skj[(int64_t)r * ld + c] = -v; });
-}
-
-// S[i, j] += L[i, k] X[k, j] for i > k, j <= k.
-__global__ void __launch_bounds__(NT) inv_update_kernel(double* X,
-                                                        const double* M,
-                                                        int64_t ld, int k,
-                                                        const int* skip) {
-  if (skip && *skip) return;
-  __shared__ double sA[BKK * LDP], sB[BKK * LDP];
-  const int i = k + 1 + blockIdx.x / (k + 1);
-  const int j = blockIdx.x % (k + 1);
-  const double* Lik = M + (int64_t)i * BM * ld + (int64_t)k * BM;
-  const double* Xkj = X + (int64_t)k * BM * ld + (int64_t)j * BM;
-  f64x4 acc[4][4];
-  gemm_core<double, true, double, false>(Lik, ld, Xkj, ld, nullptr, 0, BM, acc,
-                                         sA, sB);
-  double* Sij = X + (int64_t)i * BM * ld + (int64_t)j * BM;
-  for_each_acc(acc, [&](int r, int c, double v) { Sij[(int64_t)r * ld + c] += v; });
+  if ((int)blockIdx.x < nu) {
+    int I, J;
+    lower_tile(blockIdx.x, &I, &J);
+    I += k + 1;
+    J += k + 1;
+    const double* Lik = M + (int64_t)I * BM * ld + (int64_t)k * BM;
+    const double* Ljk = M + (int64_t)J * BM * ld + (int64_t)k * BM;
+    gemm_core<double, true, double, true>(Lik, ld, Ljk, ld, nullptr, 0, BM,
+                                          acc, sA, sB);
+    double* Mij = M + (int64_t)I * BM * ld + (int64_t)J * BM;
+    for_each_acc(acc, [&](int r, int c, double v) { Mij[(int64_t)r * ld + c] -= v; });
+  } else {
+    const int b = blockIdx.x - nu;
+    const int i = k + 1 + b / (k + 1);
+    const int j = b % (k + 1);
+    const double* Lik = M + (int64_t)i * BM * ld + (int64_t)k * BM;
+    const double* Xkj = X + (int64_t)k * BM * ld + (int64_t)j * BM;
+    gemm_core<double, true, double, false>(Lik, ld, Xkj, ld, nullptr, 0, BM,
+                                           acc, sA, sB);
+    double* Sij = X + (int64_t)i * BM * ld + (int64_t)j * BM;
+    for_each_acc(acc, [&](int r, int c, double v) { Sij[(int64_t)r * ld + c] += v; });
+  }
 }
 
 // ------------------------------------------------------ matrix-vectors ----
@@ -546,7 +633,7 @@ hipError_t launch_syrk(int precision, const void* A, int64_t lda, int64_t Tp,
 hipError_t prepare_dense_kernels() {
   static bool attr_set = false;
   if (!attr_set) {
-    const size_t lds = (size_t)BM * LDD * sizeof(double);
+    const size_t lds = kDiagLds;
     hipError_t e = hipFuncSetAttribute(
         (const void*)diag_block_kernel,
         hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
@@ -559,24 +646,20 @@ hipError_t prepare_dense_kernels() {
 hipError_t launch_potrf_trtri(double* M, double* X, int64_t np, int* fail,
                               hipStream_t st, const int* skip) {
   const int nt = (int)(np / BM);
-  const size_t lds = (size_t)BM * LDD * sizeof(double);
+  const size_t lds = kDiagLds;
   hipError_t pe = prepare_dense_kernels();
   if (pe != hipSuccess) return pe;
   for (int k = 0; k < nt; ++k) {
     hipLaunchKernelGGL(diag_block_kernel, dim3(1), dim3(DT), lds, st, M, X,
                        np, k, fail, skip);
     const int rem = nt - k - 1;
-    if (rem > 0)
-      hipLaunchKernelGGL(panel_kernel, dim3(rem), dim3(NT), 0, st, M,
-                         (const double*)X, np, k, skip);
-    if (k > 0)
-      hipLaunchKernelGGL(inv_finalize_kernel, dim3(k), dim3(NT), 0, st, X, np,
-                         k, skip);
+    if (rem + k > 0)
+      hipLaunchKernelGGL(panel_finalize_kernel, dim3(rem + k), dim3(NT), 0, st,
+                         M, X, np, k, rem, skip);
     if (rem > 0) {
-      hipLaunchKernelGGL(update_kernel, dim3(rem * (rem + 1) / 2), dim3(NT), 0,
-                         st, M, np, k, skip);
-      hipLaunchKernelGGL(inv_update_kernel, dim3(rem * (k + 1)), dim3(NT), 0,
-                         st, X, (const double*)M, np, k, skip);
+      const int nu = rem * (rem + 1) / 2, ni = rem * (k + 1);
+      hipLaunchKernelGGL(update_kernel, dim3(nu + ni), dim3(NT), 0, st, M, X,
+                         np, k, nu, skip);
     }
   }
   return hipGetLastError();
@@ -585,7 +668,7 @@ hipError_t launch_potrf_trtri(double* M, double* X, int64_t np, int* fail,
 hipError_t launch_trace_gemm(int precision, const void* A, int64_t lda,
                              int64_t Tp, const double* X, int64_t np,
                              double* rn, hipStream_t st, const int* skip) {
-  dim3 g((unsigned)(np / BM), (unsigned)(Tp / BM)), b(NT);
+  dim3 g((unsigned)((np / BM) * (Tp / BM))), b(NT);
   switch (precision) {
     case 0:
       hipLaunchKernelGGL(trace_gemm_kernel<double>, g, b, 0, st,
