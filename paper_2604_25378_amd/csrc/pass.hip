@@ -69,10 +69,10 @@ __global__ void center_convert_kernel(const double* __restrict__ R, int64_t T,
 // t the row index; the op returns the back-projection weight and updates its
 // running scalar sums (kept by thread 0 only).
 struct OpOracle {   // a2: z = Ax, psi'(z)/T, sum z^2, z^3, z^4
-  static constexpr bool kDot = true, kBack = true;
+  static constexpr bool kDot = true, kBack = true, kZ = false, kQ = false;
   static constexpr int kSums = 3;
   __device__ static double row(const PassArgs& a, int64_t t, double s,
-                               double* sums, bool lead) {
+                               double* sums, bool lead, double, double) {
     if (lead) {
       a.tout[t] = s;
       double s2 = s * s;
@@ -84,30 +84,29 @@ struct OpOracle {   // a2: z = Ax, psi'(z)/T, sum z^2, z^3, z^4
   }
 };
 struct OpValue {    // z = Ax and sum z^2, z^3, z^4 only
-  static constexpr bool kDot = true, kBack = false;
+  static constexpr bool kDot = true, kBack = false, kZ = false, kQ = false;
   static constexpr int kSums = 3;
   __device__ static double row(const PassArgs& a, int64_t t, double s,
-                               double* sums, bool lead) {
-    return OpOracle::row(a, t, s, sums, lead);
+                               double* sums, bool lead, double, double) {
+    return OpOracle::row(a, t, s, sums, lead, 0.0, 0.0);
   }
 };
 struct OpHvp {      // a4: psi''(z_t) (Av)_t / T; (Av)_t optionally stored
-  static constexpr bool kDot = true, kBack = true;
+  static constexpr bool kDot = true, kBack = true, kZ = true, kQ = false;
   static constexpr int kSums = 0;
   __device__ static double row(const PassArgs& a, int64_t t, double s,
-                               double*, bool lead) {
+                               double*, bool lead, double z, double) {
     if (lead && a.tout) a.tout[t] = s;
-    return d2psi(a.c, a.zc[t]) * s * a.invT;
+    return d2psi(a.c, z) * s * a.invT;
   }
 };
 struct OpLine {     // a8: w = Ad and the nine mixed power sums with z
-  static constexpr bool kDot = true, kBack = false;
+  static constexpr bool kDot = true, kBack = false, kZ = true, kQ = false;
   static constexpr int kSums = 9;
   __device__ static double row(const PassArgs& a, int64_t t, double w,
-                               double* sums, bool lead) {
+                               double* sums, bool lead, double z, double) {
     if (lead) {
       if (a.tout) a.tout[t] = w;
-      double z = a.zc[t];
       double z2 = z * z, w2 = w * w;
       sums[0] += z * w;        // s11
       sums[1] += z2 * w;       // s21
@@ -123,29 +122,65 @@ struct OpLine {     // a8: w = Ad and the nine mixed power sums with z
   }
 };
 struct OpDot {      // plain row dot (Av)_t, stored
-  static constexpr bool kDot = true, kBack = false;
+  static constexpr bool kDot = true, kBack = false, kZ = false, kQ = false;
   static constexpr int kSums = 0;
   __device__ static double row(const PassArgs& a, int64_t t, double s,
-                               double*, bool lead) {
+                               double*, bool lead, double, double) {
     if (lead) a.tout[t] = s;
     return 0.0;
   }
 };
 struct OpThird {    // a6: psi'''(z_t) q_t / T (third-order back-projection)
-  static constexpr bool kDot = false, kBack = true;
+  static constexpr bool kDot = false, kBack = true, kZ = true, kQ = true;
   static constexpr int kSums = 0;
-  __device__ static double row(const PassArgs& a, int64_t t, double,
-                               double*, bool) {
-    return d3psi(a.c, a.zc[t]) * a.q[t] * a.invT;
+  __device__ static double row(const PassArgs& a, int64_t, double, double*,
+                               bool, double z, double q) {
+    return d3psi(a.c, z) * q * a.invT;
   }
 };
 
-template <typename S, int NCH, int R, class Op>
-__global__ void __launch_bounds__(kPassThreads)
+// Sum of p[r] over the 64 lanes for R = 2^b rows at once: b transposing
+// exchange steps (each lane keeps half of its rows and adds the partner's
+// copy of them) leave lane l with one row, r = l / (64 / R); the remaining
+// 6 - b butterfly steps finish the sum.  R - 1 + 6 - b exchanges instead of
+// 6 R.  Every lane of row r's group of 64 / R lanes ends with the same bits.
+template <int R>
+__device__ __forceinline__ double wave_sum_rows(double (&p)[R], int lane) {
+  static_assert((R & (R - 1)) == 0 && R <= 64, "R must be a power of two");
+#pragma unroll
+  for (int half = R / 2, off = 32; half >= 1; half /= 2, off /= 2) {
+    const bool up = (lane & off) != 0;
+#pragma unroll
+    for (int q = 0; q < half; ++q) {
+      const double send = up ? p[q] : p[q + half];
+      const double keep = up ? p[q + half] : p[q];
+      p[q] = keep + __shfl_xor(send, off, 64);
+    }
+  }
+  double v = p[0];
+#pragma unroll
+  for (int off = 32 / R; off >= 1; off /= 2) v += __shfl_xor(v, off, 64);
+  return v;
+}
+
+// TPB threads per workgroup; each thread owns NCH 16-byte chunks of every
+// row; R rows per step share one reduction and one barrier.
+//
+// Loads run two row blocks ahead in two register slots.  Once a block's row
+// dots are formed, the thread parks its packed chunks in LDS (a private,
+// conflict-free slot per thread: it reads back only what it wrote) and
+// refills the register slot with the block two steps ahead, so two blocks
+// stay in flight through the reduction, the barrier and the back-projection,
+// which reads the parked copy.
+template <typename S, int TPB, int NCH, int R, class Op>
+__global__ void __launch_bounds__(TPB)
 pass_kernel(PassArgs a) {
   if (a.skip && *a.skip) return;
   constexpr int VEC = Vec16<S>::N;
-  __shared__ double red[2][R][kPassWaves];
+  constexpr int NW = TPB / 64;
+  constexpr bool kPark = Op::kDot && Op::kBack;
+  __shared__ double red[2][R][NW];
+  __shared__ u32x4 park[kPark ? R * NCH * TPB : 1];
   const int tid = threadIdx.x;
   const int wave = tid >> 6, lane = tid & 63;
   const int64_t nvec = a.lda / VEC;   // 16-byte chunks per row
@@ -160,7 +195,7 @@ pass_kernel(PassArgs a) {
   double acc[NCH][VEC];
 #pragma unroll
   for (int k = 0; k < NCH; ++k) {
-    int64_t c = tid + (int64_t)k * kPassThreads;
+    int64_t c = tid + (int64_t)k * TPB;
     valid[k] = c < nvec;
 #pragma unroll
     for (int e = 0; e < VEC; ++e) {
@@ -173,69 +208,101 @@ pass_kernel(PassArgs a) {
 #pragma unroll
   for (int i = 0; i < (Op::kSums > 0 ? Op::kSums : 1); ++i) sums[i] = 0.0;
 
-  u32x4 cur[R][NCH], nxt[R][NCH];
-  auto load_block = [&](int64_t r0, u32x4 (&dst)[R][NCH]) {
+  u32x4 slot[2][R][NCH];
+  // per-row scalars of the op (cached z, q), fetched with their block
+  double zs[2][R], qs[2][R];
+  auto load_block = [&](int64_t r0, u32x4 (&dst)[R][NCH], double (&zd)[R],
+                        double (&qd)[R]) {
+    if (r0 >= row1) return;
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      zd[r] = Op::kZ ? a.zc[r0 + r] : 0.0;
+      qd[r] = Op::kQ ? a.q[r0 + r] : 0.0;
+    }
 #pragma unroll
     for (int r = 0; r < R; ++r) {
       const u32x4* rowp = (const u32x4*)(base + (r0 + r) * row_bytes);
 #pragma unroll
       for (int k = 0; k < NCH; ++k) {
-        int64_t c = tid + (int64_t)k * kPassThreads;
+        int64_t c = tid + (int64_t)k * TPB;
         dst[r][k] = valid[k] ? __builtin_nontemporal_load(rowp + c)
                              : u32x4{0u, 0u, 0u, 0u};
       }
     }
   };
 
-  if (row0 < row1) load_block(row0, cur);
+  load_block(row0, slot[0], zs[0], qs[0]);
+  load_block(row0 + R, slot[1], zs[1], qs[1]);
   int parity = 0;
-  for (int64_t r0 = row0; r0 < row1; r0 += R) {
-    if (r0 + R < row1) load_block(r0 + R, nxt);
-    double s[R];
-    if constexpr (Op::kDot) {
+  for (int64_t r0 = row0; r0 < row1; r0 += 2 * R) {
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const int64_t rb = r0 + h * R;
+      if (rb >= row1) break;
+      u32x4 (&cur)[R][NCH] = slot[h];
+      double zr[R], qr[R];
 #pragma unroll
       for (int r = 0; r < R; ++r) {
-        double p = 0.0;
-#pragma unroll
-        for (int k = 0; k < NCH; ++k) {
-          double x[VEC];
-          unpack16<S>(cur[r][k], x);
-#pragma unroll
-          for (int e = 0; e < VEC; ++e) p = fma(x[e], v[k][e], p);
-        }
-        p = wave_sum(p);
-        if (lane == 0) red[parity][r][wave] = p;
+        zr[r] = zs[h][r];
+        qr[r] = qs[h][r];
       }
-      __syncthreads();
+      double s[R];
+      if constexpr (Op::kDot) {
+        double p[R];
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+          p[r] = 0.0;
+#pragma unroll
+          for (int k = 0; k < NCH; ++k) {
+            double x[VEC];
+            unpack16<S>(cur[r][k], x);
+#pragma unroll
+            for (int e = 0; e < VEC; ++e) p[r] = fma(x[e], v[k][e], p[r]);
+          }
+        }
+        const double ws = wave_sum_rows<R>(p, lane);
+        if ((lane & (64 / R - 1)) == 0)
+          red[parity][lane / (64 / R)][wave] = ws;
+        if constexpr (kPark) {
+#pragma unroll
+          for (int r = 0; r < R; ++r)
+#pragma unroll
+            for (int k = 0; k < NCH; ++k)
+              park[(r * NCH + k) * TPB + tid] = cur[r][k];
+        }
+        // the slot is free once the dots are formed (or parked)
+        if constexpr (kPark || !Op::kBack)
+          load_block(rb + 2 * R, cur, zs[h], qs[h]);
+        __syncthreads();
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+          double q = 0.0;
+#pragma unroll
+          for (int w = 0; w < NW; ++w) q += red[parity][r][w];
+          s[r] = q;
+        }
+        parity ^= 1;
+      } else {
+#pragma unroll
+        for (int r = 0; r < R; ++r) s[r] = 0.0;
+      }
 #pragma unroll
       for (int r = 0; r < R; ++r) {
-        double p = 0.0;
+        double om = Op::row(a, rb + r, s[r], sums, tid == 0, zr[r], qr[r]);
+        if constexpr (Op::kBack) {
 #pragma unroll
-        for (int w = 0; w < kPassWaves; ++w) p += red[parity][r][w];
-        s[r] = p;
-      }
-      parity ^= 1;
-    } else {
+          for (int k = 0; k < NCH; ++k) {
+            const u32x4 w =
+                kPark ? park[(r * NCH + k) * TPB + tid] : cur[r][k];
+            double x[VEC];
+            unpack16<S>(w, x);
 #pragma unroll
-      for (int r = 0; r < R; ++r) s[r] = 0.0;
-    }
-#pragma unroll
-    for (int r = 0; r < R; ++r) {
-      double om = Op::row(a, r0 + r, s[r], sums, tid == 0);
-      if constexpr (Op::kBack) {
-#pragma unroll
-        for (int k = 0; k < NCH; ++k) {
-          double x[VEC];
-          unpack16<S>(cur[r][k], x);
-#pragma unroll
-          for (int e = 0; e < VEC; ++e) acc[k][e] = fma(om, x[e], acc[k][e]);
+            for (int e = 0; e < VEC; ++e) acc[k][e] = fma(om, x[e], acc[k][e]);
+          }
         }
       }
+      if constexpr (!Op::kDot) load_block(rb + 2 * R, cur, zs[h], qs[h]);
     }
-#pragma unroll
-    for (int r = 0; r < R; ++r)
-#pragma unroll
-      for (int k = 0; k < NCH; ++k) cur[r][k] = nxt[r][k];
   }
 
   if constexpr (Op::kBack) {
@@ -243,7 +310,7 @@ pass_kernel(PassArgs a) {
 #pragma unroll
     for (int k = 0; k < NCH; ++k) {
       if (!valid[k]) continue;
-      int64_t c = tid + (int64_t)k * kPassThreads;
+      int64_t c = tid + (int64_t)k * TPB;
 #pragma unroll
       for (int e = 0; e < VEC; ++e) prow[c * VEC + e] = acc[k][e];
     }
@@ -299,21 +366,51 @@ __global__ void reduce_sums_kernel(const double* __restrict__ psums, int nwg,
 
 // ------------------------------------------------------------ launchers --
 
-int pass_groups(int64_t Tp, int R, int64_t* rows_per_wg) {
+// Launch shape per storage type: the row block R grows as rows get shorter
+// so one reduction serves more rows; BF16 rows are short enough that 256
+// threads per row (two workgroups per CU) give each thread whole chunks.
+template <typename S> struct PassShape;
+template <> struct PassShape<double> {
+  static constexpr int TPB = 512, R = 2, GROUPS = 256;
+};
+template <> struct PassShape<float> {
+  static constexpr int TPB = 512, R = 4, GROUPS = 256;
+};
+template <> struct PassShape<bf16_t> {
+  static constexpr int TPB = 256, R = 2, GROUPS = 512;
+};
+static_assert(PassShape<float>::GROUPS <= kMaxPassGroups, "partials buffer");
+static_assert(PassShape<bf16_t>::GROUPS <= kMaxPassGroups, "partials buffer");
+
+int pass_groups(int64_t Tp, int R, int groups, int64_t* rows_per_wg) {
   int64_t blocks = Tp / R;
-  int64_t nwg = blocks < kMaxPassGroups ? blocks : kMaxPassGroups;
+  int64_t nwg = blocks < groups ? blocks : groups;
   int64_t bpw = (blocks + nwg - 1) / nwg;
   *rows_per_wg = bpw * R;
   return (int)((Tp + *rows_per_wg - 1) / *rows_per_wg);
 }
 
-template <typename S, class Op, int R>
+// Rows per block for NCH chunks per thread: the shape's R, halved while the
+// two register slots would hold more than 12 chunks of 16 bytes each per
+// row block (register budget) or the parked block would exceed 128 KB.
+template <typename S>
+constexpr int rows_for(int nch) {
+  int r = PassShape<S>::R;
+  while (r > 1 && (r * nch > 12 ||
+                   (int64_t)r * nch * PassShape<S>::TPB * 16 > 131072))
+    r /= 2;
+  return r;
+}
+
+template <typename S, class Op>
 static hipError_t launch_nch(int nch, PassArgs a, int nwg, hipStream_t st) {
-  dim3 g(nwg), b(kPassThreads);
+  constexpr int TPB = PassShape<S>::TPB;
+  dim3 g(nwg), b(TPB);
   switch (nch) {
 #define YAND_NCH_CASE(K)                                                  \
   case K:                                                               \
-    hipLaunchKernelGGL((pass_kernel<S, K, R, Op>), g, b, 0, st, a);     \
+    hipLaunchKernelGGL((pass_kernel<S, TPB, K, rows_for<S>(K), Op>), g, b, \
+                       0, st, a);                                       \
     break;
     YAND_NCH_CASE(1)
     YAND_NCH_CASE(2)
@@ -330,28 +427,25 @@ static hipError_t launch_nch(int nch, PassArgs a, int nwg, hipStream_t st) {
   return hipGetLastError();
 }
 
-template <typename S> constexpr int rows_per_block() {
-  return sizeof(S) == 8 ? 2 : 4;
-}
-
 template <typename S>
 static hipError_t launch_pass_t(PassKind kind, PassArgs a, hipStream_t st,
                                 int* nwg_out) {
-  constexpr int R = rows_per_block<S>();
+  constexpr int TPB = PassShape<S>::TPB;
   constexpr int VEC = Vec16<S>::N;
   int64_t nvec = a.lda / VEC;
-  int nch = (int)((nvec + kPassThreads - 1) / kPassThreads);
+  int nch = (int)((nvec + TPB - 1) / TPB);
   if (nch < 1) nch = 1;
   if (nch > kMaxPassChunks) return hipErrorInvalidValue;
-  int nwg = pass_groups(a.Tp, R, &a.rows_per_wg);
+  // rows per workgroup: a multiple of every block height in use (R <= 8)
+  int nwg = pass_groups(a.Tp, 8, PassShape<S>::GROUPS, &a.rows_per_wg);
   *nwg_out = nwg;
   switch (kind) {
-    case PassKind::Oracle: return launch_nch<S, OpOracle, R>(nch, a, nwg, st);
-    case PassKind::Value: return launch_nch<S, OpValue, R>(nch, a, nwg, st);
-    case PassKind::Hvp: return launch_nch<S, OpHvp, R>(nch, a, nwg, st);
-    case PassKind::Line: return launch_nch<S, OpLine, R>(nch, a, nwg, st);
-    case PassKind::Dot: return launch_nch<S, OpDot, R>(nch, a, nwg, st);
-    case PassKind::Third: return launch_nch<S, OpThird, R>(nch, a, nwg, st);
+    case PassKind::Oracle: return launch_nch<S, OpOracle>(nch, a, nwg, st);
+    case PassKind::Value: return launch_nch<S, OpValue>(nch, a, nwg, st);
+    case PassKind::Hvp: return launch_nch<S, OpHvp>(nch, a, nwg, st);
+    case PassKind::Line: return launch_nch<S, OpLine>(nch, a, nwg, st);
+    case PassKind::Dot: return launch_nch<S, OpDot>(nch, a, nwg, st);
+    case PassKind::Third: return launch_nch<S, OpThird>(nch, a, nwg, st);
   }
   return hipErrorInvalidValue;
 }
@@ -367,8 +461,11 @@ hipError_t launch_pass(int precision, PassKind kind, const PassArgs& a,
 }
 
 int64_t max_pass_columns(int precision) {
-  int vec = precision == 0 ? 2 : precision == 1 ? 4 : 8;
-  return (int64_t)kMaxPassChunks * kPassThreads * vec;
+  switch (precision) {
+    case 0: return (int64_t)kMaxPassChunks * PassShape<double>::TPB * 2;
+    case 1: return (int64_t)kMaxPassChunks * PassShape<float>::TPB * 4;
+    default: return (int64_t)kMaxPassChunks * PassShape<bf16_t>::TPB * 8;
+  }
 }
 
 hipError_t launch_reduce_partials(const double* part, int nwg, int64_t lda,
