@@ -216,10 +216,16 @@ trace_gemm_kernel(const S* __restrict__ A, int64_t lda, int64_t Tp,
   if (skip && *skip) return;
   __shared__ double sA[2 * kStage], sB[2 * kStage];
   __shared__ double rows[2][BM];
-  // longest reductions first (J descending), so the short ones fill the tail
-  const int ntt = (int)(Tp / BM), nJ = gridDim.x / ntt;
-  const int J = nJ - 1 - (int)blockIdx.x / ntt;
-  const int64_t t0 = (int64_t)(blockIdx.x % ntt) * BM;
+  // Longest reductions first (J descending), so the short ones fill the
+  // tail.  The row-tile count is padded to a multiple of 8 so that row tile
+  // t always lands on XCD t mod 8 (workgroups go round-robin over the 8
+  // XCDs): the column tiles sharing rows of A then share one L2.
+  const int ntt = (int)(Tp / BM), ntp = (ntt + 7) / 8 * 8;
+  const int nJ = gridDim.x / ntp;
+  const int ti = (int)blockIdx.x % ntp;
+  if (ti >= ntt) return;
+  const int J = nJ - 1 - (int)blockIdx.x / ntp;
+  const int64_t t0 = (int64_t)ti * BM;
   f64x4 acc[4][4];
   gemm_core<S, true, double, true>(A + t0 * lda, lda,
                                    X + (int64_t)J * BM * ldx, ldx, nullptr, 0,
@@ -668,7 +674,7 @@ hipError_t launch_potrf_trtri(double* M, double* X, int64_t np, int* fail,
 hipError_t launch_trace_gemm(int precision, const void* A, int64_t lda,
                              int64_t Tp, const double* X, int64_t np,
                              double* rn, hipStream_t st, const int* skip) {
-  dim3 g((unsigned)((np / BM) * (Tp / BM))), b(NT);
+  dim3 g((unsigned)((np / BM) * ((Tp / BM + 7) / 8 * 8))), b(NT);
   switch (precision) {
     case 0:
       hipLaunchKernelGGL(trace_gemm_kernel<double>, g, b, 0, st,
