@@ -209,7 +209,7 @@ __global__ void __launch_bounds__(NT) syrk_kernel(const S* __restrict__ A,
 // ------------------------------------------------------- trace row norms --
 // rn[J][t] = sum_{j in tile J} (sum_k A[t][k] X[j][k])^2 for X lower.
 template <typename S>
-__global__ void __launch_bounds__(NT)
+__global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2, 2)))
 trace_gemm_kernel(const S* __restrict__ A, int64_t lda, int64_t Tp,
                   const double* __restrict__ X, int64_t ldx,
                   double* __restrict__ rn, const int* skip) {
@@ -499,7 +499,7 @@ __global__ void __launch_bounds__(DT) diag_block_kernel(double* M, double* X,
 //   blocks [0, rem):        L[I, k] = M[I, k] L_kk^-T, I = k + 1 + b (in place)
 //   blocks [rem, rem + k):  X[k, j] = -L_kk^-1 S[k, j], j = b - rem, where S
 //                           accumulated sum_{m<k} L[k, m] X[m, j] in place.
-__global__ void __launch_bounds__(NT) panel_finalize_kernel(double* M,
+__global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2, 2))) panel_finalize_kernel(double* M,
                                                             double* X,
                                                             int64_t ld, int k,
                                                             int rem,
@@ -528,7 +528,7 @@ __global__ void __launch_bounds__(NT) panel_finalize_kernel(double* M,
 //   blocks [nu, nu + ni): S[i, j] += L[i, k] X[k, j],   i > k, j <= k
 // with nu = rem (rem + 1) / 2 and ni = rem (k + 1).  The two sets touch
 // disjoint tiles (J > k versus j <= k).
-__global__ void __launch_bounds__(NT) update_kernel(double* M, double* X,
+__global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2, 2))) update_kernel(double* M, double* X,
                                                     int64_t ld, int k, int nu,
                                                     const int* skip) {
   if (skip && *skip) return;
