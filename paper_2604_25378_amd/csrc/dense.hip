@@ -18,11 +18,14 @@ namespace {
 constexpr int BM = kTile;
 constexpr int BKK = 16;
 constexpr int NT = 256;
-// LDS row pitch of the k-major tiles: with 144 doubles (1152 bytes) the four
-// k-rows one MFMA operand read touches start 32 banks apart, so each
-// half-wave reads 64 distinct banks.
-constexpr int LDP = BM + 16;
-constexpr int kStage = BKK * LDP;   // one k-slice of one operand
+// Output tiles are TM x TN (128 x 128, or 64-wide for the short launches on
+// the critical path of the factorisation).
+// LDS row pitch of the k-major slices: TM + 16 doubles, so the four k-rows
+// one MFMA operand read touches start 32 banks apart and each half-wave
+// reads 64 distinct banks.
+template <int TM>
+constexpr int ldp() { return TM + 16; }
+constexpr int LDP = ldp<BM>();
 
 // LDS layouts of one BKK-deep slice of a 128-wide operand:
 //  - operand contiguous in m in memory (KC = false): k-major, s[k * LDP + m];
@@ -30,19 +33,25 @@ constexpr int kStage = BKK * LDP;   // one k-slice of one operand
 //    LDK = BKK + 1, which keeps both the 16-byte row stores and the MFMA
 //    operand reads (16 rows x 4 k per instruction) spread over the banks.
 constexpr int LDK = BKK + 1;
-static_assert(BM * LDK <= kStage, "m-major slice must fit the stage buffer");
+// one k-slice of one operand, in either layout
+template <int TM>
+constexpr int stage_size() {
+  return TM * LDK > BKK * ldp<TM>() ? TM * LDK : BKK * ldp<TM>();
+}
+constexpr int kStage = stage_size<BM>();
 
-template <bool KC>
+template <bool KC, int TM = BM>
 __device__ __forceinline__ int lds_at(int m, int k) {
-  return KC ? m * LDK + k : k * LDP + m;
+  return KC ? m * LDK + k : k * ldp<TM>() + m;
 }
 
 // Loads one BKK-deep slice into registers and writes it to LDS (FP64).  KC:
 // element (m, k) at base[m * ld + k]; otherwise at base[k * ld + m].
-template <typename T, bool KC>
+template <typename T, bool KC, int TM = BM>
 struct Stage {
   static constexpr int VEC = Vec16<T>::N;
-  static constexpr int PER = BM * BKK / VEC / NT;
+  static constexpr int PER = TM * BKK / VEC / NT;
+  static_assert(PER >= 1, "slice smaller than the workgroup");
   u32x4 r[PER];
 
   __device__ __forceinline__ void load(const T* base, int64_t ld, int64_t k0,
@@ -56,7 +65,7 @@ struct Stage {
         int m = idx / CPR, k = (idx % CPR) * VEC;
         p = base + (int64_t)m * ld + k0 + k;
       } else {
-        constexpr int CPR = BM / VEC;
+        constexpr int CPR = TM / VEC;
         int k = idx / CPR, m = (idx % CPR) * VEC;
         p = base + (k0 + k) * ld + m;
       }
@@ -77,60 +86,63 @@ struct Stage {
 #pragma unroll
         for (int e = 0; e < VEC; ++e) {
           double sc = scale ? scale[k0 + k + e] : 1.0;
-          s[lds_at<true>(m, k + e)] = x[e] * sc;
+          s[lds_at<true, TM>(m, k + e)] = x[e] * sc;
         }
       } else {
-        constexpr int CPR = BM / VEC;
+        constexpr int CPR = TM / VEC;
         int k = idx / CPR, m = (idx % CPR) * VEC;
         double sc = scale ? scale[k0 + k] : 1.0;
 #pragma unroll
-        for (int e = 0; e < VEC; ++e) s[lds_at<false>(m + e, k)] = x[e] * sc;
+        for (int e = 0; e < VEC; ++e) s[lds_at<false, TM>(m + e, k)] = x[e] * sc;
       }
     }
   }
 };
 
-template <bool AKC, bool BKC>
+template <bool AKC, bool BKC, int TM, int TN>
 __device__ __forceinline__ void mma_slice(const double* sA, const double* sB,
-                                          f64x4 (&acc)[4][4], int wm, int wn,
-                                          int lane) {
+                                          f64x4 (&acc)[TM / 32][TN / 32],
+                                          int wm, int wn, int lane) {
+  constexpr int MB = TM / 32, NB = TN / 32;   // 16 x 16 blocks per wave
 #pragma unroll
   for (int kk = 0; kk < BKK; kk += 4) {
     const int kr = kk + (lane >> 4), c = lane & 15;
-    double a[4], b[4];
+    double a[MB], b[NB];
 #pragma unroll
-    for (int i = 0; i < 4; ++i) {
-      a[i] = sA[lds_at<AKC>(wm + i * 16 + c, kr)];
-      b[i] = sB[lds_at<BKC>(wn + i * 16 + c, kr)];
-    }
+    for (int i = 0; i < MB; ++i) a[i] = sA[lds_at<AKC, TM>(wm + i * 16 + c, kr)];
 #pragma unroll
-    for (int i = 0; i < 4; ++i)
+    for (int j = 0; j < NB; ++j) b[j] = sB[lds_at<BKC, TN>(wn + j * 16 + c, kr)];
 #pragma unroll
-      for (int j = 0; j < 4; ++j)
+    for (int i = 0; i < MB; ++i)
+#pragma unroll
+      for (int j = 0; j < NB; ++j)
         acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[i], b[j],
                                                          acc[i][j], 0, 0, 0);
   }
 }
 
-// acc (this wave's 64 x 64 block) = sum_{k in [kbeg, kend)} opA(m,k) opB(k,n),
+// acc (this wave's TM/2 x TM/2 block) = sum_{k in [kbeg, kend)} opA(m,k) opB(k,n),
 // opB optionally scaled by bscale[k].  kend - kbeg must be a multiple of BKK.
 // sA, sB hold two k-slices each (double buffer): slice s is computed from
 // buffer s % 2 while slice s + 1 waits in registers and slice s + 2 is in
 // flight from memory; one barrier per slice.
-template <typename TA, bool AKC, typename TB, bool BKC>
+template <typename TA, bool AKC, typename TB, bool BKC, int TM = BM,
+          int TN = TM>
 __device__ void gemm_core(const TA* Ab, int64_t lda, const TB* Bb,
                           int64_t ldb, const double* bscale, int64_t kbeg,
-                          int64_t kend, f64x4 (&acc)[4][4], double* sA,
-                          double* sB) {
+                          int64_t kend, f64x4 (&acc)[TM / 32][TN / 32],
+                          double* sA, double* sB) {
+  constexpr int MB = TM / 32, NB = TN / 32;
+  constexpr int STA = stage_size<TM>(), STB = stage_size<TN>();
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
-  const int wm = (w >> 1) * 64, wn = (w & 1) * 64;
+  const int wm = (w >> 1) * (TM / 2), wn = (w & 1) * (TN / 2);
 #pragma unroll
-  for (int i = 0; i < 4; ++i)
+  for (int i = 0; i < MB; ++i)
 #pragma unroll
-    for (int j = 0; j < 4; ++j) acc[i][j] = f64x4{0.0, 0.0, 0.0, 0.0};
+    for (int j = 0; j < NB; ++j) acc[i][j] = f64x4{0.0, 0.0, 0.0, 0.0};
   if (kbeg >= kend) return;
-  Stage<TA, AKC> sa;
-  Stage<TB, BKC> sb;
+  Stage<TA, AKC, TM> sa;
+  Stage<TB, BKC, TN> sb;
   sa.load(Ab, lda, kbeg, tid);
   sb.load(Bb, ldb, kbeg, tid);
   sa.store(sA, tid, nullptr, kbeg);
@@ -142,11 +154,11 @@ __device__ void gemm_core(const TA* Ab, int64_t lda, const TB* Bb,
   __syncthreads();
   int buf = 0;
   for (int64_t k0 = kbeg; k0 < kend; k0 += BKK) {
-    mma_slice<AKC, BKC>(sA + buf * kStage, sB + buf * kStage, acc, wm, wn,
-                        lane);
+    mma_slice<AKC, BKC, TM, TN>(sA + buf * STA, sB + buf * STB, acc, wm, wn,
+                                lane);
     if (k0 + BKK < kend) {
-      sa.store(sA + (buf ^ 1) * kStage, tid, nullptr, k0 + BKK);
-      sb.store(sB + (buf ^ 1) * kStage, tid, bscale, k0 + BKK);
+      sa.store(sA + (buf ^ 1) * STA, tid, nullptr, k0 + BKK);
+      sb.store(sB + (buf ^ 1) * STB, tid, bscale, k0 + BKK);
       if (k0 + 2 * BKK < kend) {
         sa.load(Ab, lda, k0 + 2 * BKK, tid);
         sb.load(Bb, ldb, k0 + 2 * BKK, tid);
@@ -157,17 +169,19 @@ __device__ void gemm_core(const TA* Ab, int64_t lda, const TB* Bb,
   }
 }
 
-// Visit this wave's accumulator entries as (row, col) inside the 128 x 128
+// Visit this wave's accumulator entries as (row, col) inside the TM x TN
 // tile: D[row][col] of 16x16x4 f64 MFMA block (i, j) is held by lane l in
 // register r with row = l / 16 + 4 r and col = l % 16 (gfx950 layout).
-template <class F>
-__device__ __forceinline__ void for_each_acc(const f64x4 (&acc)[4][4], F f) {
+template <int TM = BM, int TN = TM, class F>
+__device__ __forceinline__ void for_each_acc(
+    const f64x4 (&acc)[TM / 32][TN / 32], F f) {
+  constexpr int MB = TM / 32, NB = TN / 32;
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
-  const int wm = (w >> 1) * 64, wn = (w & 1) * 64;
+  const int wm = (w >> 1) * (TM / 2), wn = (w & 1) * (TN / 2);
 #pragma unroll
-  for (int i = 0; i < 4; ++i)
+  for (int i = 0; i < MB; ++i)
 #pragma unroll
-    for (int j = 0; j < 4; ++j)
+    for (int j = 0; j < NB; ++j)
 #pragma unroll
       for (int r = 0; r < 4; ++r)
         f(wm + i * 16 + (lane >> 4) + 4 * r, wn + j * 16 + (lane & 15),
@@ -495,66 +509,99 @@ __global__ void __launch_bounds__(DT) diag_block_kernel(double* M, double* X,
   }
 }
 
-// Step k after the diagonal block, first launch (both need only L_kk^-1):
-//   blocks [0, rem):        L[I, k] = M[I, k] L_kk^-T, I = k + 1 + b (in place)
-//   blocks [rem, rem + k):  X[k, j] = -L_kk^-1 S[k, j], j = b - rem, where S
-//                           accumulated sum_{m<k} L[k, m] X[m, j] in place.
-__global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2, 2))) panel_finalize_kernel(double* M,
-                                                            double* X,
-                                                            int64_t ld, int k,
-                                                            int rem,
-                                                            const int* skip) {
+// Step k after the diagonal block, first launch (both need only L_kk^-1),
+// each 128 x 128 tile split in two 64-wide halves on separate workgroups:
+//   tiles [0, rem):        L[I, k] = M[I, k] L_kk^-T, I = k + 1 + b, in place;
+//                          a half is a band of 64 rows, which depends only on
+//                          the same rows of M[I, k];
+//   tiles [rem, rem + k):  X[k, j] = -L_kk^-1 S[k, j], j = b - rem, where S
+//                          accumulated sum_{m<k} L[k, m] X[m, j] in place; a
+//                          half is a band of 64 columns, which depends only
+//                          on the same columns of S[k, j].
+__global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2, 2)))
+panel_finalize_kernel(double* M, double* X, int64_t ld, int k, int rem,
+                      const int* skip) {
   if (skip && *skip) return;
-  __shared__ double sA[2 * kStage], sB[2 * kStage];
+  constexpr int H = BM / 2;
+  __shared__ double sA[2 * stage_size<BM>()], sB[2 * stage_size<BM>()];
+  const int b = blockIdx.x >> 1, half = (blockIdx.x & 1) * H;
   const double* Xkk = X + (int64_t)k * BM * ld + (int64_t)k * BM;
-  f64x4 acc[4][4];
-  if ((int)blockIdx.x < rem) {
-    const int I = k + 1 + blockIdx.x;
-    double* Mik = M + (int64_t)I * BM * ld + (int64_t)k * BM;
-    gemm_core<double, true, double, true>(Mik, ld, Xkk, ld, nullptr, 0, BM,
-                                          acc, sA, sB);
-    for_each_acc(acc, [&](int r, int c, double v) { Mik[(int64_t)r * ld + c] = v; });
+  if (b < rem) {
+    const int I = k + 1 + b;
+    double* Mik = M + (int64_t)I * BM * ld + (int64_t)k * BM + (int64_t)half * ld;
+    f64x4 acc[H / 32][BM / 32];
+    gemm_core<double, true, double, true, H, BM>(Mik, ld, Xkk, ld, nullptr, 0,
+                                                 BM, acc, sA, sB);
+    for_each_acc<H, BM>(acc, [&](int r, int c, double v) {
+      Mik[(int64_t)r * ld + c] = v;
+    });
   } else {
-    const int j = blockIdx.x - rem;
-    double* Skj = X + (int64_t)k * BM * ld + (int64_t)j * BM;
-    gemm_core<double, true, double, false>(Xkk, ld, Skj, ld, nullptr, 0, BM,
-                                           acc, sA, sB);
-    for_each_acc(acc, [&](int r, int c, double v) { Skj[(int64_t)r * ld + c] = -v; });
+    const int j = b - rem;
+    double* Skj = X + (int64_t)k * BM * ld + (int64_t)j * BM + half;
+    f64x4 acc[BM / 32][H / 32];
+    gemm_core<double, true, double, false, BM, H>(Xkk, ld, Skj, ld, nullptr, 0,
+                                                  BM, acc, sA, sB);
+    for_each_acc<BM, H>(acc, [&](int r, int c, double v) {
+      Skj[(int64_t)r * ld + c] = -v;
+    });
   }
 }
 
-// Step k, second launch (needs the panel L[:, k] and the row X[k, :]):
-//   blocks [0, nu):       M[I, J] -= L[I, k] L[J, k]^T, k < J <= I
-//   blocks [nu, nu + ni): S[i, j] += L[i, k] X[k, j],   i > k, j <= k
-// with nu = rem (rem + 1) / 2 and ni = rem (k + 1).  The two sets touch
-// disjoint tiles (J > k versus j <= k).
-__global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2, 2))) update_kernel(double* M, double* X,
-                                                    int64_t ld, int k, int nu,
-                                                    const int* skip) {
+// Tile sub-blocks for the update: a 128 x 128 tile is computed as
+// (128 / TM)^2 sub-blocks of TM x TM by separate workgroups.  Safe because
+// an update reads only panel tiles it does not write.
+template <int TM>
+__device__ __forceinline__ void sub_block(int b, int* tile, int* so, int* sc) {
+  constexpr int Q = BM / TM;
+  *tile = b / (Q * Q);
+  *so = (b / Q) % Q * TM;
+  *sc = b % Q * TM;
+}
+
+// Trailing update from the panel columns [kA, kB) (tile units), in one
+// launch (needs those panels L[:, kA..kB) and rows X[kA..kB, :]):
+//   tiles [0, nu):        M[I, J] -= sum_{k in [kA, kB)} L[I, k] L[J, k]^T
+//                         for J in [jlo, jhi), J <= I < nt;
+//   tiles [nu, nu + ni):  S[i, j] += sum_{k in [max(kA, j), kB)} L[i, k] X[k, j]
+//                         for i in [ilo, ihi), j < kB (X[k, j] = 0 for k < j).
+// The two sets touch disjoint tiles (columns J >= kB versus j < kB).
+template <int TM>
+__global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2, 2)))
+update_kernel(double* M, double* X, int64_t ld, int nt, int kA, int kB,
+              int jlo, int jhi, int ilo, int nu, const int* skip) {
   if (skip && *skip) return;
-  __shared__ double sA[2 * kStage], sB[2 * kStage];
-  f64x4 acc[4][4];
-  if ((int)blockIdx.x < nu) {
-    int I, J;
-    lower_tile(blockIdx.x, &I, &J);
-    I += k + 1;
-    J += k + 1;
-    const double* Lik = M + (int64_t)I * BM * ld + (int64_t)k * BM;
-    const double* Ljk = M + (int64_t)J * BM * ld + (int64_t)k * BM;
-    gemm_core<double, true, double, true>(Lik, ld, Ljk, ld, nullptr, 0, BM,
-                                          acc, sA, sB);
+  __shared__ double sA[2 * stage_size<TM>()], sB[2 * stage_size<TM>()];
+  int b, so, sc;
+  sub_block<TM>(blockIdx.x, &b, &so, &sc);
+  f64x4 acc[TM / 32][TM / 32];
+  if (b < nu) {
+    int J = jlo;
+    while (J < jhi && b >= nt - J) {   // column J holds tiles I = J .. nt-1
+      b -= nt - J;
+      ++J;
+    }
+    const int I = J + b;
+    const double* Li = M + (int64_t)I * BM * ld + (int64_t)so * ld;
+    const double* Lj = M + (int64_t)J * BM * ld + (int64_t)sc * ld;
+    gemm_core<double, true, double, true, TM>(Li, ld, Lj, ld, nullptr,
+                                              (int64_t)kA * BM,
+                                              (int64_t)kB * BM, acc, sA, sB);
     double* Mij = M + (int64_t)I * BM * ld + (int64_t)J * BM;
-    for_each_acc(acc, [&](int r, int c, double v) { Mij[(int64_t)r * ld + c] -= v; });
+    for_each_acc<TM>(acc, [&](int r, int c, double v) {
+      Mij[(int64_t)(so + r) * ld + sc + c] -= v;
+    });
   } else {
-    const int b = blockIdx.x - nu;
-    const int i = k + 1 + b / (k + 1);
-    const int j = b % (k + 1);
-    const double* Lik = M + (int64_t)i * BM * ld + (int64_t)k * BM;
-    const double* Xkj = X + (int64_t)k * BM * ld + (int64_t)j * BM;
-    gemm_core<double, true, double, false>(Lik, ld, Xkj, ld, nullptr, 0, BM,
-                                           acc, sA, sB);
+    b -= nu;
+    const int i = ilo + b / kB, j = b % kB;
+    const int k0 = j > kA ? j : kA;
+    const double* Li = M + (int64_t)i * BM * ld + (int64_t)so * ld;
+    gemm_core<double, true, double, false, TM>(Li, ld, X + (int64_t)j * BM + sc,
+                                               ld, nullptr, (int64_t)k0 * BM,
+                                               (int64_t)kB * BM, acc, sA, sB);
     double* Sij = X + (int64_t)i * BM * ld + (int64_t)j * BM;
-    for_each_acc(acc, [&](int r, int c, double v) { Sij[(int64_t)r * ld + c] += v; });
+    for_each_acc<TM>(acc, [&](int r, int c, double v) {
+      Sij[(int64_t)(so + r) * ld + sc + c] += v;
+    });
   }
 }
 
@@ -649,24 +696,46 @@ hipError_t prepare_dense_kernels() {
   return hipSuccess;
 }
 
+// Blocked Cholesky M = L L^T with the inverse X = L^-1, two levels: steps of
+// one 128-column block inside groups of kGroup blocks.  Inside a group each
+// step updates only the group's remaining columns and inverse rows; one
+// update per group with a kGroup * 128 deep reduction then brings every
+// later column and inverse row up to date, so the trailing matrix is read
+// and written once per group instead of once per step.
+constexpr int kGroup = 4;
+
 hipError_t launch_potrf_trtri(double* M, double* X, int64_t np, int* fail,
                               hipStream_t st, const int* skip) {
   const int nt = (int)(np / BM);
   const size_t lds = kDiagLds;
   hipError_t pe = prepare_dense_kernels();
   if (pe != hipSuccess) return pe;
-  for (int k = 0; k < nt; ++k) {
-    hipLaunchKernelGGL(diag_block_kernel, dim3(1), dim3(DT), lds, st, M, X,
-                       np, k, fail, skip);
-    const int rem = nt - k - 1;
-    if (rem + k > 0)
-      hipLaunchKernelGGL(panel_finalize_kernel, dim3(rem + k), dim3(NT), 0, st,
-                         M, X, np, k, rem, skip);
-    if (rem > 0) {
-      const int nu = rem * (rem + 1) / 2, ni = rem * (k + 1);
-      hipLaunchKernelGGL(update_kernel, dim3(nu + ni), dim3(NT), 0, st, M, X,
-                         np, k, nu, skip);
+  constexpr int Q64 = (BM / 64) * (BM / 64);   // 64 x 64 sub-blocks per tile
+  auto update = [&](int kA, int kB, int jlo, int jhi, int ilo, int ihi,
+                    bool small) {
+    int nu = 0;
+    for (int J = jlo; J < jhi; ++J) nu += nt - J;
+    const int ni = (ihi - ilo) * kB;
+    if (nu + ni == 0) return;
+    if (small)
+      hipLaunchKernelGGL(update_kernel<64>, dim3((nu + ni) * Q64), dim3(NT), 0,
+                         st, M, X, np, nt, kA, kB, jlo, jhi, ilo, nu, skip);
+    else
+      hipLaunchKernelGGL(update_kernel<BM>, dim3(nu + ni), dim3(NT), 0, st, M,
+                         X, np, nt, kA, kB, jlo, jhi, ilo, nu, skip);
+  };
+  for (int g0 = 0; g0 < nt; g0 += kGroup) {
+    const int g1 = g0 + kGroup < nt ? g0 + kGroup : nt;
+    for (int k = g0; k < g1; ++k) {
+      hipLaunchKernelGGL(diag_block_kernel, dim3(1), dim3(DT), lds, st, M, X,
+                         np, k, fail, skip);
+      const int rem = nt - k - 1;
+      if (rem + k > 0)
+        hipLaunchKernelGGL(panel_finalize_kernel, dim3((rem + k) * 2),
+                           dim3(NT), 0, st, M, X, np, k, rem, skip);
+      if (k + 1 < g1) update(k, k + 1, k + 1, g1, k + 1, g1, true);
     }
+    if (g1 < nt) update(g0, g1, g1, nt, g1, nt, false);
   }
   return hipGetLastError();
 }
