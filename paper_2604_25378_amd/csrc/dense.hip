@@ -271,14 +271,14 @@ trace_gemm_kernel(const S* __restrict__ A, int64_t lda, int64_t Tp,
 // included); the strictly lower part of X stored transposed in the strict
 // upper triangle (X[i][j], i > j, at row j, column i); 1/L_ii in rdiag.
 //
-// Factorisation: right-looking in 32-column steps.  Wave 0 factors the
-// 32 x 32 diagonal sub-block in registers (lane r holds row r; column values
-// move by lane shuffles) and inverts it by forward substitution (lane c
-// solves for column c).  The sub-panel below, L21 = A21 X11^T, and the
-// trailing update A22 -= L21 L21^T run on the FP64 matrix cores.
-// Inverse: recursive doubling, X21 = -X22 (L21 X11), first for the two
-// 64 x 64 halves (32-row blocks), then for the whole block (64-row blocks),
-// again on the matrix cores.
+// Factorisation: right-looking in 16-column steps.  Wave 0 factors and
+// inverts each 16 x 16 diagonal leaf in registers (lane r holds row r; values
+// move by readlane broadcasts).  The sub-panel below, L21 = A21 X11^T, and
+// the trailing update A22 -= L21 L21^T run on the FP64 matrix cores; wave 0
+// updates the next leaf first and factors it while the other waves finish
+// the trailing update.
+// Inverse: recursive doubling, X21 = -X22 (L21 X11), for half sizes 16, 32
+// and 64, again on the matrix cores.
 constexpr int DT = 512;      // threads of the diagonal-block kernel
 constexpr int SB = 16;       // leaf width
 constexpr int LDD = BM + 1;  // padded LDS row
@@ -297,6 +297,7 @@ __device__ __forceinline__ f64x4 mfma_block(FA fa, FB fb, int r0, int c0,
                                             int kb, int ke, int lane) {
   f64x4 acc = {0.0, 0.0, 0.0, 0.0};
   const int lr = lane & 15, lk = lane >> 4;
+#pragma unroll 4
   for (int k = kb; k < ke; k += 4)
     acc = __builtin_amdgcn_mfma_f64_16x16x4f64(fa(r0 + lr, k + lk),
                                                fb(k + lk, c0 + lr), acc, 0, 0,
@@ -412,11 +413,13 @@ __global__ void __launch_bounds__(DT) diag_block_kernel(double* M, double* X,
   }
   __syncthreads();
   // ---- factorisation --------------------------------------------------------
-  for (int c0 = 0; c0 < BM; c0 += SB) {
-    if (wave == 0) leaf_chol_inv(S, rd, c0, lane, fail);
-    __syncthreads();
+  // Step c0: the sub-panel below leaf c0, then the trailing update.  Wave 0
+  // updates the next leaf's diagonal block first and factors it while the
+  // other waves finish the trailing update (disjoint blocks).
+  if (wave == 0) leaf_chol_inv(S, rd, 0, lane, fail);
+  __syncthreads();
+  for (int c0 = 0; c0 + SB < BM; c0 += SB) {
     const int r0 = c0 + SB, rem = BM - r0;
-    if (rem == 0) break;
     const int nb = rem / 16;
     // L21 = A21 X11^T: nb x (SB / 16) blocks, at most 2 per wave, stored
     // after all waves have read A21
@@ -443,20 +446,25 @@ __global__ void __launch_bounds__(DT) diag_block_kernel(double* M, double* X,
       }
     }
     __syncthreads();
-    // A22 -= L21 L21^T on the lower blocks
-    {
-      auto Lt = [&](int m, int c) { return S[c * LDD + m]; };  // L21^T
-      for (int b = wave; b < nb * (nb + 1) / 2; b += NW) {
-        int bi = 0;
-        while ((bi + 1) * (bi + 2) / 2 <= b) ++bi;
-        const int bj = b - bi * (bi + 1) / 2;
-        const f64x4 v =
-            mfma_block(Lv, Lt, r0 + 16 * bi, r0 + 16 * bj, c0, c0 + SB, lane);
+    // A22 -= L21 L21^T on the lower blocks; block 0 is the next leaf's
+    auto Lt = [&](int m, int c) { return S[c * LDD + m]; };  // L21^T
+    auto trail = [&](int b) {
+      int bi = 0;
+      while ((bi + 1) * (bi + 2) / 2 <= b) ++bi;
+      const int bj = b - bi * (bi + 1) / 2;
+      const f64x4 v =
+          mfma_block(Lv, Lt, r0 + 16 * bi, r0 + 16 * bj, c0, c0 + SB, lane);
 #pragma unroll
-        for (int q = 0; q < 4; ++q)
-          S[(r0 + 16 * bi + (lane >> 4) + 4 * q) * LDD + r0 + 16 * bj +
-            (lane & 15)] -= v[q];
-      }
+      for (int q = 0; q < 4; ++q)
+        S[(r0 + 16 * bi + (lane >> 4) + 4 * q) * LDD + r0 + 16 * bj +
+          (lane & 15)] -= v[q];
+    };
+    if (wave == 0) {
+      trail(0);
+      wave_sync();
+      leaf_chol_inv(S, rd, r0, lane, fail);
+    } else {
+      for (int b = wave; b < nb * (nb + 1) / 2; b += NW - 1) trail(b);
     }
     __syncthreads();
   }
@@ -502,9 +510,12 @@ __global__ void __launch_bounds__(DT) diag_block_kernel(double* M, double* X,
     }
     __syncthreads();
   }
+  // L_kk: lower triangle only (the upper part of M's diagonal tiles is never
+  // read again); X_kk with explicit zeros above the diagonal, which the
+  // panel, finalize and update products read as part of the full tile.
   for (int idx = tid; idx < BM * BM; idx += DT) {
     const int i = idx / BM, c = idx % BM;
-    Mk[(int64_t)i * ld + c] = c <= i ? S[i * LDD + c] : 0.0;
+    if (c <= i) Mk[(int64_t)i * ld + c] = S[i * LDD + c];
     Xk[(int64_t)i * ld + c] = c <= i ? Xv(i, c) : 0.0;
   }
 }
