@@ -78,7 +78,8 @@ def _conv(infos):
     return sum(1 for i in infos if i.status == 0 and i.gnorm <= 1e-8)
 
 
-def frontier_bench(workload, n_targets, n_plain, precision="fp64"):
+def frontier_bench(workload, n_targets, n_plain, precision="fp64",
+                   autotune=True):
     """Frontier solves/s: batched (one call, lanes advancing together with
     graph-replayed iterations) vs plain single-instance solves of the same
     instances, at ||reduced gradient|| <= 1e-8."""
@@ -95,6 +96,8 @@ def frontier_bench(workload, n_targets, n_plain, precision="fp64"):
                    for _ in targets])
     tg = np.tile(targets, 4)
     ctx = yb.Context(torch.from_numpy(R).cuda(), precision)
+    if autotune:
+        ctx.autotune()
     ctx.frontier(C4[:2], tg[:2])            # warm-up (graph path, allocations)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -121,7 +124,7 @@ def frontier_bench(workload, n_targets, n_plain, precision="fp64"):
             "plain_iterations_mean": float(np.mean(plain_its))}
 
 
-def ragged_bench(count=32, T=6000, precision="fp64"):
+def ragged_bench(count=32, T=6000, precision="fp64", autotune=True):
     """32 independent universes with n uniform in [100, 1500]: one batched
     call over all contexts vs plain single solves, budget set."""
     import torch
@@ -134,6 +137,9 @@ def ragged_bench(count=32, T=6000, precision="fp64"):
     ctxs = [yb.Context(torch.from_numpy(
         synth.factor_returns(int(m), T, 10, 0, 4.0, 0.0, 2000 + i)).cuda(),
         precision) for i, m in enumerate(sizes)]
+    if autotune:
+        for cx in ctxs:
+            cx.autotune()
     C4 = np.tile(np.array([1.0, 5.0, 2.0, 10.0]), (count, 1))
     yb.batch_solve(ctxs[:2], C4[:2])        # warm-up
     torch.cuda.synchronize()
@@ -161,7 +167,7 @@ def ragged_bench(count=32, T=6000, precision="fp64"):
 
 
 def warmstart_bench(workload, n_train_targets=16, n_points=256, n_plain=16,
-                    precision="fp64"):
+                    precision="fp64", autotune=True):
     """Frontier sweep at full scale: batched + MLP-warm-started solves vs
     batched plain-start solves vs plain single-instance solves of the same
     n_points instances, all to ||reduced gradient|| <= 1e-8.
@@ -179,6 +185,8 @@ def warmstart_bench(workload, n_train_targets=16, n_points=256, n_plain=16,
     R = synth.workload_returns(workload)
     T, n = R.shape
     ctx = yb.Context(torch.from_numpy(R).cuda(), precision)
+    if autotune:
+        ctx.autotune()
 
     def grid(gammas, k):
         tt = synth.frontier_targets(R, k)
@@ -302,6 +310,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-frontier", action="store_true")
     ap.add_argument("--frontier-points", type=int, default=256)
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="keep the built-in launch shapes")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="end with one 1 GiB device copy (PMC scale reference)")
     args = ap.parse_args()
@@ -324,6 +334,7 @@ def main():
     ctx = yb.Context(Rd, args.precision)
     del Rd
     torch.cuda.synchronize()
+    tuned = None if args.no_autotune else ctx.autotune()
     opts = yb.default_opts(max_iter=1, eps=0.0)
     w = torch.full((n,), 1.0 / n, dtype=torch.float64, device="cuda")
 
@@ -417,6 +428,7 @@ def main():
                                "budget set, direct exact-trace solve",
                    "precision": args.precision},
         "roofline": roof,
+        "autotune": tuned,
         "pass_gbps": {k: v.get("gbps") for k, v in kernels.items() if "gbps" in v},
         "hvp_pass_frac_hbm": hv.get("frac_hbm") if hv else None,
         "frontier_solves_per_s": None,
@@ -426,12 +438,13 @@ def main():
     ctx.close()
     del ctx
     if not args.no_frontier:
+        tune = not args.no_autotune
         fr = {"n1000_T12000": frontier_bench("n1000_T12000_frontier", 16, 8,
-                                             args.precision),
-              "ragged_T6000": ragged_bench(32, 6000, args.precision),
+                                             args.precision, tune),
+              "ragged_T6000": ragged_bench(32, 6000, args.precision, tune),
               "n5440_T12000": warmstart_bench(args.workload, 16,
                                               args.frontier_points, 16,
-                                              args.precision)}
+                                              args.precision, tune)}
         out["frontier"] = fr
         out["frontier_solves_per_s"] = fr["n5440_T12000"]["warm_batched_solves_per_s"]
     if not args.no_cpu:

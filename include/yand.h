@@ -189,6 +189,23 @@ int yand_profile_enable(yand_ctx* ctx, int enable);
 int yand_profile_read(yand_ctx* ctx, int index, char* name, int name_len,
                       double* total_ms, int64_t* count);
 
+/* Launch-shape autotuner (an extension for serving).  Times candidate
+ * launch shapes on this context's own A at equal weights with c = (1,5,2,10):
+ * workgroups per streaming pass (256, 384, 512, 768 or 1024, i.e. rows per
+ * workgroup) for each pass kind, and the number of 128-column blocks per
+ * group of the two-level Cholesky (2, 4 or 8).  The fastest are kept in the
+ * context and used by every later call on it (and by batched solves over
+ * it).  Results change only in rounding order.  report (host, nullable, 14
+ * doubles): chosen workgroups for the oracle, value, HVP, line-search, dot
+ * and third-order passes, the chosen group size, then the best mean times
+ * in ms in the same order.  Overwrites the context's scratch state. */
+int yand_autotune(yand_ctx* ctx, double* report);
+
+/* Read (get, host, 7 ints, nullable) and/or set (set, host, 7 ints,
+ * nullable) the launch shapes: six workgroup counts in the order above and
+ * the group size; 0 selects the built-in default. */
+int yand_tuning(yand_ctx* ctx, const int* set, int* get);
+
 /* Stateless wrapper: returns R (device, T x n contiguous) -> w_out (device),
  * FP64 storage, direct solver, budget set. */
 int yand_mvsk_solve_R(const double* R, int64_t T, int64_t n, double c1,

@@ -123,6 +123,8 @@ def load(path: str = LIB_PATH):
         "yand_warmstart_predict": (C.c_int, [vp, vp, C.c_int64, _D, _D, vp,
                                              C.POINTER(C.c_int), _D]),
         "yand_profile_enable": (C.c_int, [vp, C.c_int]),
+        "yand_autotune": (C.c_int, [vp, _D]),
+        "yand_tuning": (C.c_int, [vp, C.POINTER(C.c_int), C.POINTER(C.c_int)]),
         "yand_profile_read": (C.c_int, [vp, C.c_int, C.c_char_p, C.c_int, _D,
                                         C.POINTER(C.c_int64)]),
     }
@@ -336,6 +338,28 @@ class Context:
         _check(rc, "yand_frontier_solve", warn_ok=True)
         return W, [SolveInfo(**{k: getattr(i, k) for k, _ in yand_info._fields_})
                    for i in infos]
+
+    PASS_KINDS = ("oracle", "value", "hvp", "line", "dot", "third")
+
+    def autotune(self):
+        """Time candidate launch shapes on this context and keep the fastest.
+
+        Returns {"pass_groups": {kind: workgroups}, "chol_group": blocks,
+        "ms": {kind or "potrf_trtri": best mean ms}}."""
+        rep = (C.c_double * 14)()
+        _check(self._lib.yand_autotune(self._h, rep), "yand_autotune")
+        r = list(rep)
+        return {"pass_groups": {k: int(r[i]) for i, k in enumerate(self.PASS_KINDS)},
+                "chol_group": int(r[6]),
+                "ms": {**{k: r[7 + i] for i, k in enumerate(self.PASS_KINDS)},
+                       "potrf_trtri": r[13]}}
+
+    def tuning(self, set=None):
+        """Current launch shapes (7 ints; 0 = default); optionally set them."""
+        get = (C.c_int * 7)()
+        sv = (C.c_int * 7)(*[int(v) for v in set]) if set is not None else None
+        _check(self._lib.yand_tuning(self._h, sv, get), "yand_tuning")
+        return list(get)
 
     def profile(self, enable: bool = True):
         _check(self._lib.yand_profile_enable(self._h, int(enable)),

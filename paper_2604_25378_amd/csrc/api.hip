@@ -52,6 +52,9 @@ struct Data {
   double* AEfix = nullptr;  // 2 x Tp: A e1, A e2
   bool have_e2 = false;
   double mbar = 0.0, mnorm = 0.0;  // mean of mu and |mu - mbar|
+  // launch shapes chosen by yand_autotune (0: built-in defaults)
+  int pass_groups[6] = {0, 0, 0, 0, 0, 0};  // per PassKind
+  int chol_group = 0;
 };
 
 struct Work {
@@ -242,8 +245,10 @@ PassArgs pass_args(const Data& D, const Work& w, const double c[4]) {
 
 int run_pass(const Data& D, Work& w, PassKind kind, const PassArgs& a,
              int* nwg, const char* name) {
+  PassArgs b = a;
+  b.groups = D.pass_groups[(int)kind];
   HIPTRY(timed(w, name, [&] {
-    return launch_pass(D.precision, kind, a, w.st, nwg);
+    return launch_pass(D.precision, kind, b, w.st, nwg);
   }));
   return YAND_OK;
 }
@@ -357,7 +362,8 @@ int dir_factor(const Data& D, Work& w, int p0, const int* skip) {
   HIPTRY(launch_project(w.B, w.M, np, n, np, w.E, w.W, p0 + 1, w.sc, w.st));
   HIPTRY(launch_fill(w.X, np * np, 0.0, w.st, skip));
   HIPTRY(timed(w, "potrf_trtri", [&] {
-    return launch_potrf_trtri(w.M, w.X, np, &w.sc->fail, w.st, skip);
+    return launch_potrf_trtri(w.M, w.X, np, &w.sc->fail, w.st, skip,
+                              D.chol_group);
   }));
   return YAND_OK;
 }
@@ -1610,6 +1616,121 @@ int yand_mvsk_solve_R(const double* R, int64_t T, int64_t n, double c1,
   rc = yand_mvsk_solve(ctx, c, target, nullptr, nullptr, w_out, nullptr);
   yand_destroy(ctx);
   return rc;
+}
+
+// ----------------------------------------------------------- autotuner --
+
+int yand_autotune(yand_ctx* ctx, double* report) {
+  if (!ctx) return YAND_ERR_ARG;
+  Data& D = ctx->d;
+  Work& w = ctx->w;
+  const hipStream_t st = w.st;
+  const double c[4] = {1.0, 5.0, 2.0, 10.0};
+  int p0 = 1;
+  TRY(setup_lane(D, w, nullptr, nullptr, &p0));
+  TRY(oracle_at(D, w, c, w.x, true));
+  HIPTRY(launch_grad_project(w.g, w.E, p0, D.n, w.sc, st, -1.0));
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  HIPTRY(hipEventCreate(&e0));
+  HIPTRY(hipEventCreate(&e1));
+  struct Ev {
+    hipEvent_t a, b;
+    ~Ev() {
+      (void)hipEventDestroy(a);
+      (void)hipEventDestroy(b);
+    }
+  } guard{e0, e1};
+  // mean milliseconds of reps calls of fn on st, after one warm-up call
+  auto time_ms = [&](auto&& fn, int reps, double* ms) -> int {
+    HIPTRY(fn());
+    HIPTRY(hipEventRecord(e0, st));
+    for (int r = 0; r < reps; ++r) HIPTRY(fn());
+    HIPTRY(hipEventRecord(e1, st));
+    HIPTRY(hipEventSynchronize(e1));
+    float t = 0.f;
+    HIPTRY(hipEventElapsedTime(&t, e0, e1));
+    *ms = (double)t / reps;
+    return YAND_OK;
+  };
+  // workgroups per pass: a band of rows per workgroup; more groups hide
+  // more latency, fewer write fewer partial rows
+  static const int kCands[] = {256, 384, 512, 768, 1024};
+  static const PassKind kKinds[6] = {PassKind::Oracle, PassKind::Value,
+                                     PassKind::Hvp,    PassKind::Line,
+                                     PassKind::Dot,    PassKind::Third};
+  double best_ms[7];
+  for (int k = 0; k < 6; ++k) {
+    PassArgs a = pass_args(D, w, c);
+    a.v = w.x;
+    switch (kKinds[k]) {
+      case PassKind::Oracle:
+      case PassKind::Value: a.tout = w.z; break;
+      case PassKind::Hvp: a.zc = w.z; break;
+      case PassKind::Line: a.zc = w.z; a.tout = w.wv; break;
+      case PassKind::Dot: a.tout = w.wv; break;
+      case PassKind::Third: a.zc = w.z; a.q = w.q; break;
+    }
+    best_ms[k] = 1e30;
+    for (int g : kCands) {
+      a.groups = g;
+      int nwg = 0;
+      double ms = 0.0;
+      TRY(time_ms([&] { return launch_pass(D.precision, kKinds[k], a, st, &nwg); },
+                  5, &ms));
+      if (ms < best_ms[k]) {
+        best_ms[k] = ms;
+        D.pass_groups[k] = g;
+      }
+    }
+  }
+  // blocks per group of the two-level Cholesky: deeper group updates touch
+  // the trailing matrix less often, shallower groups shorten the steps
+  DirOpts o;
+  TRY(dir_front(D, w, c, p0, o, nullptr));
+  const int64_t n = D.n, np = D.lda;
+  best_ms[6] = 1e30;
+  for (int grp : {2, 4, 8}) {
+    double total = 0.0;
+    for (int rep = 0; rep < 2; ++rep) {
+      HIPTRY(launch_project(w.B, w.M, np, n, np, w.E, w.W, p0 + 1, w.sc, st));
+      HIPTRY(launch_fill(w.X, np * np, 0.0, st));
+      HIPTRY(hipEventRecord(e0, st));
+      HIPTRY(launch_potrf_trtri(w.M, w.X, np, &w.sc->fail, st, nullptr, grp));
+      HIPTRY(hipEventRecord(e1, st));
+      HIPTRY(hipEventSynchronize(e1));
+      float t = 0.f;
+      HIPTRY(hipEventElapsedTime(&t, e0, e1));
+      if (rep > 0) total += t;
+    }
+    if (total < best_ms[6]) {
+      best_ms[6] = total;
+      D.chol_group = grp;
+    }
+  }
+  HIPTRY(hipStreamSynchronize(st));
+  if (report) {
+    for (int k = 0; k < 6; ++k) report[k] = D.pass_groups[k];
+    report[6] = D.chol_group;
+    for (int k = 0; k < 7; ++k) report[7 + k] = best_ms[k];
+  }
+  return YAND_OK;
+}
+
+int yand_tuning(yand_ctx* ctx, const int* set, int* get) {
+  if (!ctx) return YAND_ERR_ARG;
+  Data& D = ctx->d;
+  if (set) {
+    for (int k = 0; k < 6; ++k)
+      if (set[k] < 0 || set[k] > kMaxPassGroups) return YAND_ERR_ARG;
+    if (set[6] < 0 || set[6] > 64) return YAND_ERR_ARG;
+    for (int k = 0; k < 6; ++k) D.pass_groups[k] = set[k];
+    D.chol_group = set[6];
+  }
+  if (get) {
+    for (int k = 0; k < 6; ++k) get[k] = D.pass_groups[k];
+    get[6] = D.chol_group;
+  }
+  return YAND_OK;
 }
 
 int yand_profile_enable(yand_ctx* ctx, int enable) {

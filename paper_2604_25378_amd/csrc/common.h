@@ -18,7 +18,7 @@ constexpr int kColPad = 128;
 // Pass kernels: one 512-thread workgroup per compute unit.
 constexpr int kPassThreads = 512;
 constexpr int kPassWaves = kPassThreads / 64;
-constexpr int kMaxPassGroups = 512;
+constexpr int kMaxPassGroups = 1024;
 
 inline int64_t round_up(int64_t a, int64_t b) { return (a + b - 1) / b * b; }
 

@@ -708,15 +708,17 @@ hipError_t prepare_dense_kernels() {
 }
 
 // Blocked Cholesky M = L L^T with the inverse X = L^-1, two levels: steps of
-// one 128-column block inside groups of kGroup blocks.  Inside a group each
-// step updates only the group's remaining columns and inverse rows; one
-// update per group with a kGroup * 128 deep reduction then brings every
+// one 128-column block inside groups of `group` blocks (4 unless tuned).
+// Inside a group each step updates only the group's remaining columns and
+// inverse rows; one update per group with a group * 128 deep reduction then
+// brings every
 // later column and inverse row up to date, so the trailing matrix is read
 // and written once per group instead of once per step.
-constexpr int kGroup = 4;
+constexpr int kDefaultGroup = 4;
 
 hipError_t launch_potrf_trtri(double* M, double* X, int64_t np, int* fail,
-                              hipStream_t st, const int* skip) {
+                              hipStream_t st, const int* skip, int group) {
+  const int kGroup = group > 0 ? group : kDefaultGroup;
   const int nt = (int)(np / BM);
   const size_t lds = kDiagLds;
   hipError_t pe = prepare_dense_kernels();

@@ -61,9 +61,10 @@ struct PassArgs {
   Coef c;
   double invT;
   const int* skip;      // nonzero: every workgroup returns at once
+  int groups;           // workgroups to launch (0: the shape's default)
 };
 
-int pass_groups(int64_t Tp, int R, int64_t* rows_per_wg);
+int pass_groups(int64_t Tp, int R, int groups, int64_t* rows_per_wg);
 int64_t max_pass_columns(int precision);
 hipError_t launch_pass(int precision, PassKind kind, const PassArgs& a,
                        hipStream_t st, int* nwg);
@@ -90,7 +91,8 @@ hipError_t launch_syrk(int precision, const void* A, int64_t lda, int64_t Tp,
 // kTile) and X = L^-1 (lower; X must be zero on entry).  *fail != 0 on exit
 // when a pivot was not positive.
 hipError_t launch_potrf_trtri(double* M, double* X, int64_t np, int* fail,
-                              hipStream_t st, const int* skip = nullptr);
+                              hipStream_t st, const int* skip = nullptr,
+                              int group = 0);
 // Sets the LDS attribute of the diagonal-block kernel (call before capture).
 hipError_t prepare_dense_kernels();
 // rn[J][t] = sum_{j in tile J} (sum_k A[t][k] X[j][k])^2  (X lower)

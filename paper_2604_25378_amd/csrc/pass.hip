@@ -437,7 +437,9 @@ static hipError_t launch_pass_t(PassKind kind, PassArgs a, hipStream_t st,
   if (nch < 1) nch = 1;
   if (nch > kMaxPassChunks) return hipErrorInvalidValue;
   // rows per workgroup: a multiple of every block height in use (R <= 8)
-  int nwg = pass_groups(a.Tp, 8, PassShape<S>::GROUPS, &a.rows_per_wg);
+  int groups = a.groups > 0 ? a.groups : PassShape<S>::GROUPS;
+  if (groups > kMaxPassGroups) groups = kMaxPassGroups;
+  int nwg = pass_groups(a.Tp, 8, groups, &a.rows_per_wg);
   *nwg_out = nwg;
   switch (kind) {
     case PassKind::Oracle: return launch_nch<S, OpOracle>(nch, a, nwg, st);

@@ -87,3 +87,8 @@ def test_mlp_entry_points_reject_bad_arguments_without_device(lib):
     assert out.value is None
     assert lib.yand_warmstart_predict(None, None, 1, None, None, None, None,
                                       None) == -1
+
+
+def test_autotune_rejects_null_context(lib):
+    assert lib.yand_autotune(None, None) == -1
+    assert lib.yand_tuning(None, None, None) == -1
