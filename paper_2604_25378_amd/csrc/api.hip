@@ -360,7 +360,6 @@ int dir_front(const Data& D, Work& w, const double c[4], int p0,
 int dir_factor(const Data& D, Work& w, int p0, const int* skip) {
   const int64_t n = D.n, np = D.lda;
   HIPTRY(launch_project(w.B, w.M, np, n, np, w.E, w.W, p0 + 1, w.sc, w.st));
-  HIPTRY(launch_fill(w.X, np * np, 0.0, w.st, skip));
   HIPTRY(timed(w, "potrf_trtri", [&] {
     return launch_potrf_trtri(w.M, w.X, np, &w.sc->fail, w.st, skip,
                               D.chol_group);
@@ -1693,7 +1692,6 @@ int yand_autotune(yand_ctx* ctx, double* report) {
     double total = 0.0;
     for (int rep = 0; rep < 2; ++rep) {
       HIPTRY(launch_project(w.B, w.M, np, n, np, w.E, w.W, p0 + 1, w.sc, st));
-      HIPTRY(launch_fill(w.X, np * np, 0.0, st));
       HIPTRY(hipEventRecord(e0, st));
       HIPTRY(launch_potrf_trtri(w.M, w.X, np, &w.sc->fail, st, nullptr, grp));
       HIPTRY(hipEventRecord(e1, st));

@@ -574,7 +574,9 @@ __device__ __forceinline__ void sub_block(int b, int* tile, int* so, int* sc) {
 //   tiles [0, nu):        M[I, J] -= sum_{k in [kA, kB)} L[I, k] L[J, k]^T
 //                         for J in [jlo, jhi), J <= I < nt;
 //   tiles [nu, nu + ni):  S[i, j] += sum_{k in [max(kA, j), kB)} L[i, k] X[k, j]
-//                         for i in [ilo, ihi), j < kB (X[k, j] = 0 for k < j).
+//                         for i in [ilo, ihi), j < kB (X[k, j] = 0 for k < j);
+//                         stored rather than added when j >= kA (the first
+//                         contribution), so X needs no clearing beforehand.
 // The two sets touch disjoint tiles (columns J >= kB versus j < kB).
 template <int TM>
 __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2, 2)))
@@ -609,9 +611,13 @@ update_kernel(double* M, double* X, int64_t ld, int nt, int kA, int kB,
     gemm_core<double, true, double, false, TM>(Li, ld, X + (int64_t)j * BM + sc,
                                                ld, nullptr, (int64_t)k0 * BM,
                                                (int64_t)kB * BM, acc, sA, sB);
+    // the update whose reduction starts at k = j brings the first
+    // contribution (X[k, j] = 0 for k < j): it stores, later ones add
     double* Sij = X + (int64_t)i * BM * ld + (int64_t)j * BM;
+    const bool first = j >= kA;
     for_each_acc<TM>(acc, [&](int r, int c, double v) {
-      Sij[(int64_t)(so + r) * ld + sc + c] += v;
+      double* p = Sij + (int64_t)(so + r) * ld + sc + c;
+      *p = first ? v : *p + v;
     });
   }
 }

@@ -88,7 +88,8 @@ hipError_t launch_syrk(int precision, const void* A, int64_t lda, int64_t Tp,
                        const double* s, double* B, hipStream_t st,
                        const int* skip = nullptr);
 // In-place Cholesky of the lower triangle of M (np x np, np multiple of
-// kTile) and X = L^-1 (lower; X must be zero on entry).  *fail != 0 on exit
+// kTile) and X = L^-1 (lower triangle and the diagonal blocks' upper zeros;
+// the tiles above the diagonal blocks are left untouched).  *fail != 0 on exit
 // when a pivot was not positive.
 hipError_t launch_potrf_trtri(double* M, double* X, int64_t np, int* fail,
                               hipStream_t st, const int* skip = nullptr,
