@@ -45,89 +45,160 @@ __device__ __forceinline__ int lds_at(int m, int k) {
   return KC ? m * LDK + k : k * ldp<TM>() + m;
 }
 
-// Loads one BKK-deep slice into registers and writes it to LDS (FP64).  KC:
-// element (m, k) at base[m * ld + k]; otherwise at base[k * ld + m].
-template <typename T, bool KC, int TM = BM>
+// One BKK-deep slice of one operand, moved global -> registers -> LDS in
+// 16-byte chunks (PER per thread).  KC: element (m, k) at base[m * ld + k];
+// otherwise at base[k * ld + m].  SC: the operand is scaled by scale[k]
+// (KC = false only); each chunk's factor is fetched with the chunk.
+template <typename T, bool KC, int TM = BM, bool SC = false>
 struct Stage {
+  static_assert(!(SC && KC), "scaled operands are stored k-major");
   static constexpr int VEC = Vec16<T>::N;
   static constexpr int PER = TM * BKK / VEC / NT;
   static_assert(PER >= 1, "slice smaller than the workgroup");
   u32x4 r[PER];
+  double sc[PER];
 
-  __device__ __forceinline__ void load(const T* base, int64_t ld, int64_t k0,
-                                       int tid) {
-#pragma unroll
-    for (int i = 0; i < PER; ++i) {
-      int idx = tid + i * NT;
-      const T* p;
-      if constexpr (KC) {
-        constexpr int CPR = BKK / VEC;
-        int m = idx / CPR, k = (idx % CPR) * VEC;
-        p = base + (int64_t)m * ld + k0 + k;
-      } else {
-        constexpr int CPR = TM / VEC;
-        int k = idx / CPR, m = (idx % CPR) * VEC;
-        p = base + (k0 + k) * ld + m;
-      }
-      r[i] = *(const u32x4*)p;
+  __device__ __forceinline__ void chunk_at(int i, int tid, int* m, int* k) const {
+    const int idx = tid + i * NT;
+    if constexpr (KC) {
+      constexpr int CPR = BKK / VEC;
+      *m = idx / CPR;
+      *k = (idx % CPR) * VEC;
+    } else {
+      constexpr int CPR = TM / VEC;
+      *k = idx / CPR;
+      *m = (idx % CPR) * VEC;
     }
   }
 
-  __device__ __forceinline__ void store(double* s, int tid,
-                                        const double* scale, int64_t k0) {
+  __device__ __forceinline__ void load1(int i, const T* base, int64_t ld,
+                                        int64_t k0, const double* scale,
+                                        int tid) {
+    int m, k;
+    chunk_at(i, tid, &m, &k);
+    const T* p = KC ? base + (int64_t)m * ld + k0 + k : base + (k0 + k) * ld + m;
+    r[i] = *(const u32x4*)p;
+    if constexpr (SC) sc[i] = scale[k0 + k];
+  }
+
+  __device__ __forceinline__ void store1(int i, double* s, int tid) const {
+    int m, k;
+    chunk_at(i, tid, &m, &k);
+    double x[VEC];
+    unpack16<T>(r[i], x);
+    if constexpr (KC) {
 #pragma unroll
-    for (int i = 0; i < PER; ++i) {
-      int idx = tid + i * NT;
-      double x[VEC];
-      unpack16<T>(r[i], x);
-      if constexpr (KC) {
-        constexpr int CPR = BKK / VEC;
-        int m = idx / CPR, k = (idx % CPR) * VEC;
+      for (int e = 0; e < VEC; ++e) s[lds_at<true, TM>(m, k + e)] = x[e];
+    } else {
 #pragma unroll
-        for (int e = 0; e < VEC; ++e) {
-          double sc = scale ? scale[k0 + k + e] : 1.0;
-          s[lds_at<true, TM>(m, k + e)] = x[e] * sc;
-        }
-      } else {
-        constexpr int CPR = TM / VEC;
-        int k = idx / CPR, m = (idx % CPR) * VEC;
-        double sc = scale ? scale[k0 + k] : 1.0;
-#pragma unroll
-        for (int e = 0; e < VEC; ++e) s[lds_at<false, TM>(m + e, k)] = x[e] * sc;
-      }
+      for (int e = 0; e < VEC; ++e)
+        s[lds_at<false, TM>(m + e, k)] = SC ? x[e] * sc[i] : x[e];
     }
+  }
+
+  __device__ __forceinline__ void load(const T* base, int64_t ld, int64_t k0,
+                                       const double* scale, int tid) {
+#pragma unroll
+    for (int i = 0; i < PER; ++i) load1(i, base, ld, k0, scale, tid);
+  }
+  __device__ __forceinline__ void store(double* s, int tid) const {
+#pragma unroll
+    for (int i = 0; i < PER; ++i) store1(i, s, tid);
   }
 };
 
-template <bool AKC, bool BKC, int TM, int TN>
-__device__ __forceinline__ void mma_slice(const double* sA, const double* sB,
-                                          f64x4 (&acc)[TM / 32][TN / 32],
-                                          int wm, int wn, int lane) {
-  constexpr int MB = TM / 32, NB = TN / 32;   // 16 x 16 blocks per wave
+// The memory operations of one slice of the pipeline, in issue order:
+// chunk c of A to LDS, chunk c of B to LDS, then the next-but-one slice's
+// chunk c of A and of B into the freed registers.  Operation q runs after
+// MFMA group q * G / NOPS, so every chunk waits a full slice between its
+// load and its store.
+template <int PA, int PB>
+struct PipeOps {
+  static constexpr int N = 2 * PA + 2 * PB;
+  // kind: 0 store A, 1 store B, 2 load A, 3 load B; chunk index in *c
+  static constexpr int kind(int q, int* c) {
+    int o = 0;
+    for (int ch = 0; ch < (PA > PB ? PA : PB); ++ch)
+      for (int kd = 0; kd < 4; ++kd) {
+        const bool isA = kd == 0 || kd == 2;
+        if (ch >= (isA ? PA : PB)) continue;
+        if (o == q) {
+          *c = ch;
+          return kd;
+        }
+        ++o;
+      }
+    return -1;
+  }
+};
+
+// One slice: MFMAs on the LDS buffers (rA, rB), the next k-step's fragments
+// read while the current ones are multiplied; STORE writes the slice held in
+// registers to (wA, wB), LOAD fetches the slice at kl into the registers.
+// Each group of NB MFMAs (one A fragment) is followed by the memory
+// operations that fall on it; scheduling barriers keep that interleaving.
+template <bool STORE, bool LOAD, typename TA, bool AKC, typename TB, bool BKC,
+          int TM, int TN, bool BS>
+__device__ __forceinline__ void core_slice(
+    const double* rA, const double* rB, double* wA, double* wB,
+    Stage<TA, AKC, TM>& sa, Stage<TB, BKC, TN, BS>& sb, const TA* Ab,
+    int64_t lda, const TB* Bb, int64_t ldb, const double* bscale, int64_t kl,
+    f64x4 (&acc)[TM / 32][TN / 32], int wm, int wn, int lane, int tid) {
+  constexpr int MB = TM / 32, NB = TN / 32, G = 4 * MB;
+  using Ops = PipeOps<Stage<TA, AKC, TM>::PER, Stage<TB, BKC, TN, BS>::PER>;
+  const int c = lane & 15, kq = lane >> 4;
+  double a[MB], b[NB];
 #pragma unroll
-  for (int kk = 0; kk < BKK; kk += 4) {
-    const int kr = kk + (lane >> 4), c = lane & 15;
-    double a[MB], b[NB];
+  for (int i = 0; i < MB; ++i) a[i] = rA[lds_at<AKC, TM>(wm + i * 16 + c, kq)];
 #pragma unroll
-    for (int i = 0; i < MB; ++i) a[i] = sA[lds_at<AKC, TM>(wm + i * 16 + c, kr)];
+  for (int j = 0; j < NB; ++j) b[j] = rB[lds_at<BKC, TN>(wn + j * 16 + c, kq)];
 #pragma unroll
-    for (int j = 0; j < NB; ++j) b[j] = sB[lds_at<BKC, TN>(wn + j * 16 + c, kr)];
+  for (int t = 0; t < BKK / 4; ++t) {
+    double an[MB], bn[NB];
+    if (t + 1 < BKK / 4) {
+      const int kr = 4 * (t + 1) + kq;
 #pragma unroll
-    for (int i = 0; i < MB; ++i)
+      for (int i = 0; i < MB; ++i) an[i] = rA[lds_at<AKC, TM>(wm + i * 16 + c, kr)];
+#pragma unroll
+      for (int j = 0; j < NB; ++j) bn[j] = rB[lds_at<BKC, TN>(wn + j * 16 + c, kr)];
+    }
+#pragma unroll
+    for (int i = 0; i < MB; ++i) {
 #pragma unroll
       for (int j = 0; j < NB; ++j)
-        acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[i], b[j],
-                                                         acc[i][j], 0, 0, 0);
+        acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[i], b[j], acc[i][j],
+                                                         0, 0, 0);
+      __builtin_amdgcn_sched_barrier(0);
+      const int g = t * MB + i;
+#pragma unroll
+      for (int q = 0; q < Ops::N; ++q) {
+        if (q * G / Ops::N != g) continue;
+        int ch = 0;
+        const int kd = Ops::kind(q, &ch);
+        if (STORE && kd == 0) sa.store1(ch, wA, tid);
+        if (STORE && kd == 1) sb.store1(ch, wB, tid);
+        if (LOAD && kd == 2) sa.load1(ch, Ab, lda, kl, nullptr, tid);
+        if (LOAD && kd == 3) sb.load1(ch, Bb, ldb, kl, bscale, tid);
+      }
+      __builtin_amdgcn_sched_barrier(0);
+    }
+    if (t + 1 < BKK / 4) {
+#pragma unroll
+      for (int i = 0; i < MB; ++i) a[i] = an[i];
+#pragma unroll
+      for (int j = 0; j < NB; ++j) b[j] = bn[j];
+    }
   }
 }
 
-// acc (this wave's TM/2 x TM/2 block) = sum_{k in [kbeg, kend)} opA(m,k) opB(k,n),
-// opB optionally scaled by bscale[k].  kend - kbeg must be a multiple of BKK.
-// sA, sB hold two k-slices each (double buffer): slice s is computed from
-// buffer s % 2 while slice s + 1 waits in registers and slice s + 2 is in
-// flight from memory; one barrier per slice.
+// acc (this wave's TM/2 x TN/2 block) = sum_{k in [kbeg, kend)} opA(m,k) opB(k,n),
+// opB scaled by bscale[k] when BS.  kend - kbeg must be a multiple of BKK.
+// sA, sB hold two k-slices each (double buffer): slice s is multiplied from
+// buffer s % 2 while slice s + 1 moves from registers into the other buffer
+// and slice s + 2 is fetched into the registers, both interleaved with the
+// MFMAs; one barrier per slice.  LDS is free again on return.
 template <typename TA, bool AKC, typename TB, bool BKC, int TM = BM,
-          int TN = TM>
+          int TN = TM, bool BS = false>
 __device__ void gemm_core(const TA* Ab, int64_t lda, const TB* Bb,
                           int64_t ldb, const double* bscale, int64_t kbeg,
                           int64_t kend, f64x4 (&acc)[TM / 32][TN / 32],
@@ -141,31 +212,51 @@ __device__ void gemm_core(const TA* Ab, int64_t lda, const TB* Bb,
 #pragma unroll
     for (int j = 0; j < NB; ++j) acc[i][j] = f64x4{0.0, 0.0, 0.0, 0.0};
   if (kbeg >= kend) return;
+  const int64_t ns = (kend - kbeg) / BKK;
   Stage<TA, AKC, TM> sa;
-  Stage<TB, BKC, TN> sb;
-  sa.load(Ab, lda, kbeg, tid);
-  sb.load(Bb, ldb, kbeg, tid);
-  sa.store(sA, tid, nullptr, kbeg);
-  sb.store(sB, tid, bscale, kbeg);
-  if (kbeg + BKK < kend) {
-    sa.load(Ab, lda, kbeg + BKK, tid);
-    sb.load(Bb, ldb, kbeg + BKK, tid);
+  Stage<TB, BKC, TN, BS> sb;
+  sa.load(Ab, lda, kbeg, nullptr, tid);
+  sb.load(Bb, ldb, kbeg, bscale, tid);
+  sa.store(sA, tid);
+  sb.store(sB, tid);
+  if (ns > 1) {
+    // same chunk order as the loads inside the loop, so that the wait
+    // counts the compiler derives at the loop head stay exact
+    using Ops = PipeOps<Stage<TA, AKC, TM>::PER, Stage<TB, BKC, TN, BS>::PER>;
+#pragma unroll
+    for (int q = 0; q < Ops::N; ++q) {
+      int ch = 0;
+      const int kd = Ops::kind(q, &ch);
+      if (kd == 2) sa.load1(ch, Ab, lda, kbeg + BKK, nullptr, tid);
+      if (kd == 3) sb.load1(ch, Bb, ldb, kbeg + BKK, bscale, tid);
+      __builtin_amdgcn_sched_barrier(0);
+    }
   }
   __syncthreads();
-  int buf = 0;
-  for (int64_t k0 = kbeg; k0 < kend; k0 += BKK) {
-    mma_slice<AKC, BKC, TM, TN>(sA + buf * STA, sB + buf * STB, acc, wm, wn,
-                                lane);
-    if (k0 + BKK < kend) {
-      sa.store(sA + (buf ^ 1) * STA, tid, nullptr, k0 + BKK);
-      sb.store(sB + (buf ^ 1) * STB, tid, bscale, k0 + BKK);
-      if (k0 + 2 * BKK < kend) {
-        sa.load(Ab, lda, k0 + 2 * BKK, tid);
-        sb.load(Bb, ldb, k0 + 2 * BKK, tid);
-      }
-    }
+  int64_t si = 0;
+  for (; si + 2 < ns; ++si) {
+    const int b = (int)(si & 1);
+    const int64_t k0 = kbeg + si * BKK;
+    core_slice<true, true>(sA + b * STA, sB + b * STB, sA + (b ^ 1) * STA,
+                           sB + (b ^ 1) * STB, sa, sb, Ab, lda, Bb, ldb, bscale,
+                           k0 + 2 * BKK, acc, wm, wn, lane, tid);
     __syncthreads();
-    buf ^= 1;
+  }
+  if (si + 1 < ns) {
+    const int b = (int)(si & 1);
+    const int64_t k0 = kbeg + si * BKK;
+    core_slice<true, false>(sA + b * STA, sB + b * STB, sA + (b ^ 1) * STA,
+                            sB + (b ^ 1) * STB, sa, sb, Ab, lda, Bb, ldb,
+                            bscale, 0, acc, wm, wn, lane, tid);
+    __syncthreads();
+    ++si;
+  }
+  {
+    const int b = (int)(si & 1);
+    core_slice<false, false>(sA + b * STA, sB + b * STB, nullptr, nullptr, sa,
+                             sb, Ab, lda, Bb, ldb, bscale, 0, acc, wm, wn, lane,
+                             tid);
+    __syncthreads();
   }
 }
 
@@ -199,7 +290,8 @@ __device__ __forceinline__ void lower_tile(int64_t b, int* I, int* J) {
 // ------------------------------------------------------------------ SYRK --
 // B = A^T diag(s) A, lower tiles computed, written to both triangles.
 template <typename S>
-__global__ void __launch_bounds__(NT) syrk_kernel(const S* __restrict__ A,
+__global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2, 2)))
+syrk_kernel(const S* __restrict__ A,
                                                   int64_t lda, int64_t Tp,
                                                   const double* __restrict__ s,
                                                   double* __restrict__ B,
@@ -209,8 +301,8 @@ __global__ void __launch_bounds__(NT) syrk_kernel(const S* __restrict__ A,
   int I, J;
   lower_tile(blockIdx.x, &I, &J);
   f64x4 acc[4][4];
-  gemm_core<S, false, S, false>(A + (int64_t)I * BM, lda, A + (int64_t)J * BM,
-                                lda, s, 0, Tp, acc, sA, sB);
+  gemm_core<S, false, S, false, BM, BM, true>(
+      A + (int64_t)I * BM, lda, A + (int64_t)J * BM, lda, s, 0, Tp, acc, sA, sB);
   double* Bij = B + (int64_t)I * BM * lda + (int64_t)J * BM;
   double* Bji = B + (int64_t)J * BM * lda + (int64_t)I * BM;
   const bool mirror = I != J;
@@ -271,14 +363,16 @@ trace_gemm_kernel(const S* __restrict__ A, int64_t lda, int64_t Tp,
 // included); the strictly lower part of X stored transposed in the strict
 // upper triangle (X[i][j], i > j, at row j, column i); 1/L_ii in rdiag.
 //
-// Factorisation: right-looking in 16-column steps.  Wave 0 factors and
-// inverts each 16 x 16 diagonal leaf in registers (lane r holds row r; values
-// move by readlane broadcasts).  The sub-panel below, L21 = A21 X11^T, and
-// the trailing update A22 -= L21 L21^T run on the FP64 matrix cores; wave 0
-// updates the next leaf first and factors it while the other waves finish
-// the trailing update.
-// Inverse: recursive doubling, X21 = -X22 (L21 X11), for half sizes 16, 32
-// and 64, again on the matrix cores.
+// Factorisation: right-looking in 16-column steps.  Wave 0 factors each
+// 16 x 16 diagonal leaf in registers (lane r holds row r; values move by
+// readlane broadcasts).  The sub-panel below, L21 = A21 L11^-T, is a forward
+// substitution with one row per lane; the trailing update A22 -= L21 L21^T
+// runs on the FP64 matrix cores, and wave 0 updates the next leaf first and
+// factors it while the other waves finish the trailing update.  Only the
+// factor sits on this serial chain.
+// Inverse: the eight leaves in parallel (one wave each), then recursive
+// doubling, X21 = -X22 (L21 X11), for half sizes 16, 32 and 64 on the matrix
+// cores.
 constexpr int DT = 512;      // threads of the diagonal-block kernel
 constexpr int SB = 16;       // leaf width
 constexpr int LDD = BM + 1;  // padded LDS row
@@ -321,18 +415,17 @@ __device__ __forceinline__ double rsqrt_nr(double p) {
   return fma(0.5 * y, r, y);
 }
 
-// Wave 0: Cholesky and inverse of the SB x SB diagonal sub-block at (c0, c0).
-// Lane r holds row r of the block.  Factor: column j is scaled by its pivot
-// and applied to the rows below; the reciprocal pivots 1 / L_jj are kept.
-// Inverse, row by row: X[m] = (e_m - sum_{m'<m} L[m][m'] X[m']) / L[m][m];
-// row m is broadcast once its sum is complete and applied to the rows below.
-__device__ __forceinline__ void leaf_chol_inv(double* S, double* rd, int c0,
-                                              int lane, int* fail) {
+// Wave 0: Cholesky factor of the SB x SB diagonal sub-block at (c0, c0).
+// Lane r holds row r of the block: column j is scaled by its pivot and
+// applied to the rows below.  Stores L (lower triangle) and 1 / L_jj in rd.
+__device__ __forceinline__ void leaf_chol(double* S, double* rd, int c0,
+                                          int lane, int* fail) {
   const int r = lane & (SB - 1);  // lanes >= SB mirror lanes < SB, never store
-  double a[SB], rp[SB];
+  double a[SB];
 #pragma unroll
   for (int j = 0; j < SB; ++j) a[j] = S[(c0 + r) * LDD + c0 + j];
   bool bad = false;
+  double rpr = 0.0;
   // Branch-free: every lane runs every step.  Entries right of the diagonal
   // of a lane's row are never read by other lanes nor stored, so the
   // column update needs no mask.
@@ -344,40 +437,52 @@ __device__ __forceinline__ void leaf_chol_inv(double* S, double* rd, int c0,
       p = 1.0;
     }
     const double y = rsqrt_nr(p);
-    rp[j] = y;
+    rpr = r == j ? y : rpr;
     const double scaled = a[j] * y;
     a[j] = r == j ? p * y : (r > j ? scaled : a[j]);
 #pragma unroll
     for (int c = j + 1; c < SB; ++c) a[c] = fma(-a[j], bcast(a[j], c), a[c]);
   }
   if (bad && lane == 0) atomicOr(fail, 1);
-  // x (lane r) accumulates sum_{m<r} L[r][m] X[m][:]; row m of X is formed
-  // from lane m's accumulator as it is broadcast.
-  double x[SB];
+  if (lane < SB) {
 #pragma unroll
-  for (int c = 0; c < SB; ++c) x[c] = 0.0;
+    for (int j = 0; j < SB; ++j)
+      if (j <= r) S[(c0 + r) * LDD + c0 + j] = a[j];
+    rd[c0 + r] = rpr;
+  }
+}
+
+// One wave: inverse X of the factored leaf at (c0, c0), row by row:
+// X[m] = (e_m - sum_{m'<m} L[m][m'] X[m']) / L[m][m].  Lane r holds row r
+// and accumulates sum_{m<r} L[r][m] X[m][:]; row m of X is formed from lane
+// m's accumulator as it is broadcast.  The strict lower part of X is parked
+// transposed in the leaf's strict upper triangle.
+__device__ __forceinline__ void leaf_inv(double* S, const double* rd, int c0,
+                                         int lane) {
+  const int r = lane & (SB - 1);
+  double a[SB], rp[SB], x[SB];
+#pragma unroll
+  for (int j = 0; j < SB; ++j) {
+    const double v = S[(c0 + r) * LDD + c0 + j];
+    a[j] = j < r ? v : 0.0;
+    rp[j] = rd[c0 + j];
+    x[j] = 0.0;
+  }
 #pragma unroll
   for (int m = 0; m + 1 < SB; ++m) {
-    const double am = r > m ? a[m] : 0.0;
 #pragma unroll
     for (int c = 0; c <= m; ++c) {
       const double xmc = ((c == m ? 1.0 : 0.0) - bcast(x[c], m)) * rp[m];
-      x[c] = fma(am, xmc, x[c]);
+      x[c] = fma(a[m], xmc, x[c]);
     }
   }
-  double rpr = 0.0;
-#pragma unroll
-  for (int j = 0; j < SB; ++j) rpr = j == r ? rp[j] : rpr;
+  const double rpr = rd[c0 + r];
 #pragma unroll
   for (int c = 0; c < SB; ++c) x[c] = ((c == r ? 1.0 : 0.0) - x[c]) * rpr;
   if (lane < SB) {
 #pragma unroll
-    for (int j = 0; j < SB; ++j) {
-      if (j <= r) S[(c0 + r) * LDD + c0 + j] = a[j];
-      // X[r][j] for j < r, parked at (c0 + j, c0 + r)
+    for (int j = 0; j < SB; ++j)
       if (j < r) S[(c0 + j) * LDD + c0 + r] = x[j];
-    }
-    rd[c0 + r] = rpr;
   }
 }
 
@@ -416,34 +521,29 @@ __global__ void __launch_bounds__(DT) diag_block_kernel(double* M, double* X,
   // Step c0: the sub-panel below leaf c0, then the trailing update.  Wave 0
   // updates the next leaf's diagonal block first and factors it while the
   // other waves finish the trailing update (disjoint blocks).
-  if (wave == 0) leaf_chol_inv(S, rd, 0, lane, fail);
+  if (wave == 0) leaf_chol(S, rd, 0, lane, fail);
   __syncthreads();
   for (int c0 = 0; c0 + SB < BM; c0 += SB) {
     const int r0 = c0 + SB, rem = BM - r0;
     const int nb = rem / 16;
-    // L21 = A21 X11^T: nb x (SB / 16) blocks, at most 2 per wave, stored
-    // after all waves have read A21
-    {
-      constexpr int CB = SB / 16;
-      f64x4 res[2];
+    // L21 = A21 L11^-T by forward substitution, one row per lane:
+    // L[i][j] = (A[i][j] - sum_{m<j} L[i][m] L[j][m]) / L[j][j], with the
+    // leaf's entries read at uniform addresses (LDS broadcasts)
+    if (tid < rem) {
+      double* row = S + (r0 + tid) * LDD + c0;
+      const double* L11 = S + c0 * LDD + c0;
+      double l[SB];
 #pragma unroll
-      for (int sl = 0; sl < 2; ++sl) {
-        const int b = wave + sl * NW, bi = b / CB, bj = b % CB;
-        if (b < nb * CB)
-          res[sl] = mfma_block(Lv, Xt, r0 + 16 * bi, c0 + 16 * bj, c0,
-                               c0 + 16 * bj + 16, lane);
+      for (int j = 0; j < SB; ++j) l[j] = row[j];
+#pragma unroll
+      for (int j = 0; j < SB; ++j) {
+        double t = l[j];
+#pragma unroll
+        for (int m = 0; m < j; ++m) t = fma(-l[m], L11[j * LDD + m], t);
+        l[j] = t * rd[c0 + j];
       }
-      __syncthreads();
 #pragma unroll
-      for (int sl = 0; sl < 2; ++sl) {
-        const int b = wave + sl * NW, bi = b / CB, bj = b % CB;
-        if (b < nb * CB) {
-#pragma unroll
-          for (int q = 0; q < 4; ++q)
-            S[(r0 + 16 * bi + (lane >> 4) + 4 * q) * LDD + c0 + 16 * bj +
-              (lane & 15)] = res[sl][q];
-        }
-      }
+      for (int j = 0; j < SB; ++j) row[j] = l[j];
     }
     __syncthreads();
     // A22 -= L21 L21^T on the lower blocks; block 0 is the next leaf's
@@ -462,13 +562,17 @@ __global__ void __launch_bounds__(DT) diag_block_kernel(double* M, double* X,
     if (wave == 0) {
       trail(0);
       wave_sync();
-      leaf_chol_inv(S, rd, r0, lane, fail);
+      leaf_chol(S, rd, r0, lane, fail);
     } else {
       for (int b = wave; b < nb * (nb + 1) / 2; b += NW - 1) trail(b);
     }
     __syncthreads();
   }
-  // ---- inverse: X21 = -X22 (L21 X11) at half sizes 32, then 64 ---------------
+  // ---- inverse: the leaves' inverses, one wave each, then
+  // X21 = -X22 (L21 X11) at half sizes 16, 32 and 64 --------------------------
+  static_assert(BM / SB == NW, "one leaf per wave");
+  leaf_inv(S, rd, wave * SB, lane);
+  __syncthreads();
   auto Tv = [&](int m, int c) { return S[c * LDD + m]; };  // parked T / X21
   for (int h = SB; h < BM; h *= 2) {
     const int nh = BM / (2 * h);         // independent problems

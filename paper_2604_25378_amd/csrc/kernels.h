@@ -83,7 +83,7 @@ hipError_t launch_center(const double* R, int64_t T, int64_t n, int64_t ldr,
 // ---- dense FP64 MFMA kernels (dense.hip) ----------------------------------
 constexpr int kTile = 128;  // output tile and Cholesky block size
 
-// B = A^T diag(s) A / 1 (full symmetric n x n, ldb = lda), s length Tp.
+// B = A^T diag(s) A (full symmetric n x n, ldb = lda), s length Tp, non-null.
 hipError_t launch_syrk(int precision, const void* A, int64_t lda, int64_t Tp,
                        const double* s, double* B, hipStream_t st,
                        const int* skip = nullptr);
