@@ -364,18 +364,19 @@ trace_gemm_kernel(const S* __restrict__ A, int64_t lda, int64_t Tp,
 // upper triangle (X[i][j], i > j, at row j, column i); 1/L_ii in rdiag.
 //
 // Factorisation: right-looking in 16-column steps.  Wave 0 factors each
-// 16 x 16 diagonal leaf in registers (lane r holds row r; values move by
-// readlane broadcasts).  The sub-panel below, L21 = A21 L11^-T, is a forward
-// substitution with one row per lane; the trailing update A22 -= L21 L21^T
-// runs on the FP64 matrix cores, and wave 0 updates the next leaf first and
-// factors it while the other waves finish the trailing update.  Only the
-// factor sits on this serial chain.
+// panel (the 16 columns from the diagonal down) in registers, the leaf's
+// values moving between lanes by DPP row broadcasts.  The trailing update A22 -= L21 L21^T
+// runs on the FP64 matrix cores: first the next panel's blocks, one per wave,
+// then the rest on waves 1-7 while wave 0 factors that panel.
 // Inverse: the eight leaves in parallel (one wave each), then recursive
 // doubling, X21 = -X22 (L21 X11), for half sizes 16, 32 and 64 on the matrix
 // cores.
 constexpr int DT = 512;      // threads of the diagonal-block kernel
 constexpr int SB = 16;       // leaf width
-constexpr int LDD = BM + 1;  // padded LDS row
+// padded LDS row: 130 doubles = 4 banks mod 64, so the 16 rows x 4 k of an
+// MFMA operand read (16 lanes down a column, 4 k across) hit 64 distinct
+// banks
+constexpr int LDD = BM + 2;
 constexpr size_t kDiagLds = ((size_t)BM * LDD + BM) * sizeof(double);
 
 __device__ __forceinline__ void wave_sync() {
@@ -383,20 +384,38 @@ __device__ __forceinline__ void wave_sync() {
   __builtin_amdgcn_wave_barrier();
 }
 
-// One 16 x 16 output block: sum_{k in [kb, ke)} fa(r0 + i, k) fb(k, c0 + j),
-// ke - kb a multiple of 4.  Lane l holds (r0 + l/16 + 4 r, c0 + l%16) in
-// component r of the result.
+// One 16 x 16 output block: sum_{k in [kb, kb + 16 NC)} fa(r0 + i, k)
+// fb(k, c0 + j).  Every operand is read from LDS before the first MFMA (one
+// round trip instead of one per MFMA), and two accumulators alternate.
+// Lane l holds (r0 + l/16 + 4 r, c0 + l%16) in component r of the result.
+template <int NC, class FA, class FB>
+__device__ __forceinline__ f64x4 mfma_block_n(FA fa, FB fb, int r0, int c0,
+                                              int kb, int lane) {
+  const int lr = lane & 15, lk = lane >> 4;
+  double a[4 * NC], b[4 * NC];
+#pragma unroll
+  for (int q = 0; q < 4 * NC; ++q) {
+    a[q] = fa(r0 + lr, kb + 4 * q + lk);
+    b[q] = fb(kb + 4 * q + lk, c0 + lr);
+  }
+  f64x4 acc[2] = {{0.0, 0.0, 0.0, 0.0}, {0.0, 0.0, 0.0, 0.0}};
+#pragma unroll
+  for (int q = 0; q < 4 * NC; ++q)
+    acc[q & 1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[q], b[q], acc[q & 1],
+                                                      0, 0, 0);
+  return acc[0] + acc[1];
+}
+
+// The same for ke - kb in {16, 32, 48, 64} (uniform).
 template <class FA, class FB>
 __device__ __forceinline__ f64x4 mfma_block(FA fa, FB fb, int r0, int c0,
                                             int kb, int ke, int lane) {
-  f64x4 acc = {0.0, 0.0, 0.0, 0.0};
-  const int lr = lane & 15, lk = lane >> 4;
-#pragma unroll 4
-  for (int k = kb; k < ke; k += 4)
-    acc = __builtin_amdgcn_mfma_f64_16x16x4f64(fa(r0 + lr, k + lk),
-                                               fb(k + lk, c0 + lr), acc, 0, 0,
-                                               0);
-  return acc;
+  switch ((ke - kb) / 16) {
+    case 1: return mfma_block_n<1>(fa, fb, r0, c0, kb, lane);
+    case 2: return mfma_block_n<2>(fa, fb, r0, c0, kb, lane);
+    case 3: return mfma_block_n<3>(fa, fb, r0, c0, kb, lane);
+    default: return mfma_block_n<4>(fa, fb, r0, c0, kb, lane);
+  }
 }
 
 // Value of v in lane l (l uniform), read through the scalar unit.
@@ -415,41 +434,139 @@ __device__ __forceinline__ double rsqrt_nr(double p) {
   return fma(0.5 * y, r, y);
 }
 
-// Wave 0: Cholesky factor of the SB x SB diagonal sub-block at (c0, c0).
-// Lane r holds row r of the block: column j is scaled by its pivot and
-// applied to the rows below.  Stores L (lower triangle) and 1 / L_jj in rd.
-__device__ __forceinline__ void leaf_chol(double* S, double* rd, int c0,
-                                          int lane, int* fail) {
-  const int r = lane & (SB - 1);  // lanes >= SB mirror lanes < SB, never store
-  double a[SB];
+// 1 / p for p > 0: hardware estimate refined by one Newton-Raphson step
+// r <- r + r (1 - p r) (relative error of the estimate squares).
+__device__ __forceinline__ double rcp_nr(double p) {
+  const double r = __builtin_amdgcn_rcp(p);
+  return fma(r, fma(-p, r, 1.0), r);
+}
+
+// Value of v in lane n of this lane's row of 16 (DPP row broadcast).
+template <int N>
+__device__ __forceinline__ double row_bcast(double v) {
+  return __builtin_amdgcn_update_dpp(0.0, v, 0x150 + N, 0xF, 0xF, false);
+}
+
+// Columns C >= J + 2 of every slot: A[r][C] -= u_r A[C][J] + v_r A[C][J+1].
+template <int J, int C, int NS>
+__device__ __forceinline__ void panel_update(double (&a)[3][SB],
+                                             const double (&u)[NS],
+                                             const double (&v)[NS]) {
+  if constexpr (C < SB) {
+    const double l0 = row_bcast<C>(a[0][J]), l1 = row_bcast<C>(a[0][J + 1]);
 #pragma unroll
-  for (int j = 0; j < SB; ++j) a[j] = S[(c0 + r) * LDD + c0 + j];
+    for (int s = 0; s < NS; ++s) {
+      a[s][C] = fma(-v[s], l1, fma(-u[s], l0, a[s][C]));
+      // keep the update here: sunk to its first use it would hold every
+      // broadcast value live until the end of the panel
+      asm volatile("" : "+v"(a[s][C]));
+    }
+    panel_update<J, C + 1, NS>(a, u, v);
+  }
+}
+
+// Elimination of the column pair (J, J + 1) of the panel (see panel_chol)
+// with its 2 x 2 pivot block B = [[b11, b21], [b21, b22]], then the pairs
+// after it.  The rows' pair entries P = [A[r][J], A[r][J+1]] stay as they
+// are; the columns after the pair lose P B^-1 P^T.  B^-1 comes from the
+// determinant in closed form, one reciprocal per pair on the serial chain.
+template <int J, int NS>
+__device__ __forceinline__ void panel_pairs(double (&a)[3][SB],
+                                            double (&bb)[SB / 2][3],
+                                            bool& bad) {
+  if constexpr (J < SB) {
+    double b11 = row_bcast<J>(a[0][J]);
+    double b21 = row_bcast<J + 1>(a[0][J]);
+    double b22 = row_bcast<J + 1>(a[0][J + 1]);
+    double det = fma(b11, b22, -b21 * b21);
+    const bool ok = b11 > 0.0 && b11 < INFINITY && det > 0.0 && det < INFINITY;
+    bad = bad || !ok;
+    b11 = ok ? b11 : 1.0;
+    b21 = ok ? b21 : 0.0;
+    b22 = ok ? b22 : 1.0;
+    det = ok ? det : 1.0;
+    bb[J / 2][0] = b11;
+    bb[J / 2][1] = b21;
+    bb[J / 2][2] = det;
+    const double rdet = rcp_nr(det);
+    const double w11 = b22 * rdet, w21 = -b21 * rdet, w22 = b11 * rdet;
+    double u[NS], v[NS];
+#pragma unroll
+    for (int s = 0; s < NS; ++s) {
+      u[s] = fma(a[s][J], w11, a[s][J + 1] * w21);
+      v[s] = fma(a[s][J], w21, a[s][J + 1] * w22);
+    }
+    panel_update<J, J + 2, NS>(a, u, v);
+    panel_pairs<J + 2, NS>(a, bb, bad);
+  }
+}
+
+// One wave: Cholesky factor of the panel S[c0:BM, c0:c0+SB], whose trailing
+// updates are complete.  Slot 0 of lane l holds leaf row c0 + l % 16 (each
+// row of 16 lanes a copy of the leaf, so that the leaf's entries reach every
+// lane by a row broadcast); slots 1 and 2 hold rows c0 + 16 + l and
+// c0 + 80 + l below the leaf (NS slots in use).  Block elimination with 2 x 2
+// pivots leaves, per column pair, the pair entries P of each row and the
+// pivot block B (kept as b11, b21, det); afterwards L_B = chol(B) and the
+// rows' factor entries P L_B^-T are formed off the serial chain.  Stores L (on and below the
+// diagonal) and 1 / L_jj in rd.  Leaf entries right of the diagonal are
+// updated too but never broadcast nor stored.
+template <int NS>
+__device__ __forceinline__ void panel_chol(double* S, double* rd, int c0,
+                                           int lane, int* fail) {
+  const int row[3] = {c0 + (lane & 15), c0 + 16 + lane, c0 + 80 + lane};
+  double a[3][SB], bb[SB / 2][3];
+#pragma unroll
+  for (int s = 0; s < 3; ++s) {
+    // rows past the block read row BM - 1 and are zeroed (no divergence)
+    const int rr = row[s] < BM ? row[s] : BM - 1;
+    const bool in = row[s] < BM;
+#pragma unroll
+    for (int j = 0; j < SB; ++j) {
+      const double v = s < NS ? S[rr * LDD + c0 + j] : 0.0;
+      a[s][j] = in ? v : 0.0;
+    }
+  }
   bool bad = false;
+  panel_pairs<0, NS>(a, bb, bad);
+  if (bad && lane == 0) atomicOr(fail, 1);
   double rpr = 0.0;
-  // Branch-free: every lane runs every step.  Entries right of the diagonal
-  // of a lane's row are never read by other lanes nor stored, so the
-  // column update needs no mask.
+#pragma unroll
+  for (int q = 0; q < SB / 2; ++q) {
+    // L_B = [[l11, 0], [l21, l22]], l22^2 = det / b11: y1 = 1 / l11,
+    // y2 = 1 / l22
+    const double y1 = rsqrt_nr(bb[q][0]);
+    const double l21 = bb[q][1] * y1;
+    const double y2 = rsqrt_nr(bb[q][2] * y1 * y1);
+#pragma unroll
+    for (int s = 0; s < NS; ++s) {
+      const double x1 = a[s][2 * q] * y1;
+      a[s][2 * q + 1] = (a[s][2 * q + 1] - x1 * l21) * y2;
+      a[s][2 * q] = x1;
+    }
+    rpr = (lane & 15) == 2 * q ? y1 : ((lane & 15) == 2 * q + 1 ? y2 : rpr);
+  }
 #pragma unroll
   for (int j = 0; j < SB; ++j) {
-    double p = bcast(a[j], j);
-    if (!(p > 0.0) || !isfinite(p)) {
-      bad = true;
-      p = 1.0;
-    }
-    const double y = rsqrt_nr(p);
-    rpr = r == j ? y : rpr;
-    const double scaled = a[j] * y;
-    a[j] = r == j ? p * y : (r > j ? scaled : a[j]);
+    if (lane < SB && j <= lane) S[row[0] * LDD + c0 + j] = a[0][j];
 #pragma unroll
-    for (int c = j + 1; c < SB; ++c) a[c] = fma(-a[j], bcast(a[j], c), a[c]);
+    for (int s = 1; s < NS; ++s)
+      if (row[s] < BM) S[row[s] * LDD + c0 + j] = a[s][j];
   }
-  if (bad && lane == 0) atomicOr(fail, 1);
-  if (lane < SB) {
-#pragma unroll
-    for (int j = 0; j < SB; ++j)
-      if (j <= r) S[(c0 + r) * LDD + c0 + j] = a[j];
-    rd[c0 + r] = rpr;
-  }
+  if (lane < SB) rd[c0 + lane] = rpr;
+}
+
+// Slots in use for the panel at c0: rows below the leaf, BM - c0 - SB of
+// them, over 64 lanes.
+__device__ __forceinline__ void panel_chol_at(double* S, double* rd, int c0,
+                                              int lane, int* fail) {
+  const int below = BM - c0 - SB;
+  if (below > 64)
+    panel_chol<3>(S, rd, c0, lane, fail);
+  else if (below > 0)
+    panel_chol<2>(S, rd, c0, lane, fail);
+  else
+    panel_chol<1>(S, rd, c0, lane, fail);
 }
 
 // One wave: inverse X of the factored leaf at (c0, c0), row by row:
@@ -498,8 +615,11 @@ __global__ void __launch_bounds__(DT) diag_block_kernel(double* M, double* X,
   double* Mk = M + (int64_t)k * BM * ld + (int64_t)k * BM;
   double* Xk = X + (int64_t)k * BM * ld + (int64_t)k * BM;
   auto Lv = [&](int i, int j) { return S[i * LDD + j]; };  // i >= j only
+  // both candidates are read (in bounds for any i, j < BM) and selected, so
+  // operand reads do not diverge
   auto Xv = [&](int i, int j) {
-    return i > j ? S[j * LDD + i] : (i == j ? rd[i] : 0.0);
+    const double u = S[j * LDD + i], d = rd[i];
+    return i > j ? u : (i == j ? d : 0.0);
   };
   auto Xt = [&](int m, int c) { return Xv(c, m); };  // X^T
   {
@@ -521,37 +641,13 @@ __global__ void __launch_bounds__(DT) diag_block_kernel(double* M, double* X,
   // Step c0: the sub-panel below leaf c0, then the trailing update.  Wave 0
   // updates the next leaf's diagonal block first and factors it while the
   // other waves finish the trailing update (disjoint blocks).
-  if (wave == 0) leaf_chol(S, rd, 0, lane, fail);
+  if (wave == 0) panel_chol_at(S, rd, 0, lane, fail);
   __syncthreads();
+  auto Lt = [&](int m, int c) { return S[c * LDD + m]; };  // L^T
   for (int c0 = 0; c0 + SB < BM; c0 += SB) {
-    const int r0 = c0 + SB, rem = BM - r0;
-    const int nb = rem / 16;
-    // L21 = A21 L11^-T by forward substitution, one row per lane:
-    // L[i][j] = (A[i][j] - sum_{m<j} L[i][m] L[j][m]) / L[j][j], with the
-    // leaf's entries read at uniform addresses (LDS broadcasts)
-    if (tid < rem) {
-      double* row = S + (r0 + tid) * LDD + c0;
-      const double* L11 = S + c0 * LDD + c0;
-      double l[SB];
-#pragma unroll
-      for (int j = 0; j < SB; ++j) l[j] = row[j];
-#pragma unroll
-      for (int j = 0; j < SB; ++j) {
-        double t = l[j];
-#pragma unroll
-        for (int m = 0; m < j; ++m) t = fma(-l[m], L11[j * LDD + m], t);
-        l[j] = t * rd[c0 + j];
-      }
-#pragma unroll
-      for (int j = 0; j < SB; ++j) row[j] = l[j];
-    }
-    __syncthreads();
-    // A22 -= L21 L21^T on the lower blocks; block 0 is the next leaf's
-    auto Lt = [&](int m, int c) { return S[c * LDD + m]; };  // L21^T
-    auto trail = [&](int b) {
-      int bi = 0;
-      while ((bi + 1) * (bi + 2) / 2 <= b) ++bi;
-      const int bj = b - bi * (bi + 1) / 2;
+    const int r0 = c0 + SB, nb = (BM - r0) / 16;
+    // A22 -= L21 L21^T, 16 x 16 block (bi, bj) of A22, bi >= bj
+    auto trail = [&](int bi, int bj) {
       const f64x4 v =
           mfma_block(Lv, Lt, r0 + 16 * bi, r0 + 16 * bj, c0, c0 + SB, lane);
 #pragma unroll
@@ -559,12 +655,18 @@ __global__ void __launch_bounds__(DT) diag_block_kernel(double* M, double* X,
         S[(r0 + 16 * bi + (lane >> 4) + 4 * q) * LDD + r0 + 16 * bj +
           (lane & 15)] -= v[q];
     };
+    // the next panel's blocks first, one per wave
+    if (wave < nb) trail(wave, 0);
+    __syncthreads();
+    // wave 0 factors the next panel while the others update the rest
     if (wave == 0) {
-      trail(0);
-      wave_sync();
-      leaf_chol(S, rd, r0, lane, fail);
+      panel_chol_at(S, rd, r0, lane, fail);
     } else {
-      for (int b = wave; b < nb * (nb + 1) / 2; b += NW - 1) trail(b);
+      for (int b = wave - 1; b < (nb - 1) * nb / 2; b += NW - 1) {
+        int bi = 0;
+        while ((bi + 1) * (bi + 2) / 2 <= b) ++bi;
+        trail(bi + 1, b - bi * (bi + 1) / 2 + 1);
+      }
     }
     __syncthreads();
   }
