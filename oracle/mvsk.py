@@ -16,7 +16,8 @@ of each function:
 
 * centering, objective, moments, gradient, HVP, third-order action,
   line-search coefficients, step selection, feasibility cap, reduced basis,
-  affine-normal direction, solve loop: pinned (tests/test_oracle_*.py).
+  affine-normal direction, solve loop, simplex projection, projected-KKT
+  residual, boundary block: pinned (tests/test_oracle_*.py).
 * PCG inner iterates: parity unpinned per iteration (the paper does not name
   its preconditioner); pinned only at solve level through uniqueness of the
   minimiser under the convexity certificate.
@@ -37,7 +38,8 @@ __all__ = [
     "tangent_basis", "householder_frame", "Direction", "affine_normal",
     "linesearch_coeffs", "alpha_max", "quartic_value", "select_step",
     "Options", "SolveInfo", "solve", "certified_convex", "Unbounded",
-    "Indefinite",
+    "Indefinite", "project_simplex", "kkt_residual", "face_free",
+    "face_basis",
 ]
 
 
@@ -316,6 +318,68 @@ def alpha_max(x, d, tau):
     return float(np.min((x[neg] - tau) / (-d[neg])))
 
 
+def project_simplex(y, tau=0.0):
+    """Euclidean projection onto Delta(tau) = {x : x_i >= tau, 1^T x = 1},
+    the projection of the projected trial step (reduced-simplex wrapper of
+    the implementation appendix).  Shifted by tau it is the projection onto
+    the simplex of mass s = 1 - n tau, done by the sorting method (Held,
+    Wolfe and Crowder 1974; Duchi et al. 2008): with u = y - tau sorted
+    decreasingly, rho is the last j with u_(j) > (sum_{i<=j} u_(i) - s) / j,
+    theta = (sum_{i<=rho} u_(i) - s) / rho and x = max(u - theta, 0) + tau.
+    """
+    y = np.asarray(y, dtype=np.float64)
+    n = y.size
+    s = 1.0 - n * tau
+    if not s > 0.0:
+        raise ValueError("tau must be below 1/n")
+    u = y - tau
+    v = np.sort(u)[::-1]
+    cs = np.cumsum(v)
+    j = np.arange(1, n + 1)
+    rho = int(j[v - (cs - s) / j > 0.0][-1])
+    # theta from a correctly rounded sum over the support (the running sum
+    # above only locates rho)
+    theta = (math.fsum(v[:rho]) - s) / rho
+    return np.maximum(u - theta, 0.0) + tau
+
+
+def kkt_residual(A, mu, c, x):
+    """Projected-simplex KKT residual |x - Pi_Delta(x - grad f(x))|_2.
+
+    The computational study evaluates solutions by a projected-simplex KKT
+    residual against a 1e-6 target without stating its formula; this is the
+    standard projected-gradient residual on Delta = Delta(0).  It vanishes
+    exactly at the KKT points of min f over the simplex and equals the
+    tangent-gradient norm |P_1 grad f| at interior points where the unit
+    projected-gradient step stays inside.
+    """
+    g = gradient(A, mu, c, x)
+    return float(np.linalg.norm(x - project_simplex(x - g, 0.0)))
+
+
+def face_free(x, g, tau):
+    """Free coordinates of the current face of Delta(tau) (boundary block of
+    Algorithm 1: continuation on the exposed active face).  Coordinates
+    above the slice bound, x_i > tau (1 + 1e-6), are free; a bound
+    coordinate is released when its multiplier g_i - nu is negative, with nu
+    the mean of g over the coordinates above the bound (the budget
+    multiplier of the face problem)."""
+    strict = x > tau * (1.0 + 1e-6)
+    nu = float(np.sum(g[strict])) / int(np.count_nonzero(strict))
+    return strict | (g < nu)
+
+
+def face_basis(free):
+    """Orthonormal basis of the face's tangent space {d : d_i = 0 off the
+    free set, sum_i d_i = 0}: the budget tangent basis of the free
+    coordinates, zero on the bound ones."""
+    n, k = free.size, int(np.count_nonzero(free))
+    U = np.zeros((n, k - 1))
+    if k > 1:
+        U[free] = tangent_basis(np.ones((k, 1)))
+    return U
+
+
 def quartic_value(coef, alpha):
     return (coef[0] + coef[1] * alpha + coef[2] * alpha**2
             + coef[3] * alpha**3 + coef[4] * alpha**4)
@@ -368,6 +432,8 @@ class Options:
     solver: 'direct' (YAND-MVSK small) or 'pcg' (YAND-MVSK large).
     feasible_set: 'budget' (affine hull, no cap) or 'simplex' (cap on
     Delta(tau), Lemma 'Interior-safe steplength cap').
+    eta: nominal projected trial step of the boundary block (0.05 in Table
+    'YAND-MVSK parameter settings'); 0 keeps the capped raw step only.
     """
     solver: str = "direct"
     feasible_set: str = "budget"
@@ -378,6 +444,7 @@ class Options:
     krylov_tol: float = 1e-3
     krylov_maxit: int = 15
     tau: float = 1e-8
+    eta: float = 0.05
     stall_recovery: bool = True
     restart_max_iter: int = 120
 
@@ -397,34 +464,62 @@ class SolveInfo:
     cg_iters: int = 0
     oracle_passes: int = 0
     ls_passes: int = 0
+    kkt: float = math.nan
+    projected_steps: int = 0
     history: list = field(default_factory=list)
 
 
 def _iterate(A, mu, c, x, U, opts: Options, solver, krylov_maxit, max_iter,
-             info: SolveInfo, t0):
-    """Run outer iterations from x; return (x, converged, stalled)."""
+             info: SolveInfo, t0, eta=None):
+    """Run outer iterations from x; return (x, converged, stalled).
+
+    Simplex with eta > 0 runs the boundary block of Algorithm 1 and the
+    reduced-simplex wrapper of the implementation appendix:
+      * the direction lives on the current face (face_free, face_basis), so
+        coordinates at the slice bound stay there unless released;
+      * when the cap alpha_max(x, d; tau) is below the nominal step eta, the
+        trial x + eta d is projected onto Delta(tau) and the line search runs
+        on the corrected segment x + a (xbar - x), a in [0, 1], provided
+        that segment is a descent direction and not numerically zero;
+        otherwise the capped raw step is taken, which exposes the next face;
+      * the stopping test also accepts a projected-KKT residual
+        (kkt_residual) at or below eps.
+    With eta = 0 the simplex set only caps the raw step.
+    """
+    eta = opts.eta if eta is None else eta
+    simplex = opts.feasible_set == "simplex"
+    faces = simplex and eta > 0.0
     small = 0
     f_prev = objective(A, mu, c, x)
     for _ in range(max_iter):
         g = gradient(A, mu, c, x)
         info.oracle_passes += 1
-        gn = float(np.linalg.norm(U.T @ g))
+        Ui = face_basis(face_free(x, g, opts.tau)) if faces else U
+        gn = float(np.linalg.norm(Ui.T @ g))
         info.gnorm = gn
-        if gn <= opts.eps:
+        if simplex:
+            info.kkt = float(np.linalg.norm(x - project_simplex(x - g, 0.0)))
+        if gn <= opts.eps or (simplex and info.kkt <= opts.eps):
             return x, True, False
         if time.perf_counter() - t0 > opts.max_elapsed:
             return x, False, True
         reg = opts.reg if solver == "pcg" else 0.0
-        dr = affine_normal(A, mu, c, x, U, solver=solver, reg=reg,
+        dr = affine_normal(A, mu, c, x, Ui, solver=solver, reg=reg,
                            krylov_tol=opts.krylov_tol,
                            krylov_maxit=krylov_maxit)
         info.cg_iters += dr.cg_iters
-        coef = linesearch_coeffs(A, mu, c, x, dr.d)
+        d = dr.d
+        amax = alpha_max(x, d, opts.tau) if simplex else math.inf
+        if faces and amax < eta:
+            dbar = project_simplex(x + eta * d, opts.tau) - x
+            if (np.max(np.abs(dbar)) > 1e-15 * np.max(np.abs(x))
+                    and float(g @ dbar) < 0.0):
+                d, amax = dbar, 1.0
+                info.projected_steps += 1
+        coef = linesearch_coeffs(A, mu, c, x, d)
         info.ls_passes += 1
-        amax = (alpha_max(x, dr.d, opts.tau)
-                if opts.feasible_set == "simplex" else math.inf)
         alpha = select_step(coef, amax)
-        x = x + alpha * dr.d
+        x = x + alpha * d
         info.iterations += 1
         f_new = quartic_value(coef, alpha)
         info.history.append((gn, alpha, f_new))
@@ -436,19 +531,27 @@ def _iterate(A, mu, c, x, U, opts: Options, solver, krylov_maxit, max_iter,
             small = 0
         f_prev = f_new
     g = gradient(A, mu, c, x)
-    info.gnorm = float(np.linalg.norm(U.T @ g))
-    return x, info.gnorm <= opts.eps, True
+    Ui = face_basis(face_free(x, g, opts.tau)) if faces else U
+    info.gnorm = float(np.linalg.norm(Ui.T @ g))
+    conv = info.gnorm <= opts.eps
+    if simplex:
+        info.kkt = float(np.linalg.norm(x - project_simplex(x - g, 0.0)))
+        conv = conv or info.kkt <= opts.eps
+    return x, conv, True
 
 
 def solve(R, c, target=None, x0=None, opts: Options | None = None):
     """Algorithm 1 (YAND-MVSK) in FP64 with explicit reduced bases.
 
     Stall recovery (reading of the 'stall-recovery restarts' of Table
-    'YAND-MVSK parameter settings' for the affine budget set): when the
-    baseline budget ends above eps, or the objective stops decreasing for 3
-    iterations, restart from the current iterate with restart_max_iter
-    iterations, first with twice the Krylov budget, then with the direct
-    solve.  Status: 0 converged, 1 iteration budget exhausted.
+    'YAND-MVSK parameter settings'): when the baseline budget ends above
+    eps, or the objective stops decreasing for 3 iterations, restart from
+    the current iterate with restart_max_iter iterations.  Budget set: first
+    with twice the Krylov budget, then with the direct solve.  Simplex: with
+    the projected trial steps 0.045, then 0.02, of the same table.  The
+    boundary block needs the budget hull alone; with a return target it is
+    off (capped steps only).
+    Status: 0 converged, 1 iteration budget exhausted.
     """
     opts = opts or Options()
     c = np.asarray(c, dtype=np.float64)
@@ -459,15 +562,22 @@ def solve(R, c, target=None, x0=None, opts: Options | None = None):
         raise ValueError("start outside the interior slice")
     U = tangent_basis(C)
     info = SolveInfo()
+    eta = opts.eta if target is None else 0.0
     t0 = time.perf_counter()
     x, conv, stalled = _iterate(A, mu, c, x, U, opts, opts.solver,
-                                opts.krylov_maxit, opts.max_iter, info, t0)
+                                opts.krylov_maxit, opts.max_iter, info, t0,
+                                eta)
     if not conv and opts.stall_recovery and opts.solver == "pcg":
-        for solver, kmax in (("pcg", 2 * opts.krylov_maxit), ("direct", 0)):
+        if opts.feasible_set == "simplex" and eta > 0.0:
+            plan = [("pcg", opts.krylov_maxit, 0.045),
+                    ("pcg", opts.krylov_maxit, 0.02)]
+        else:
+            plan = [("pcg", 2 * opts.krylov_maxit, eta), ("direct", 0, eta)]
+        for solver, kmax, e in plan:
             info.restarts += 1
             t0 = time.perf_counter()
             x, conv, stalled = _iterate(A, mu, c, x, U, opts, solver, kmax,
-                                        opts.restart_max_iter, info, t0)
+                                        opts.restart_max_iter, info, t0, e)
             if conv:
                 break
     info.f = objective(A, mu, c, x)
