@@ -71,6 +71,9 @@ typedef struct yand_opts {
   double tau;             /* interior margin of Delta(tau) (1e-8)             */
   int stall_recovery;     /* PCG: restart twice when stalled                  */
   int restart_max_iter;   /* outer budget of each restart (120)               */
+  double eta;             /* simplex boundary block: nominal projected trial
+                             step (0.05; 0 = capped raw steps only).  Active
+                             on YAND_SET_SIMPLEX without a return target.    */
 } yand_opts;
 
 /* Per-solve report: counters follow the oracle-query accounting of the
@@ -90,6 +93,10 @@ typedef struct yand_info {
   int64_t third_passes;   /* third-order back-projection passes over A        */
   int64_t ls_passes;      /* line-search passes over A                        */
   int64_t dense_traces;   /* exact-trace factorisations                       */
+  double kkt;             /* projected-simplex KKT residual at w_out
+                             |w - Pi_Delta(w - grad f(w))|_2 (simplex set;
+                             NaN on the budget set)                          */
+  int projected_steps;    /* iterations that took the projected trial segment */
 } yand_info;
 
 /* Fill *opts with the direct configuration (YAND-MVSK small). */
@@ -137,6 +144,21 @@ int yand_linesearch_coeffs(yand_ctx* ctx, const double c[4], const double* w,
 int yand_select_step(yand_ctx* ctx, const double coef[5], double alpha_max,
                      double* alpha);
 
+/* Euclidean projection onto Delta(tau) = {x : x_i >= tau, sum_i x_i = 1}
+ * (the projected trial step of the implementation appendix's reduced-simplex
+ * wrapper): x = Pi(y).  y, x device (n doubles; may not overlap).  One
+ * workgroup on the null stream: bisection for the threshold theta of
+ * x_i = max(y_i - tau - theta, 0) + tau, then theta formed from the
+ * support.  Returns after the projection is done.  YAND_ERR_ARG when
+ * n < 1, tau < 0 or tau >= 1/n, or a pointer is NULL. */
+int yand_project_simplex(const double* y, int64_t n, double tau, double* x);
+
+/* Projected-simplex KKT residual |w - Pi_Delta(w - grad f(w))|_2 at w
+ * (device, n), the solution-quality metric of the computational study,
+ * written to *kkt (host).  Delta = Delta(0). */
+int yand_kkt_residual(yand_ctx* ctx, const double c[4], const double* w,
+                      double* kkt);
+
 /* Affine-normal direction with the exact log-det trace at the feasible point
  * w (Section 4.2 and Section 4.4; factor 1/(m+1) of Appendix B, Proposition
  * "A sufficient condition for the imported bounded-direction hypothesis"),
@@ -149,7 +171,13 @@ int yand_affine_normal(yand_ctx* ctx, const double c[4], const double* target,
                        double* gnorm);
 
 /* Algorithm 1: solve from w0 (device, n; NULL = equal weights moved onto the
- * target constraint) and write w_out (device, n).  info (host) is nullable. */
+ * target constraint) and write w_out (device, n).  info (host) is nullable.
+ * On YAND_SET_SIMPLEX without a target and with opts->eta > 0 the boundary
+ * block of Algorithm 1 runs: the direction lives on the current face of
+ * Delta(tau) (bound coordinates with a negative multiplier are released),
+ * a step capped below eta is replaced by the line search on the corrected
+ * segment Pi_{Delta(tau)}(w + eta d) - w when that is a descent direction,
+ * and the run also stops when the projected-KKT residual is <= eps. */
 int yand_mvsk_solve(yand_ctx* ctx, const double c[4], const double* target,
                     const double* w0, const yand_opts* opts, double* w_out,
                     yand_info* info);

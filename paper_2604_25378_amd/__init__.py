@@ -17,6 +17,7 @@ from .binding import (  # noqa: F401
     from_reduced,
     is_certified_convex,
     load,
+    project_simplex,
     reduced_coords,
     solve_R,
     warmstart_features,

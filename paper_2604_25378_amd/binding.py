@@ -41,7 +41,7 @@ class yand_opts(C.Structure):
                 ("max_elapsed", C.c_double), ("regularization", C.c_double),
                 ("krylov_tol", C.c_double), ("krylov_maxit", C.c_int),
                 ("tau", C.c_double), ("stall_recovery", C.c_int),
-                ("restart_max_iter", C.c_int)]
+                ("restart_max_iter", C.c_int), ("eta", C.c_double)]
 
 
 class yand_info(C.Structure):
@@ -51,7 +51,8 @@ class yand_info(C.Structure):
                 ("elapsed", C.c_double), ("lambda_used", C.c_double),
                 ("oracle_passes", C.c_int64), ("hvp_passes", C.c_int64),
                 ("third_passes", C.c_int64), ("ls_passes", C.c_int64),
-                ("dense_traces", C.c_int64)]
+                ("dense_traces", C.c_int64), ("kkt", C.c_double),
+                ("projected_steps", C.c_int)]
 
 
 class yand_mlp_opts(C.Structure):
@@ -123,6 +124,8 @@ def load(path: str = LIB_PATH):
         "yand_warmstart_predict": (C.c_int, [vp, vp, C.c_int64, _D, _D, vp,
                                              C.POINTER(C.c_int), _D]),
         "yand_profile_enable": (C.c_int, [vp, C.c_int]),
+        "yand_project_simplex": (C.c_int, [vp, C.c_int64, C.c_double, vp]),
+        "yand_kkt_residual": (C.c_int, [vp, _D, vp, _D]),
         "yand_autotune": (C.c_int, [vp, _D]),
         "yand_tuning": (C.c_int, [vp, C.POINTER(C.c_int), C.POINTER(C.c_int)]),
         "yand_profile_read": (C.c_int, [vp, C.c_int, C.c_char_p, C.c_int, _D,
@@ -180,6 +183,17 @@ def default_opts(**kw) -> yand_opts:
     return o
 
 
+def project_simplex(y, tau: float = 0.0):
+    """Euclidean projection of y onto Delta(tau) on the GPU."""
+    torch = _torch()
+    y = _dev(y)
+    out = torch.empty_like(y)
+    _check(load().yand_project_simplex(C.c_void_p(y.data_ptr()), y.numel(),
+                                       float(tau), C.c_void_p(out.data_ptr())),
+           "yand_project_simplex")
+    return out
+
+
 def is_certified_convex(c) -> bool:
     return bool(load().yand_is_certified_convex(_c4(c)))
 
@@ -199,6 +213,8 @@ class SolveInfo:
     third_passes: int
     ls_passes: int
     dense_traces: int
+    kkt: float
+    projected_steps: int
 
 
 class Context:
@@ -283,6 +299,14 @@ class Context:
                                         C.byref(al))
         _check(rc, "yand_select_step")
         return al.value
+
+    def kkt_residual(self, c, w) -> float:
+        w = _dev(w, self.n)
+        k = C.c_double()
+        _check(self._lib.yand_kkt_residual(self._h, _c4(c),
+                                           C.c_void_p(w.data_ptr()),
+                                           C.byref(k)), "yand_kkt_residual")
+        return k.value
 
     def affine_normal(self, c, w, target=None, opts: yand_opts | None = None):
         torch = _torch()

@@ -69,6 +69,7 @@ struct Work {
   double *part = nullptr, *psums = nullptr, *sums = nullptr,
          *trpart = nullptr;
   double *B = nullptr, *M = nullptr, *X = nullptr, *rn = nullptr;
+  double *mask = nullptr, *ptmp = nullptr;  // face mask, projection scratch
   DevScalars* sc = nullptr;
   bool own_sc = true;
   DevScalars hs{};
@@ -162,7 +163,7 @@ void free_work(Work& w) {
                     w.AE,    w.E,      w.W,     w.t3,     w.r,    w.y,
                     w.y2,    w.hv,     w.s_t,   w.pcg_s,  w.pcg_res,
                     w.pcg_p, w.pcg_u,  w.part,  w.psums,  w.sums, w.trpart,
-                    w.B,     w.M,      w.X,     w.rn};
+                    w.B,     w.M,      w.X,     w.rn,     w.mask, w.ptmp};
   for (double* p : ptrs)
     if (p) (void)hipFree(p);
   if (w.sc && w.own_sc) (void)hipFree(w.sc);
@@ -187,6 +188,7 @@ int alloc_work(Work& w, const Data& D, DevScalars* sc_external) {
       (rc = alloc((void**)&w.pcg_res, nb)) ||
       (rc = alloc((void**)&w.pcg_p, nb)) ||
       (rc = alloc((void**)&w.pcg_u, nb)) ||
+      (rc = alloc((void**)&w.mask, nb)) || (rc = alloc((void**)&w.ptmp, nb)) ||
       (rc = alloc((void**)&w.part,
                   (size_t)kMaxPassGroups * lda * sizeof(double))) ||
       (rc = alloc((void**)&w.psums,
@@ -323,7 +325,15 @@ struct DirOpts {
   int krylov_maxit = 15;
   double tau = 1e-8;
   int simplex = 0;
+  // simplex boundary block (budget hull only): face continuation and the
+  // projected trial step with nominal step eta
+  bool faces = false;
+  double eta = 0.0;
 };
+
+const double* face_mask(const Work& w, const DirOpts& o) {
+  return o.faces ? w.mask : nullptr;
+}
 
 struct DirStats {
   int cg = 0;
@@ -352,14 +362,17 @@ int dir_front(const Data& D, Work& w, const double c[4], int p0,
     return launch_syrk(D.precision, D.A, D.lda, Tp, w.s_t, w.B, w.st, skip);
   }));
   HIPTRY(launch_symm_multi(w.B, np, n, w.E, p, w.W, w.st, skip));
-  HIPTRY(launch_trace_scale(w.B, np, n, w.E, w.W, p, o.reg, w.sc, w.st));
+  HIPTRY(launch_trace_scale(w.B, np, n, w.E, w.W, p, o.reg, w.sc, w.st,
+                            face_mask(w, o)));
   return YAND_OK;
 }
 
 // Projection of B into M and the factorisation M = L L^T, X = L^-1.
-int dir_factor(const Data& D, Work& w, int p0, const int* skip) {
+int dir_factor(const Data& D, Work& w, int p0, const int* skip,
+               const double* mask = nullptr) {
   const int64_t n = D.n, np = D.lda;
-  HIPTRY(launch_project(w.B, w.M, np, n, np, w.E, w.W, p0 + 1, w.sc, w.st));
+  HIPTRY(launch_project(w.B, w.M, np, n, np, w.E, w.W, p0 + 1, w.sc, w.st,
+                        mask));
   HIPTRY(timed(w, "potrf_trtri", [&] {
     return launch_potrf_trtri(w.M, w.X, np, &w.sc->fail, w.st, skip,
                               D.chol_group);
@@ -369,14 +382,24 @@ int dir_factor(const Data& D, Work& w, int p0, const int* skip) {
 
 // Exact trace q, third-order back-projection t3 and r = P_S(B nu - |G|/(m+1) t3).
 int dir_trace(const Data& D, Work& w, const double c[4], int p0,
-              const int* skip) {
+              const int* skip, const double* mask = nullptr) {
   const int64_t n = D.n, np = D.lda, Tp = D.Tp;
   const int p = p0 + 1;
   HIPTRY(timed(w, "trace_gemm", [&] {
     return launch_trace_gemm(D.precision, D.A, D.lda, Tp, w.X, np, w.rn, w.st,
                              skip);
   }));
-  HIPTRY(launch_copy(w.AE, D.AEfix, (int64_t)p0 * Tp, w.st, skip));
+  if (mask) {
+    // the face's frame column E[0] = mask / sqrt(nfree): A E[0] afresh
+    PassArgs a = pass_args(D, w, c);
+    a.v = w.E;
+    a.tout = w.AE;
+    a.skip = skip;
+    int nwg;
+    TRY(run_pass(D, w, PassKind::Dot, a, &nwg, "dot_pass"));
+  } else {
+    HIPTRY(launch_copy(w.AE, D.AEfix, (int64_t)p0 * Tp, w.st, skip));
+  }
   HIPTRY(launch_trace_weight(w.rn, (int)D.nt, Tp, w.AE, p, w.sc, w.q, w.st));
   {
     PassArgs a = pass_args(D, w, c);
@@ -388,9 +411,9 @@ int dir_trace(const Data& D, Work& w, const double c[4], int p0,
     HIPTRY(launch_reduce_partials(w.part, nwg, D.lda, n, 1.0, 0.0, nullptr,
                                   w.t3, w.st, skip));
   }
-  const double mp1 = (double)(n - p0 + 1);
+  const double mp1 = mask ? -1.0 : (double)(n - p0 + 1);
   HIPTRY(launch_rhs(w.W + (int64_t)p0 * n, w.t3, w.E, p, n, mp1, w.sc, w.r,
-                    w.st));
+                    w.st, mask));
   return YAND_OK;
 }
 
@@ -401,7 +424,10 @@ int dir_direct_solve(const Data& D, Work& w, int p0, const double* x,
   HIPTRY(launch_trmv(w.X, np, n, w.r, w.y, w.trpart, false, w.st, skip));
   HIPTRY(launch_trmv(w.X, np, n, w.y, w.y2, w.trpart, true, w.st, skip));
   HIPTRY(launch_direction(w.y2, w.E, p0 + 1, n, x, D.mu, o.tau, o.simplex, d,
-                          w.sc, w.st));
+                          w.sc, w.st, face_mask(w, o)));
+  if (o.faces)
+    HIPTRY(launch_boundary(x, w.g, D.mu, n, o.tau, o.eta, d, w.ptmp, w.sc,
+                           w.st));
   return YAND_OK;
 }
 
@@ -437,7 +463,7 @@ __global__ void __launch_bounds__(PT)
 pcg_init_kernel(const double* __restrict__ r, const double* __restrict__ B,
                 int64_t ld, const double* __restrict__ E, int p, int64_t n,
                 double* s, double* res, double* pv, double* u,
-                DevScalars* sc) {
+                DevScalars* sc, const double* __restrict__ mask) {
   __shared__ double sh[4 * 16];
   const int tid = threadIdx.x;
   const double lam = sc->lambda;
@@ -445,7 +471,7 @@ pcg_init_kernel(const double* __restrict__ r, const double* __restrict__ B,
   for (int64_t j = tid; j < n; j += PT) {
     s[j] = 0.0;
     res[j] = r[j];
-    double uj = r[j] / precond_diag(B, ld, j, lam);
+    double uj = (mask ? mask[j] : 1.0) * r[j] / precond_diag(B, ld, j, lam);
     u[j] = uj;
     for (int a = 0; a < p; ++a) dots[a] += E[a * n + j] * uj;
     dots[3] += r[j] * r[j];
@@ -472,13 +498,13 @@ __global__ void __launch_bounds__(PT)
 pcg_update_kernel(const double* __restrict__ Hp, const double* __restrict__ B,
                   int64_t ld, const double* __restrict__ E, int p, int64_t n,
                   double* s, double* res, double* pv, double* u, double* Ap,
-                  DevScalars* sc) {
+                  DevScalars* sc, const double* __restrict__ mask) {
   __shared__ double sh[4 * 16];
   const int tid = threadIdx.x;
   const double lam = sc->lambda;
   double dots[4] = {0, 0, 0, 0};
   for (int64_t j = tid; j < n; j += PT) {
-    double a = Hp[j] + lam * pv[j];
+    double a = (mask ? mask[j] : 1.0) * (Hp[j] + lam * pv[j]);
     Ap[j] = a;
     for (int k = 0; k < p; ++k) dots[k] += E[k * n + j] * a;
   }
@@ -498,7 +524,7 @@ pcg_update_kernel(const double* __restrict__ Hp, const double* __restrict__ B,
     s[j] += al * pv[j];
     double rj = res[j] - al * Ap[j];
     res[j] = rj;
-    double uj = rj / precond_diag(B, ld, j, lam);
+    double uj = (mask ? mask[j] : 1.0) * rj / precond_diag(B, ld, j, lam);
     u[j] = uj;
     for (int k = 0; k < p; ++k) d2[k] += E[k * n + j] * uj;
     d2[3] += rj * rj;
@@ -526,8 +552,10 @@ int dir_pcg_solve(const Data& D, Work& w, const double c[4], int p0,
                   DirStats* stats) {
   const int64_t n = D.n, np = D.lda;
   const int p = p0 + 1;
+  const double* mask = face_mask(w, o);
   hipLaunchKernelGGL(pcg_init_kernel, dim3(1), dim3(PT), 0, w.st, w.r, w.B, np,
-                     w.E, p, n, w.pcg_s, w.pcg_res, w.pcg_p, w.pcg_u, w.sc);
+                     w.E, p, n, w.pcg_s, w.pcg_res, w.pcg_p, w.pcg_u, w.sc,
+                     mask);
   TRY(sync_scalars(w));
   const double r0 = std::sqrt(w.hs.aux[2]);
   int it = 0;
@@ -535,7 +563,7 @@ int dir_pcg_solve(const Data& D, Work& w, const double c[4], int p0,
     TRY(hvp_cached(D, w, c, w.pcg_p, w.hv, nullptr));
     hipLaunchKernelGGL(pcg_update_kernel, dim3(1), dim3(PT), 0, w.st, w.hv,
                        w.B, np, w.E, p, n, w.pcg_s, w.pcg_res, w.pcg_p,
-                       w.pcg_u, w.y, w.sc);
+                       w.pcg_u, w.y, w.sc, mask);
     ++it;
     TRY(sync_scalars(w));
     if (std::sqrt(w.hs.aux[1]) <= o.krylov_tol * r0) break;
@@ -543,7 +571,10 @@ int dir_pcg_solve(const Data& D, Work& w, const double c[4], int p0,
   }
   if (stats) stats->cg += it;
   HIPTRY(launch_direction(w.pcg_s, w.E, p, n, x, D.mu, o.tau, o.simplex, d,
-                          w.sc, w.st));
+                          w.sc, w.st, mask));
+  if (o.faces)
+    HIPTRY(launch_boundary(x, w.g, D.mu, n, o.tau, o.eta, d, w.ptmp, w.sc,
+                           w.st));
   return YAND_OK;
 }
 
@@ -555,7 +586,7 @@ int direction_eager(const Data& D, Work& w, const double c[4], int p0,
                     DirStats* stats) {
   TRY(dir_front(D, w, c, p0, o, nullptr));
   for (int attempt = 0;; ++attempt) {
-    TRY(dir_factor(D, w, p0, nullptr));
+    TRY(dir_factor(D, w, p0, nullptr, face_mask(w, o)));
     TRY(sync_scalars(w));
     if (!w.hs.fail) break;
     if (attempt >= 8) return YAND_ERR_INDEFINITE;
@@ -564,7 +595,7 @@ int direction_eager(const Data& D, Work& w, const double c[4], int p0,
                        lam);
     if (stats) stats->escalations++;
   }
-  TRY(dir_trace(D, w, c, p0, nullptr));
+  TRY(dir_trace(D, w, c, p0, nullptr, face_mask(w, o)));
   if (o.solver == YAND_SOLVER_DIRECT)
     return dir_direct_solve(D, w, p0, x, o, d, nullptr);
   return dir_pcg_solve(D, w, c, p0, x, o, d, stats);
@@ -573,14 +604,28 @@ int direction_eager(const Data& D, Work& w, const double c[4], int p0,
 // One outer iteration of the direct configuration, enqueued with no host
 // synchronisation: oracle, stationarity (sets done when |G| <= eps), exact-
 // trace direction, line search, step, update.
+// After the oracle pass at w.x: the face of Delta(tau) (boundary block),
+// the projected gradient with the done test, and on the simplex the
+// projected-KKT residual, which also ends the run at or below eps.
+int stationarity(const Data& D, Work& w, const DirOpts& o, int p0,
+                 double eps) {
+  if (o.faces)
+    HIPTRY(launch_face(w.x, w.g, D.n, o.tau, w.E, w.mask, w.sc, w.st));
+  HIPTRY(launch_grad_project(w.g, w.E, p0, D.n, w.sc, w.st, eps,
+                             face_mask(w, o)));
+  if (o.simplex)
+    HIPTRY(launch_kkt(w.x, w.g, D.n, eps, w.ptmp, w.sc, w.st));
+  return YAND_OK;
+}
+
 int enqueue_iteration(const Data& D, Work& w, const double c[4], int p0,
                       const DirOpts& o, double eps) {
   const int* skip = &w.sc->done;
   TRY(oracle_at(D, w, c, w.x, true, &w.sc->frozen));
-  HIPTRY(launch_grad_project(w.g, w.E, p0, D.n, w.sc, w.st, eps));
+  TRY(stationarity(D, w, o, p0, eps));
   TRY(dir_front(D, w, c, p0, o, skip));
-  TRY(dir_factor(D, w, p0, skip));
-  TRY(dir_trace(D, w, c, p0, skip));
+  TRY(dir_factor(D, w, p0, skip, face_mask(w, o)));
+  TRY(dir_trace(D, w, c, p0, skip, face_mask(w, o)));
   TRY(dir_direct_solve(D, w, p0, w.x, o, w.d, skip));
   TRY(line_at(D, w, c, w.d, 1, skip));
   HIPTRY(launch_axpy(w.x, w.d, D.n, w.sc, w.st));
@@ -699,6 +744,7 @@ int after_iteration(Lane& L, const yand_opts& opts, const DirOpts& o) {
   L.info.oracle_passes++;
   L.info.f = s.f;
   L.info.gnorm = s.gn;
+  L.info.kkt = o.simplex ? s.kkt : NAN;
   if (s.nonfinite) {
     L.rc = YAND_ERR_NONFINITE;
     L.active = false;
@@ -726,6 +772,7 @@ int after_iteration(Lane& L, const yand_opts& opts, const DirOpts& o) {
   L.info.dense_traces++;
   L.info.third_passes++;
   L.info.ls_passes++;
+  if (w.hs.projected) L.info.projected_steps++;
   L.info.lambda_used = w.hs.lambda;
   if (w.hs.status != 0) {
     L.rc = YAND_ERR_UNBOUNDED;
@@ -747,14 +794,15 @@ int after_iteration(Lane& L, const yand_opts& opts, const DirOpts& o) {
 }
 
 // Final stationarity check of a lane that stopped without converging.
-int final_check(Lane& L, const yand_opts& opts) {
+int final_check(Lane& L, const yand_opts& opts, const DirOpts& o) {
   Work& w = *L.w;
   hipLaunchKernelGGL(set_frozen_kernel, dim3(1), dim3(64), 0, w.st, w.sc, 0);
   TRY(oracle_at(*L.D, w, L.c, w.x, true));
-  HIPTRY(launch_grad_project(w.g, w.E, L.p0, L.D->n, w.sc, w.st, opts.eps));
+  TRY(stationarity(*L.D, w, o, L.p0, opts.eps));
   TRY(sync_scalars(w));
   L.info.f = w.hs.f;
   L.info.gnorm = w.hs.gn;
+  L.info.kkt = o.simplex ? w.hs.kkt : NAN;
   L.info.oracle_passes++;
   if (w.hs.done) L.converged = true;
   return YAND_OK;
@@ -859,7 +907,7 @@ int run_lanes(std::vector<Lane>& lanes, const yand_opts& opts,
   cleanup();
   if (rc) return rc;
   for (auto& L : lanes)
-    if (L.rc == YAND_OK && !L.converged) TRY(final_check(L, opts));
+    if (L.rc == YAND_OK && !L.converged) TRY(final_check(L, opts, o));
   return YAND_OK;
 }
 
@@ -978,6 +1026,7 @@ void yand_default_opts(yand_opts* o) {
   o->tau = 1e-8;
   o->stall_recovery = 1;
   o->restart_max_iter = 120;
+  o->eta = 0.05;
 }
 
 void yand_large_opts(yand_opts* o) {
@@ -1176,6 +1225,27 @@ int yand_affine_normal(yand_ctx* ctx, const double c[4], const double* target,
   return W.hs.nonfinite ? YAND_ERR_NONFINITE : YAND_OK;
 }
 
+int yand_project_simplex(const double* y, int64_t n, double tau, double* x) {
+  if (!y || !x || n < 1 || !(tau >= 0.0) || !(tau * (double)n < 1.0))
+    return YAND_ERR_ARG;
+  HIPTRY(launch_project_simplex(y, n, tau, x, nullptr));
+  HIPTRY(hipStreamSynchronize(nullptr));
+  return YAND_OK;
+}
+
+int yand_kkt_residual(yand_ctx* ctx, const double c[4], const double* w,
+                      double* kkt) {
+  if (!ctx || !w || !kkt) return YAND_ERR_ARG;
+  TRY(check_c(c));
+  Work& W = ctx->w;
+  hipLaunchKernelGGL(set_frozen_kernel, dim3(1), dim3(64), 0, W.st, W.sc, 0);
+  TRY(oracle_at(ctx->d, W, c, w, true));
+  HIPTRY(launch_kkt(w, W.g, ctx->d.n, -1.0, W.ptmp, W.sc, W.st));
+  TRY(sync_scalars(W));
+  *kkt = W.hs.kkt;
+  return W.hs.nonfinite ? YAND_ERR_NONFINITE : YAND_OK;
+}
+
 // PCG configuration with stall recovery (eager; the Krylov test is on the host).
 static int solve_pcg(yand_ctx* ctx, const double c[4], int p0,
                      const yand_opts& opts, yand_info& inf, bool* converged) {
@@ -1184,17 +1254,29 @@ static int solve_pcg(yand_ctx* ctx, const double c[4], int p0,
   DirOpts o;
   o.tau = opts.tau;
   o.simplex = opts.feasible_set == YAND_SET_SIMPLEX;
+  o.faces = o.simplex && opts.eta > 0.0 && p0 == 1;
   struct Phase {
     int solver, kmax, max_iter;
-    double reg;
+    double reg, eta;
   };
+  // stall recovery: budget set, twice the Krylov budget then the direct
+  // solve; simplex boundary block, the projected trial steps 0.045 then
+  // 0.02 (Appendix D, Table "YAND-MVSK parameter settings")
   std::vector<Phase> phases;
   phases.push_back({YAND_SOLVER_PCG, opts.krylov_maxit, opts.max_iter,
-                    opts.regularization});
+                    opts.regularization, opts.eta});
   if (opts.stall_recovery) {
-    phases.push_back({YAND_SOLVER_PCG, 2 * opts.krylov_maxit,
-                      opts.restart_max_iter, opts.regularization});
-    phases.push_back({YAND_SOLVER_DIRECT, 0, opts.restart_max_iter, 0.0});
+    if (o.faces) {
+      phases.push_back({YAND_SOLVER_PCG, opts.krylov_maxit,
+                        opts.restart_max_iter, opts.regularization, 0.045});
+      phases.push_back({YAND_SOLVER_PCG, opts.krylov_maxit,
+                        opts.restart_max_iter, opts.regularization, 0.02});
+    } else {
+      phases.push_back({YAND_SOLVER_PCG, 2 * opts.krylov_maxit,
+                        opts.restart_max_iter, opts.regularization, opts.eta});
+      phases.push_back({YAND_SOLVER_DIRECT, 0, opts.restart_max_iter, 0.0,
+                        opts.eta});
+    }
   }
   *converged = false;
   for (size_t ph = 0; ph < phases.size() && !*converged; ++ph) {
@@ -1202,19 +1284,21 @@ static int solve_pcg(yand_ctx* ctx, const double c[4], int p0,
     o.solver = phases[ph].solver;
     o.krylov_maxit = phases[ph].kmax;
     o.reg = phases[ph].reg;
+    o.eta = phases[ph].eta;
     const auto t_phase = std::chrono::steady_clock::now();
     int small = 0;
     double f_prev = NAN;
     for (int it = 0;; ++it) {
       TRY(oracle_at(D, w, c, w.x, true));
       inf.oracle_passes++;
-      HIPTRY(launch_grad_project(w.g, w.E, p0, D.n, w.sc, w.st));
+      TRY(stationarity(D, w, o, p0, opts.eps));
       TRY(sync_scalars(w));
       inf.f = w.hs.f;
       inf.gnorm = w.hs.gn;
+      inf.kkt = o.simplex ? w.hs.kkt : NAN;
       if (w.hs.nonfinite) return YAND_ERR_NONFINITE;
       if (std::isnan(f_prev)) f_prev = w.hs.f;
-      if (w.hs.gn <= opts.eps) {
+      if (w.hs.done) {
         *converged = true;
         break;
       }
@@ -1233,6 +1317,7 @@ static int solve_pcg(yand_ctx* ctx, const double c[4], int p0,
       inf.ls_passes++;
       TRY(sync_scalars(w));
       inf.lambda_used = w.hs.lambda;
+      if (w.hs.projected) inf.projected_steps++;
       if (w.hs.status != 0) return YAND_ERR_UNBOUNDED;
       HIPTRY(launch_axpy(w.x, w.d, D.n, w.sc, w.st));
       inf.iterations++;
@@ -1254,7 +1339,8 @@ static bool valid_opts(const yand_opts& o) {
          (o.solver == YAND_SOLVER_DIRECT || o.solver == YAND_SOLVER_PCG) &&
          (o.feasible_set == YAND_SET_BUDGET ||
           o.feasible_set == YAND_SET_SIMPLEX) &&
-         o.krylov_maxit >= 0 && o.restart_max_iter >= 0;
+         o.krylov_maxit >= 0 && o.restart_max_iter >= 0 && o.eta >= 0.0 &&
+         std::isfinite(o.eta);
 }
 
 int yand_mvsk_solve(yand_ctx* ctx, const double c[4], const double* target,
@@ -1284,6 +1370,8 @@ int yand_mvsk_solve(yand_ctx* ctx, const double c[4], const double* target,
     DirOpts o;
     o.tau = opts.tau;
     o.simplex = opts.feasible_set == YAND_SET_SIMPLEX;
+    o.faces = o.simplex && opts.eta > 0.0 && p0 == 1;
+    o.eta = opts.eta;
     std::vector<Lane> lanes(1);
     Lane& L = lanes[0];
     L.D = &D;
@@ -1351,6 +1439,8 @@ static int batch_solve(int64_t B, yand_ctx* const* ctxs, const double* C4,
   DirOpts o;
   o.tau = opts.tau;
   o.simplex = opts.feasible_set == YAND_SET_SIMPLEX;
+  o.faces = o.simplex && opts.eta > 0.0 && !targets;
+  o.eta = opts.eta;
   // lane count: bounded by max_lanes and by free device memory
   size_t freeb = 0, totalb = 0;
   (void)hipMemGetInfo(&freeb, &totalb);

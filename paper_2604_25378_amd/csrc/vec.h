@@ -27,28 +27,59 @@ struct DevScalars {
   int pad;
   int done;          // |G| <= eps at this iteration: the rest is skipped
   int frozen;        // lane stopped by the host: every pass is skipped
+  double kkt;        // projected-simplex KKT residual (simplex set)
+  double nfree;      // free coordinates of the current face (simplex set)
+  int projected;     // this iteration took the projected trial segment
+  int pad2;
 };
+
+// Face masks: mask[j] = 1 for a free coordinate of the current face of
+// Delta(tau), 0 for a bound one; nullptr means every coordinate is free
+// (affine budget set).  With a mask the first frame column E[0] holds
+// mask / sqrt(nfree), and the projector P_S = diag(mask) - sum_a e_a e_a^T.
 
 // eps < 0: never mark done.  Also clears fail and status for the iteration.
 hipError_t launch_grad_project(const double* g, double* E, int p0, int64_t n,
                                DevScalars* sc, hipStream_t st,
-                               double eps = -1.0);
+                               double eps = -1.0,
+                               const double* mask = nullptr);
 hipError_t launch_trace_scale(const double* B, int64_t ld, int64_t n,
                               const double* E, const double* W, int p,
-                              double reg, DevScalars* sc, hipStream_t st);
+                              double reg, DevScalars* sc, hipStream_t st,
+                              const double* mask = nullptr);
 hipError_t launch_project(const double* B, double* M, int64_t ld, int64_t n,
                           int64_t np, const double* E, const double* W, int p,
-                          const DevScalars* sc, hipStream_t st);
+                          const DevScalars* sc, hipStream_t st,
+                          const double* mask = nullptr);
 hipError_t launch_trace_weight(const double* rn, int nt, int64_t Tp,
                                const double* AE, int p, const DevScalars* sc,
                                double* q, hipStream_t st);
+// mp1 < 0: take m + 1 from the face (nfree - p + 2).
 hipError_t launch_rhs(const double* Bnu, const double* t3, const double* E,
                       int p, int64_t n, double mp1, const DevScalars* sc,
-                      double* r, hipStream_t st);
+                      double* r, hipStream_t st, const double* mask = nullptr);
 hipError_t launch_direction(const double* y, const double* E, int p,
                             int64_t n, const double* x, const double* mu,
                             double tau, int simplex, double* d,
-                            DevScalars* sc, hipStream_t st);
+                            DevScalars* sc, hipStream_t st,
+                            const double* mask = nullptr);
+// Face of Delta(tau) at x: mask, E[0] = mask / sqrt(nfree), sc->nfree.
+hipError_t launch_face(const double* x, const double* g, int64_t n, double tau,
+                       double* E, double* mask, DevScalars* sc,
+                       hipStream_t st);
+// sc->kkt = |x - Pi_Delta(x - g)|_2; done when kkt <= eps (eps >= 0).
+// tmp: n doubles.
+hipError_t launch_kkt(const double* x, const double* g, int64_t n, double eps,
+                      double* tmp, DevScalars* sc, hipStream_t st);
+// Boundary block: when sc->amax < eta, replace d by the corrected segment
+// Pi_{Delta(tau)}(x + eta d) - x if it is a nonzero descent direction (cap
+// 1, mu^T d updated, sc->projected set).  tmp: n doubles.
+hipError_t launch_boundary(const double* x, const double* g, const double* mu,
+                           int64_t n, double tau, double eta, double* d,
+                           double* tmp, DevScalars* sc, hipStream_t st);
+// out = Pi_{Delta(tau)}(y) (one workgroup).
+hipError_t launch_project_simplex(const double* y, int64_t n, double tau,
+                                  double* out, hipStream_t st);
 // dst[i] = src[i] unless *skip; fill dst with v unless *skip.
 hipError_t launch_copy(double* dst, const double* src, int64_t count,
                        hipStream_t st, const int* skip = nullptr);

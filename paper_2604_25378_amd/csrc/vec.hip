@@ -30,12 +30,18 @@ __device__ void block_sum(double (&v)[K], double* sh) {
   __syncthreads();
 }
 
+// Mask value of coordinate j (1 when there is no mask).
+__device__ __forceinline__ double mk(const double* m, int64_t j) {
+  return m ? m[j] : 1.0;
+}
+
 // G = g - sum_{a<p0} (e_a^T g) e_a, gn = |G|, nu = G / gn stored as E[p0].
 // (Definition "Tangent-gradient residual"; Proposition "Affine-subspace
 // reduction": |gbar| = |P_T g|.)
 __global__ void __launch_bounds__(VT)
 grad_project_kernel(const double* __restrict__ g, double* __restrict__ E,
-                    int p0, int64_t n, DevScalars* sc, double eps) {
+                    int p0, int64_t n, DevScalars* sc, double eps,
+                    const double* __restrict__ mask) {
   __shared__ double sh[4 * VW];
   const int tid = threadIdx.x;
   double dots[2] = {0.0, 0.0};
@@ -44,7 +50,7 @@ grad_project_kernel(const double* __restrict__ g, double* __restrict__ E,
   block_sum(dots, sh);
   double ss[1] = {0.0};
   for (int64_t j = tid; j < n; j += VT) {
-    double G = g[j];
+    double G = mk(mask, j) * g[j];
     for (int a = 0; a < p0; ++a) G -= dots[a] * E[a * n + j];
     ss[0] += G * G;
   }
@@ -52,7 +58,7 @@ grad_project_kernel(const double* __restrict__ g, double* __restrict__ E,
   const double gn = sqrt(ss[0]);
   const double inv = gn > 0.0 ? 1.0 / gn : 0.0;
   for (int64_t j = tid; j < n; j += VT) {
-    double G = g[j];
+    double G = mk(mask, j) * g[j];
     for (int a = 0; a < p0; ++a) G -= dots[a] * E[a * n + j];
     E[p0 * n + j] = G * inv;
   }
@@ -65,6 +71,7 @@ grad_project_kernel(const double* __restrict__ g, double* __restrict__ E,
     sc->fail = 0;
     sc->status = 0;
     sc->alpha = 0.0;
+    sc->projected = 0;
   }
 }
 
@@ -73,12 +80,15 @@ grad_project_kernel(const double* __restrict__ g, double* __restrict__ E,
 __global__ void __launch_bounds__(VT)
 trace_scale_kernel(const double* __restrict__ B, int64_t ld, int64_t n,
                    const double* __restrict__ E, const double* __restrict__ W,
-                   int p, double reg, DevScalars* sc) {
+                   int p, double reg, DevScalars* sc,
+                   const double* __restrict__ mask) {
   if (sc->done) return;
   __shared__ double sh[4 * VW];
   const int tid = threadIdx.x;
+  // traces over the free coordinates of the face
+  const double neff = mask ? sc->nfree : (double)n;
   double t[1] = {0.0};
-  for (int64_t j = tid; j < n; j += VT) t[0] += B[j * ld + j];
+  for (int64_t j = tid; j < n; j += VT) t[0] += mk(mask, j) * B[j * ld + j];
   block_sum(t, sh);
   double ge[9];
   for (int a = 0; a < p; ++a) {
@@ -95,10 +105,10 @@ trace_scale_kernel(const double* __restrict__ B, int64_t ld, int64_t n,
       for (int b = 0; b < p; ++b)
         sc->GE[a * 3 + b] = 0.5 * (ge[a * 3 + b] + ge[b * 3 + a]);
     sc->tr = t[0];
-    double gam = t[0] / (double)n;
+    double gam = t[0] / neff;
     if (!(gam > 0.0) || !isfinite(gam)) gam = 1.0;
     sc->gamma = gam;
-    double tang = (t[0] - trg) / (double)(n - p);
+    double tang = (t[0] - trg) / (neff - (double)p);
     if (!(tang > 0.0) || !isfinite(tang)) tang = gam;
     sc->tang_scale = tang;
     sc->lambda = reg * tang;
@@ -106,12 +116,17 @@ trace_scale_kernel(const double* __restrict__ B, int64_t ld, int64_t n,
 }
 
 // Lower triangle of M = P_S B P_S + lambda P_S + gamma (I - P_S), with
-// P_S = I - E E^T; identity on the padding.
+// P_S = diag(mask) - E E^T; identity on the padding.  A bound coordinate i
+// of a face gets M_ii = 1e30 gamma instead of gamma: any positive scale of
+// that block leaves K = P_S M^-1 P_S unchanged, and this one makes its share
+// a_ti^2 / M_ii of |L^-1 a_t|^2 vanish below FP64 resolution, so the exact
+// trace needs no correction for the bound coordinates.
 __global__ void project_kernel(const double* __restrict__ B, double* M,
                                int64_t ld, int64_t n, int64_t np,
                                const double* __restrict__ E,
                                const double* __restrict__ W, int p,
-                               const DevScalars* __restrict__ sc) {
+                               const DevScalars* __restrict__ sc,
+                               const double* __restrict__ mask) {
   if (sc->done) return;
   const int64_t i = blockIdx.y;
   const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -126,15 +141,16 @@ __global__ void project_kernel(const double* __restrict__ B, double* M,
       wi[a] = W[a * n + i];
       wj[a] = W[a * n + j];
     }
-    v = B[i * ld + j];
+    const double mi = mk(mask, i), mj = mk(mask, j);
+    v = mi * mj * B[i * ld + j];
     double ee = 0.0;
     for (int a = 0; a < p; ++a) {
-      v -= ei[a] * wj[a] + wi[a] * ej[a];
+      v -= ei[a] * (mj * wj[a]) + (mi * wi[a]) * ej[a];
       ee += ei[a] * ej[a];
       for (int b = 0; b < p; ++b) v += ei[a] * sc->GE[a * 3 + b] * ej[b];
     }
     v += (gam - lam) * ee;
-    if (i == j) v += lam;
+    if (i == j) v += mi != 0.0 ? lam : 1e30 * gam;
   } else {
     v = i == j ? 1.0 : 0.0;
   }
@@ -164,19 +180,21 @@ __global__ void trace_weight_kernel(const double* __restrict__ rn, int nt,
 __global__ void __launch_bounds__(VT)
 rhs_kernel(const double* __restrict__ Bnu, const double* __restrict__ t3,
            const double* __restrict__ E, int p, int64_t n, double mp1,
-           const DevScalars* __restrict__ sc, double* __restrict__ r) {
+           const DevScalars* __restrict__ sc, double* __restrict__ r,
+           const double* __restrict__ mask) {
   if (sc->done) return;
   __shared__ double sh[4 * VW];
   const int tid = threadIdx.x;
+  if (mp1 < 0.0) mp1 = sc->nfree - (double)p + 2.0;
   const double coef = sc->gn / mp1;
   double dots[3] = {0.0, 0.0, 0.0};
   for (int64_t j = tid; j < n; j += VT) {
-    double v = Bnu[j] - coef * t3[j];
+    double v = mk(mask, j) * (Bnu[j] - coef * t3[j]);
     for (int a = 0; a < p; ++a) dots[a] += E[a * n + j] * v;
   }
   block_sum(dots, sh);
   for (int64_t j = tid; j < n; j += VT) {
-    double v = Bnu[j] - coef * t3[j];
+    double v = mk(mask, j) * (Bnu[j] - coef * t3[j]);
     for (int a = 0; a < p; ++a) v -= dots[a] * E[a * n + j];
     r[j] = v;
   }
@@ -188,7 +206,8 @@ __global__ void __launch_bounds__(VT)
 direction_kernel(const double* __restrict__ y, const double* __restrict__ E,
                  int p, int64_t n, const double* __restrict__ x,
                  const double* __restrict__ mu, double tau, int simplex,
-                 double* __restrict__ d, DevScalars* sc) {
+                 double* __restrict__ d, DevScalars* sc,
+                 const double* __restrict__ mask) {
   if (sc->done) return;
   __shared__ double sh[4 * VW];
   const int tid = threadIdx.x;
@@ -199,7 +218,7 @@ direction_kernel(const double* __restrict__ y, const double* __restrict__ E,
   double md[1] = {0.0};
   double am = INFINITY;
   for (int64_t j = tid; j < n; j += VT) {
-    double v = y[j];
+    double v = mk(mask, j) * y[j];
     for (int a = 0; a < p; ++a) v -= dots[a] * E[a * n + j];
     v -= E[(p - 1) * n + j];
     d[j] = v;
@@ -215,6 +234,160 @@ direction_kernel(const double* __restrict__ y, const double* __restrict__ E,
     for (int i = 0; i < VW; ++i) m = fmin(m, sh[i]);
     sc->mud = md[0];
     sc->amax = simplex ? m : INFINITY;
+  }
+}
+
+// ------------------------------------------------ simplex boundary block --
+// Largest value over the workgroup (all threads get it).
+__device__ double block_max(double v, double* sh) {
+  const int tid = threadIdx.x;
+  v = -wave_min(-v);
+  if ((tid & 63) == 0) sh[tid >> 6] = v;
+  __syncthreads();
+  double m = -INFINITY;
+  for (int i = 0; i < VW; ++i) m = fmax(m, sh[i]);
+  __syncthreads();
+  return m;
+}
+
+// out = Pi_{Delta(tau)}(y), y_j = fy(j), by one workgroup: with u = y - tau
+// and s = 1 - n tau, the threshold theta solves h(theta) = s for the
+// decreasing h(theta) = sum_j max(u_j - theta, 0).  Bisection on
+// [max u - s, max u] (where h >= s and h = 0) until the interval stops
+// shrinking brackets theta between two neighbouring doubles; theta is then
+// formed exactly from the support {u_j > lo}: (sum_S u_j - s) / |S|, and
+// out_j = max(u_j - theta, 0) + tau.  Every loop bound and branch depends
+// only on block-reduced values, so all threads take the same path.
+template <class FY>
+__device__ void simplex_project(FY fy, int64_t n, double tau, double* out,
+                                double* sh) {
+  const int tid = threadIdx.x;
+  const double s = 1.0 - (double)n * tau;
+  double mx = -INFINITY;
+  for (int64_t j = tid; j < n; j += VT) mx = fmax(mx, fy(j) - tau);
+  mx = block_max(mx, sh);
+  double lo = mx - s, hi = mx;
+  for (int it = 0; it < 200; ++it) {
+    const double mid = 0.5 * (lo + hi);
+    if (!(mid > lo && mid < hi)) break;
+    double h[1] = {0.0};
+    for (int64_t j = tid; j < n; j += VT) h[0] += fmax(fy(j) - tau - mid, 0.0);
+    block_sum(h, sh);
+    if (h[0] >= s)
+      lo = mid;
+    else
+      hi = mid;
+  }
+  double v[2] = {0.0, 0.0};
+  for (int64_t j = tid; j < n; j += VT) {
+    const double u = fy(j) - tau;
+    if (u > lo) {
+      v[0] += u;
+      v[1] += 1.0;
+    }
+  }
+  block_sum(v, sh);
+  const double theta = (v[0] - s) / v[1];
+  for (int64_t j = tid; j < n; j += VT)
+    out[j] = fmax(fy(j) - tau - theta, 0.0) + tau;
+  __syncthreads();
+}
+
+__global__ void __launch_bounds__(VT)
+project_simplex_kernel(const double* __restrict__ y, int64_t n, double tau,
+                       double* __restrict__ out) {
+  __shared__ double sh[4 * VW];
+  simplex_project([&](int64_t j) { return y[j]; }, n, tau, out, sh);
+}
+
+// Face of Delta(tau) at x (boundary block of Algorithm 1: continuation on
+// the exposed face).  Coordinates above the slice bound, x_j > tau (1 +
+// 1e-6), are free; a bound coordinate is released when its multiplier
+// g_j - nu is negative, nu the mean of g over the coordinates above the
+// bound.  Writes the mask, E[0] = mask / sqrt(nfree) and sc->nfree.
+__global__ void __launch_bounds__(VT)
+face_kernel(const double* __restrict__ x, const double* __restrict__ g,
+            int64_t n, double tau, double* __restrict__ E,
+            double* __restrict__ mask, DevScalars* sc) {
+  if (sc->frozen) return;
+  __shared__ double sh[4 * VW];
+  const int tid = threadIdx.x;
+  const double thr = tau * (1.0 + 1e-6);
+  double v[2] = {0.0, 0.0};
+  for (int64_t j = tid; j < n; j += VT)
+    if (x[j] > thr) {
+      v[0] += g[j];
+      v[1] += 1.0;
+    }
+  block_sum(v, sh);
+  const double nu = v[0] / v[1];
+  double cnt[1] = {0.0};
+  for (int64_t j = tid; j < n; j += VT) {
+    const double m = (x[j] > thr || g[j] < nu) ? 1.0 : 0.0;
+    mask[j] = m;
+    cnt[0] += m;
+  }
+  block_sum(cnt, sh);
+  const double inv = 1.0 / sqrt(cnt[0]);
+  for (int64_t j = tid; j < n; j += VT) E[j] = mask[j] * inv;
+  if (tid == 0) sc->nfree = cnt[0];
+}
+
+// Projected-simplex KKT residual |x - Pi_Delta(x - g)|_2 (Delta = Delta(0)).
+__global__ void __launch_bounds__(VT)
+kkt_kernel(const double* __restrict__ x, const double* __restrict__ g,
+           int64_t n, double eps, double* __restrict__ tmp, DevScalars* sc) {
+  if (sc->frozen) return;
+  __shared__ double sh[4 * VW];
+  const int tid = threadIdx.x;
+  simplex_project([&](int64_t j) { return x[j] - g[j]; }, n, 0.0, tmp, sh);
+  double r[1] = {0.0};
+  for (int64_t j = tid; j < n; j += VT) {
+    const double e = x[j] - tmp[j];
+    r[0] += e * e;
+  }
+  block_sum(r, sh);
+  if (tid == 0) {
+    const double k = sqrt(r[0]);
+    sc->kkt = k;
+    if (eps >= 0.0 && k <= eps) sc->done = 1;
+  }
+}
+
+// Boundary block: the raw step is capped below the nominal step eta, so the
+// trial x + eta d is projected onto Delta(tau) and the corrected segment
+// dbar = xbar - x replaces d (cap 1) when it is a descent direction
+// (g^T dbar < 0) and not numerically zero (max |dbar| > 1e-15 max |x|).
+// Otherwise d stays and the capped step exposes the next face.
+__global__ void __launch_bounds__(VT)
+boundary_kernel(const double* __restrict__ x, const double* __restrict__ g,
+                const double* __restrict__ mu, int64_t n, double tau,
+                double eta, double* __restrict__ d, double* __restrict__ tmp,
+                DevScalars* sc) {
+  if (sc->done || !(sc->amax < eta)) return;
+  __shared__ double sh[4 * VW];
+  const int tid = threadIdx.x;
+  simplex_project([&](int64_t j) { return x[j] + eta * d[j]; }, n, tau, tmp,
+                  sh);
+  double dm = 0.0, xm = 0.0;
+  double v[2] = {0.0, 0.0};
+  for (int64_t j = tid; j < n; j += VT) {
+    const double db = tmp[j] - x[j];
+    tmp[j] = db;
+    dm = fmax(dm, fabs(db));
+    xm = fmax(xm, fabs(x[j]));
+    v[0] += g[j] * db;
+    v[1] += mu[j] * db;
+  }
+  dm = block_max(dm, sh);
+  xm = block_max(xm, sh);
+  block_sum(v, sh);
+  if (!(dm > 1e-15 * xm && v[0] < 0.0)) return;
+  for (int64_t j = tid; j < n; j += VT) d[j] = tmp[j];
+  if (tid == 0) {
+    sc->mud = v[1];
+    sc->amax = 1.0;
+    sc->projected = 1;
   }
 }
 
@@ -432,24 +605,27 @@ __global__ void fill_kernel(double* __restrict__ dst, int64_t count, double v,
 // ------------------------------------------------------------ launchers --
 
 hipError_t launch_grad_project(const double* g, double* E, int p0, int64_t n,
-                               DevScalars* sc, hipStream_t st, double eps) {
+                               DevScalars* sc, hipStream_t st, double eps,
+                               const double* mask) {
   hipLaunchKernelGGL(grad_project_kernel, dim3(1), dim3(VT), 0, st, g, E, p0,
-                     n, sc, eps);
+                     n, sc, eps, mask);
   return hipGetLastError();
 }
 hipError_t launch_trace_scale(const double* B, int64_t ld, int64_t n,
                               const double* E, const double* W, int p,
-                              double reg, DevScalars* sc, hipStream_t st) {
+                              double reg, DevScalars* sc, hipStream_t st,
+                              const double* mask) {
   hipLaunchKernelGGL(trace_scale_kernel, dim3(1), dim3(VT), 0, st, B, ld, n,
-                     E, W, p, reg, sc);
+                     E, W, p, reg, sc, mask);
   return hipGetLastError();
 }
 hipError_t launch_project(const double* B, double* M, int64_t ld, int64_t n,
                           int64_t np, const double* E, const double* W, int p,
-                          const DevScalars* sc, hipStream_t st) {
+                          const DevScalars* sc, hipStream_t st,
+                          const double* mask) {
   dim3 g((unsigned)((np + 255) / 256), (unsigned)np);
   hipLaunchKernelGGL(project_kernel, g, dim3(256), 0, st, B, M, ld, n, np, E,
-                     W, p, sc);
+                     W, p, sc, mask);
   return hipGetLastError();
 }
 hipError_t launch_trace_weight(const double* rn, int nt, int64_t Tp,
@@ -461,17 +637,44 @@ hipError_t launch_trace_weight(const double* rn, int nt, int64_t Tp,
 }
 hipError_t launch_rhs(const double* Bnu, const double* t3, const double* E,
                       int p, int64_t n, double mp1, const DevScalars* sc,
-                      double* r, hipStream_t st) {
+                      double* r, hipStream_t st, const double* mask) {
   hipLaunchKernelGGL(rhs_kernel, dim3(1), dim3(VT), 0, st, Bnu, t3, E, p, n,
-                     mp1, sc, r);
+                     mp1, sc, r, mask);
   return hipGetLastError();
 }
 hipError_t launch_direction(const double* y, const double* E, int p,
                             int64_t n, const double* x, const double* mu,
                             double tau, int simplex, double* d,
-                            DevScalars* sc, hipStream_t st) {
+                            DevScalars* sc, hipStream_t st,
+                            const double* mask) {
   hipLaunchKernelGGL(direction_kernel, dim3(1), dim3(VT), 0, st, y, E, p, n,
-                     x, mu, tau, simplex, d, sc);
+                     x, mu, tau, simplex, d, sc, mask);
+  return hipGetLastError();
+}
+hipError_t launch_face(const double* x, const double* g, int64_t n, double tau,
+                       double* E, double* mask, DevScalars* sc,
+                       hipStream_t st) {
+  hipLaunchKernelGGL(face_kernel, dim3(1), dim3(VT), 0, st, x, g, n, tau, E,
+                     mask, sc);
+  return hipGetLastError();
+}
+hipError_t launch_kkt(const double* x, const double* g, int64_t n, double eps,
+                      double* tmp, DevScalars* sc, hipStream_t st) {
+  hipLaunchKernelGGL(kkt_kernel, dim3(1), dim3(VT), 0, st, x, g, n, eps, tmp,
+                     sc);
+  return hipGetLastError();
+}
+hipError_t launch_boundary(const double* x, const double* g, const double* mu,
+                           int64_t n, double tau, double eta, double* d,
+                           double* tmp, DevScalars* sc, hipStream_t st) {
+  hipLaunchKernelGGL(boundary_kernel, dim3(1), dim3(VT), 0, st, x, g, mu, n,
+                     tau, eta, d, tmp, sc);
+  return hipGetLastError();
+}
+hipError_t launch_project_simplex(const double* y, int64_t n, double tau,
+                                  double* out, hipStream_t st) {
+  hipLaunchKernelGGL(project_simplex_kernel, dim3(1), dim3(VT), 0, st, y, n,
+                     tau, out);
   return hipGetLastError();
 }
 hipError_t launch_coef_step(const double* sums, double invT, Coef c,

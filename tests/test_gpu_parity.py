@@ -212,16 +212,18 @@ def test_solve_R_wrapper():
 
 @pytest.mark.parametrize("iters", [1, 2, 4])
 def test_simplex_iterations_match_oracle(iters):
-    """SIMPLEX set: the interior-safe step cap binds from the first step on
-    n12_T500 with c = (1,1,1,1) (the budget minimiser holds weights near
-    -21); the GPU iterates follow the oracle's element by element."""
+    """SIMPLEX set with capped raw steps only (eta = 0): the interior-safe
+    step cap binds from the first step on n12_T500 with c = (1,1,1,1) (the
+    budget minimiser holds weights near -21); the GPU iterates follow the
+    oracle's element by element."""
     R = synth.workload_returns("n12_T500")
     c = np.array([1.0, 1.0, 1.0, 1.0])
     print(f"[case] simplex n12_T500 iters={iters}", flush=True)
-    xr, _ = O.solve(R, c, opts=O.Options(feasible_set="simplex", max_iter=iters, eps=0.0))
+    xr, _ = O.solve(R, c, opts=O.Options(feasible_set="simplex", max_iter=iters, eps=0.0,
+                                         eta=0.0))
     ctx = yb.Context(torch.from_numpy(R).cuda())
     w, info = ctx.solve(c, opts=yb.default_opts(feasible_set="simplex", max_iter=iters,
-                                                eps=0.0))
+                                                eps=0.0, eta=0.0))
     w = w.cpu().numpy()
     assert info.iterations == iters
     assert np.abs(w - xr).max() <= 1e-9

@@ -1,0 +1,111 @@
+"""GPU parity of the simplex boundary block: the projection onto Delta(tau),
+the projected-KKT residual, and solves whose iterates use face continuation
+and projected trial steps, all through the C-ABI against the FP64 oracle.
+
+Tolerances: the projection's threshold comes from a block sum instead of a
+correctly rounded one, so outputs agree to a few ulps of max|y| per
+coordinate (bound 1e-13 max(1, |y|_inf)); the KKT residual is a norm of
+such differences plus the gradient's rounding (relative 1e-9); iterates of
+a solve agree to 1e-9 like the other solve-level parity tests.
+"""
+
+import numpy as np
+import pytest
+
+import oracle as O
+import synth
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+from paper_2604_25378_amd import binding as yb  # noqa: E402
+
+
+@pytest.mark.parametrize("n", [1, 2, 13, 1000, 1024, 1025, 5440])
+@pytest.mark.parametrize("tau", [0.0, 1e-8, 1e-4])
+def test_projection_matches_oracle(n, tau):
+    if tau * n >= 1.0:
+        pytest.skip("tau >= 1/n")
+    print(f"[case] projection n={n} tau={tau}", flush=True)
+    rng = np.random.default_rng(n + int(1e9 * tau))
+    for y in (rng.standard_normal(n), rng.standard_normal(n) / n, np.full(n, 2.5),
+              O.project_simplex(rng.random(n), tau)):
+        got = yb.project_simplex(torch.from_numpy(y), tau).cpu().numpy()
+        ref = O.project_simplex(y, tau)
+        assert np.abs(got - ref).max() <= 1e-13 * max(1.0, np.abs(y).max())
+        assert got.min() >= tau * (1 - 1e-12)
+
+
+@pytest.mark.parametrize("wl", ["n12_T500", "n400_T4800"])
+def test_kkt_residual_matches_oracle(wl):
+    print(f"[case] kkt {wl}", flush=True)
+    R = synth.workload_returns(wl)
+    mu, A = O.center(R)
+    n = mu.size
+    c = np.array(synth.WORKLOADS[wl]["c"])
+    ctx = yb.Context(torch.from_numpy(R).cuda())
+    rng = np.random.default_rng(5)
+    x = rng.random(n)
+    x /= x.sum()
+    for w in (np.full(n, 1.0 / n), np.eye(n)[int(np.argmax(mu))], x):
+        got = ctx.kkt_residual(c, w)
+        assert got == pytest.approx(O.kkt_residual(A, mu, c, w), rel=1e-9, abs=1e-18)
+    ctx.close()
+
+
+@pytest.mark.parametrize("iters", [1, 3, 6, 11])
+def test_boundary_block_iterates_match_oracle(iters):
+    """n12_T500 with c = (1,1,1,1): the optimum sits on a two-asset face;
+    the run takes projected trial steps and then continues on that face."""
+    print(f"[case] simplex boundary block iters={iters}", flush=True)
+    R = synth.workload_returns("n12_T500")
+    c = np.array([1.0, 1.0, 1.0, 1.0])
+    xr, ir = O.solve(R, c, opts=O.Options(feasible_set="simplex", max_iter=iters, eps=0.0))
+    ctx = yb.Context(torch.from_numpy(R).cuda())
+    w, info = ctx.solve(c, opts=yb.default_opts(feasible_set="simplex", max_iter=iters, eps=0.0))
+    w = w.cpu().numpy()
+    assert info.iterations == iters
+    assert info.projected_steps == ir.projected_steps
+    assert np.abs(w - xr).max() <= 1e-9
+    assert w.min() >= 1e-8 * (1 - 1e-9) and abs(w.sum() - 1.0) <= 1e-12
+    ctx.close()
+
+
+def test_boundary_block_solve_reaches_simplex_minimiser():
+    R = synth.workload_returns("n12_T500")
+    mu, A = O.center(R)
+    c = np.array([1.0, 1.0, 1.0, 1.0])
+    xr, ir = O.solve(R, c, opts=O.Options(feasible_set="simplex"))
+    ctx = yb.Context(torch.from_numpy(R).cuda())
+    w, info = ctx.solve(c, opts=yb.default_opts(feasible_set="simplex"))
+    w = w.cpu().numpy()
+    print(f"GPU {info.iterations} it, {info.projected_steps} projected, kkt {info.kkt:.2e}", flush=True)
+    assert info.status == 0 and ir.status == 0
+    assert info.iterations == ir.iterations
+    assert np.abs(w - xr).max() <= 1e-9
+    assert info.kkt == pytest.approx(O.kkt_residual(A, mu, c, w), rel=1e-8)
+    assert info.kkt <= 1e-6
+    ctx.close()
+
+
+@pytest.mark.parametrize("gamma", [3.0, 8.0])
+def test_boundary_block_certified_convex_direct_and_pcg(gamma):
+    """CRRA coefficients (certified convex): a unique minimiser over the
+    simplex, reached by the direct and the PCG configurations alike and by
+    the oracle."""
+    print(f"[case] simplex CRRA gamma={gamma} n400_T4800", flush=True)
+    R = synth.workload_returns("n400_T4800")
+    mu, A = O.center(R)
+    c = synth.crra_coefficients(gamma)
+    xr, ir = O.solve(R, c, opts=O.Options(feasible_set="simplex"))
+    ctx = yb.Context(torch.from_numpy(R).cuda())
+    wd, idr = ctx.solve(c, opts=yb.default_opts(feasible_set="simplex"))
+    wp, ipc = ctx.solve(c, opts=yb.default_opts(large=True, feasible_set="simplex"))
+    wd, wp = wd.cpu().numpy(), wp.cpu().numpy()
+    print(f"direct {idr.iterations} it kkt {idr.kkt:.2e}; pcg {ipc.iterations} it "
+          f"kkt {ipc.kkt:.2e}; oracle {ir.iterations} it kkt {ir.kkt:.2e}", flush=True)
+    assert idr.status == 0 and ir.status == 0
+    assert np.abs(wd - xr).max() <= 1e-6
+    assert ipc.status in (0, 1, 2)
+    assert O.objective(A, mu, c, wp) <= O.objective(A, mu, c, xr) + 1e-9
+    ctx.close()
