@@ -166,6 +166,63 @@ def ragged_bench(count=32, T=6000, precision="fp64", autotune=True):
             "max_abs_w_diff_vs_plain": dev}
 
 
+OUTCOME = {0: "converged", 1: "iteration budget", 2: "stalled after restarts"}
+
+
+def simplex_bench(precision="fp64"):
+    """Simplex set with the boundary block (face continuation, projected
+    trial step, projected-KKT stop) on the paper's synthetic coefficient-
+    stress generator: returns uniform on [-0.1, 0.4], T = 252, profiles
+    [10,1,10,1], [1,10,1,10], [10,10,10,10]; the direct configuration at
+    n = 100 and the PCG configuration with stall recovery at n = 1000 and
+    5440 (n > T: the regularised stress regime).  Reports the rate, the
+    iterations and the projected-KKT hits at the study's 1e-6 target."""
+    import torch
+
+    import synth
+    from paper_2604_25378_amd import binding as yb
+
+    profiles = ([10.0, 1.0, 10.0, 1.0], [1.0, 10.0, 1.0, 10.0],
+                [10.0, 10.0, 10.0, 10.0])
+    res = {}
+    for n, large in ((100, False), (1000, True), (5440, True)):
+        log(f"simplex boundary block: n={n} T=252 "
+            f"({'PCG' if large else 'direct'})")
+        R = synth.uniform_returns(n, 252, seed=n)
+        ctx = yb.Context(torch.from_numpy(R).cuda(), precision)
+        opts = yb.default_opts(large=large, feasible_set="simplex")
+        ctx.solve(profiles[2], opts=yb.default_opts(large=large,
+                                                    feasible_set="simplex",
+                                                    max_iter=2))  # warm-up
+        torch.cuda.synchronize()
+        times, infos, outcome = [], [], []
+        for c in profiles:
+            t0 = time.perf_counter()
+            try:
+                _, info = ctx.solve(c, opts=opts)
+                outcome.append(OUTCOME.get(info.status, str(info.status)))
+            except yb.YandError as e:   # e.g. indefinite outside the certificate
+                info = None
+                outcome.append(yb.ERRORS.get(e.code, str(e.code)))
+            torch.cuda.synchronize()
+            times.append(time.perf_counter() - t0)
+            infos.append(info)
+        ctx.close()
+        ok = [i for i in infos if i is not None]
+        res[f"n{n}_T252"] = {
+            "config": "PCG (large), stall recovery" if large else "direct (small)",
+            "profiles": [list(c) for c in profiles],
+            "outcome": outcome,
+            "solves_per_s": len(profiles) / sum(times),
+            "median_s": float(np.median(times)),
+            "iterations": [i.iterations if i else None for i in infos],
+            "projected_steps": [i.projected_steps if i else None for i in infos],
+            "restarts": [i.restarts if i else None for i in infos],
+            "kkt": [i.kkt if i else None for i in infos],
+            "kkt_hits_1e-6": f"{sum(i.kkt <= 1e-6 for i in ok)}/{len(infos)}"}
+    return res
+
+
 def warmstart_bench(workload, n_train_targets=16, n_points=256, n_plain=16,
                     precision="fp64", autotune=True):
     """Frontier sweep at full scale: batched + MLP-warm-started solves vs
@@ -446,6 +503,7 @@ def main():
                                               args.frontier_points, 16,
                                               args.precision, tune)}
         out["frontier"] = fr
+        out["simplex"] = simplex_bench(args.precision)
         out["frontier_solves_per_s"] = fr["n5440_T12000"]["warm_batched_solves_per_s"]
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(R, c)

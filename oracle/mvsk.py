@@ -526,10 +526,11 @@ def _iterate(A, mu, c, x, U, opts: Options, solver, krylov_maxit, max_iter,
         if f_prev - f_new < 1e-14 * abs(f_prev):
             small += 1
             if small >= 3:
-                return x, False, True
+                break
         else:
             small = 0
         f_prev = f_new
+    # budget spent or stalled: the reported state is that of the returned x
     g = gradient(A, mu, c, x)
     Ui = face_basis(face_free(x, g, opts.tau)) if faces else U
     info.gnorm = float(np.linalg.norm(Ui.T @ g))

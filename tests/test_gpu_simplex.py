@@ -109,3 +109,38 @@ def test_boundary_block_certified_convex_direct_and_pcg(gamma):
     assert ipc.status in (0, 1, 2)
     assert O.objective(A, mu, c, wp) <= O.objective(A, mu, c, xr) + 1e-9
     ctx.close()
+
+
+@pytest.mark.parametrize("n,large,c", [
+    (60, False, (10.0, 1.0, 10.0, 1.0)),
+    (60, False, (10.0, 10.0, 10.0, 10.0)),
+    (300, True, (10.0, 10.0, 10.0, 10.0)),
+])
+def test_uniform_T252_matches_oracle(n, large, c):
+    """The paper's synthetic coefficient-stress generator (returns uniform on
+    [-0.1, 0.4], T = 252), direct configuration below T and the PCG
+    configuration with stall recovery above it (n > T: the regularised
+    stress regime).  Same outcome, iterations and iterates as the oracle."""
+    print(f"[case] uniform T=252 n={n} {'PCG' if large else 'direct'} c={c}", flush=True)
+    R = synth.uniform_returns(n, 252, seed=n)
+    if large:
+        oo = O.Options.large()
+        oo.feasible_set = "simplex"
+    else:
+        oo = O.Options(feasible_set="simplex")
+    xr, ir = O.solve(R, c, opts=oo)
+    ctx = yb.Context(torch.from_numpy(R).cuda())
+    w, info = ctx.solve(c, opts=yb.default_opts(large=large, feasible_set="simplex"))
+    w = w.cpu().numpy()
+    assert info.status == ir.status and info.iterations == ir.iterations
+    assert info.restarts == ir.restarts
+    assert np.abs(w - xr).max() <= (1e-8 if large else 1e-9)
+    # the residual is dominated by the bound coordinates' tau = 1e-8, so it
+    # is compared through the projection's nonexpansiveness:
+    # |kkt(w) - kkt(xr)| <= 2 |w - xr| + |grad f(w) - grad f(xr)|
+    mu, A = O.center(R)
+    bound = (2.0 * np.linalg.norm(w - xr)
+             + np.linalg.norm(O.gradient(A, mu, np.array(c), w)
+                              - O.gradient(A, mu, np.array(c), xr)))
+    assert abs(info.kkt - ir.kkt) <= bound + 1e-12 * ir.kkt + 1e-15
+    ctx.close()
