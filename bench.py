@@ -223,6 +223,93 @@ def simplex_bench(precision="fp64"):
     return res
 
 
+def conditioning_bench(precision="fp64"):
+    """The controlled CRRA conditioning benchmark of the computational study
+    and its n > T stress counterpart: CRRA gamma = 6, kappa_+(AU) in {1, 10,
+    1e2, 1e3} prescribed by synth.conditioned_returns (A x0 = 0), simplex
+    with the boundary block, PCG configuration with stall recovery; three
+    instances (seeds) per level after one untimed warm-up solve, medians of
+    time, iterations and projected-KKT residual."""
+    import torch
+
+    import synth
+    from paper_2604_25378_amd import binding as yb
+
+    c = synth.crra_coefficients(6.0)
+    opts = yb.default_opts(large=True, feasible_set="simplex")
+    res = {}
+    for n, T in ((1000, 2000), (5000, 252)):
+        rows = {}
+        for kappa in (1.0, 10.0, 100.0, 1000.0):
+            log(f"conditioning: n={n} T={T} kappa={kappa:g}")
+            times, its, kkts, stat = [], [], [], []
+            for seed in (0, 1, 2):
+                R = synth.conditioned_returns(n, T, kappa, seed)
+                ctx = yb.Context(torch.from_numpy(R).cuda(), precision)
+                if seed == 0:
+                    ctx.solve(c, opts=opts)     # untimed warm-up
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                _, info = ctx.solve(c, opts=opts)
+                torch.cuda.synchronize()
+                times.append(time.perf_counter() - t0)
+                its.append(info.iterations)
+                kkts.append(info.kkt)
+                stat.append(OUTCOME.get(info.status, str(info.status)))
+                ctx.close()
+            rows[f"kappa={kappa:g}"] = {
+                "median_s": float(np.median(times)),
+                "median_iterations": float(np.median(its)),
+                "median_kkt": float(np.median(kkts)),
+                "outcome": stat}
+        res[f"n{n}_T{T}"] = rows
+    return res
+
+
+def line_search_bench(precision="fp64"):
+    """The direct-configuration line-search diagnostic: Armijo backtracking
+    against the exact quartic rule on the T = 252 coefficient-stress
+    generator (three profiles), simplex with the boundary block; mean time,
+    iterations and projected-KKT residual per n-block."""
+    import torch
+
+    import synth
+    from paper_2604_25378_amd import binding as yb
+
+    profiles = ([10.0, 1.0, 10.0, 1.0], [1.0, 10.0, 1.0, 10.0],
+                [10.0, 10.0, 10.0, 10.0])
+    res = {}
+    for block in ((4, 8, 12), (20, 40, 60, 80, 100)):
+        row = {}
+        for rule in ("armijo", "exact"):
+            opts = yb.default_opts(feasible_set="simplex", linesearch=rule)
+            times, its, kkts, errors = [], [], [], 0
+            for n in block:
+                ctx = yb.Context(torch.from_numpy(
+                    synth.uniform_returns(n, 252, seed=n)).cuda(), precision)
+                ctx.solve(profiles[2], opts=opts)        # warm-up
+                for c in profiles:
+                    torch.cuda.synchronize()
+                    t0 = time.perf_counter()
+                    try:
+                        _, info = ctx.solve(c, opts=opts)
+                    except yb.YandError:
+                        errors += 1
+                        continue
+                    torch.cuda.synchronize()
+                    times.append(time.perf_counter() - t0)
+                    its.append(info.iterations)
+                    kkts.append(info.kkt)
+                ctx.close()
+            row[rule] = {"mean_s": float(np.mean(times)),
+                         "median_s": float(np.median(times)),
+                         "mean_iterations": float(np.mean(its)),
+                         "mean_kkt": float(np.mean(kkts)),
+                         "solves": len(times), "errors": errors}
+        res["n in " + ",".join(map(str, block))] = row
+    return res
+
+
 def warmstart_bench(workload, n_train_targets=16, n_points=256, n_plain=16,
                     precision="fp64", autotune=True):
     """Frontier sweep at full scale: batched + MLP-warm-started solves vs
@@ -504,6 +591,8 @@ def main():
                                               args.precision, tune)}
         out["frontier"] = fr
         out["simplex"] = simplex_bench(args.precision)
+        out["conditioning"] = conditioning_bench(args.precision)
+        out["line_search"] = line_search_bench(args.precision)
         out["frontier_solves_per_s"] = fr["n5440_T12000"]["warm_batched_solves_per_s"]
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(R, c)

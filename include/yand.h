@@ -53,6 +53,12 @@ enum { YAND_FP64 = 0, YAND_FP32 = 1, YAND_BF16 = 2 };
 enum { YAND_SOLVER_DIRECT = 0, YAND_SOLVER_PCG = 1 };
 /* Feasible set: affine budget hull (no cap) or the slice Delta(tau). */
 enum { YAND_SET_BUDGET = 0, YAND_SET_SIMPLEX = 1 };
+/* Step rule on the quartic line model: the exact rule (Proposition "Quartic
+ * exact line search from sample power sums") or Armijo backtracking (the
+ * rule of the convergence theory; sigma = 1e-4, halving from min(1,
+ * alpha_max), the Armijo diagnostic of Table "YAND-MVSK parameter
+ * settings"). */
+enum { YAND_LS_EXACT = 0, YAND_LS_ARMIJO = 1 };
 
 typedef struct yand_ctx yand_ctx;
 
@@ -74,6 +80,7 @@ typedef struct yand_opts {
   double eta;             /* simplex boundary block: nominal projected trial
                              step (0.05; 0 = capped raw steps only).  Active
                              on YAND_SET_SIMPLEX without a return target.    */
+  int linesearch;         /* YAND_LS_EXACT (default) or YAND_LS_ARMIJO        */
 } yand_opts;
 
 /* Per-solve report: counters follow the oracle-query accounting of the
@@ -94,8 +101,8 @@ typedef struct yand_info {
   int64_t ls_passes;      /* line-search passes over A                        */
   int64_t dense_traces;   /* exact-trace factorisations                       */
   double kkt;             /* projected-simplex KKT residual at w_out
-                             |w - Pi_Delta(w - grad f(w))|_2 (simplex set;
-                             NaN on the budget set)                          */
+                             |w - Pi_Delta(tau)(w - grad f(w))|_2 (simplex
+                             set; NaN on the budget set)                     */
   int projected_steps;    /* iterations that took the projected trial segment */
 } yand_info;
 
@@ -153,11 +160,13 @@ int yand_select_step(yand_ctx* ctx, const double coef[5], double alpha_max,
  * n < 1, tau < 0 or tau >= 1/n, or a pointer is NULL. */
 int yand_project_simplex(const double* y, int64_t n, double tau, double* x);
 
-/* Projected-simplex KKT residual |w - Pi_Delta(w - grad f(w))|_2 at w
- * (device, n), the solution-quality metric of the computational study,
- * written to *kkt (host).  Delta = Delta(0). */
+/* Projected-simplex KKT residual |w - Pi_Delta(tau)(w - grad f(w))|_2 at
+ * w (device, n), the solution-quality metric of the computational study
+ * (the paper gives no formula; this is the projected-gradient residual on
+ * the slice), written to *kkt (host).  yand_mvsk_solve reports it with the
+ * solve's tau.  YAND_ERR_ARG when tau < 0 or tau >= 1/n. */
 int yand_kkt_residual(yand_ctx* ctx, const double c[4], const double* w,
-                      double* kkt);
+                      double tau, double* kkt);
 
 /* Affine-normal direction with the exact log-det trace at the feasible point
  * w (Section 4.2 and Section 4.4; factor 1/(m+1) of Appendix B, Proposition

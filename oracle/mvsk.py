@@ -39,7 +39,7 @@ __all__ = [
     "linesearch_coeffs", "alpha_max", "quartic_value", "select_step",
     "Options", "SolveInfo", "solve", "certified_convex", "Unbounded",
     "Indefinite", "project_simplex", "kkt_residual", "face_free",
-    "face_basis",
+    "face_basis", "armijo_step",
 ]
 
 
@@ -343,18 +343,21 @@ def project_simplex(y, tau=0.0):
     return np.maximum(u - theta, 0.0) + tau
 
 
-def kkt_residual(A, mu, c, x):
-    """Projected-simplex KKT residual |x - Pi_Delta(x - grad f(x))|_2.
+def kkt_residual(A, mu, c, x, tau=0.0):
+    """Projected-simplex KKT residual |x - Pi_Delta(tau)(x - grad f(x))|_2.
 
     The computational study evaluates solutions by a projected-simplex KKT
     residual against a 1e-6 target without stating its formula; this is the
-    standard projected-gradient residual on Delta = Delta(0).  It vanishes
-    exactly at the KKT points of min f over the simplex and equals the
-    tangent-gradient norm |P_1 grad f| at interior points where the unit
-    projected-gradient step stays inside.
+    standard projected-gradient residual on the slice Delta(tau) the solver
+    works on.  It vanishes exactly at the KKT points of min f over
+    Delta(tau) and equals the tangent-gradient norm |P_1 grad f| at interior
+    points where the unit projected-gradient step stays inside.  (Against
+    Delta(0) a KKT point of Delta(tau) with n_b coordinates on the bound
+    keeps the floor tau sqrt(n_b^2 / (n - n_b) + n_b): the bound coordinates
+    drop to 0 and their mass n_b tau spreads over the free ones.)
     """
     g = gradient(A, mu, c, x)
-    return float(np.linalg.norm(x - project_simplex(x - g, 0.0)))
+    return float(np.linalg.norm(x - project_simplex(x - g, tau)))
 
 
 def face_free(x, g, tau):
@@ -421,6 +424,24 @@ def select_step(coef, amax=math.inf):
     return float(cands[np.argmax(ok)])
 
 
+def armijo_step(coef, amax=math.inf, sigma=1e-4, rho=0.5, max_halvings=60):
+    """Armijo backtracking on the quartic line model (the line-search rule of
+    the convergence theory and of the Armijo diagnostic of Table 'YAND-MVSK
+    parameter settings'): from alpha = min(1, amax), halve until
+    phi(alpha) - phi(0) <= sigma alpha phi'(0), phi'(0) = A1.  The model is
+    exact, so each trial costs no pass over A.  The paper fixes only
+    sigma in (0, 1); sigma = 1e-4, rho = 1/2 and 60 halvings (then 0) are
+    readings."""
+    A1, A2, A3, A4 = (float(v) for v in coef[1:5])
+    a = min(1.0, amax)
+    for _ in range(max_halvings):
+        dec = a * (A1 + a * (A2 + a * (A3 + a * A4)))
+        if dec <= sigma * a * A1:
+            return a
+        a *= rho
+    return 0.0
+
+
 # ---------------------------------------------------------------------------
 # Algorithm 1: the outer loop.
 # ---------------------------------------------------------------------------
@@ -434,6 +455,7 @@ class Options:
     Delta(tau), Lemma 'Interior-safe steplength cap').
     eta: nominal projected trial step of the boundary block (0.05 in Table
     'YAND-MVSK parameter settings'); 0 keeps the capped raw step only.
+    linesearch: 'exact' (quartic exact rule) or 'armijo' (armijo_step).
     """
     solver: str = "direct"
     feasible_set: str = "budget"
@@ -445,6 +467,7 @@ class Options:
     krylov_maxit: int = 15
     tau: float = 1e-8
     eta: float = 0.05
+    linesearch: str = "exact"
     stall_recovery: bool = True
     restart_max_iter: int = 120
 
@@ -483,7 +506,7 @@ def _iterate(A, mu, c, x, U, opts: Options, solver, krylov_maxit, max_iter,
         that segment is a descent direction and not numerically zero;
         otherwise the capped raw step is taken, which exposes the next face;
       * the stopping test also accepts a projected-KKT residual
-        (kkt_residual) at or below eps.
+        (kkt_residual on Delta(tau)) at or below eps.
     With eta = 0 the simplex set only caps the raw step.
     """
     eta = opts.eta if eta is None else eta
@@ -498,7 +521,8 @@ def _iterate(A, mu, c, x, U, opts: Options, solver, krylov_maxit, max_iter,
         gn = float(np.linalg.norm(Ui.T @ g))
         info.gnorm = gn
         if simplex:
-            info.kkt = float(np.linalg.norm(x - project_simplex(x - g, 0.0)))
+            info.kkt = float(np.linalg.norm(
+                x - project_simplex(x - g, opts.tau)))
         if gn <= opts.eps or (simplex and info.kkt <= opts.eps):
             return x, True, False
         if time.perf_counter() - t0 > opts.max_elapsed:
@@ -518,7 +542,8 @@ def _iterate(A, mu, c, x, U, opts: Options, solver, krylov_maxit, max_iter,
                 info.projected_steps += 1
         coef = linesearch_coeffs(A, mu, c, x, d)
         info.ls_passes += 1
-        alpha = select_step(coef, amax)
+        alpha = (armijo_step(coef, amax) if opts.linesearch == "armijo"
+                 else select_step(coef, amax))
         x = x + alpha * d
         info.iterations += 1
         f_new = quartic_value(coef, alpha)
@@ -536,7 +561,7 @@ def _iterate(A, mu, c, x, U, opts: Options, solver, krylov_maxit, max_iter,
     info.gnorm = float(np.linalg.norm(Ui.T @ g))
     conv = info.gnorm <= opts.eps
     if simplex:
-        info.kkt = float(np.linalg.norm(x - project_simplex(x - g, 0.0)))
+        info.kkt = float(np.linalg.norm(x - project_simplex(x - g, opts.tau)))
         conv = conv or info.kkt <= opts.eps
     return x, conv, True
 

@@ -27,6 +27,7 @@ ERRORS = {
 PRECISIONS = {"fp64": 0, "fp32": 1, "bf16": 2}
 SOLVERS = {"direct": 0, "pcg": 1}
 SETS = {"budget": 0, "simplex": 1}
+LINESEARCH = {"exact": 0, "armijo": 1}
 
 
 class YandError(RuntimeError):
@@ -41,7 +42,8 @@ class yand_opts(C.Structure):
                 ("max_elapsed", C.c_double), ("regularization", C.c_double),
                 ("krylov_tol", C.c_double), ("krylov_maxit", C.c_int),
                 ("tau", C.c_double), ("stall_recovery", C.c_int),
-                ("restart_max_iter", C.c_int), ("eta", C.c_double)]
+                ("restart_max_iter", C.c_int), ("eta", C.c_double),
+                ("linesearch", C.c_int)]
 
 
 class yand_info(C.Structure):
@@ -125,7 +127,7 @@ def load(path: str = LIB_PATH):
                                              C.POINTER(C.c_int), _D]),
         "yand_profile_enable": (C.c_int, [vp, C.c_int]),
         "yand_project_simplex": (C.c_int, [vp, C.c_int64, C.c_double, vp]),
-        "yand_kkt_residual": (C.c_int, [vp, _D, vp, _D]),
+        "yand_kkt_residual": (C.c_int, [vp, _D, vp, C.c_double, _D]),
         "yand_autotune": (C.c_int, [vp, _D]),
         "yand_tuning": (C.c_int, [vp, C.POINTER(C.c_int), C.POINTER(C.c_int)]),
         "yand_profile_read": (C.c_int, [vp, C.c_int, C.c_char_p, C.c_int, _D,
@@ -179,6 +181,8 @@ def default_opts(**kw) -> yand_opts:
             v = SOLVERS[v] if isinstance(v, str) else v
         if k == "feasible_set":
             v = SETS[v] if isinstance(v, str) else v
+        if k == "linesearch":
+            v = LINESEARCH[v] if isinstance(v, str) else v
         setattr(o, k, v)
     return o
 
@@ -300,12 +304,13 @@ class Context:
         _check(rc, "yand_select_step")
         return al.value
 
-    def kkt_residual(self, c, w) -> float:
+    def kkt_residual(self, c, w, tau: float = 0.0) -> float:
         w = _dev(w, self.n)
         k = C.c_double()
         _check(self._lib.yand_kkt_residual(self._h, _c4(c),
                                            C.c_void_p(w.data_ptr()),
-                                           C.byref(k)), "yand_kkt_residual")
+                                           float(tau), C.byref(k)),
+               "yand_kkt_residual")
         return k.value
 
     def affine_normal(self, c, w, target=None, opts: yand_opts | None = None):

@@ -329,6 +329,7 @@ struct DirOpts {
   // projected trial step with nominal step eta
   bool faces = false;
   double eta = 0.0;
+  int select = 1;  // step rule for line_at: 1 exact quartic, 2 Armijo
 };
 
 const double* face_mask(const Work& w, const DirOpts& o) {
@@ -614,7 +615,7 @@ int stationarity(const Data& D, Work& w, const DirOpts& o, int p0,
   HIPTRY(launch_grad_project(w.g, w.E, p0, D.n, w.sc, w.st, eps,
                              face_mask(w, o)));
   if (o.simplex)
-    HIPTRY(launch_kkt(w.x, w.g, D.n, eps, w.ptmp, w.sc, w.st));
+    HIPTRY(launch_kkt(w.x, w.g, D.n, o.tau, eps, w.ptmp, w.sc, w.st));
   return YAND_OK;
 }
 
@@ -627,7 +628,7 @@ int enqueue_iteration(const Data& D, Work& w, const double c[4], int p0,
   TRY(dir_factor(D, w, p0, skip, face_mask(w, o)));
   TRY(dir_trace(D, w, c, p0, skip, face_mask(w, o)));
   TRY(dir_direct_solve(D, w, p0, w.x, o, w.d, skip));
-  TRY(line_at(D, w, c, w.d, 1, skip));
+  TRY(line_at(D, w, c, w.d, o.select, skip));
   HIPTRY(launch_axpy(w.x, w.d, D.n, w.sc, w.st));
   return YAND_OK;
 }
@@ -765,7 +766,7 @@ int after_iteration(Lane& L, const yand_opts& opts, const DirOpts& o) {
       L.active = false;
       return YAND_OK;
     }
-    TRY(line_at(*L.D, w, L.c, w.d, 1, nullptr));
+    TRY(line_at(*L.D, w, L.c, w.d, o.select, nullptr));
     HIPTRY(launch_axpy(w.x, w.d, L.D->n, w.sc, w.st));
     TRY(sync_scalars(w));
   }
@@ -1027,6 +1028,7 @@ void yand_default_opts(yand_opts* o) {
   o->stall_recovery = 1;
   o->restart_max_iter = 120;
   o->eta = 0.05;
+  o->linesearch = YAND_LS_EXACT;
 }
 
 void yand_large_opts(yand_opts* o) {
@@ -1234,13 +1236,14 @@ int yand_project_simplex(const double* y, int64_t n, double tau, double* x) {
 }
 
 int yand_kkt_residual(yand_ctx* ctx, const double c[4], const double* w,
-                      double* kkt) {
-  if (!ctx || !w || !kkt) return YAND_ERR_ARG;
+                      double tau, double* kkt) {
+  if (!ctx || !w || !kkt || !(tau >= 0.0) || !(tau * (double)ctx->d.n < 1.0))
+    return YAND_ERR_ARG;
   TRY(check_c(c));
   Work& W = ctx->w;
   hipLaunchKernelGGL(set_frozen_kernel, dim3(1), dim3(64), 0, W.st, W.sc, 0);
   TRY(oracle_at(ctx->d, W, c, w, true));
-  HIPTRY(launch_kkt(w, W.g, ctx->d.n, -1.0, W.ptmp, W.sc, W.st));
+  HIPTRY(launch_kkt(w, W.g, ctx->d.n, tau, -1.0, W.ptmp, W.sc, W.st));
   TRY(sync_scalars(W));
   *kkt = W.hs.kkt;
   return W.hs.nonfinite ? YAND_ERR_NONFINITE : YAND_OK;
@@ -1255,6 +1258,7 @@ static int solve_pcg(yand_ctx* ctx, const double c[4], int p0,
   o.tau = opts.tau;
   o.simplex = opts.feasible_set == YAND_SET_SIMPLEX;
   o.faces = o.simplex && opts.eta > 0.0 && p0 == 1;
+  o.select = opts.linesearch == YAND_LS_ARMIJO ? 2 : 1;
   struct Phase {
     int solver, kmax, max_iter;
     double reg, eta;
@@ -1313,7 +1317,7 @@ static int solve_pcg(yand_ctx* ctx, const double c[4], int p0,
       inf.third_passes++;
       inf.cg_iters += ds.cg;
       inf.hvp_passes += ds.cg;
-      TRY(line_at(D, w, c, w.d, 1, nullptr));
+      TRY(line_at(D, w, c, w.d, o.select, nullptr));
       inf.ls_passes++;
       TRY(sync_scalars(w));
       inf.lambda_used = w.hs.lambda;
@@ -1340,7 +1344,8 @@ static bool valid_opts(const yand_opts& o) {
          (o.feasible_set == YAND_SET_BUDGET ||
           o.feasible_set == YAND_SET_SIMPLEX) &&
          o.krylov_maxit >= 0 && o.restart_max_iter >= 0 && o.eta >= 0.0 &&
-         std::isfinite(o.eta);
+         std::isfinite(o.eta) &&
+         (o.linesearch == YAND_LS_EXACT || o.linesearch == YAND_LS_ARMIJO);
 }
 
 int yand_mvsk_solve(yand_ctx* ctx, const double c[4], const double* target,
@@ -1372,6 +1377,7 @@ int yand_mvsk_solve(yand_ctx* ctx, const double c[4], const double* target,
     o.simplex = opts.feasible_set == YAND_SET_SIMPLEX;
     o.faces = o.simplex && opts.eta > 0.0 && p0 == 1;
     o.eta = opts.eta;
+    o.select = opts.linesearch == YAND_LS_ARMIJO ? 2 : 1;
     std::vector<Lane> lanes(1);
     Lane& L = lanes[0];
     L.D = &D;
@@ -1441,6 +1447,7 @@ static int batch_solve(int64_t B, yand_ctx* const* ctxs, const double* C4,
   o.simplex = opts.feasible_set == YAND_SET_SIMPLEX;
   o.faces = o.simplex && opts.eta > 0.0 && !targets;
   o.eta = opts.eta;
+  o.select = opts.linesearch == YAND_LS_ARMIJO ? 2 : 1;
   // lane count: bounded by max_lanes and by free device memory
   size_t freeb = 0, totalb = 0;
   (void)hipMemGetInfo(&freeb, &totalb);

@@ -67,10 +67,10 @@ hipError_t launch_direction(const double* y, const double* E, int p,
 hipError_t launch_face(const double* x, const double* g, int64_t n, double tau,
                        double* E, double* mask, DevScalars* sc,
                        hipStream_t st);
-// sc->kkt = |x - Pi_Delta(x - g)|_2; done when kkt <= eps (eps >= 0).
+// sc->kkt = |x - Pi_Delta(tau)(x - g)|_2; done when kkt <= eps (eps >= 0).
 // tmp: n doubles.
-hipError_t launch_kkt(const double* x, const double* g, int64_t n, double eps,
-                      double* tmp, DevScalars* sc, hipStream_t st);
+hipError_t launch_kkt(const double* x, const double* g, int64_t n, double tau,
+                      double eps, double* tmp, DevScalars* sc, hipStream_t st);
 // Boundary block: when sc->amax < eta, replace d by the corrected segment
 // Pi_{Delta(tau)}(x + eta d) - x if it is a nonzero descent direction (cap
 // 1, mu^T d updated, sc->projected set).  tmp: n doubles.

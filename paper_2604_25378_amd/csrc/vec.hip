@@ -333,14 +333,15 @@ face_kernel(const double* __restrict__ x, const double* __restrict__ g,
   if (tid == 0) sc->nfree = cnt[0];
 }
 
-// Projected-simplex KKT residual |x - Pi_Delta(x - g)|_2 (Delta = Delta(0)).
+// Projected-simplex KKT residual |x - Pi_Delta(tau)(x - g)|_2.
 __global__ void __launch_bounds__(VT)
 kkt_kernel(const double* __restrict__ x, const double* __restrict__ g,
-           int64_t n, double eps, double* __restrict__ tmp, DevScalars* sc) {
+           int64_t n, double tau, double eps, double* __restrict__ tmp,
+           DevScalars* sc) {
   if (sc->frozen) return;
   __shared__ double sh[4 * VW];
   const int tid = threadIdx.x;
-  simplex_project([&](int64_t j) { return x[j] - g[j]; }, n, 0.0, tmp, sh);
+  simplex_project([&](int64_t j) { return x[j] - g[j]; }, n, tau, tmp, sh);
   double r[1] = {0.0};
   for (int64_t j = tid; j < n; j += VT) {
     const double e = x[j] - tmp[j];
@@ -523,8 +524,22 @@ __device__ int quartic_step(const double* A, double amax, double* alpha) {
   return 0;
 }
 
+// Armijo backtracking on the quartic line model: from min(1, amax), halve
+// until phi(a) - phi(0) <= 1e-4 a phi'(0) (phi'(0) = A1), at most 60 times
+// (then 0).  The model is exact, so no trial needs a pass over A.
+__device__ double armijo_step(const double* A, double amax) {
+  double a = fmin(1.0, amax);
+  for (int k = 0; k < 60; ++k) {
+    const double dec = a * (A[1] + a * (A[2] + a * (A[3] + a * A[4])));
+    if (dec <= 1e-4 * a * A[1]) return a;
+    a *= 0.5;
+  }
+  return 0.0;
+}
+
 // Assemble A0..A4 (Proposition "Quartic exact line search from sample power
-// sums") from the reduced sums and pick the step.
+// sums") from the reduced sums and pick the step: select 1 the exact rule,
+// select 2 Armijo backtracking.
 __global__ void coef_step_kernel(const double* __restrict__ sums, double invT,
                                  Coef c, int select, DevScalars* sc) {
   if (threadIdx.x != 0) return;
@@ -544,7 +559,12 @@ __global__ void coef_step_kernel(const double* __restrict__ sums, double invT,
   A[2] = c.c2 * s02 - 3.0 * c.c3 * s12 + 6.0 * c.c4 * s22;
   A[3] = -c.c3 * s03 + 4.0 * c.c4 * s13;
   A[4] = c.c4 * s04;
-  if (select) sc->status = quartic_step(A, sc->amax, &sc->alpha);
+  if (select == 2) {
+    sc->alpha = armijo_step(A, sc->amax);
+    sc->status = 0;
+  } else if (select) {
+    sc->status = quartic_step(A, sc->amax, &sc->alpha);
+  }
 }
 
 __global__ void select_step_kernel(DevScalars* sc) {
@@ -658,10 +678,11 @@ hipError_t launch_face(const double* x, const double* g, int64_t n, double tau,
                      mask, sc);
   return hipGetLastError();
 }
-hipError_t launch_kkt(const double* x, const double* g, int64_t n, double eps,
-                      double* tmp, DevScalars* sc, hipStream_t st) {
-  hipLaunchKernelGGL(kkt_kernel, dim3(1), dim3(VT), 0, st, x, g, n, eps, tmp,
-                     sc);
+hipError_t launch_kkt(const double* x, const double* g, int64_t n, double tau,
+                      double eps, double* tmp, DevScalars* sc,
+                      hipStream_t st) {
+  hipLaunchKernelGGL(kkt_kernel, dim3(1), dim3(VT), 0, st, x, g, n, tau, eps,
+                     tmp, sc);
   return hipGetLastError();
 }
 hipError_t launch_boundary(const double* x, const double* g, const double* mu,

@@ -15,3 +15,4 @@ from .factor_model import (  # noqa: F401
     frontier_targets,
     ragged_universe_sizes,
 )
+from .conditioning import conditioned_returns, conditioning_spectrum  # noqa: F401

@@ -56,6 +56,7 @@ def test_default_opts_follow_parameter_table(lib):
     assert lg.restart_max_iter == 120 and lg.stall_recovery == 1
     # projected trial step 0.05 in both configurations
     assert o.eta == 0.05 and lg.eta == 0.05
+    assert o.linesearch == 0 and lg.linesearch == 0   # exact quartic rule
 
 
 def test_simplex_entry_points_reject_bad_arguments_without_device(lib):
@@ -65,7 +66,7 @@ def test_simplex_entry_points_reject_bad_arguments_without_device(lib):
     assert lib.yand_project_simplex(p, 4, 0.25, p) == -1   # tau >= 1/n
     assert lib.yand_project_simplex(p, 4, -1e-9, p) == -1
     k = C.c_double()
-    assert lib.yand_kkt_residual(None, (C.c_double * 4)(1, 1, 1, 1), p, C.byref(k)) == -1
+    assert lib.yand_kkt_residual(None, (C.c_double * 4)(1, 1, 1, 1), p, 0.0, C.byref(k)) == -1
 
 
 def test_create_rejects_bad_arguments_without_device(lib):

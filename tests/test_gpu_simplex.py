@@ -48,8 +48,9 @@ def test_kkt_residual_matches_oracle(wl):
     x = rng.random(n)
     x /= x.sum()
     for w in (np.full(n, 1.0 / n), np.eye(n)[int(np.argmax(mu))], x):
-        got = ctx.kkt_residual(c, w)
-        assert got == pytest.approx(O.kkt_residual(A, mu, c, w), rel=1e-9, abs=1e-18)
+        for tau in (0.0, 1e-8):
+            got = ctx.kkt_residual(c, w, tau)
+            assert got == pytest.approx(O.kkt_residual(A, mu, c, w, tau), rel=1e-9, abs=1e-18)
     ctx.close()
 
 
@@ -83,8 +84,8 @@ def test_boundary_block_solve_reaches_simplex_minimiser():
     assert info.status == 0 and ir.status == 0
     assert info.iterations == ir.iterations
     assert np.abs(w - xr).max() <= 1e-9
-    assert info.kkt == pytest.approx(O.kkt_residual(A, mu, c, w), rel=1e-8)
-    assert info.kkt <= 1e-6
+    assert info.kkt == pytest.approx(O.kkt_residual(A, mu, c, w, 1e-8), rel=1e-8, abs=1e-12)
+    assert info.kkt <= 1e-8
     ctx.close()
 
 

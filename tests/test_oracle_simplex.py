@@ -163,3 +163,62 @@ def test_eta_zero_keeps_capped_steps():
     x, info = O.solve(R, [1.0, 1.0, 1.0, 1.0],
                       opts=O.Options(feasible_set="simplex", eta=0.0, max_iter=50))
     assert info.projected_steps == 0 and info.status == 1
+
+
+def test_armijo_step_conditions():
+    """The accepted step satisfies the sufficient-decrease condition on the
+    quartic, and the step twice as long (when tried) did not."""
+    rng = np.random.default_rng(11)
+    for _ in range(200):
+        A = rng.standard_normal(5)
+        A[1] = -abs(A[1]) - 1e-3          # descent
+        A[4] = abs(A[4])
+        amax = rng.choice([math.inf, 0.3, 2.0])
+        a = O.armijo_step(A, amax)
+        phi = lambda t: A[1] * t + A[2] * t**2 + A[3] * t**3 + A[4] * t**4
+        assert 0.0 < a <= min(1.0, amax)
+        assert phi(a) <= 1e-4 * a * A[1] + 1e-15
+        if a < min(1.0, amax):
+            assert phi(2 * a) > 1e-4 * 2 * a * A[1]
+
+
+def test_armijo_solves_reach_the_exact_rule_minimiser():
+    """Budget set, certified-convex CRRA: Armijo and exact steps end within
+    the stopping tolerance of the same unique minimiser, |x - x*| <=
+    |gbar| / lambda_min of the reduced Hessian for both runs; on n12_T500
+    simplex both end on the same two-asset face."""
+    R = synth.workload_returns("n400_T4800")
+    mu, A = O.center(R)
+    c = synth.crra_coefficients(6.0)
+    xe, ie = O.solve(R, c)
+    xa, ia = O.solve(R, c, opts=O.Options(linesearch="armijo"))
+    assert ie.status == 0 and ia.status == 0
+    U = O.tangent_basis(np.ones((mu.size, 1)))
+    H = U.T @ (A.T @ (O.d2psi(c, A @ xe)[:, None] * A) / A.shape[0]) @ U
+    lam = float(np.linalg.eigvalsh(H)[0])
+    assert np.linalg.norm(xa - xe) <= 1.1 * (ie.gnorm + ia.gnorm) / lam
+    R = synth.workload_returns("n12_T500")
+    xe, ie = O.solve(R, [1.0, 1.0, 1.0, 1.0], opts=O.Options(feasible_set="simplex"))
+    xa, ia = O.solve(R, [1.0, 1.0, 1.0, 1.0],
+                     opts=O.Options(feasible_set="simplex", linesearch="armijo"))
+    assert ia.status == 0
+    assert np.array_equal(xa > 1e-6, xe > 1e-6)
+
+
+def test_kkt_on_the_slice_and_the_floor_against_delta0():
+    """At the boundary block's solution on n12_T500 (two free coordinates,
+    ten on the bound tau), the residual on the slice vanishes to the
+    stopping tolerance, while against Delta(0) it keeps the floor
+    tau sqrt(n_b^2 / n_free + n_b): the bound coordinates drop to 0 and
+    their mass n_b tau spreads over the free ones."""
+    R = synth.workload_returns("n12_T500")
+    mu, A = O.center(R)
+    c = np.array([1.0, 1.0, 1.0, 1.0])
+    x, info = O.solve(R, c, opts=O.Options(feasible_set="simplex"))
+    tau = 1e-8
+    nb = int(np.count_nonzero(x <= tau * (1 + 1e-6)))
+    assert nb == 10
+    assert O.kkt_residual(A, mu, c, x, tau) <= 1e-8
+    assert info.kkt == pytest.approx(O.kkt_residual(A, mu, c, x, tau), rel=1e-12, abs=1e-20)
+    floor = tau * math.sqrt(nb * nb / 2.0 + nb)
+    assert O.kkt_residual(A, mu, c, x, 0.0) == pytest.approx(floor, rel=1e-3)
