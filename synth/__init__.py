@@ -8,6 +8,7 @@ part of the method.
 
 from .factor_model import (  # noqa: F401
     factor_returns,
+    priced_factor_returns,
     uniform_returns,
     crra_coefficients,
     WORKLOADS,

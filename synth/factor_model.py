@@ -58,6 +58,18 @@ def factor_returns(n: int, T: int, K: int, S: int, nu: float, p_jump: float,
     return np.ascontiguousarray(R, dtype=np.float64)
 
 
+def priced_factor_returns(n: int, T: int, K: int, nu: float, seed: int,
+                          premium: float = 5e-4) -> np.ndarray:
+    """Factor returns ``G(n, T, K, 0, nu, 0, seed)`` plus a drift that prices
+    market risk: asset i earns ``premium * beta[i, 0]`` per bar, with beta
+    the loadings the generator drew first (recomputed here from the same
+    seed).  Stands in for a panel whose riskier assets carry higher means,
+    which a return floor needs to bind."""
+    R = factor_returns(n, T, K, 0, nu, 0.0, seed)
+    beta = np.random.default_rng(seed).normal(1.0, 0.3, size=(n, K))
+    return np.ascontiguousarray(R + premium * beta[:, 0][None, :])
+
+
 def uniform_returns(n: int, T: int, seed: int, lo: float = -0.1,
                     hi: float = 0.4) -> np.ndarray:
     """Independent returns on [lo, hi]: the synthetic benchmark of Section 6.1."""

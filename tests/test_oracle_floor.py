@@ -1,0 +1,156 @@
+"""Pins of the oracle's return-floor protocol (real-data comparison of the
+Section 'Computational Study': coefficients normalised by the equal-weight
+moment magnitudes, c1 calibrated so the long-only portfolio's in-sample mean
+meets the q-th percentile of the asset means).
+
+Every expected value here is computed without the oracle's solver: the
+closed-form two-asset portfolio, moments taken straight from R, order
+statistics by hand, the scaling law of the normalisation, and brackets
+formed by independent solves around the returned c1."""
+
+import numpy as np
+import pytest
+
+import oracle as O
+import synth
+
+KURT = (1.0, 1.0, 10.0)   # kurtosis-focused profile (p2, p3, p4)
+
+
+def _raw_moments(R, x):
+    """mean return and central moments 2..4 of the portfolio R x, from R."""
+    r = R @ x
+    z = r - r.mean()
+    return r.mean(), np.mean(z**2), np.mean(z**3), np.mean(z**4)
+
+
+def _floor_by_hand(mu, q):
+    s = sorted(mu)
+    h = (len(s) - 1) * q
+    lo = int(np.floor(h))
+    hi = min(lo + 1, len(s) - 1)
+    return s[lo] + (h - lo) * (s[hi] - s[lo])
+
+
+def test_normalisation_from_equal_weight_moments():
+    R = synth.priced_factor_returns(20, 300, 3, 5.0, 5)
+    res = O.return_floor(R, KURT, 0.3)
+    n = R.shape[1]
+    _, m2, m3, m4 = _raw_moments(R, np.full(n, 1.0 / n))
+    assert res.c[1] == pytest.approx(KURT[0] / abs(m2), rel=1e-12)
+    assert res.c[2] == pytest.approx(KURT[1] / abs(m3), rel=1e-12)
+    assert res.c[3] == pytest.approx(KURT[2] / abs(m4), rel=1e-12)
+
+
+@pytest.mark.parametrize("q", [0.0, 0.3, 0.5, 0.77, 1.0])
+def test_floor_is_the_percentile_of_asset_means(q):
+    R = synth.priced_factor_returns(21, 200, 3, 5.0, 6)
+    res = O.return_floor(R, KURT, q, max_rounds=2)
+    mu = R.mean(axis=0)
+    assert res.floor == pytest.approx(_floor_by_hand(mu, q), rel=1e-14)
+
+
+def test_slack_floor_keeps_c1_zero():
+    # q = 0: the floor is the smallest asset mean, which every simplex
+    # portfolio meets, so the protocol must stop after the c1 = 0 solve.
+    R = synth.priced_factor_returns(20, 300, 3, 5.0, 5)
+    res = O.return_floor(R, KURT, 0.0)
+    assert res.c[0] == 0.0 and res.solves == 1
+    assert res.ret >= res.floor
+
+
+def _two_asset_case():
+    R = synth.priced_factor_returns(2, 400, 3, 5.0, 3)
+    mu = R.mean(axis=0)
+    return R, mu
+
+
+@pytest.mark.parametrize("q", [0.5, 0.8])
+def test_two_assets_closed_form_weights(q):
+    # With two assets the floor fixes the portfolio: t mu_1 + (1-t) mu_2 =
+    # floor.  The minimum-risk portfolio (c1 = 0) of this panel earns less
+    # than these floors, so the calibration must reach that t.
+    R, mu = _two_asset_case()
+    res = O.return_floor(R, KURT, q)
+    floor = _floor_by_hand(mu, q)
+    t = (floor - mu[1]) / (mu[0] - mu[1])
+    assert res.c[0] > 0.0
+    assert res.x[0] == pytest.approx(t, abs=1e-9)
+    assert abs(res.ret - floor) <= 1e-9 * abs(mu[0] - mu[1])
+
+
+@pytest.mark.parametrize("q", [0.5, 0.8])
+def test_two_assets_c1_from_first_order_condition(q):
+    # At an interior two-asset optimum d/dt f(t, 1-t) = 0, so
+    # c1 (mu_1 - mu_2) = d/dt [c2 m2 - c3 m3 + c4 m4], with the moments taken
+    # from R directly and the derivative by central differences.
+    R, mu = _two_asset_case()
+    res = O.return_floor(R, KURT, q)
+    c = res.c
+    t = res.x[0]
+
+    def risk(s):
+        _, m2, m3, m4 = _raw_moments(R, np.array([s, 1.0 - s]))
+        return c[1] * m2 - c[2] * m3 + c[3] * m4
+
+    h = 1e-5
+    slope = (risk(t + h) - risk(t - h)) / (2 * h)
+    assert c[0] == pytest.approx(slope / (mu[0] - mu[1]), rel=1e-5)
+
+
+def test_scaling_returns_scales_c1_inversely():
+    # R -> s R scales mu and the floor by s and m_k by s^k; the normalised
+    # c2..c4 absorb the moments, so the same weights must come back with c1/s.
+    R = synth.priced_factor_returns(20, 300, 3, 5.0, 5)
+    a = O.return_floor(R, KURT, 0.5)
+    b = O.return_floor(2.0 * R, KURT, 0.5)
+    assert b.floor == pytest.approx(2.0 * a.floor, rel=1e-14)
+    assert b.c[0] == pytest.approx(a.c[0] / 2.0, rel=1e-6)
+    assert np.max(np.abs(a.x - b.x)) < 1e-7
+
+
+@pytest.mark.parametrize("q", [0.4, 0.6])
+def test_returned_c1_brackets_the_floor(q):
+    # Independent solves just below and just above the returned c1 must
+    # straddle the floor (the mean of the minimiser is nondecreasing in c1 on
+    # this convex profile), and the returned mean sits within the stopping
+    # tolerance.
+    R = synth.priced_factor_returns(20, 300, 3, 5.0, 5)
+    res = O.return_floor(R, KURT, q)
+    mu = R.mean(axis=0)
+    spread = mu.max() - mu.min()
+    assert res.c[0] > 0.0
+    assert abs(res.ret - res.floor) <= 1e-9 * spread
+    opts = O.Options(feasible_set="simplex")
+    for f, side in ((0.98, -1), (1.02, 1)):
+        c = res.c.copy()
+        c[0] *= f
+        x, _ = O.solve(R, c, opts=opts)
+        assert side * (mu @ x - res.floor) > 0.0
+
+
+def test_mean_return_monotone_in_c1():
+    # The property the root-find leans on, checked on a grid of solves.
+    R = synth.priced_factor_returns(20, 300, 3, 5.0, 5)
+    res = O.return_floor(R, KURT, 0.5)
+    opts = O.Options(feasible_set="simplex")
+    rets = []
+    for f in (0.0, 0.25, 0.5, 1.0, 2.0, 4.0):
+        c = res.c.copy()
+        c[0] *= f
+        x, _ = O.solve(R, c, opts=opts)
+        rets.append(R.mean(axis=0) @ x)
+    assert all(b >= a - 1e-12 for a, b in zip(rets, rets[1:]))
+
+
+def test_profile_outside_certificate_raises():
+    # The skew-focused profile normalised on this panel fails the coefficient
+    # certificate 8 c2 c4 > 3 c3^2; the solve reports the indefinite tangent
+    # Hessian and the protocol passes the error on.
+    R = synth.priced_factor_returns(20, 300, 3, 5.0, 5)
+    n = R.shape[1]
+    _, m2, m3, m4 = _raw_moments(R, np.full(n, 1.0 / n))
+    c2, c3, c4 = 1.0 / m2, 10.0 / abs(m3), 1.0 / m4
+    assert not 8.0 * c2 * c4 > 3.0 * c3**2
+    with pytest.raises(O.Indefinite):
+        O.return_floor(R, (1.0, 10.0, 1.0), 0.5)
