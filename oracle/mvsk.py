@@ -360,16 +360,20 @@ def kkt_residual(A, mu, c, x, tau=0.0):
     return float(np.linalg.norm(x - project_simplex(x - g, tau)))
 
 
-def face_free(x, g, tau):
+def face_free(x, g, tau, hold=None):
     """Free coordinates of the current face of Delta(tau) (boundary block of
     Algorithm 1: continuation on the exposed active face).  Coordinates
     above the slice bound, x_i > tau (1 + 1e-6), are free; a bound
     coordinate is released when its multiplier g_i - nu is negative, with nu
     the mean of g over the coordinates above the bound (the budget
-    multiplier of the face problem)."""
+    multiplier of the face problem), unless the face solver holds it at the
+    bound (hold, see _iterate)."""
     strict = x > tau * (1.0 + 1e-6)
     nu = float(np.sum(g[strict])) / int(np.count_nonzero(strict))
-    return strict | (g < nu)
+    release = g < nu
+    if hold is not None:
+        release &= ~hold
+    return strict | release
 
 
 def face_basis(free):
@@ -505,6 +509,13 @@ def _iterate(A, mu, c, x, U, opts: Options, solver, krylov_maxit, max_iter,
         on the corrected segment x + a (xbar - x), a in [0, 1], provided
         that segment is a descent direction and not numerically zero;
         otherwise the capped raw step is taken, which exposes the next face;
+      * when neither segment gives a step (the corrected segment is no
+        descent direction) the released coordinates at the bound that the
+        direction drives further down are handed to the face solver: they
+        are held at the bound, so the following iterations run on that
+        lower-dimensional face; the holds are dropped once the held face is
+        stationary (|reduced gradient| <= eps), which then counts as
+        convergence only without holds;
       * the stopping test also accepts a projected-KKT residual
         (kkt_residual on Delta(tau)) at or below eps.
     With eta = 0 the simplex set only caps the raw step.
@@ -514,17 +525,28 @@ def _iterate(A, mu, c, x, U, opts: Options, solver, krylov_maxit, max_iter,
     faces = simplex and eta > 0.0
     small = 0
     f_prev = objective(A, mu, c, x)
+    hold = np.zeros(x.size, dtype=bool)
+    release = False
+    thr = opts.tau * (1.0 + 1e-6)
     for _ in range(max_iter):
         g = gradient(A, mu, c, x)
         info.oracle_passes += 1
-        Ui = face_basis(face_free(x, g, opts.tau)) if faces else U
+        if release:
+            hold[:] = False
+            release = False
+        free = face_free(x, g, opts.tau, hold) if faces else None
+        Ui = face_basis(free) if faces else U
         gn = float(np.linalg.norm(Ui.T @ g))
         info.gnorm = gn
         if simplex:
             info.kkt = float(np.linalg.norm(
                 x - project_simplex(x - g, opts.tau)))
-        if gn <= opts.eps or (simplex and info.kkt <= opts.eps):
+        if simplex and info.kkt <= opts.eps:
             return x, True, False
+        if gn <= opts.eps:
+            if not hold.any():
+                return x, True, False
+            release = True
         if time.perf_counter() - t0 > opts.max_elapsed:
             return x, False, True
         reg = opts.reg if solver == "pcg" else 0.0
@@ -540,6 +562,8 @@ def _iterate(A, mu, c, x, U, opts: Options, solver, krylov_maxit, max_iter,
                     and float(g @ dbar) < 0.0):
                 d, amax = dbar, 1.0
                 info.projected_steps += 1
+            else:
+                hold |= free & (x <= thr) & (d < 0.0)
         coef = linesearch_coeffs(A, mu, c, x, d)
         info.ls_passes += 1
         alpha = (armijo_step(coef, amax) if opts.linesearch == "armijo"
@@ -638,9 +662,10 @@ def return_floor(R, profile, q, opts: Options | None = None, max_rounds=40):
     The root-find over solves is a reading (the paper gives none).  It leans
     on the mean return of the minimiser being nondecreasing in c1 (true when
     f is convex: compare the optimality of the two minimisers).  c1 = 0 first
-    (kept when it already meets the floor; negative c1 would reward a lower
-    mean); then c1 = 1 / (max mu - min mu), growing by factors of 4 until the
-    floor is met; then geometric bisection of the bracket (its midpoint is
+    (kept when it already meets the floor, or when all asset means are
+    equal; negative c1 would reward a lower mean); then
+    c1 = 1 / (max mu - min mu), growing by factors of 4 until the floor is
+    met; then geometric bisection of the bracket (its midpoint is
     c_hi / 2 while the lower end is 0), at most max_rounds rounds each,
     stopping once |mu^T x - floor| <= 1e-9 (max mu - min mu).  Every solve
     starts from equal weights.  The closest solve is returned (ties to the
@@ -651,7 +676,12 @@ def return_floor(R, profile, q, opts: Options | None = None, max_rounds=40):
     mu, A = center(R)
     n = mu.size
     m = moments(A, mu, np.full(n, 1.0 / n))
-    base = np.array([0.0, p2 / abs(m[1]), p3 / abs(m[2]), p4 / abs(m[3])])
+    base = np.zeros(4)
+    for k, p in ((1, p2), (2, p3), (3, p4)):
+        if p != 0.0:
+            if m[k] == 0.0:
+                raise ValueError("profile weight on a vanishing moment")
+            base[k] = p / abs(m[k])
     floor = float(np.quantile(mu, q))
     spread = float(mu.max() - mu.min())
     tol = 1e-9 * spread
@@ -675,7 +705,7 @@ def return_floor(R, profile, q, opts: Options | None = None, max_rounds=40):
 
     lo = run(0.0)
     keep(lo)
-    if lo[0] < floor:
+    if lo[0] < floor and spread > 0.0:
         hi = run(1.0 / spread)
         keep(hi)
         k = 0

@@ -59,15 +59,24 @@ def factor_returns(n: int, T: int, K: int, S: int, nu: float, p_jump: float,
 
 
 def priced_factor_returns(n: int, T: int, K: int, nu: float, seed: int,
-                          premium: float = 5e-4) -> np.ndarray:
-    """Factor returns ``G(n, T, K, 0, nu, 0, seed)`` plus a drift that prices
-    market risk: asset i earns ``premium * beta[i, 0]`` per bar, with beta
-    the loadings the generator drew first (recomputed here from the same
-    seed).  Stands in for a panel whose riskier assets carry higher means,
-    which a return floor needs to bind."""
+                          premium: float = 5e-4,
+                          p_crash: float = 0.01) -> np.ndarray:
+    """A panel whose riskier assets carry higher means and whose market
+    falls in rare crashes, as a return floor and a skew preference need.
+
+    ``G(n, T, K, 0, nu, 0, seed)`` plus two terms on the first loading
+    ``beta[:, 0]`` (the draws of ``G`` recomputed from the same seed):
+    a drift ``premium * beta[i, 0]`` per bar, and crash bars (probability
+    p_crash each) on which asset i moves by ``-|J_t| beta[i, 0]`` with
+    ``J_t ~ N(0, (10 * 0.002)^2)``.  The crash mask and sizes come from
+    ``numpy.random.default_rng((seed, 1))``, mask first."""
     R = factor_returns(n, T, K, 0, nu, 0.0, seed)
-    beta = np.random.default_rng(seed).normal(1.0, 0.3, size=(n, K))
-    return np.ascontiguousarray(R + premium * beta[:, 0][None, :])
+    lead = np.random.default_rng(seed).normal(1.0, 0.3, size=(n, K))[:, 0]
+    rng = np.random.default_rng((seed, 1))
+    mask = rng.random(T) < p_crash
+    sizes = -np.abs(rng.normal(0.0, 10.0 * BAR_VOL, size=T))
+    R += np.where(mask, sizes, 0.0)[:, None] * lead[None, :]
+    return np.ascontiguousarray(R + premium * lead[None, :])
 
 
 def uniform_returns(n: int, T: int, seed: int, lo: float = -0.1,

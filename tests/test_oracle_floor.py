@@ -60,7 +60,7 @@ def test_slack_floor_keeps_c1_zero():
 
 
 def _two_asset_case():
-    R = synth.priced_factor_returns(2, 400, 3, 5.0, 3)
+    R = synth.priced_factor_returns(2, 400, 3, 5.0, 4)
     mu = R.mean(axis=0)
     return R, mu
 

@@ -222,3 +222,27 @@ def test_kkt_on_the_slice_and_the_floor_against_delta0():
     assert info.kkt == pytest.approx(O.kkt_residual(A, mu, c, x, tau), rel=1e-12, abs=1e-20)
     floor = tau * math.sqrt(nb * nb / 2.0 + nb)
     assert O.kkt_residual(A, mu, c, x, 0.0) == pytest.approx(floor, rel=1e-3)
+
+
+def test_face_solver_takes_over_when_no_segment_descends():
+    # A crash-skewed panel where the direction on the released face drives a
+    # bound coordinate further down and the projected segment is no descent
+    # direction either: without handing those coordinates to the face solver
+    # the run stalls at zero steps with f = 10.92 and a KKT residual near 1.
+    # With the hand-off it must reach the simplex KKT point.
+    R = synth.priced_factor_returns(60, 600, 3, 5.0, 3)
+    mu, A = O.center(R)
+    n = R.shape[1]
+    m = O.moments(A, mu, np.full(n, 1.0 / n))
+    c = np.array([4434.270595, 1.0 / m[1], 1.0 / abs(m[2]), 10.0 / m[3]])
+    x, info = O.solve(R, c, opts=O.Options(feasible_set="simplex"))
+    assert info.status == 0
+    assert O.kkt_residual(A, mu, c, x, 1e-8) <= 1e-8
+    assert O.objective(A, mu, c, x) < 10.0
+    # KKT on Delta(tau) read off directly: one multiplier on the support,
+    # nothing below it on the bound coordinates
+    g = O.gradient(A, mu, c, x)
+    sup = x > 1e-8 * (1.0 + 1e-6)
+    nu = g[sup].mean()
+    assert np.max(np.abs(g[sup] - nu)) <= 1e-7 * np.max(np.abs(g))
+    assert np.all(g[~sup] >= nu - 1e-7 * np.max(np.abs(g)))
