@@ -191,6 +191,36 @@ int yand_mvsk_solve(yand_ctx* ctx, const double c[4], const double* target,
                     const double* w0, const yand_opts* opts, double* w_out,
                     yand_info* info);
 
+/* Return-floor protocol of the real-data comparison (Section "Computational
+ * Study"): the long-only MVSK portfolio whose in-sample mean return
+ * mu^T w lies as close as possible to the floor, the q-th percentile of the
+ * asset means (linear interpolation between order statistics at (n-1) q).
+ *  - Normalisation: c_k = profile[k-2] / |m_k(1/n)| for k = 2, 3, 4, the
+ *    moments of the equal-weight portfolio (profile = (p2, p3, p4), host).
+ *  - Calibration of c1 (the paper gives no rule; this one leans on mu^T w
+ *    of the minimiser being nondecreasing in c1, which holds when f is
+ *    convex): c1 = 0 first, kept when it meets the floor (or when all asset
+ *    means are equal); else c1 = 1 / (max mu - min mu), times 4 until the
+ *    floor is met; then geometric bisection of the bracket (c_hi / 2 while
+ *    the lower end is 0).  Each phase takes at most max_rounds solves; the
+ *    bisection stops once |mu^T w - floor| <= 1e-9 (max mu - min mu).
+ *    Every solve is yand_mvsk_solve from equal weights with opts (NULL: the
+ *    direct configuration on YAND_SET_SIMPLEX; a non-NULL opts must select
+ *    YAND_SET_SIMPLEX).
+ * Outputs (all but w_out nullable): the closest solve (ties to the larger
+ * c1): c_out[4] and floor_out, ret_out (host), its weights w_out (device, n)
+ * and info (host), and the number of solves (host).  Returns that solve's
+ * status (0 or a warning).  YAND_ERR_ARG for q outside [0, 1], a negative
+ * or non-finite profile entry, max_rounds < 0, a nonzero profile entry
+ * whose equal-weight moment is 0, or opts not on the simplex; a solve's
+ * error (YAND_ERR_INDEFINITE outside the convexity certificate) ends the
+ * protocol and is returned, with the outputs left unset.  Allocates one
+ * n-vector of device memory for the duration of the call. */
+int yand_return_floor(yand_ctx* ctx, const double profile[3], double q,
+                      const yand_opts* opts, int max_rounds, double c_out[4],
+                      double* floor_out, double* ret_out, double* w_out,
+                      yand_info* info, int* solves);
+
 /* Batched efficient-frontier solve on one context (shared A): instance b
  * minimises with preference vector C4[4b..4b+3] (host) and, when targets
  * (host, length B) is not NULL, the return target targets[b].  W0 (device,

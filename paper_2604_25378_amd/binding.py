@@ -128,6 +128,10 @@ def load(path: str = LIB_PATH):
         "yand_profile_enable": (C.c_int, [vp, C.c_int]),
         "yand_project_simplex": (C.c_int, [vp, C.c_int64, C.c_double, vp]),
         "yand_kkt_residual": (C.c_int, [vp, _D, vp, C.c_double, _D]),
+        "yand_return_floor": (C.c_int, [vp, _D, C.c_double,
+                                        C.POINTER(yand_opts), C.c_int, _D, _D,
+                                        _D, vp, C.POINTER(yand_info),
+                                        C.POINTER(C.c_int)]),
         "yand_autotune": (C.c_int, [vp, _D]),
         "yand_tuning": (C.c_int, [vp, C.POINTER(C.c_int), C.POINTER(C.c_int)]),
         "yand_profile_read": (C.c_int, [vp, C.c_int, C.c_char_p, C.c_int, _D,
@@ -340,6 +344,26 @@ class Context:
             C.byref(info))
         _check(rc, "yand_mvsk_solve", warn_ok=not raise_on_warning)
         return out, SolveInfo(**{k: getattr(info, k) for k, _ in yand_info._fields_})
+
+    def return_floor(self, profile, q: float, opts: yand_opts | None = None,
+                     max_rounds: int = 40):
+        """Return-floor protocol: (c, w, floor, ret, info, solves) of the
+        long-only solve whose mean return is closest to the q-th percentile
+        of the asset means, with c2..c4 normalised from profile (p2, p3, p4).
+        """
+        torch = _torch()
+        out = torch.empty(self.n, dtype=torch.float64, device="cuda")
+        prof = (C.c_double * 3)(*[float(v) for v in profile])
+        c = (C.c_double * 4)()
+        fl, ret, ns = C.c_double(), C.c_double(), C.c_int()
+        info = yand_info()
+        rc = self._lib.yand_return_floor(
+            self._h, prof, float(q), C.byref(opts) if opts else None,
+            int(max_rounds), c, C.byref(fl), C.byref(ret),
+            C.c_void_p(out.data_ptr()), C.byref(info), C.byref(ns))
+        _check(rc, "yand_return_floor", warn_ok=True)
+        si = SolveInfo(**{k: getattr(info, k) for k, _ in yand_info._fields_})
+        return list(c), out, fl.value, ret.value, si, ns.value
 
     def frontier(self, C4, targets=None, opts: yand_opts | None = None,
                  W0=None):

@@ -70,6 +70,7 @@ struct Work {
          *trpart = nullptr;
   double *B = nullptr, *M = nullptr, *X = nullptr, *rn = nullptr;
   double *mask = nullptr, *ptmp = nullptr;  // face mask, projection scratch
+  double* hold = nullptr;  // coordinates the face solver holds at the bound
   DevScalars* sc = nullptr;
   bool own_sc = true;
   DevScalars hs{};
@@ -163,7 +164,8 @@ void free_work(Work& w) {
                     w.AE,    w.E,      w.W,     w.t3,     w.r,    w.y,
                     w.y2,    w.hv,     w.s_t,   w.pcg_s,  w.pcg_res,
                     w.pcg_p, w.pcg_u,  w.part,  w.psums,  w.sums, w.trpart,
-                    w.B,     w.M,      w.X,     w.rn,     w.mask, w.ptmp};
+                    w.B,     w.M,      w.X,     w.rn,     w.mask, w.ptmp,
+                    w.hold};
   for (double* p : ptrs)
     if (p) (void)hipFree(p);
   if (w.sc && w.own_sc) (void)hipFree(w.sc);
@@ -189,6 +191,7 @@ int alloc_work(Work& w, const Data& D, DevScalars* sc_external) {
       (rc = alloc((void**)&w.pcg_p, nb)) ||
       (rc = alloc((void**)&w.pcg_u, nb)) ||
       (rc = alloc((void**)&w.mask, nb)) || (rc = alloc((void**)&w.ptmp, nb)) ||
+      (rc = alloc((void**)&w.hold, nb)) ||
       (rc = alloc((void**)&w.part,
                   (size_t)kMaxPassGroups * lda * sizeof(double))) ||
       (rc = alloc((void**)&w.psums,
@@ -427,8 +430,8 @@ int dir_direct_solve(const Data& D, Work& w, int p0, const double* x,
   HIPTRY(launch_direction(w.y2, w.E, p0 + 1, n, x, D.mu, o.tau, o.simplex, d,
                           w.sc, w.st, face_mask(w, o)));
   if (o.faces)
-    HIPTRY(launch_boundary(x, w.g, D.mu, n, o.tau, o.eta, d, w.ptmp, w.sc,
-                           w.st));
+    HIPTRY(launch_boundary(x, w.g, D.mu, n, o.tau, o.eta, d, w.ptmp, w.mask,
+                           w.hold, w.sc, w.st));
   return YAND_OK;
 }
 
@@ -574,8 +577,8 @@ int dir_pcg_solve(const Data& D, Work& w, const double c[4], int p0,
   HIPTRY(launch_direction(w.pcg_s, w.E, p, n, x, D.mu, o.tau, o.simplex, d,
                           w.sc, w.st, mask));
   if (o.faces)
-    HIPTRY(launch_boundary(x, w.g, D.mu, n, o.tau, o.eta, d, w.ptmp, w.sc,
-                           w.st));
+    HIPTRY(launch_boundary(x, w.g, D.mu, n, o.tau, o.eta, d, w.ptmp, w.mask,
+                           w.hold, w.sc, w.st));
   return YAND_OK;
 }
 
@@ -611,7 +614,8 @@ int direction_eager(const Data& D, Work& w, const double c[4], int p0,
 int stationarity(const Data& D, Work& w, const DirOpts& o, int p0,
                  double eps) {
   if (o.faces)
-    HIPTRY(launch_face(w.x, w.g, D.n, o.tau, w.E, w.mask, w.sc, w.st));
+    HIPTRY(launch_face(w.x, w.g, D.n, o.tau, w.E, w.mask, w.hold, w.sc,
+                       w.st));
   HIPTRY(launch_grad_project(w.g, w.E, p0, D.n, w.sc, w.st, eps,
                              face_mask(w, o)));
   if (o.simplex)
@@ -694,6 +698,7 @@ int setup_lane(const Data& D, Work& w, const double* target,
   *p0 = target ? 2 : 1;
   if (target && (!D.have_e2 || !std::isfinite(*target))) return YAND_ERR_ARG;
   hipLaunchKernelGGL(set_frozen_kernel, dim3(1), dim3(64), 0, w.st, w.sc, 0);
+  HIPTRY(launch_reset_hold(w.hold, D.n, w.sc, w.st));
   HIPTRY(launch_copy(w.E, D.Efix, (int64_t)(*p0) * D.n, w.st));
   if (w0)
     HIPTRY(launch_copy(w.x, w0, D.n, w.st));
@@ -798,6 +803,7 @@ int after_iteration(Lane& L, const yand_opts& opts, const DirOpts& o) {
 int final_check(Lane& L, const yand_opts& opts, const DirOpts& o) {
   Work& w = *L.w;
   hipLaunchKernelGGL(set_frozen_kernel, dim3(1), dim3(64), 0, w.st, w.sc, 0);
+  HIPTRY(launch_reset_hold(w.hold, L.D->n, w.sc, w.st));
   TRY(oracle_at(*L.D, w, L.c, w.x, true));
   TRY(stationarity(*L.D, w, o, L.p0, opts.eps));
   TRY(sync_scalars(w));
@@ -907,8 +913,11 @@ int run_lanes(std::vector<Lane>& lanes, const yand_opts& opts,
   if (graph) (void)hipGraphDestroy(graph);
   cleanup();
   if (rc) return rc;
-  for (auto& L : lanes)
+  for (auto& L : lanes) {
     if (L.rc == YAND_OK && !L.converged) TRY(final_check(L, opts, o));
+    // holds belong to one solve: later calls on the work start without them
+    HIPTRY(launch_reset_hold(L.w->hold, L.D->n, L.w->sc, L.w->st));
+  }
   return YAND_OK;
 }
 
@@ -1292,6 +1301,7 @@ static int solve_pcg(yand_ctx* ctx, const double c[4], int p0,
     const auto t_phase = std::chrono::steady_clock::now();
     int small = 0;
     double f_prev = NAN;
+    HIPTRY(launch_reset_hold(w.hold, D.n, w.sc, w.st));
     for (int it = 0;; ++it) {
       TRY(oracle_at(D, w, c, w.x, true));
       inf.oracle_passes++;
@@ -1334,7 +1344,21 @@ static int solve_pcg(yand_ctx* ctx, const double c[4], int p0,
       }
       f_prev = A[0] - dec;
     }
+    if (!*converged) {
+      // budget spent or stalled: the phase's state is that of x on its own
+      // face, without the face solver's holds
+      HIPTRY(launch_reset_hold(w.hold, D.n, w.sc, w.st));
+      TRY(oracle_at(D, w, c, w.x, true));
+      TRY(stationarity(D, w, o, p0, opts.eps));
+      TRY(sync_scalars(w));
+      inf.f = w.hs.f;
+      inf.gnorm = w.hs.gn;
+      inf.kkt = o.simplex ? w.hs.kkt : NAN;
+      if (w.hs.nonfinite) return YAND_ERR_NONFINITE;
+      *converged = w.hs.done != 0;
+    }
   }
+  HIPTRY(launch_reset_hold(w.hold, D.n, w.sc, w.st));
   return YAND_OK;
 }
 
@@ -1700,6 +1724,133 @@ int yand_warmstart_predict(yand_ctx* ctx, yand_mlp* mlp, int64_t B,
   HIPTRY(hipStreamSynchronize(st));
   flush_timed(ctx->prof, st);
   return YAND_OK;
+}
+
+// ------------------------------------------------ return-floor protocol --
+
+namespace {
+
+// Linear interpolation between order statistics at (n - 1) q.
+double percentile(std::vector<double> v, double q) {
+  std::sort(v.begin(), v.end());
+  const double h = (double)(v.size() - 1) * q;
+  const size_t lo = (size_t)std::floor(h);
+  const size_t hi = std::min(lo + 1, v.size() - 1);
+  return v[lo] + (h - (double)lo) * (v[hi] - v[lo]);
+}
+
+struct DeviceVec {
+  double* p = nullptr;
+  ~DeviceVec() {
+    if (p) (void)hipFree(p);
+  }
+};
+
+}  // namespace
+
+int yand_return_floor(yand_ctx* ctx, const double profile[3], double q,
+                      const yand_opts* opts_in, int max_rounds,
+                      double c_out[4], double* floor_out, double* ret_out,
+                      double* w_out, yand_info* info, int* solves_out) {
+  if (!ctx || !profile || !w_out || !(q >= 0.0 && q <= 1.0) ||
+      max_rounds < 0)
+    return YAND_ERR_ARG;
+  for (int k = 0; k < 3; ++k)
+    if (!(profile[k] >= 0.0) || !std::isfinite(profile[k]))
+      return YAND_ERR_ARG;
+  yand_opts opts;
+  if (opts_in) {
+    opts = *opts_in;
+  } else {
+    yand_default_opts(&opts);
+    opts.feasible_set = YAND_SET_SIMPLEX;
+  }
+  if (opts.feasible_set != YAND_SET_SIMPLEX || !valid_opts(opts))
+    return YAND_ERR_ARG;
+  const Data& D = ctx->d;
+  const int64_t n = D.n;
+
+  double mom[4];
+  TRY(equal_weight_moments(ctx, mom));
+  double base[4] = {0.0, 0.0, 0.0, 0.0};
+  for (int k = 0; k < 3; ++k) {
+    if (profile[k] == 0.0) continue;
+    if (mom[k + 1] == 0.0) return YAND_ERR_ARG;
+    base[k + 1] = profile[k] / std::fabs(mom[k + 1]);
+  }
+  std::vector<double> mu(n), x(n);
+  HIPTRY(hipMemcpyAsync(mu.data(), D.mu, n * sizeof(double),
+                        hipMemcpyDeviceToHost, ctx->w.st));
+  HIPTRY(hipStreamSynchronize(ctx->w.st));
+  const double floor_v = percentile(mu, q);
+  const auto mm = std::minmax_element(mu.begin(), mu.end());
+  const double spread = *mm.second - *mm.first;
+  const double tol = 1e-9 * spread;
+
+  DeviceVec cur;
+  HIPTRY(hipMalloc((void**)&cur.p, n * sizeof(double)));
+
+  struct Pt {
+    double ret, c1;
+  };
+  Pt best{0.0, -1.0};
+  bool have_best = false;
+  yand_info best_info{};
+  int solves = 0;
+
+  // One solve from equal weights at the mean coefficient c1; the closest
+  // solve so far (ties to the larger c1) is kept in w_out.
+  auto run = [&](double c1, Pt* out) -> int {
+    double c[4] = {c1, base[1], base[2], base[3]};
+    yand_info inf{};
+    const int rc = yand_mvsk_solve(ctx, c, nullptr, nullptr, &opts, cur.p,
+                                   &inf);
+    ++solves;
+    if (rc < 0) return rc;
+    HIPTRY(hipMemcpy(x.data(), cur.p, n * sizeof(double),
+                     hipMemcpyDeviceToHost));
+    double r = 0.0;
+    for (int64_t i = 0; i < n; ++i) r += mu[i] * x[i];
+    out->ret = r;
+    out->c1 = c1;
+    const double e = std::fabs(r - floor_v), eb = std::fabs(best.ret - floor_v);
+    if (!have_best || e < eb || (e == eb && c1 > best.c1)) {
+      best = *out;
+      best_info = inf;
+      have_best = true;
+      HIPTRY(hipMemcpy(w_out, cur.p, n * sizeof(double),
+                       hipMemcpyDeviceToDevice));
+    }
+    return YAND_OK;
+  };
+
+  Pt lo, hi, mid;
+  TRY(run(0.0, &lo));
+  if (lo.ret < floor_v && spread > 0.0) {
+    TRY(run(1.0 / spread, &hi));
+    for (int k = 0; hi.ret < floor_v && k < max_rounds; ++k) {
+      lo = hi;
+      TRY(run(4.0 * hi.c1, &hi));
+    }
+    for (int k = 0; hi.ret >= floor_v && std::fabs(best.ret - floor_v) > tol &&
+                    k < max_rounds;
+         ++k) {
+      TRY(run(lo.c1 == 0.0 ? 0.5 * hi.c1 : std::sqrt(lo.c1 * hi.c1), &mid));
+      if (mid.ret >= floor_v)
+        hi = mid;
+      else
+        lo = mid;
+    }
+  }
+  if (c_out) {
+    c_out[0] = best.c1;
+    for (int k = 1; k < 4; ++k) c_out[k] = base[k];
+  }
+  if (floor_out) *floor_out = floor_v;
+  if (ret_out) *ret_out = best.ret;
+  if (info) *info = best_info;
+  if (solves_out) *solves_out = solves;
+  return best_info.status;
 }
 
 int yand_mvsk_solve_R(const double* R, int64_t T, int64_t n, double c1,

@@ -24,13 +24,13 @@ struct DevScalars {
   int status;        // quartic step status (0 or -6)
   int fail;          // Cholesky pivot failure
   int nonfinite;     // NaN/Inf seen
-  int pad;
+  int nhold;         // coordinates the face solver holds at the bound
   int done;          // |G| <= eps at this iteration: the rest is skipped
   int frozen;        // lane stopped by the host: every pass is skipped
   double kkt;        // projected-simplex KKT residual (simplex set)
   double nfree;      // free coordinates of the current face (simplex set)
   int projected;     // this iteration took the projected trial segment
-  int pad2;
+  int release;       // drop the holds at the next face evaluation
 };
 
 // Face masks: mask[j] = 1 for a free coordinate of the current face of
@@ -65,18 +65,24 @@ hipError_t launch_direction(const double* y, const double* E, int p,
                             const double* mask = nullptr);
 // Face of Delta(tau) at x: mask, E[0] = mask / sqrt(nfree), sc->nfree.
 hipError_t launch_face(const double* x, const double* g, int64_t n, double tau,
-                       double* E, double* mask, DevScalars* sc,
+                       double* E, double* mask, double* hold, DevScalars* sc,
                        hipStream_t st);
+// hold[j] = 0 for every j, sc->nhold = sc->release = 0.
+hipError_t launch_reset_hold(double* hold, int64_t n, DevScalars* sc,
+                             hipStream_t st);
 // sc->kkt = |x - Pi_Delta(tau)(x - g)|_2; done when kkt <= eps (eps >= 0).
 // tmp: n doubles.
 hipError_t launch_kkt(const double* x, const double* g, int64_t n, double tau,
                       double eps, double* tmp, DevScalars* sc, hipStream_t st);
 // Boundary block: when sc->amax < eta, replace d by the corrected segment
 // Pi_{Delta(tau)}(x + eta d) - x if it is a nonzero descent direction (cap
-// 1, mu^T d updated, sc->projected set).  tmp: n doubles.
+// 1, mu^T d updated, sc->projected set); otherwise hold the free
+// coordinates at the bound that d drives down (hold[j] = 1, sc->nhold
+// counts them) for the face solver.  tmp: n doubles.
 hipError_t launch_boundary(const double* x, const double* g, const double* mu,
                            int64_t n, double tau, double eta, double* d,
-                           double* tmp, DevScalars* sc, hipStream_t st);
+                           double* tmp, const double* mask, double* hold,
+                           DevScalars* sc, hipStream_t st);
 // out = Pi_{Delta(tau)}(y) (one workgroup).
 hipError_t launch_project_simplex(const double* y, int64_t n, double tau,
                                   double* out, hipStream_t st);

@@ -65,9 +65,14 @@ grad_project_kernel(const double* __restrict__ g, double* __restrict__ E,
   if (tid == 0) {
     sc->gn = gn;
     if (!isfinite(gn)) sc->nonfinite = 1;
-    sc->done = (eps >= 0.0 && (sc->frozen || gn <= eps)) || !isfinite(gn)
+    // a face the face solver holds is only a stop once the holds are gone:
+    // at a held face's stationary point they are dropped instead
+    const bool flat = eps >= 0.0 && gn <= eps;
+    sc->done = (eps >= 0.0 && (sc->frozen || (flat && sc->nhold == 0))) ||
+                       !isfinite(gn)
                    ? 1
                    : 0;
+    if (flat && sc->nhold > 0 && !sc->frozen) sc->release = 1;
     sc->fail = 0;
     sc->status = 0;
     sc->alpha = 0.0;
@@ -304,14 +309,18 @@ project_simplex_kernel(const double* __restrict__ y, int64_t n, double tau,
 // the exposed face).  Coordinates above the slice bound, x_j > tau (1 +
 // 1e-6), are free; a bound coordinate is released when its multiplier
 // g_j - nu is negative, nu the mean of g over the coordinates above the
-// bound.  Writes the mask, E[0] = mask / sqrt(nfree) and sc->nfree.
+// bound, unless the face solver holds it (hold[j] != 0).  When the previous
+// stationarity test asked for it (sc->release), the holds are dropped
+// first.  Writes the mask, E[0] = mask / sqrt(nfree) and sc->nfree.
 __global__ void __launch_bounds__(VT)
 face_kernel(const double* __restrict__ x, const double* __restrict__ g,
             int64_t n, double tau, double* __restrict__ E,
-            double* __restrict__ mask, DevScalars* sc) {
+            double* __restrict__ mask, double* __restrict__ hold,
+            DevScalars* sc) {
   if (sc->frozen) return;
   __shared__ double sh[4 * VW];
   const int tid = threadIdx.x;
+  const bool rel = sc->release != 0;
   const double thr = tau * (1.0 + 1e-6);
   double v[2] = {0.0, 0.0};
   for (int64_t j = tid; j < n; j += VT)
@@ -323,14 +332,31 @@ face_kernel(const double* __restrict__ x, const double* __restrict__ g,
   const double nu = v[0] / v[1];
   double cnt[1] = {0.0};
   for (int64_t j = tid; j < n; j += VT) {
-    const double m = (x[j] > thr || g[j] < nu) ? 1.0 : 0.0;
+    if (rel) hold[j] = 0.0;
+    const bool held = !rel && hold[j] != 0.0;
+    const double m = (x[j] > thr || (g[j] < nu && !held)) ? 1.0 : 0.0;
     mask[j] = m;
     cnt[0] += m;
   }
   block_sum(cnt, sh);
   const double inv = 1.0 / sqrt(cnt[0]);
   for (int64_t j = tid; j < n; j += VT) E[j] = mask[j] * inv;
-  if (tid == 0) sc->nfree = cnt[0];
+  if (tid == 0) {
+    sc->nfree = cnt[0];
+    if (rel) {
+      sc->nhold = 0;
+      sc->release = 0;
+    }
+  }
+}
+
+__global__ void __launch_bounds__(VT)
+reset_hold_kernel(double* __restrict__ hold, int64_t n, DevScalars* sc) {
+  for (int64_t j = threadIdx.x; j < n; j += VT) hold[j] = 0.0;
+  if (threadIdx.x == 0) {
+    sc->nhold = 0;
+    sc->release = 0;
+  }
 }
 
 // Projected-simplex KKT residual |x - Pi_Delta(tau)(x - g)|_2.
@@ -359,11 +385,14 @@ kkt_kernel(const double* __restrict__ x, const double* __restrict__ g,
 // trial x + eta d is projected onto Delta(tau) and the corrected segment
 // dbar = xbar - x replaces d (cap 1) when it is a descent direction
 // (g^T dbar < 0) and not numerically zero (max |dbar| > 1e-15 max |x|).
-// Otherwise d stays and the capped step exposes the next face.
+// Otherwise d stays and the capped step exposes the next face; the free
+// coordinates already at the bound (x_j <= tau (1 + 1e-6)) that d drives
+// down are handed to the face solver, which holds them at the bound.
 __global__ void __launch_bounds__(VT)
 boundary_kernel(const double* __restrict__ x, const double* __restrict__ g,
                 const double* __restrict__ mu, int64_t n, double tau,
                 double eta, double* __restrict__ d, double* __restrict__ tmp,
+                const double* __restrict__ mask, double* __restrict__ hold,
                 DevScalars* sc) {
   if (sc->done || !(sc->amax < eta)) return;
   __shared__ double sh[4 * VW];
@@ -383,7 +412,18 @@ boundary_kernel(const double* __restrict__ x, const double* __restrict__ g,
   dm = block_max(dm, sh);
   xm = block_max(xm, sh);
   block_sum(v, sh);
-  if (!(dm > 1e-15 * xm && v[0] < 0.0)) return;
+  if (!(dm > 1e-15 * xm && v[0] < 0.0)) {
+    const double thr = tau * (1.0 + 1e-6);
+    double cnt[1] = {0.0};
+    for (int64_t j = tid; j < n; j += VT)
+      if (mask[j] != 0.0 && x[j] <= thr && d[j] < 0.0 && hold[j] == 0.0) {
+        hold[j] = 1.0;
+        cnt[0] += 1.0;
+      }
+    block_sum(cnt, sh);
+    if (tid == 0) sc->nhold += (int)cnt[0];
+    return;
+  }
   for (int64_t j = tid; j < n; j += VT) d[j] = tmp[j];
   if (tid == 0) {
     sc->mud = v[1];
@@ -672,10 +712,16 @@ hipError_t launch_direction(const double* y, const double* E, int p,
   return hipGetLastError();
 }
 hipError_t launch_face(const double* x, const double* g, int64_t n, double tau,
-                       double* E, double* mask, DevScalars* sc,
+                       double* E, double* mask, double* hold, DevScalars* sc,
                        hipStream_t st) {
   hipLaunchKernelGGL(face_kernel, dim3(1), dim3(VT), 0, st, x, g, n, tau, E,
-                     mask, sc);
+                     mask, hold, sc);
+  return hipGetLastError();
+}
+hipError_t launch_reset_hold(double* hold, int64_t n, DevScalars* sc,
+                             hipStream_t st) {
+  hipLaunchKernelGGL(reset_hold_kernel, dim3(1), dim3(VT), 0, st, hold, n,
+                     sc);
   return hipGetLastError();
 }
 hipError_t launch_kkt(const double* x, const double* g, int64_t n, double tau,
@@ -687,9 +733,10 @@ hipError_t launch_kkt(const double* x, const double* g, int64_t n, double tau,
 }
 hipError_t launch_boundary(const double* x, const double* g, const double* mu,
                            int64_t n, double tau, double eta, double* d,
-                           double* tmp, DevScalars* sc, hipStream_t st) {
+                           double* tmp, const double* mask, double* hold,
+                           DevScalars* sc, hipStream_t st) {
   hipLaunchKernelGGL(boundary_kernel, dim3(1), dim3(VT), 0, st, x, g, mu, n,
-                     tau, eta, d, tmp, sc);
+                     tau, eta, d, tmp, mask, hold, sc);
   return hipGetLastError();
 }
 hipError_t launch_project_simplex(const double* y, int64_t n, double tau,

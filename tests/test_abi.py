@@ -67,6 +67,9 @@ def test_simplex_entry_points_reject_bad_arguments_without_device(lib):
     assert lib.yand_project_simplex(p, 4, -1e-9, p) == -1
     k = C.c_double()
     assert lib.yand_kkt_residual(None, (C.c_double * 4)(1, 1, 1, 1), p, 0.0, C.byref(k)) == -1
+    prof = (C.c_double * 3)(1, 1, 10)
+    assert lib.yand_return_floor(None, prof, 0.5, None, 40, None, None, None,
+                                 p, None, None) == -1
 
 
 def test_create_rejects_bad_arguments_without_device(lib):
