@@ -266,6 +266,54 @@ def conditioning_bench(precision="fp64"):
     return res
 
 
+def return_floor_bench(precision="fp64"):
+    """The return-floor protocol of the real-data comparison on a synthetic
+    stand-in for the intraday panel: synth.priced_factor_returns(1000,
+    12000, K=3, nu=5, seed 0) (riskier assets earn more, the market crashes
+    now and then), simplex, PCG configuration with stall recovery.  The
+    kurtosis-focused profile over the paper's floor sweep q in {0.4, 0.5,
+    0.6}, and the balanced and skew-focused profiles at q = 0.5.  Each case
+    is one yand_return_floor call: time, number of solves, calibrated c1,
+    outcome of the returned solve and its distance to the floor."""
+    import torch
+
+    import synth
+    from paper_2604_25378_amd import binding as yb
+
+    n, T = 1000, 12000
+    R = synth.priced_factor_returns(n, T, 3, 5.0, 0)
+    mu = R.mean(axis=0)
+    spread = float(mu.max() - mu.min())
+    ctx = yb.Context(torch.from_numpy(R).cuda(), precision)
+    opts = yb.default_opts(large=True, feasible_set="simplex")
+    ctx.solve([0.0, 1.0, 1.0, 1.0], opts=opts)     # untimed warm-up
+    cases = [("kurtosis", (1.0, 1.0, 10.0), q) for q in (0.4, 0.5, 0.6)]
+    cases += [("balanced", (1.0, 1.0, 1.0), 0.5),
+              ("skew", (1.0, 10.0, 1.0), 0.5)]
+    rows = []
+    for name, prof, q in cases:
+        log(f"return floor: n={n} T={T} {name} q={q}")
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        row = {"profile": name, "p2_p3_p4": list(prof), "q": q}
+        try:
+            c, w, floor, ret, info, solves = ctx.return_floor(prof, q, opts=opts)
+            el = time.perf_counter() - t0
+            row.update({
+                "seconds": el, "solves": solves, "ms_per_solve": 1e3 * el / solves,
+                "c1": c[0], "outcome": OUTCOME.get(info.status, str(info.status)),
+                "iterations": info.iterations, "kkt": info.kkt,
+                "gap_to_floor_rel_spread": (ret - floor) / spread,
+                "support": int((w > 1e-6).sum().item())})
+        except yb.YandError as e:
+            row.update({"seconds": time.perf_counter() - t0,
+                        "outcome": yb.ERRORS.get(e.code, str(e.code))})
+        rows.append(row)
+    ctx.close()
+    return {"workload": f"priced_factor n{n}_T{T}", "config": "PCG (large), simplex",
+            "cases": rows}
+
+
 def line_search_bench(precision="fp64"):
     """The direct-configuration line-search diagnostic: Armijo backtracking
     against the exact quartic rule on the T = 252 coefficient-stress
@@ -593,6 +641,7 @@ def main():
         out["simplex"] = simplex_bench(args.precision)
         out["conditioning"] = conditioning_bench(args.precision)
         out["line_search"] = line_search_bench(args.precision)
+        out["return_floor"] = return_floor_bench(args.precision)
         out["frontier_solves_per_s"] = fr["n5440_T12000"]["warm_batched_solves_per_s"]
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(R, c)
