@@ -71,6 +71,11 @@ struct Work {
   double *B = nullptr, *M = nullptr, *X = nullptr, *rn = nullptr;
   double *mask = nullptr, *ptmp = nullptr;  // face mask, projection scratch
   double* hold = nullptr;  // coordinates the face solver holds at the bound
+  // T < n push-through trace: Gram partials, G, C, L^-1 of C, diag(B)
+  double *tGp = nullptr, *tG = nullptr, *tC = nullptr, *tX = nullptr,
+         *bdiag = nullptr;
+  int tK = 0;
+  int64_t tld = 0;
   DevScalars* sc = nullptr;
   bool own_sc = true;
   DevScalars hs{};
@@ -165,7 +170,7 @@ void free_work(Work& w) {
                     w.y2,    w.hv,     w.s_t,   w.pcg_s,  w.pcg_res,
                     w.pcg_p, w.pcg_u,  w.part,  w.psums,  w.sums, w.trpart,
                     w.B,     w.M,      w.X,     w.rn,     w.mask, w.ptmp,
-                    w.hold};
+                    w.hold,  w.tGp,    w.tG,    w.tC,     w.tX,   w.bdiag};
   for (double* p : ptrs)
     if (p) (void)hipFree(p);
   if (w.sc && w.own_sc) (void)hipFree(w.sc);
@@ -212,6 +217,19 @@ int alloc_work(Work& w, const Data& D, DevScalars* sc_external) {
   HIPTRY(launch_fill(w.q, Tp, 0.0, w.st));
   HIPTRY(launch_fill(w.AE, 3 * Tp, 0.0, w.st));
   HIPTRY(launch_fill(w.s_t, Tp, 0.0, w.st));
+  return YAND_OK;
+}
+
+int ensure_thin(Work& w, const Data& D) {
+  if (w.tG) return YAND_OK;
+  w.tld = round_up(D.T, 128);
+  w.tK = thin_splits(D.T);
+  const size_t mm = (size_t)w.tld * w.tld * sizeof(double);
+  TRY(alloc((void**)&w.tGp, mm * w.tK));
+  TRY(alloc((void**)&w.tG, mm));
+  TRY(alloc((void**)&w.tC, mm));
+  TRY(alloc((void**)&w.tX, mm));
+  TRY(alloc((void**)&w.bdiag, (size_t)D.lda * sizeof(double)));
   return YAND_OK;
 }
 
@@ -455,9 +473,11 @@ __device__ void bsum(double (&v)[K], double* sh) {
   __syncthreads();
 }
 
-__device__ double precond_diag(const double* B, int64_t ld, int64_t j,
+// Jacobi preconditioner diag(B) + lambda; the diagonal of B sits at
+// bd[j * bs] (bs = ld + 1 for the dense B, 1 for a separate vector).
+__device__ double precond_diag(const double* bd, int64_t bs, int64_t j,
                                double lam) {
-  double dj = B[j * ld + j] + lam;
+  double dj = bd[j * bs] + lam;
   return dj > 0.0 ? dj : 1.0;
 }
 
@@ -465,7 +485,7 @@ __device__ double precond_diag(const double* B, int64_t ld, int64_t j,
 // preconditioner P_S diag(B + lambda)^-1 P_S; r already in S.
 __global__ void __launch_bounds__(PT)
 pcg_init_kernel(const double* __restrict__ r, const double* __restrict__ B,
-                int64_t ld, const double* __restrict__ E, int p, int64_t n,
+                int64_t bs, const double* __restrict__ E, int p, int64_t n,
                 double* s, double* res, double* pv, double* u,
                 DevScalars* sc, const double* __restrict__ mask) {
   __shared__ double sh[4 * 16];
@@ -475,7 +495,7 @@ pcg_init_kernel(const double* __restrict__ r, const double* __restrict__ B,
   for (int64_t j = tid; j < n; j += PT) {
     s[j] = 0.0;
     res[j] = r[j];
-    double uj = (mask ? mask[j] : 1.0) * r[j] / precond_diag(B, ld, j, lam);
+    double uj = (mask ? mask[j] : 1.0) * r[j] / precond_diag(B, bs, j, lam);
     u[j] = uj;
     for (int a = 0; a < p; ++a) dots[a] += E[a * n + j] * uj;
     dots[3] += r[j] * r[j];
@@ -500,7 +520,7 @@ pcg_init_kernel(const double* __restrict__ r, const double* __restrict__ B,
 
 __global__ void __launch_bounds__(PT)
 pcg_update_kernel(const double* __restrict__ Hp, const double* __restrict__ B,
-                  int64_t ld, const double* __restrict__ E, int p, int64_t n,
+                  int64_t bs, const double* __restrict__ E, int p, int64_t n,
                   double* s, double* res, double* pv, double* u, double* Ap,
                   DevScalars* sc, const double* __restrict__ mask) {
   __shared__ double sh[4 * 16];
@@ -528,7 +548,7 @@ pcg_update_kernel(const double* __restrict__ Hp, const double* __restrict__ B,
     s[j] += al * pv[j];
     double rj = res[j] - al * Ap[j];
     res[j] = rj;
-    double uj = (mask ? mask[j] : 1.0) * rj / precond_diag(B, ld, j, lam);
+    double uj = (mask ? mask[j] : 1.0) * rj / precond_diag(B, bs, j, lam);
     u[j] = uj;
     for (int k = 0; k < p; ++k) d2[k] += E[k * n + j] * uj;
     d2[3] += rj * rj;
@@ -553,11 +573,11 @@ pcg_update_kernel(const double* __restrict__ Hp, const double* __restrict__ B,
 
 int dir_pcg_solve(const Data& D, Work& w, const double c[4], int p0,
                   const double* x, const DirOpts& o, double* d,
-                  DirStats* stats) {
-  const int64_t n = D.n, np = D.lda;
+                  DirStats* stats, const double* bd, int64_t bs) {
+  const int64_t n = D.n;
   const int p = p0 + 1;
   const double* mask = face_mask(w, o);
-  hipLaunchKernelGGL(pcg_init_kernel, dim3(1), dim3(PT), 0, w.st, w.r, w.B, np,
+  hipLaunchKernelGGL(pcg_init_kernel, dim3(1), dim3(PT), 0, w.st, w.r, bd, bs,
                      w.E, p, n, w.pcg_s, w.pcg_res, w.pcg_p, w.pcg_u, w.sc,
                      mask);
   TRY(sync_scalars(w));
@@ -566,7 +586,7 @@ int dir_pcg_solve(const Data& D, Work& w, const double c[4], int p0,
   while (it < o.krylov_maxit && r0 > 0.0) {
     TRY(hvp_cached(D, w, c, w.pcg_p, w.hv, nullptr));
     hipLaunchKernelGGL(pcg_update_kernel, dim3(1), dim3(PT), 0, w.st, w.hv,
-                       w.B, np, w.E, p, n, w.pcg_s, w.pcg_res, w.pcg_p,
+                       bd, bs, w.E, p, n, w.pcg_s, w.pcg_res, w.pcg_p,
                        w.pcg_u, w.y, w.sc, mask);
     ++it;
     TRY(sync_scalars(w));
@@ -585,9 +605,75 @@ int dir_pcg_solve(const Data& D, Work& w, const double c[4], int p0,
 // Eager direction with regularisation escalation (host reads the Cholesky
 // flag) and either solver.  The oracle pass and the gradient projection must
 // already have run at x with the done flag clear.
+// Exact trace by the T < n push-through (thin.hip): the frame's A e_a, the
+// Gram matrix G of the rows of A P_S, C = S^1/2 G S^1/2 + lambda I, its
+// factor and inverse, q, the third-order pass and the right-hand side; also
+// diag(B) for the preconditioner and W[p0] = B nu from one HVP pass.  Returns
+// with *ok = false (and the fail flag clear) when the identity does not
+// apply at this iterate (some psi''(z_t) <= 0) or C's factorisation fails.
+int dir_thin(const Data& D, Work& w, const double c[4], int p0,
+             const DirOpts& o, bool* ok) {
+  TRY(ensure_thin(w, D));
+  const int64_t n = D.n, Tp = D.Tp;
+  const int p = p0 + 1;
+  const double* mask = face_mask(w, o);
+  hipLaunchKernelGGL(psi2_weight_kernel, dim3((unsigned)((Tp + 255) / 256)),
+                     dim3(256), 0, w.st, w.z, Tp, to_coef(c),
+                     1.0 / (double)D.T, w.s_t, nullptr);
+  if (mask) {
+    PassArgs a = pass_args(D, w, c);
+    a.v = w.E;
+    a.tout = w.AE;
+    int nwg;
+    TRY(run_pass(D, w, PassKind::Dot, a, &nwg, "dot_pass"));
+  } else {
+    HIPTRY(launch_copy(w.AE, D.AEfix, (int64_t)p0 * Tp, w.st));
+  }
+  // W[p0] = B nu and A nu in one HVP pass
+  TRY(hvp_cached(D, w, c, w.E + (int64_t)p0 * n, w.W + (int64_t)p0 * n,
+                 w.AE + (int64_t)p0 * Tp));
+  HIPTRY(timed(w, "thin_gram", [&] {
+    return launch_thin_gram(D.precision, D.A, D.lda, D.T, n, mask, w.tK,
+                            w.tGp, w.tld, w.AE, Tp, p, w.tG, w.st);
+  }));
+  HIPTRY(launch_thin_factor_input(w.tG, w.tld, D.T, w.s_t, w.AE, Tp, p, n,
+                                  o.reg, mask, w.sc, w.tC, w.st));
+  HIPTRY(timed(w, "thin_potrf_trtri", [&] {
+    return launch_potrf_trtri(w.tC, w.tX, w.tld, &w.sc->fail, w.st, nullptr,
+                              0);
+  }));
+  TRY(sync_scalars(w));
+  *ok = !w.hs.ptbad && !w.hs.fail;
+  if (!*ok) {
+    hipLaunchKernelGGL(set_lambda_kernel, dim3(1), dim3(64), 0, w.st, w.sc,
+                       0.0);
+    return YAND_OK;
+  }
+  HIPTRY(launch_thin_q(w.tX, w.tld, D.T, Tp, w.s_t, w.sc, w.q, w.st));
+  {
+    PassArgs a = pass_args(D, w, c);
+    a.zc = w.z;
+    a.q = w.q;
+    int nwg;
+    TRY(run_pass(D, w, PassKind::Third, a, &nwg, "third_pass"));
+    HIPTRY(launch_reduce_partials(w.part, nwg, D.lda, n, 1.0, 0.0, nullptr,
+                                  w.t3, w.st));
+  }
+  const double mp1 = mask ? -1.0 : (double)(n - p0 + 1);
+  HIPTRY(launch_rhs(w.W + (int64_t)p0 * n, w.t3, w.E, p, n, mp1, w.sc, w.r,
+                    w.st, mask));
+  HIPTRY(launch_bdiag(D.precision, D.A, D.lda, D.T, n, w.s_t, w.bdiag, w.st));
+  return YAND_OK;
+}
+
 int direction_eager(const Data& D, Work& w, const double c[4], int p0,
                     const double* x, const DirOpts& o, double* d,
                     DirStats* stats) {
+  if (o.solver == YAND_SOLVER_PCG && o.reg > 0.0 && 2 * D.T <= D.n) {
+    bool ok = false;
+    TRY(dir_thin(D, w, c, p0, o, &ok));
+    if (ok) return dir_pcg_solve(D, w, c, p0, x, o, d, stats, w.bdiag, 1);
+  }
   TRY(dir_front(D, w, c, p0, o, nullptr));
   for (int attempt = 0;; ++attempt) {
     TRY(dir_factor(D, w, p0, nullptr, face_mask(w, o)));
@@ -602,7 +688,7 @@ int direction_eager(const Data& D, Work& w, const double c[4], int p0,
   TRY(dir_trace(D, w, c, p0, nullptr, face_mask(w, o)));
   if (o.solver == YAND_SOLVER_DIRECT)
     return dir_direct_solve(D, w, p0, x, o, d, nullptr);
-  return dir_pcg_solve(D, w, c, p0, x, o, d, stats);
+  return dir_pcg_solve(D, w, c, p0, x, o, d, stats, w.B, D.lda + 1);
 }
 
 // One outer iteration of the direct configuration, enqueued with no host

@@ -112,4 +112,30 @@ hipError_t launch_symm_multi(const double* B, int64_t ldb, int64_t n,
                              hipStream_t st, const int* skip = nullptr);
 
 
+// ---- T < n push-through of the exact trace (thin.hip) ----
+struct DevScalars;
+// Column splits of the Gram kernel for T rows (1..8).
+int thin_splits(int64_t T);
+// G = A diag(mask) A^T - sum_{a<p} (A e_a)(A e_a)^T, lower triangle of the
+// T x T leading block of G (ld ldg); Gp holds K x ldg x ldg partials.
+hipError_t launch_thin_gram(int precision, const void* A, int64_t lda,
+                            int64_t T, int64_t n, const double* mask, int K,
+                            double* Gp, int64_t ldg, const double* AE,
+                            int64_t Tp, int p, double* G, hipStream_t st);
+// Scales (lambda, gamma, trace, ptbad) into sc and the lower triangle of
+// C = S^1/2 G S^1/2 + lambda I (identity padding to ldg).
+hipError_t launch_thin_factor_input(const double* G, int64_t ldg, int64_t T,
+                                    const double* s, const double* AE,
+                                    int64_t Tp, int p, int64_t n, double reg,
+                                    const double* mask, DevScalars* sc,
+                                    double* C, hipStream_t st);
+// q_t = (1 - lambda (C^-1)_tt) / s_t from X = L^-1 (ld ldg); 0 for t >= T.
+hipError_t launch_thin_q(const double* X, int64_t ldg, int64_t T, int64_t Tp,
+                         const double* s, const DevScalars* sc, double* q,
+                         hipStream_t st);
+// bd_j = sum_t s_t A_tj^2.
+hipError_t launch_bdiag(int precision, const void* A, int64_t lda, int64_t T,
+                        int64_t n, const double* s, double* bd,
+                        hipStream_t st);
+
 }  // namespace yand

@@ -31,6 +31,8 @@ struct DevScalars {
   double nfree;      // free coordinates of the current face (simplex set)
   int projected;     // this iteration took the projected trial segment
   int release;       // drop the holds at the next face evaluation
+  int ptbad;         // push-through trace not applicable (psi'' <= 0, lambda 0)
+  int pad3;
 };
 
 // Face masks: mask[j] = 1 for a free coordinate of the current face of

@@ -1,0 +1,153 @@
+"""GPU parity of the T < n push-through exact trace (PCG configuration with
+2 T <= n) against the FP64 oracle, which factors the reduced tangent
+Hessian explicitly.
+
+Direction level: both sides run the PCG u-solve to convergence
+(krylov_tol 1e-13), so the direction d = Q u - nu depends on the exact
+trace alone and not on the two preconditioners (the library's Jacobi
+preconditioner lives in ambient coordinates, the oracle's in reduced ones);
+compared to 1e-8 of |d|_inf, the direction tolerance of the dense path.
+Solve level: the PCG configuration with stall recovery on the simplex,
+the converged minimiser to 1e-7.  Fallback: where psi'' < 0 at
+some bar the identity does not apply and the dense route runs instead.
+"""
+
+import numpy as np
+import pytest
+
+import oracle as O
+import synth
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+from paper_2604_25378_amd import binding as yb  # noqa: E402
+
+
+def _close(got, ref, rtol):
+    scale = max(np.abs(ref).max(), 1e-300)
+    err = np.abs(np.asarray(got) - ref).max() / scale
+    assert err <= rtol, f"relative error {err:.3e} > {rtol:.1e}"
+
+
+CASES = {
+    # uniform [-0.1, 0.4] returns, CRRA gamma = 6 (certified, psi'' > 0)
+    "uniform_n400_T120": lambda: (synth.uniform_returns(400, 120, seed=4),
+                                  synth.crra_coefficients(6.0)),
+    # heavy-tailed factor panel, ragged T against the 32-row Gram tiles
+    "factor_n640_T200": lambda: (synth.factor_returns(640, 200, 3, 0, 5.0,
+                                                      0.0, 11),
+                                 np.array([1.0, 5.0, 2.0, 10.0])),
+}
+# Relative regularisation 1e-2 in the direction tests.  With n > T the
+# directions outside A's row space carry only lambda, so at the default
+# 1e-4 the reduced system has cond ~ 1e4 and the converged PCG solves still
+# differ by ~1e-8 in u on the two sides (residual floor ~1e-12 times the
+# condition number), which would mask the trace; 1e-2 brings cond to ~1e2.
+REG = {"uniform_n400_T120": 1e-2, "factor_n640_T200": 1e-2}
+
+
+@pytest.mark.parametrize("name", list(CASES))
+@pytest.mark.parametrize("with_target", [False, True])
+def test_thin_direction_matches_oracle(name, with_target):
+    print(f"[case] thin direction {name} target={with_target}", flush=True)
+    R, c = CASES[name]()
+    mu, A = O.center(R)
+    n = mu.size
+    target = float(np.quantile(mu, 0.6)) if with_target else None
+    Cm, b = O.constraints(mu, target)
+    U = O.tangent_basis(Cm)
+    rng = np.random.default_rng(8)
+    x0 = np.full(n, 1.0 / n) + 0.3 / n * rng.normal(size=n)
+    x = O.feasible_start(Cm, b, x0 - (x0.sum() - 1.0) / n)
+    ref = O.affine_normal(A, mu, c, x, U, solver="pcg", reg=REG[name],
+                          krylov_tol=1e-13, krylov_maxit=4000)
+    ctx = yb.Context(torch.from_numpy(R).cuda())
+    opts = yb.default_opts(large=True, krylov_tol=1e-13, krylov_maxit=4000,
+                           regularization=REG[name])
+    d, gn = ctx.affine_normal(c, x, target=target, opts=opts)
+    ctx.close()
+    assert gn == pytest.approx(ref.gnorm, rel=1e-12)
+    _close(d.cpu().numpy(), ref.d, 1e-8)
+
+
+def test_thin_solve_matches_oracle():
+    """Simplex, PCG configuration with stall recovery: a certified-convex
+    instance with a unique minimiser; the per-iteration PCG solves stop at
+    krylov_tol 1e-3 under different preconditioners, so the runs are
+    compared at their converged point."""
+    print("[case] thin solve uniform n400 T120 simplex", flush=True)
+    R, c = CASES["uniform_n400_T120"]()
+    mu, A = O.center(R)
+    oo = O.Options.large()
+    oo.feasible_set = "simplex"
+    xr, ir = O.solve(R, c, opts=oo)
+    ctx = yb.Context(torch.from_numpy(R).cuda())
+    w, info = ctx.solve(c, opts=yb.default_opts(large=True,
+                                                feasible_set="simplex"))
+    ctx.close()
+    w = w.cpu().numpy()
+    print(f"GPU {info.status} {info.iterations} it kkt {info.kkt:.1e}; "
+          f"oracle {ir.status} {ir.iterations} it", flush=True)
+    assert info.status == 0 and ir.status == 0
+    assert info.kkt <= 1e-8
+    assert np.abs(w - xr).max() <= 1e-7
+    assert O.objective(A, mu, c, w) == pytest.approx(
+        O.objective(A, mu, c, xr), rel=1e-10)
+
+
+@pytest.mark.parametrize("precision", ["fp32", "bf16"])
+def test_thin_reduced_storage_matches_rounded_oracle(precision):
+    """FP32/BF16 storage: the Gram and diagonal kernels read the stored A;
+    the oracle runs on the same rounded matrix."""
+    print(f"[case] thin direction storage={precision}", flush=True)
+    R, c = CASES["factor_n640_T200"]()
+    mu, A = O.center(R)
+    f32 = A.astype(np.float32)
+    if precision == "fp32":
+        Ar = f32.astype(np.float64)
+    else:
+        bits = f32.view(np.uint32).astype(np.uint64)
+        bits = (bits + 0x7FFF + ((bits >> 16) & 1)) & 0xFFFF0000
+        Ar = bits.astype(np.uint32).view(np.float32).astype(np.float64)
+    n = mu.size
+    Cm, b = O.constraints(mu, None)
+    U = O.tangent_basis(Cm)
+    x = np.full(n, 1.0 / n)
+    ref = O.affine_normal(Ar, mu, c, x, U, solver="pcg", reg=1e-2,
+                          krylov_tol=1e-13, krylov_maxit=4000)
+    ctx = yb.Context(torch.from_numpy(R).cuda(), precision)
+    opts = yb.default_opts(large=True, krylov_tol=1e-13, krylov_maxit=4000,
+                           regularization=1e-2)
+    d, _ = ctx.affine_normal(c, x, opts=opts)
+    ctx.close()
+    _close(d.cpu().numpy(), ref.d, 1e-8)
+
+
+def test_thin_falls_back_where_psi2_negative():
+    """c = (10, 1, 10, 1): psi''(s) = 2 - 60 s + 12 s^2 is negative for
+    0.034 < s < 4.97, which the centred uniform returns reach, so the
+    identity does not apply; the dense route gives the oracle's direction."""
+    print("[case] thin fallback psi'' < 0", flush=True)
+    R = synth.uniform_returns(300, 120, seed=5)
+    c = np.array([10.0, 1.0, 10.0, 1.0])
+    mu, A = O.center(R)
+    n = mu.size
+    x = np.full(n, 0.1 / n)
+    x[7] += 0.9                      # concentrated: |z_t| reaches 0.2
+    assert O.d2psi(c, A @ x).min() < 0.0
+    U = O.tangent_basis(O.constraints(mu, None)[0])
+    try:
+        ref = O.affine_normal(A, mu, c, x, U, solver="pcg", reg=1e-4,
+                              krylov_tol=1e-13, krylov_maxit=4000)
+    except O.Indefinite:
+        ref = None
+    ctx = yb.Context(torch.from_numpy(R).cuda())
+    opts = yb.default_opts(large=True, krylov_tol=1e-13, krylov_maxit=4000)
+    if ref is None:
+        with pytest.raises(yb.YandError):
+            ctx.affine_normal(c, x, opts=opts)
+    else:
+        d, _ = ctx.affine_normal(c, x, opts=opts)
+        _close(d.cpu().numpy(), ref.d, 1e-8)
+    ctx.close()
