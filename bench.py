@@ -16,6 +16,7 @@ from __future__ import annotations
 
 import argparse
 import json
+import math
 import os
 import sys
 import time
@@ -312,6 +313,72 @@ def return_floor_bench(precision="fp64"):
     ctx.close()
     return {"workload": f"priced_factor n{n}_T{T}", "config": "PCG (large), simplex",
             "cases": rows}
+
+
+REGIME_BLOCKS = (("n<=60", (20, 40, 60)), ("80<=n<=100", (80, 100)),
+                 ("120<=n<=200", (120, 160, 200)),
+                 ("250<=n<=500", (250, 350, 500)),
+                 ("600<=n<=1000", (600, 800, 1000)))
+
+
+def regime_bench(precision="fp64"):
+    """The direct-versus-PCG regime comparison of the computational study on
+    the T = 252 coefficient-stress generator (uniform returns on [-0.1, 0.4],
+    profiles [10,1,10,1], [1,10,1,10], [10,10,10,10]), simplex with the
+    boundary block, through n = 1000.  Per n-block: median time of each
+    configuration, the median instance-wise ratio direct / PCG, projected-KKT
+    hits at 1e-6, and objective ties (both within 1e-6 of the better value;
+    a run that errors counts as neither)."""
+    import torch
+
+    import synth
+    from paper_2604_25378_amd import binding as yb
+
+    profiles = ([10.0, 1.0, 10.0, 1.0], [1.0, 10.0, 1.0, 10.0],
+                [10.0, 10.0, 10.0, 10.0])
+    res = {}
+    for block, ns in REGIME_BLOCKS:
+        log(f"regime: {block}")
+        t_s, t_l, ratio, hit_s, hit_l, ties, runs = [], [], [], 0, 0, 0, 0
+        for n in ns:
+            ctx = yb.Context(torch.from_numpy(
+                synth.uniform_returns(n, 252, seed=n)).cuda(), precision)
+            for large in (False, True):    # untimed warm-up per configuration
+                ctx.solve(profiles[2], opts=yb.default_opts(
+                    large=large, feasible_set="simplex", max_iter=2))
+            for c in profiles:
+                runs += 1
+                out = {}
+                for large in (False, True):
+                    opts = yb.default_opts(large=large, feasible_set="simplex")
+                    torch.cuda.synchronize()
+                    t0 = time.perf_counter()
+                    try:
+                        w, info = ctx.solve(c, opts=opts)
+                        torch.cuda.synchronize()
+                        f = ctx.eval(c, w, grad=False)[0]
+                        out[large] = (time.perf_counter() - t0, info.kkt, f)
+                    except yb.YandError:
+                        out[large] = (time.perf_counter() - t0, math.inf,
+                                      math.inf)
+                (ts, ks, fs), (tl, kl, fl) = out[False], out[True]
+                t_s.append(ts)
+                t_l.append(tl)
+                ratio.append(ts / tl)
+                hit_s += ks <= 1e-6
+                hit_l += kl <= 1e-6
+                best = min(fs, fl)
+                ties += (math.isfinite(best) and fs - best <= 1e-6
+                         and fl - best <= 1e-6)
+            ctx.close()
+        res[block] = {"n": list(ns), "runs": runs,
+                      "direct_median_s": float(np.median(t_s)),
+                      "pcg_median_s": float(np.median(t_l)),
+                      "median_ratio_direct_over_pcg": float(np.median(ratio)),
+                      "kkt_hits_direct": f"{hit_s}/{runs}",
+                      "kkt_hits_pcg": f"{hit_l}/{runs}",
+                      "objective_ties": f"{ties}/{runs}"}
+    return res
 
 
 def line_search_bench(precision="fp64"):
@@ -642,6 +709,7 @@ def main():
         out["conditioning"] = conditioning_bench(args.precision)
         out["line_search"] = line_search_bench(args.precision)
         out["return_floor"] = return_floor_bench(args.precision)
+        out["regime"] = regime_bench(args.precision)
         out["frontier_solves_per_s"] = fr["n5440_T12000"]["warm_batched_solves_per_s"]
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(R, c)

@@ -296,15 +296,16 @@ int oracle_at(const Data& D, Work& w, const double c[4], const double* x,
 }
 
 int hvp_cached(const Data& D, Work& w, const double c[4], const double* v,
-               double* hv, double* tout) {
+               double* hv, double* tout, const int* skip = nullptr) {
   PassArgs a = pass_args(D, w, c);
   a.v = v;
   a.zc = w.z;
   a.tout = tout;
+  a.skip = skip;
   int nwg = 0;
   TRY(run_pass(D, w, PassKind::Hvp, a, &nwg, "hvp_pass"));
   HIPTRY(launch_reduce_partials(w.part, nwg, D.lda, D.n, 1.0, 0.0, nullptr, hv,
-                                w.st));
+                                w.st, skip));
   return YAND_OK;
 }
 
@@ -515,6 +516,8 @@ pcg_init_kernel(const double* __restrict__ r, const double* __restrict__ B,
     sc->aux[1] = dots[3];
     sc->aux[2] = dots[3];
     sc->aux[3] = 0.0;
+    sc->cgit = 0;
+    sc->cgdone = dots[3] > 0.0 ? 0 : 1;
   }
 }
 
@@ -522,7 +525,9 @@ __global__ void __launch_bounds__(PT)
 pcg_update_kernel(const double* __restrict__ Hp, const double* __restrict__ B,
                   int64_t bs, const double* __restrict__ E, int p, int64_t n,
                   double* s, double* res, double* pv, double* u, double* Ap,
-                  DevScalars* sc, const double* __restrict__ mask) {
+                  DevScalars* sc, const double* __restrict__ mask,
+                  double tol) {
+  if (sc->cgdone) return;
   __shared__ double sh[4 * 16];
   const int tid = threadIdx.x;
   const double lam = sc->lambda;
@@ -568,6 +573,10 @@ pcg_update_kernel(const double* __restrict__ Hp, const double* __restrict__ B,
     sc->aux[0] = rzn[0];
     sc->aux[1] = d2[3];
     if (!(pap[0] > 0.0)) sc->aux[3] = 1.0;  // curvature breakdown
+    sc->cgit += 1;
+    // stop on |res| <= tol |r0| or a breakdown; later iterations are skipped
+    if (sqrt(d2[3]) <= tol * sqrt(sc->aux[2]) || !(pap[0] > 0.0))
+      sc->cgdone = 1;
   }
 }
 
@@ -580,19 +589,17 @@ int dir_pcg_solve(const Data& D, Work& w, const double c[4], int p0,
   hipLaunchKernelGGL(pcg_init_kernel, dim3(1), dim3(PT), 0, w.st, w.r, bd, bs,
                      w.E, p, n, w.pcg_s, w.pcg_res, w.pcg_p, w.pcg_u, w.sc,
                      mask);
-  TRY(sync_scalars(w));
-  const double r0 = std::sqrt(w.hs.aux[2]);
-  int it = 0;
-  while (it < o.krylov_maxit && r0 > 0.0) {
-    TRY(hvp_cached(D, w, c, w.pcg_p, w.hv, nullptr));
+  // krylov_maxit iterations enqueued without host synchronisation: the
+  // update kernel raises cgdone at convergence or breakdown, and every later
+  // HVP pass and update returns at once
+  for (int it = 0; it < o.krylov_maxit; ++it) {
+    TRY(hvp_cached(D, w, c, w.pcg_p, w.hv, nullptr, &w.sc->cgdone));
     hipLaunchKernelGGL(pcg_update_kernel, dim3(1), dim3(PT), 0, w.st, w.hv,
                        bd, bs, w.E, p, n, w.pcg_s, w.pcg_res, w.pcg_p,
-                       w.pcg_u, w.y, w.sc, mask);
-    ++it;
-    TRY(sync_scalars(w));
-    if (std::sqrt(w.hs.aux[1]) <= o.krylov_tol * r0) break;
-    if (w.hs.aux[3] != 0.0) break;
+                       w.pcg_u, w.y, w.sc, mask, o.krylov_tol);
   }
+  TRY(sync_scalars(w));
+  const int it = w.hs.cgit;
   if (stats) stats->cg += it;
   HIPTRY(launch_direction(w.pcg_s, w.E, p, n, x, D.mu, o.tau, o.simplex, d,
                           w.sc, w.st, mask));
@@ -602,9 +609,6 @@ int dir_pcg_solve(const Data& D, Work& w, const double c[4], int p0,
   return YAND_OK;
 }
 
-// Eager direction with regularisation escalation (host reads the Cholesky
-// flag) and either solver.  The oracle pass and the gradient projection must
-// already have run at x with the done flag clear.
 // Exact trace by the T < n push-through (thin.hip): the frame's A e_a, the
 // Gram matrix G of the rows of A P_S, C = S^1/2 G S^1/2 + lambda I, its
 // factor and inverse, q, the third-order pass and the right-hand side; also
@@ -666,6 +670,10 @@ int dir_thin(const Data& D, Work& w, const double c[4], int p0,
   return YAND_OK;
 }
 
+// Eager direction with regularisation escalation (host reads the Cholesky
+// flag) and either solver.  The oracle pass and the gradient projection must
+// already have run at x with the done flag clear.  The PCG configuration
+// with 2 T <= n takes the push-through trace when it applies.
 int direction_eager(const Data& D, Work& w, const double c[4], int p0,
                     const double* x, const DirOpts& o, double* d,
                     DirStats* stats) {

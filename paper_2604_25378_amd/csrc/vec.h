@@ -32,6 +32,8 @@ struct DevScalars {
   int projected;     // this iteration took the projected trial segment
   int release;       // drop the holds at the next face evaluation
   int ptbad;         // push-through trace not applicable (psi'' <= 0, lambda 0)
+  int cgdone;        // PCG: converged or broke down, later steps skipped
+  int cgit;          // PCG: iterations taken
   int pad3;
 };
 
