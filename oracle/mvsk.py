@@ -194,19 +194,20 @@ class Direction:
     cg_iters: int = 0
 
 
-def _pcg(Bmat, rhs, tol, maxit):
-    """Jacobi-preconditioned CG on the reduced tangent system, start 0.
+def _pcg(Bmat, rhs, tol, maxit, precond):
+    """Preconditioned CG on the reduced tangent system, start 0.
 
     Reading of the 'pcg reduced solve' of Table 'YAND-MVSK parameter
-    settings': stop when ||r_k|| <= tol ||r_0|| or after maxit iterations.
+    settings' (the paper names no preconditioner): stop when
+    ||r_k|| <= tol ||r_0|| or after maxit iterations.  precond(r) applies
+    the preconditioner's inverse.
     """
-    Minv = 1.0 / np.diag(Bmat)
     u = np.zeros_like(rhs)
     r = rhs.copy()
     r0 = np.linalg.norm(r)
     if r0 == 0.0:
         return u, 0
-    zv = Minv * r
+    zv = precond(r)
     p = zv.copy()
     rz = r @ zv
     it = 0
@@ -218,7 +219,7 @@ def _pcg(Bmat, rhs, tol, maxit):
         it += 1
         if np.linalg.norm(r) <= tol * r0:
             break
-        zv = Minv * r
+        zv = precond(r)
         rz_new = r @ zv
         p = zv + (rz_new / rz) * p
         rz = rz_new
@@ -244,7 +245,9 @@ def affine_normal(A, mu, c, x, U, *, solver="direct", reg=0.0,
     ``reg`` is relative: lam = reg * trace(Q^T H_red Q) / (m - 1).  The direct
     solver starts at reg (0 by default) and escalates lam on a failed Cholesky
     factorisation; the PCG solver keeps the factorisation only for the exact
-    trace and solves for u by ``_pcg``.
+    trace and solves for u by ``_pcg``, preconditioned by the Jacobi inverse
+    of the ambient Hessian diagonal (plus lam) restricted to the reduced
+    space.
     """
     T = A.shape[0]
     m = U.shape[1]
@@ -281,7 +284,12 @@ def affine_normal(A, mu, c, x, U, *, solver="direct", reg=0.0,
     if solver == "direct":
         u = sla.cho_solve((L, True), rhs)
     elif solver == "pcg":
-        u, cg_iters = _pcg(Bm, rhs, krylov_tol, krylov_maxit)
+        # Jacobi on the ambient Hessian diagonal, restricted to the reduced
+        # space: V^T diag(A^T diag(psi''/T) A + lam)^-1 V
+        dj = np.sum(A * A * (D2 / T)[:, None], axis=0) + lam
+        dj = np.where(dj > 0.0, dj, 1.0)
+        u, cg_iters = _pcg(Bm, rhs, krylov_tol, krylov_maxit,
+                           lambda r: V.T @ ((V @ r) / dj))
     else:
         raise ValueError(solver)
     dy = Q @ u - nu

@@ -90,10 +90,44 @@ def test_thin_solve_matches_oracle():
     print(f"GPU {info.status} {info.iterations} it kkt {info.kkt:.1e}; "
           f"oracle {ir.status} {ir.iterations} it", flush=True)
     assert info.status == 0 and ir.status == 0
+    assert info.iterations == ir.iterations
     assert info.kkt <= 1e-8
-    assert np.abs(w - xr).max() <= 1e-7
+    assert np.abs(w - xr).max() <= 1e-8
     assert O.objective(A, mu, c, w) == pytest.approx(
         O.objective(A, mu, c, xr), rel=1e-10)
+
+
+@pytest.mark.parametrize("route", ["thin", "dense"])
+@pytest.mark.parametrize("iters", [1, 4])
+def test_pcg_iterates_match_oracle(route, iters):
+    """Default PCG settings (krylov_tol 1e-3, 15 iterations): both sides use
+    the Jacobi inverse of the ambient Hessian diagonal on the tangent space,
+    so the truncated inner solves, and with them the outer iterates, agree
+    element by element.  thin: n = 400, T = 120 (2 T <= n) on the simplex
+    (on the budget hull with n > T the iterates run off along A's null
+    space, where every difference grows); dense: n = 300, T = 1000 on the
+    budget hull."""
+    print(f"[case] PCG iterates route={route} iters={iters}", flush=True)
+    if route == "thin":
+        R, c = CASES["uniform_n400_T120"]()
+        fs = "simplex"
+    else:
+        R = synth.factor_returns(300, 1000, 5, 0, 5.0, 0.0, 7)
+        c = np.array([1.0, 5.0, 2.0, 10.0])
+        fs = "budget"
+    oo = O.Options.large()
+    oo.max_iter, oo.eps, oo.stall_recovery = iters, 0.0, False
+    oo.feasible_set = fs
+    xr, ir = O.solve(R, c, opts=oo)
+    ctx = yb.Context(torch.from_numpy(R).cuda())
+    w, info = ctx.solve(c, opts=yb.default_opts(large=True, max_iter=iters,
+                                                eps=0.0, stall_recovery=0,
+                                                feasible_set=fs))
+    ctx.close()
+    assert info.iterations == iters and info.cg_iters == ir.cg_iters
+    # the direction tolerance: a different preconditioner would differ at
+    # the truncation level (krylov_tol 1e-3), rounding stays near 1e-9
+    _close(w.cpu().numpy(), xr, 1e-8)
 
 
 @pytest.mark.parametrize("precision", ["fp32", "bf16"])
