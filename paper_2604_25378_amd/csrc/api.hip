@@ -73,7 +73,7 @@ struct Work {
   double* hold = nullptr;  // coordinates the face solver holds at the bound
   // T < n push-through trace: Gram partials, G, C, L^-1 of C, diag(B)
   double *tGp = nullptr, *tG = nullptr, *tC = nullptr, *tX = nullptr,
-         *bdiag = nullptr;
+         *bdiag = nullptr, *tpart = nullptr;
   int tK = 0;
   int64_t tld = 0;
   DevScalars* sc = nullptr;
@@ -170,7 +170,8 @@ void free_work(Work& w) {
                     w.y2,    w.hv,     w.s_t,   w.pcg_s,  w.pcg_res,
                     w.pcg_p, w.pcg_u,  w.part,  w.psums,  w.sums, w.trpart,
                     w.B,     w.M,      w.X,     w.rn,     w.mask, w.ptmp,
-                    w.hold,  w.tGp,    w.tG,    w.tC,     w.tX,   w.bdiag};
+                    w.hold,  w.tGp,    w.tG,    w.tC,     w.tX,   w.bdiag,
+                    w.tpart};
   for (double* p : ptrs)
     if (p) (void)hipFree(p);
   if (w.sc && w.own_sc) (void)hipFree(w.sc);
@@ -230,6 +231,9 @@ int ensure_thin(Work& w, const Data& D) {
   TRY(alloc((void**)&w.tC, mm));
   TRY(alloc((void**)&w.tX, mm));
   TRY(alloc((void**)&w.bdiag, (size_t)D.lda * sizeof(double)));
+  const int64_t ldp = D.lda > w.tld ? D.lda : w.tld;
+  TRY(alloc((void**)&w.tpart,
+            (size_t)thin_part_rows(D.T) * ldp * sizeof(double)));
   return YAND_OK;
 }
 
@@ -653,7 +657,8 @@ int dir_thin(const Data& D, Work& w, const double c[4], int p0,
                        0.0);
     return YAND_OK;
   }
-  HIPTRY(launch_thin_q(w.tX, w.tld, D.T, Tp, w.s_t, w.sc, w.q, w.st));
+  HIPTRY(launch_thin_q(w.tX, w.tld, D.T, Tp, w.s_t, w.sc, w.tpart, w.q,
+                       w.st));
   {
     PassArgs a = pass_args(D, w, c);
     a.zc = w.z;
@@ -666,7 +671,8 @@ int dir_thin(const Data& D, Work& w, const double c[4], int p0,
   const double mp1 = mask ? -1.0 : (double)(n - p0 + 1);
   HIPTRY(launch_rhs(w.W + (int64_t)p0 * n, w.t3, w.E, p, n, mp1, w.sc, w.r,
                     w.st, mask));
-  HIPTRY(launch_bdiag(D.precision, D.A, D.lda, D.T, n, w.s_t, w.bdiag, w.st));
+  HIPTRY(launch_bdiag(D.precision, D.A, D.lda, D.T, n, w.s_t, w.tpart,
+                      w.bdiag, w.st));
   return YAND_OK;
 }
 

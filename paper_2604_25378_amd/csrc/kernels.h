@@ -114,8 +114,11 @@ hipError_t launch_symm_multi(const double* B, int64_t ldb, int64_t n,
 
 // ---- T < n push-through of the exact trace (thin.hip) ----
 struct DevScalars;
-// Column splits of the Gram kernel for T rows (1..8).
+// Column splits of the Gram kernel for T rows (1..64, partials <= 64 MiB).
 int thin_splits(int64_t T);
+// Rows of the partial-sum scratch (each ld long) that launch_thin_q
+// (ld = ldg) and launch_bdiag (ld = lda) need for T rows.
+int64_t thin_part_rows(int64_t T);
 // G = A diag(mask) A^T - sum_{a<p} (A e_a)(A e_a)^T, lower triangle of the
 // T x T leading block of G (ld ldg); Gp holds K x ldg x ldg partials.
 hipError_t launch_thin_gram(int precision, const void* A, int64_t lda,
@@ -130,12 +133,13 @@ hipError_t launch_thin_factor_input(const double* G, int64_t ldg, int64_t T,
                                     const double* mask, DevScalars* sc,
                                     double* C, hipStream_t st);
 // q_t = (1 - lambda (C^-1)_tt) / s_t from X = L^-1 (ld ldg); 0 for t >= T.
+// part: thin_part_rows(T) x ldg scratch.
 hipError_t launch_thin_q(const double* X, int64_t ldg, int64_t T, int64_t Tp,
-                         const double* s, const DevScalars* sc, double* q,
-                         hipStream_t st);
-// bd_j = sum_t s_t A_tj^2.
+                         const double* s, const DevScalars* sc, double* part,
+                         double* q, hipStream_t st);
+// bd_j = sum_t s_t A_tj^2.  part: thin_part_rows(T) x lda scratch.
 hipError_t launch_bdiag(int precision, const void* A, int64_t lda, int64_t T,
-                        int64_t n, const double* s, double* bd,
+                        int64_t n, const double* s, double* part, double* bd,
                         hipStream_t st);
 
 }  // namespace yand

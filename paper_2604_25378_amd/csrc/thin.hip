@@ -19,9 +19,9 @@ namespace yand {
 
 namespace {
 
-constexpr int GT = 32;    // G tile edge
+constexpr int GT = 64;    // G tile edge
 constexpr int GJ = 32;    // columns of A per LDS stage
-constexpr int GTH = 256;  // threads: a 32 x 32 tile, 4 outputs each
+constexpr int GTH = 256;  // threads: a 64 x 64 tile, 4 x 4 outputs each
 constexpr int RT = 256;   // threads of the single-workgroup kernels
 
 __device__ double rt_sum(double v, double* sh) {
@@ -47,7 +47,8 @@ __device__ double rt_min(double v, double* sh) {
 
 // Partial Gram blocks Gp[k][t][u] = sum_{j in chunk k} m_j A_tj A_uj for the
 // lower tiles (u-tile <= t-tile).  blockIdx.x walks the lower tiles row by
-// row, blockIdx.y the column chunks of width `chunk`.
+// row, blockIdx.y the column chunks of width `chunk`.  Each thread holds a
+// 4 x 4 block of the 64 x 64 tile; the stage is stored k-major in LDS.
 template <typename S>
 __global__ void __launch_bounds__(GTH)
 gram_kernel(const S* __restrict__ A, int64_t lda, int64_t T, int64_t n,
@@ -61,10 +62,14 @@ gram_kernel(const S* __restrict__ A, int64_t lda, int64_t T, int64_t n,
   const int64_t t0 = (int64_t)tI * GT, u0 = (int64_t)rem * GT;
   const int64_t j0 = (int64_t)blockIdx.y * chunk;
   const int64_t j1 = j0 + chunk < n ? j0 + chunk : n;
-  __shared__ double sa[GT][GJ + 1], sb[GT][GJ + 1];
+  __shared__ double sa[GJ][GT + 2], sb[GJ][GT + 2];
   const int tid = threadIdx.x;
-  const int r = tid >> 3, c0 = (tid & 7) * 4;
-  double acc[4] = {0.0, 0.0, 0.0, 0.0};
+  const int ty = tid >> 4, tx = tid & 15;
+  double acc[4][4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int q = 0; q < 4; ++q) acc[i][q] = 0.0;
   for (int64_t jb = j0; jb < j1; jb += GJ) {
     for (int e = tid; e < GT * GJ; e += GTH) {
       const int rr = e / GJ, cc = e % GJ;
@@ -72,21 +77,31 @@ gram_kernel(const S* __restrict__ A, int64_t lda, int64_t T, int64_t n,
       const int64_t ta = t0 + rr, ub = u0 + rr;
       const bool inj = j < j1;
       const double m = inj ? (mask ? mask[j] : 1.0) : 0.0;
-      sa[rr][cc] = (inj && ta < T) ? m * to_f64(A[ta * lda + j]) : 0.0;
-      sb[rr][cc] = (inj && ub < T) ? to_f64(A[ub * lda + j]) : 0.0;
+      sa[cc][rr] = (inj && ta < T) ? m * to_f64(A[ta * lda + j]) : 0.0;
+      sb[cc][rr] = (inj && ub < T) ? to_f64(A[ub * lda + j]) : 0.0;
     }
     __syncthreads();
-#pragma unroll 8
+#pragma unroll 4
     for (int k = 0; k < GJ; ++k) {
-      const double a = sa[r][k];
+      double a[4], b[4];
 #pragma unroll
-      for (int q = 0; q < 4; ++q) acc[q] += a * sb[c0 + q][k];
+      for (int i = 0; i < 4; ++i) {
+        a[i] = sa[k][ty * 4 + i];
+        b[i] = sb[k][tx * 4 + i];
+      }
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) acc[i][q] += a[i] * b[q];
     }
     __syncthreads();
   }
-  double* out = Gp + (int64_t)blockIdx.y * ldg * ldg + (t0 + r) * ldg + u0 + c0;
+  double* out = Gp + (int64_t)blockIdx.y * ldg * ldg + (t0 + ty * 4) * ldg +
+                u0 + tx * 4;
 #pragma unroll
-  for (int q = 0; q < 4; ++q) out[q] = acc[q];
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int q = 0; q < 4; ++q) out[(int64_t)i * ldg + q] = acc[i][q];
 }
 
 // G[t][u] = sum_k Gp[k][t][u] - sum_a (A e_a)_t (A e_a)_u, lower triangle,
@@ -155,10 +170,33 @@ __global__ void thin_build_kernel(const double* __restrict__ G, int64_t ldg,
   C[t * ldg + u] = v;
 }
 
-// q_t = (1 - lambda (C^-1)_tt) / s_t with (C^-1)_tt = sum_{i >= t} X_it^2,
-// X = L^-1 (lower, row-major); 0 on the padding rows.
-__global__ void thin_q_kernel(const double* __restrict__ X, int64_t ldg,
-                              int64_t T, int64_t Tp,
+// Partial column norms of X = L^-1 (lower, row-major): part[b][t] =
+// sum_{i in rows [64 b, 64 b + 64), i >= t, i < T} X_it^2; a workgroup takes
+// 64 columns and 64 rows (4 groups of 16 rows, summed in LDS).
+__global__ void __launch_bounds__(256)
+thin_colnorm_kernel(const double* __restrict__ X, int64_t ldg, int64_t T,
+                    double* __restrict__ part) {
+  __shared__ double sh[4][64];
+  const int c = threadIdx.x & 63, g = threadIdx.x >> 6;
+  const int64_t t = (int64_t)blockIdx.x * 64 + c;
+  const int64_t i0 = (int64_t)blockIdx.y * 64 + g * 16;
+  double v = 0.0;
+  if (t < T)
+    for (int64_t i = i0 > t ? i0 : t; i < i0 + 16 && i < T; ++i) {
+      const double x = X[i * ldg + t];
+      v += x * x;
+    }
+  sh[g][c] = v;
+  __syncthreads();
+  if (g == 0 && t < T)
+    part[(int64_t)blockIdx.y * ldg + t] = sh[0][c] + sh[1][c] + sh[2][c] +
+                                          sh[3][c];
+}
+
+// q_t = (1 - lambda (C^-1)_tt) / s_t with (C^-1)_tt the sum of the nb
+// partial column norms; 0 on the padding rows.
+__global__ void thin_q_kernel(const double* __restrict__ part, int nb,
+                              int64_t ldg, int64_t T, int64_t Tp,
                               const double* __restrict__ s,
                               const DevScalars* __restrict__ sc,
                               double* __restrict__ q) {
@@ -169,25 +207,36 @@ __global__ void thin_q_kernel(const double* __restrict__ X, int64_t ldg,
     return;
   }
   double c = 0.0;
-  for (int64_t i = t; i < T; ++i) {
-    const double x = X[i * ldg + t];
-    c += x * x;
-  }
+  for (int b = 0; b < nb; ++b) c += part[(int64_t)b * ldg + t];
   q[t] = (1.0 - sc->lambda * c) / s[t];
 }
 
-// bd_j = sum_t s_t A_tj^2 = diag(A^T S A), the Jacobi preconditioner.
+// Partial Jacobi diagonal: part[b][j] = sum_{t in [16 b, 16 b + 16), t < T}
+// s_t A_tj^2; bd_j = sum_b part[b][j] = diag(A^T S A).
+constexpr int kBdRows = 16;
 template <typename S>
-__global__ void bdiag_kernel(const S* __restrict__ A, int64_t lda, int64_t T,
-                             int64_t n, const double* __restrict__ s,
-                             double* __restrict__ bd) {
+__global__ void bdiag_part_kernel(const S* __restrict__ A, int64_t lda,
+                                  int64_t T, int64_t n,
+                                  const double* __restrict__ s,
+                                  double* __restrict__ part) {
   const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (j >= n) return;
+  const int64_t t0 = (int64_t)blockIdx.y * kBdRows;
   double v = 0.0;
-  for (int64_t t = 0; t < T; ++t) {
+  for (int64_t t = t0; t < t0 + kBdRows && t < T; ++t) {
     const double a = to_f64(A[t * lda + j]);
     v += s[t] * a * a;
   }
+  part[(int64_t)blockIdx.y * lda + j] = v;
+}
+
+__global__ void bdiag_sum_kernel(const double* __restrict__ part, int nb,
+                                 int64_t lda, int64_t n,
+                                 double* __restrict__ bd) {
+  const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= n) return;
+  double v = 0.0;
+  for (int b = 0; b < nb; ++b) v += part[(int64_t)b * lda + j];
   bd[j] = v;
 }
 
@@ -206,9 +255,13 @@ hipError_t gram_t(const void* A, int64_t lda, int64_t T, int64_t n,
 
 template <typename S>
 hipError_t bdiag_t(const void* A, int64_t lda, int64_t T, int64_t n,
-                   const double* s, double* bd, hipStream_t st) {
-  hipLaunchKernelGGL(bdiag_kernel<S>, dim3((unsigned)((n + 255) / 256)),
-                     dim3(256), 0, st, (const S*)A, lda, T, n, s, bd);
+                   const double* s, double* part, double* bd, hipStream_t st) {
+  const int nb = (int)((T + kBdRows - 1) / kBdRows);
+  hipLaunchKernelGGL(bdiag_part_kernel<S>,
+                     dim3((unsigned)((n + 255) / 256), (unsigned)nb),
+                     dim3(256), 0, st, (const S*)A, lda, T, n, s, part);
+  hipLaunchKernelGGL(bdiag_sum_kernel, dim3((unsigned)((n + 255) / 256)),
+                     dim3(256), 0, st, part, nb, lda, n, bd);
   return hipGetLastError();
 }
 
@@ -217,8 +270,17 @@ hipError_t bdiag_t(const void* A, int64_t lda, int64_t T, int64_t n,
 int thin_splits(int64_t T) {
   const int64_t nT = (T + GT - 1) / GT;
   const int64_t ntile = nT * (nT + 1) / 2;
-  int64_t K = (512 + ntile - 1) / ntile;
-  return (int)(K < 1 ? 1 : (K > 8 ? 8 : K));
+  const int64_t ldg = round_up(T, 128);
+  int64_t K = (1024 + ntile - 1) / ntile;
+  // partials at most 64 MiB
+  const int64_t kmem = ((int64_t)64 << 20) / (ldg * ldg * 8);
+  if (K > kmem) K = kmem;
+  return (int)(K < 1 ? 1 : (K > 64 ? 64 : K));
+}
+
+int64_t thin_part_rows(int64_t T) {
+  const int64_t a = (T + 63) / 64, b = (T + kBdRows - 1) / kBdRows;
+  return a > b ? a : b;
 }
 
 hipError_t launch_thin_gram(int precision, const void* A, int64_t lda,
@@ -252,20 +314,23 @@ hipError_t launch_thin_factor_input(const double* G, int64_t ldg, int64_t T,
 }
 
 hipError_t launch_thin_q(const double* X, int64_t ldg, int64_t T, int64_t Tp,
-                         const double* s, const DevScalars* sc, double* q,
-                         hipStream_t st) {
+                         const double* s, const DevScalars* sc, double* part,
+                         double* q, hipStream_t st) {
+  const int nb = (int)((T + 63) / 64);
+  hipLaunchKernelGGL(thin_colnorm_kernel, dim3((unsigned)nb, (unsigned)nb),
+                     dim3(256), 0, st, X, ldg, T, part);
   hipLaunchKernelGGL(thin_q_kernel, dim3((unsigned)((Tp + 255) / 256)),
-                     dim3(256), 0, st, X, ldg, T, Tp, s, sc, q);
+                     dim3(256), 0, st, part, nb, ldg, T, Tp, s, sc, q);
   return hipGetLastError();
 }
 
 hipError_t launch_bdiag(int precision, const void* A, int64_t lda, int64_t T,
-                        int64_t n, const double* s, double* bd,
+                        int64_t n, const double* s, double* part, double* bd,
                         hipStream_t st) {
   switch (precision) {
-    case 1: return bdiag_t<float>(A, lda, T, n, s, bd, st);
-    case 2: return bdiag_t<bf16_t>(A, lda, T, n, s, bd, st);
-    default: return bdiag_t<double>(A, lda, T, n, s, bd, st);
+    case 1: return bdiag_t<float>(A, lda, T, n, s, part, bd, st);
+    case 2: return bdiag_t<bf16_t>(A, lda, T, n, s, part, bd, st);
+    default: return bdiag_t<double>(A, lda, T, n, s, part, bd, st);
   }
 }
 

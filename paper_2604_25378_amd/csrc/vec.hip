@@ -256,43 +256,75 @@ __device__ double block_max(double v, double* sh) {
 }
 
 // out = Pi_{Delta(tau)}(y), y_j = fy(j), by one workgroup: with u = y - tau
-// and s = 1 - n tau, the threshold theta solves h(theta) = s for the
-// decreasing h(theta) = sum_j max(u_j - theta, 0).  Bisection on
-// [max u - s, max u] (where h >= s and h = 0) until the interval stops
-// shrinking brackets theta between two neighbouring doubles; theta is then
-// formed exactly from the support {u_j > lo}: (sum_S u_j - s) / |S|, and
-// out_j = max(u_j - theta, 0) + tau.  Every loop bound and branch depends
-// only on block-reduced values, so all threads take the same path.
+// and s = 1 - n tau, out_j = max(u_j - theta, 0) + tau where theta solves
+// h(theta) = sum_j max(u_j - theta, 0) = s.
+// Michelot's method first (Michelot 1986): theta from the current support,
+// theta = (sum_S u_j - s) / |S|, then S = {u_j > theta}, until S stops
+// shrinking; theta only grows (kept nondecreasing under rounding), so the
+// support is monotone and the loop ends, usually within a few passes.
+// Should it not settle within kMichelot passes, bisection on
+// [max u - s, max u] (where h >= s and h = 0) runs until the interval stops
+// shrinking and the support is {u_j > lo}.  Either way theta is formed from
+// the final support.  Every loop bound and branch depends only on
+// block-reduced values, so all threads take the same path.
+constexpr int kMichelot = 64;
 template <class FY>
 __device__ void simplex_project(FY fy, int64_t n, double tau, double* out,
                                 double* sh) {
   const int tid = threadIdx.x;
   const double s = 1.0 - (double)n * tau;
-  double mx = -INFINITY;
-  for (int64_t j = tid; j < n; j += VT) mx = fmax(mx, fy(j) - tau);
-  mx = block_max(mx, sh);
-  double lo = mx - s, hi = mx;
-  for (int it = 0; it < 200; ++it) {
-    const double mid = 0.5 * (lo + hi);
-    if (!(mid > lo && mid < hi)) break;
-    double h[1] = {0.0};
-    for (int64_t j = tid; j < n; j += VT) h[0] += fmax(fy(j) - tau - mid, 0.0);
-    block_sum(h, sh);
-    if (h[0] >= s)
-      lo = mid;
-    else
-      hi = mid;
-  }
   double v[2] = {0.0, 0.0};
-  for (int64_t j = tid; j < n; j += VT) {
-    const double u = fy(j) - tau;
-    if (u > lo) {
-      v[0] += u;
-      v[1] += 1.0;
-    }
-  }
+  for (int64_t j = tid; j < n; j += VT) v[0] += fy(j) - tau;
   block_sum(v, sh);
-  const double theta = (v[0] - s) / v[1];
+  double theta = (v[0] - s) / (double)n, cnt = (double)n;
+  bool settled = false;
+  for (int it = 0; it < kMichelot; ++it) {
+    double w[2] = {0.0, 0.0};
+    for (int64_t j = tid; j < n; j += VT) {
+      const double u = fy(j) - tau;
+      if (u > theta) {
+        w[0] += u;
+        w[1] += 1.0;
+      }
+    }
+    block_sum(w, sh);
+    if (!(w[1] > 0.0)) break;
+    const double th = (w[0] - s) / w[1];
+    if (w[1] == cnt) {
+      theta = th;
+      settled = true;
+      break;
+    }
+    cnt = w[1];
+    theta = fmax(theta, th);
+  }
+  if (!settled) {
+    double mx = -INFINITY;
+    for (int64_t j = tid; j < n; j += VT) mx = fmax(mx, fy(j) - tau);
+    mx = block_max(mx, sh);
+    double lo = mx - s, hi = mx;
+    for (int it = 0; it < 200; ++it) {
+      const double mid = 0.5 * (lo + hi);
+      if (!(mid > lo && mid < hi)) break;
+      double h[1] = {0.0};
+      for (int64_t j = tid; j < n; j += VT) h[0] += fmax(fy(j) - tau - mid, 0.0);
+      block_sum(h, sh);
+      if (h[0] >= s)
+        lo = mid;
+      else
+        hi = mid;
+    }
+    double w[2] = {0.0, 0.0};
+    for (int64_t j = tid; j < n; j += VT) {
+      const double u = fy(j) - tau;
+      if (u > lo) {
+        w[0] += u;
+        w[1] += 1.0;
+      }
+    }
+    block_sum(w, sh);
+    theta = (w[0] - s) / w[1];
+  }
   for (int64_t j = tid; j < n; j += VT)
     out[j] = fmax(fy(j) - tau - theta, 0.0) + tau;
   __syncthreads();
