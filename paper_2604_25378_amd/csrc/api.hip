@@ -487,41 +487,53 @@ __device__ double precond_diag(const double* bd, int64_t bs, int64_t j,
 }
 
 // Projected PCG on P_S (H + lambda) P_S s = r (s in S) with the Jacobi
-// preconditioner P_S diag(B + lambda)^-1 P_S; r already in S.
+// preconditioner P_S diag(B + lambda)^-1 P_S; r already in S.  Inner
+// products with a projected vector come from the unprojected one and its
+// frame components, x^T P_S y = x^T y - sum_a (e_a^T x)(e_a^T y) (with
+// P_S = diag(mask) - E E^T and x, y zero off the face), so each CG step
+// needs two block reductions.  Taking x^T y alone would be exact for x in S
+// but lets the rounding residue of the residual outside S into the products
+// once the residual itself is small.
 __global__ void __launch_bounds__(PT)
 pcg_init_kernel(const double* __restrict__ r, const double* __restrict__ B,
                 int64_t bs, const double* __restrict__ E, int p, int64_t n,
                 double* s, double* res, double* pv, double* u,
                 DevScalars* sc, const double* __restrict__ mask) {
-  __shared__ double sh[4 * 16];
+  __shared__ double sh[8 * 16];
   const int tid = threadIdx.x;
   const double lam = sc->lambda;
-  double dots[4] = {0, 0, 0, 0};
+  // E^T u (p), E^T r (p), r^T u, r^T r
+  double dt[8] = {0, 0, 0, 0, 0, 0, 0, 0};
   for (int64_t j = tid; j < n; j += PT) {
     s[j] = 0.0;
-    res[j] = r[j];
-    double uj = (mask ? mask[j] : 1.0) * r[j] / precond_diag(B, bs, j, lam);
+    const double rj = r[j];
+    const double uj = (mask ? mask[j] : 1.0) * rj / precond_diag(B, bs, j, lam);
     u[j] = uj;
-    for (int a = 0; a < p; ++a) dots[a] += E[a * n + j] * uj;
-    dots[3] += r[j] * r[j];
+    for (int a = 0; a < p; ++a) {
+      dt[a] += E[a * n + j] * uj;
+      dt[3 + a] += E[a * n + j] * rj;
+    }
+    dt[6] += rj * uj;
+    dt[7] += rj * rj;
   }
-  bsum(dots, sh);
-  double rz[1] = {0.0};
+  bsum(dt, sh);
+  double rz = dt[6];
+  const double rr = dt[7];
+  for (int a = 0; a < p; ++a) rz -= dt[3 + a] * dt[a];
   for (int64_t j = tid; j < n; j += PT) {
     double uj = u[j];
-    for (int a = 0; a < p; ++a) uj -= dots[a] * E[a * n + j];
+    for (int a = 0; a < p; ++a) uj -= dt[a] * E[a * n + j];
     u[j] = uj;
     pv[j] = uj;
-    rz[0] += res[j] * uj;
+    res[j] = r[j];
   }
-  bsum(rz, sh);
   if (tid == 0) {
-    sc->aux[0] = rz[0];
-    sc->aux[1] = dots[3];
-    sc->aux[2] = dots[3];
+    sc->aux[0] = rz;
+    sc->aux[1] = rr;
+    sc->aux[2] = rr;
     sc->aux[3] = 0.0;
     sc->cgit = 0;
-    sc->cgdone = dots[3] > 0.0 ? 0 : 1;
+    sc->cgdone = rr > 0.0 ? 0 : 1;
   }
 }
 
@@ -532,54 +544,60 @@ pcg_update_kernel(const double* __restrict__ Hp, const double* __restrict__ B,
                   DevScalars* sc, const double* __restrict__ mask,
                   double tol) {
   if (sc->cgdone) return;
-  __shared__ double sh[4 * 16];
+  __shared__ double sh[8 * 16];
   const int tid = threadIdx.x;
   const double lam = sc->lambda;
-  double dots[4] = {0, 0, 0, 0};
+  // E^T Ap (p), E^T pv (p), pv^T Ap
+  double d1[7] = {0, 0, 0, 0, 0, 0, 0};
   for (int64_t j = tid; j < n; j += PT) {
-    double a = (mask ? mask[j] : 1.0) * (Hp[j] + lam * pv[j]);
+    const double a = (mask ? mask[j] : 1.0) * (Hp[j] + lam * pv[j]);
     Ap[j] = a;
-    for (int k = 0; k < p; ++k) dots[k] += E[k * n + j] * a;
+    for (int k = 0; k < p; ++k) {
+      d1[k] += E[k * n + j] * a;
+      d1[3 + k] += E[k * n + j] * pv[j];
+    }
+    d1[6] += pv[j] * a;
   }
-  bsum(dots, sh);
-  double pap[1] = {0.0};
+  bsum(d1, sh);
+  double pap = d1[6];
+  for (int k = 0; k < p; ++k) pap -= d1[3 + k] * d1[k];
+  const double rz = sc->aux[0];
+  const double al = pap > 0.0 ? rz / pap : 0.0;
+  // E^T u (p), E^T res (p), res^T u, res^T res (new residual)
+  double d2[8] = {0, 0, 0, 0, 0, 0, 0, 0};
   for (int64_t j = tid; j < n; j += PT) {
     double a = Ap[j];
-    for (int k = 0; k < p; ++k) a -= dots[k] * E[k * n + j];
-    Ap[j] = a;
-    pap[0] += pv[j] * a;
-  }
-  bsum(pap, sh);
-  const double rz = sc->aux[0];
-  const double al = pap[0] > 0.0 ? rz / pap[0] : 0.0;
-  double d2[4] = {0, 0, 0, 0};
-  for (int64_t j = tid; j < n; j += PT) {
+    for (int k = 0; k < p; ++k) a -= d1[k] * E[k * n + j];
     s[j] += al * pv[j];
-    double rj = res[j] - al * Ap[j];
+    const double rj = res[j] - al * a;
     res[j] = rj;
-    double uj = (mask ? mask[j] : 1.0) * rj / precond_diag(B, bs, j, lam);
+    const double uj = (mask ? mask[j] : 1.0) * rj / precond_diag(B, bs, j, lam);
     u[j] = uj;
-    for (int k = 0; k < p; ++k) d2[k] += E[k * n + j] * uj;
-    d2[3] += rj * rj;
+    for (int k = 0; k < p; ++k) {
+      d2[k] += E[k * n + j] * uj;
+      d2[3 + k] += E[k * n + j] * rj;
+    }
+    d2[6] += rj * uj;
+    d2[7] += rj * rj;
   }
   bsum(d2, sh);
-  double rzn[1] = {0.0};
+  double rzn = d2[6];
+  const double rr = d2[7];
+  for (int k = 0; k < p; ++k) rzn -= d2[3 + k] * d2[k];
+  const double beta = rz > 0.0 ? rzn / rz : 0.0;
   for (int64_t j = tid; j < n; j += PT) {
     double uj = u[j];
     for (int k = 0; k < p; ++k) uj -= d2[k] * E[k * n + j];
     u[j] = uj;
-    rzn[0] += res[j] * uj;
+    pv[j] = uj + beta * pv[j];
   }
-  bsum(rzn, sh);
-  const double beta = rz > 0.0 ? rzn[0] / rz : 0.0;
-  for (int64_t j = tid; j < n; j += PT) pv[j] = u[j] + beta * pv[j];
   if (tid == 0) {
-    sc->aux[0] = rzn[0];
-    sc->aux[1] = d2[3];
-    if (!(pap[0] > 0.0)) sc->aux[3] = 1.0;  // curvature breakdown
+    sc->aux[0] = rzn;
+    sc->aux[1] = rr;
+    if (!(pap > 0.0)) sc->aux[3] = 1.0;  // curvature breakdown
     sc->cgit += 1;
     // stop on |res| <= tol |r0| or a breakdown; later iterations are skipped
-    if (sqrt(d2[3]) <= tol * sqrt(sc->aux[2]) || !(pap[0] > 0.0))
+    if (sqrt(rr) <= tol * sqrt(sc->aux[2]) || !(pap > 0.0))
       sc->cgdone = 1;
   }
 }
