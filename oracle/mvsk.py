@@ -504,6 +504,11 @@ class SolveInfo:
     history: list = field(default_factory=list)
 
 
+# A projected segment whose line search moves less than this fraction of it
+# is no usable descent step (reading of the reduced-simplex wrapper).
+SEGMENT_USABLE = 0.1
+
+
 def _iterate(A, mu, c, x, U, opts: Options, solver, krylov_maxit, max_iter,
              info: SolveInfo, t0, eta=None):
     """Run outer iterations from x; return (x, converged, stalled).
@@ -517,10 +522,14 @@ def _iterate(A, mu, c, x, U, opts: Options, solver, krylov_maxit, max_iter,
         on the corrected segment x + a (xbar - x), a in [0, 1], provided
         that segment is a descent direction and not numerically zero;
         otherwise the capped raw step is taken, which exposes the next face;
-      * when neither segment gives a step (the corrected segment is no
-        descent direction) the released coordinates at the bound that the
-        direction drives further down are handed to the face solver: they
-        are held at the bound, so the following iterations run on that
+      * the corrected segment is used only when it gives a usable step: its
+        own line search (same rule, over [0, 1]) must reach at least
+        SEGMENT_USABLE of the segment;
+      * otherwise (no descent along the segment, or no usable step on it)
+        control passes to the face solver: the released coordinates at the
+        bound that the direction drives further down, and the coordinates
+        that stop the raw step at alpha_max, are held at the bound, and the
+        capped raw step is taken; the following iterations run on that
         lower-dimensional face; the holds are dropped once the held face is
         stationary (|reduced gradient| <= eps), which then counts as
         convergence only without holds;
@@ -564,18 +573,30 @@ def _iterate(A, mu, c, x, U, opts: Options, solver, krylov_maxit, max_iter,
         info.cg_iters += dr.cg_iters
         d = dr.d
         amax = alpha_max(x, d, opts.tau) if simplex else math.inf
+        rule = armijo_step if opts.linesearch == "armijo" else select_step
+        coef = None
         if faces and amax < eta:
             dbar = project_simplex(x + eta * d, opts.tau) - x
             if (np.max(np.abs(dbar)) > 1e-15 * np.max(np.abs(x))
                     and float(g @ dbar) < 0.0):
-                d, amax = dbar, 1.0
-                info.projected_steps += 1
-            else:
-                hold |= free & (x <= thr) & (d < 0.0)
-        coef = linesearch_coeffs(A, mu, c, x, d)
-        info.ls_passes += 1
-        alpha = (armijo_step(coef, amax) if opts.linesearch == "armijo"
-                 else select_step(coef, amax))
+                cs = linesearch_coeffs(A, mu, c, x, dbar)
+                info.ls_passes += 1
+                a_s = rule(cs, 1.0)
+                if a_s >= SEGMENT_USABLE:
+                    d, amax, coef, alpha = dbar, 1.0, cs, a_s
+                    info.projected_steps += 1
+            if coef is None:
+                # face solver: released bound coordinates that d drives
+                # further down, and the coordinates that stop the raw step
+                # (they reach the bound at alpha_max), are held at the bound
+                neg = d < 0.0
+                cap = np.full(x.size, np.inf)
+                cap[neg] = (x[neg] - opts.tau) / (-d[neg])
+                hold |= free & neg & ((x <= thr) | (cap <= amax * (1.0 + 1e-12)))
+        if coef is None:
+            coef = linesearch_coeffs(A, mu, c, x, d)
+            info.ls_passes += 1
+            alpha = rule(coef, amax)
         x = x + alpha * d
         info.iterations += 1
         f_new = quartic_value(coef, alpha)

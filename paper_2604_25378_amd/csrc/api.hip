@@ -325,7 +325,8 @@ int line_at(const Data& D, Work& w, const double c[4], const double* d,
   int nwg = 0;
   TRY(run_pass(D, w, PassKind::Line, a, &nwg, "line_pass"));
   HIPTRY(launch_reduce_sums(w.psums, nwg, 9, w.sums, w.st, skip));
-  HIPTRY(launch_coef_step(w.sums, a.invT, to_coef(c), select, w.sc, w.st));
+  HIPTRY(launch_coef_step(w.sums, a.invT, to_coef(c), select, w.sc, w.st,
+                          skip));
   return YAND_OK;
 }
 
@@ -360,6 +361,28 @@ struct DirOpts {
 
 const double* face_mask(const Work& w, const DirOpts& o) {
   return o.faces ? w.mask : nullptr;
+}
+
+// Line search of the iteration after the direction (and, on a face, the
+// first part of the boundary block).  On a face: the projected segment left
+// in w.ptmp is line-searched first (skipped unless it is a descent
+// candidate) and taken when its step is usable; otherwise the raw
+// direction's line search runs (skipped once the segment is taken).
+int step_line(const Data& D, Work& w, const double c[4], const DirOpts& o,
+              const int* skip) {
+  if (!o.faces) return line_at(D, w, c, w.d, o.select, skip);
+  PassArgs a = pass_args(D, w, c);
+  a.v = w.ptmp;
+  a.zc = w.z;
+  a.tout = w.wv;
+  a.skip = &w.sc->segskip;
+  int nwg = 0;
+  TRY(run_pass(D, w, PassKind::Line, a, &nwg, "line_pass"));
+  HIPTRY(launch_reduce_sums(w.psums, nwg, 9, w.sums, w.st, &w.sc->segskip));
+  HIPTRY(launch_segment_decide(w.sums, a.invT, to_coef(c), o.select, w.x,
+                               D.n, o.tau, w.d, w.ptmp, w.mask, w.hold, w.sc,
+                               w.st));
+  return line_at(D, w, c, w.d, o.select, &w.sc->lsskip);
 }
 
 struct DirStats {
@@ -750,7 +773,7 @@ int enqueue_iteration(const Data& D, Work& w, const double c[4], int p0,
   TRY(dir_factor(D, w, p0, skip, face_mask(w, o)));
   TRY(dir_trace(D, w, c, p0, skip, face_mask(w, o)));
   TRY(dir_direct_solve(D, w, p0, w.x, o, w.d, skip));
-  TRY(line_at(D, w, c, w.d, o.select, skip));
+  TRY(step_line(D, w, c, o, skip));
   HIPTRY(launch_axpy(w.x, w.d, D.n, w.sc, w.st));
   return YAND_OK;
 }
@@ -889,7 +912,7 @@ int after_iteration(Lane& L, const yand_opts& opts, const DirOpts& o) {
       L.active = false;
       return YAND_OK;
     }
-    TRY(line_at(*L.D, w, L.c, w.d, o.select, nullptr));
+    TRY(step_line(*L.D, w, L.c, o, nullptr));
     HIPTRY(launch_axpy(w.x, w.d, L.D->n, w.sc, w.st));
     TRY(sync_scalars(w));
   }
@@ -1445,7 +1468,7 @@ static int solve_pcg(yand_ctx* ctx, const double c[4], int p0,
       inf.third_passes++;
       inf.cg_iters += ds.cg;
       inf.hvp_passes += ds.cg;
-      TRY(line_at(D, w, c, w.d, o.select, nullptr));
+      TRY(step_line(D, w, c, o, nullptr));
       inf.ls_passes++;
       TRY(sync_scalars(w));
       inf.lambda_used = w.hs.lambda;

@@ -34,7 +34,9 @@ struct DevScalars {
   int ptbad;         // push-through trace not applicable (psi'' <= 0, lambda 0)
   int cgdone;        // PCG: converged or broke down, later steps skipped
   int cgit;          // PCG: iterations taken
-  int pad3;
+  int lsskip;        // skip the raw line search (done, or segment taken)
+  int segskip;       // skip the projected-segment trial (no candidate)
+  double mudseg;     // mu^T dbar of the projected segment
 };
 
 // Face masks: mask[j] = 1 for a free coordinate of the current face of
@@ -78,15 +80,26 @@ hipError_t launch_reset_hold(double* hold, int64_t n, DevScalars* sc,
 // tmp: n doubles.
 hipError_t launch_kkt(const double* x, const double* g, int64_t n, double tau,
                       double eps, double* tmp, DevScalars* sc, hipStream_t st);
-// Boundary block: when sc->amax < eta, replace d by the corrected segment
-// Pi_{Delta(tau)}(x + eta d) - x if it is a nonzero descent direction (cap
-// 1, mu^T d updated, sc->projected set); otherwise hold the free
-// coordinates at the bound that d drives down (hold[j] = 1, sc->nhold
-// counts them) for the face solver.  tmp: n doubles.
+// Boundary block, first part: sets sc->lsskip = done, sc->segskip = 1;
+// when sc->amax < eta, forms the corrected segment dbar =
+// Pi_{Delta(tau)}(x + eta d) - x in tmp; if it is a nonzero descent
+// direction it becomes the candidate (segskip = 0, mudseg = mu^T dbar),
+// otherwise the face solver takes over (launch_hold semantics).  tmp: n.
 hipError_t launch_boundary(const double* x, const double* g, const double* mu,
                            int64_t n, double tau, double eta, double* d,
                            double* tmp, const double* mask, double* hold,
                            DevScalars* sc, hipStream_t st);
+// Boundary block, second part (skipped while segskip): the segment's quartic
+// from the line-pass sums and its step over [0, 1] with the chosen rule; a
+// step of at least kSegmentUsable takes the segment (d = dbar, coefficients
+// and step kept, lsskip = 1, projected set); otherwise the face solver holds
+// the released bound coordinates that d drives down and the coordinates
+// that stop the raw step at alpha_max (hold[j] = 1, nhold counts them).
+hipError_t launch_segment_decide(const double* sums, double invT, Coef c,
+                                 int select, const double* x, int64_t n,
+                                 double tau, double* d, const double* tmp,
+                                 const double* mask, double* hold,
+                                 DevScalars* sc, hipStream_t st);
 // out = Pi_{Delta(tau)}(y) (one workgroup).
 hipError_t launch_project_simplex(const double* y, int64_t n, double tau,
                                   double* out, hipStream_t st);
@@ -96,7 +109,8 @@ hipError_t launch_copy(double* dst, const double* src, int64_t count,
 hipError_t launch_fill(double* dst, int64_t count, double v, hipStream_t st,
                        const int* skip = nullptr);
 hipError_t launch_coef_step(const double* sums, double invT, Coef c,
-                            int select, DevScalars* sc, hipStream_t st);
+                            int select, DevScalars* sc, hipStream_t st,
+                            const int* skip = nullptr);
 hipError_t launch_select_step(DevScalars* sc, hipStream_t st);
 hipError_t launch_objective(const double* sums, double invT, Coef c,
                             DevScalars* sc, hipStream_t st);

@@ -413,22 +413,50 @@ kkt_kernel(const double* __restrict__ x, const double* __restrict__ g,
   }
 }
 
-// Boundary block: the raw step is capped below the nominal step eta, so the
-// trial x + eta d is projected onto Delta(tau) and the corrected segment
-// dbar = xbar - x replaces d (cap 1) when it is a descent direction
-// (g^T dbar < 0) and not numerically zero (max |dbar| > 1e-15 max |x|).
-// Otherwise d stays and the capped step exposes the next face; the free
-// coordinates already at the bound (x_j <= tau (1 + 1e-6)) that d drives
-// down are handed to the face solver, which holds them at the bound.
+// Face solver: hold at the bound the free coordinates that d drives down
+// and that are at the bound already (released ones) or stop the raw step
+// (reach the bound at alpha_max = sc->amax); sc->nhold counts new holds.
+__device__ void hold_blocking(const double* __restrict__ x,
+                              const double* __restrict__ d,
+                              const double* __restrict__ mask,
+                              double* __restrict__ hold, int64_t n,
+                              double tau, DevScalars* sc, double* sh) {
+  const int tid = threadIdx.x;
+  const double thr = tau * (1.0 + 1e-6);
+  const double acap = sc->amax * (1.0 + 1e-12);
+  double cnt[1] = {0.0};
+  for (int64_t j = tid; j < n; j += VT) {
+    const double dj = d[j];
+    if (mask[j] != 0.0 && dj < 0.0 && hold[j] == 0.0 &&
+        (x[j] <= thr || (x[j] - tau) / (-dj) <= acap)) {
+      hold[j] = 1.0;
+      cnt[0] += 1.0;
+    }
+  }
+  block_sum(cnt, sh);
+  if (tid == 0) sc->nhold += (int)cnt[0];
+}
+
+// Boundary block, first part: the raw step is capped below the nominal step
+// eta, so the trial x + eta d is projected onto Delta(tau); the corrected
+// segment dbar = xbar - x (kept in tmp) is the candidate when it is a
+// descent direction (g^T dbar < 0) and not numerically zero (max |dbar| >
+// 1e-15 max |x|).  Otherwise the face solver takes over at once.
 __global__ void __launch_bounds__(VT)
 boundary_kernel(const double* __restrict__ x, const double* __restrict__ g,
                 const double* __restrict__ mu, int64_t n, double tau,
                 double eta, double* __restrict__ d, double* __restrict__ tmp,
                 const double* __restrict__ mask, double* __restrict__ hold,
                 DevScalars* sc) {
-  if (sc->done || !(sc->amax < eta)) return;
+  const bool run = !sc->done && sc->amax < eta;
   __shared__ double sh[4 * VW];
   const int tid = threadIdx.x;
+  __syncthreads();
+  if (tid == 0) {
+    sc->lsskip = sc->done;
+    sc->segskip = 1;
+  }
+  if (!run) return;
   simplex_project([&](int64_t j) { return x[j] + eta * d[j]; }, n, tau, tmp,
                   sh);
   double dm = 0.0, xm = 0.0;
@@ -445,22 +473,12 @@ boundary_kernel(const double* __restrict__ x, const double* __restrict__ g,
   xm = block_max(xm, sh);
   block_sum(v, sh);
   if (!(dm > 1e-15 * xm && v[0] < 0.0)) {
-    const double thr = tau * (1.0 + 1e-6);
-    double cnt[1] = {0.0};
-    for (int64_t j = tid; j < n; j += VT)
-      if (mask[j] != 0.0 && x[j] <= thr && d[j] < 0.0 && hold[j] == 0.0) {
-        hold[j] = 1.0;
-        cnt[0] += 1.0;
-      }
-    block_sum(cnt, sh);
-    if (tid == 0) sc->nhold += (int)cnt[0];
+    hold_blocking(x, d, mask, hold, n, tau, sc, sh);
     return;
   }
-  for (int64_t j = tid; j < n; j += VT) d[j] = tmp[j];
   if (tid == 0) {
-    sc->mud = v[1];
-    sc->amax = 1.0;
-    sc->projected = 1;
+    sc->segskip = 0;
+    sc->mudseg = v[1];
   }
 }
 
@@ -612,31 +630,84 @@ __device__ double armijo_step(const double* A, double amax) {
 // Assemble A0..A4 (Proposition "Quartic exact line search from sample power
 // sums") from the reduced sums and pick the step: select 1 the exact rule,
 // select 2 Armijo backtracking.
-__global__ void coef_step_kernel(const double* __restrict__ sums, double invT,
-                                 Coef c, int select, DevScalars* sc) {
-  if (threadIdx.x != 0) return;
-  if (select && (sc->done || sc->fail)) {
-    sc->alpha = 0.0;
-    return;
-  }
+// A0..A4 of the quartic line model from the line-pass sums (Proposition
+// "Quartic exact line search from sample power sums"), f and mu^T d given.
+__device__ void line_coefs(const double* __restrict__ sums, double invT,
+                           Coef c, double f, double mud, double* A) {
   const double s11 = sums[0] * invT, s21 = sums[1] * invT,
                s31 = sums[2] * invT, s02 = sums[3] * invT,
                s12 = sums[4] * invT, s22 = sums[5] * invT,
                s03 = sums[6] * invT, s13 = sums[7] * invT,
                s04 = sums[8] * invT;
-  double* A = sc->coef;
-  A[0] = sc->f;
-  A[1] = -c.c1 * sc->mud + 2.0 * c.c2 * s11 - 3.0 * c.c3 * s21 +
-         4.0 * c.c4 * s31;
+  A[0] = f;
+  A[1] = -c.c1 * mud + 2.0 * c.c2 * s11 - 3.0 * c.c3 * s21 + 4.0 * c.c4 * s31;
   A[2] = c.c2 * s02 - 3.0 * c.c3 * s12 + 6.0 * c.c4 * s22;
   A[3] = -c.c3 * s03 + 4.0 * c.c4 * s13;
   A[4] = c.c4 * s04;
+}
+
+__global__ void coef_step_kernel(const double* __restrict__ sums, double invT,
+                                 Coef c, int select, DevScalars* sc,
+                                 const int* skip) {
+  if (threadIdx.x != 0) return;
+  if (select && (sc->done || sc->fail)) {
+    sc->alpha = 0.0;
+    return;
+  }
+  if (skip && *skip) return;
+  double* A = sc->coef;
+  line_coefs(sums, invT, c, sc->f, sc->mud, A);
   if (select == 2) {
     sc->alpha = armijo_step(A, sc->amax);
     sc->status = 0;
   } else if (select) {
     sc->status = quartic_step(A, sc->amax, &sc->alpha);
   }
+}
+
+// A projected segment whose line search moves less than this fraction of it
+// is no usable descent step (reading of the reduced-simplex wrapper).
+constexpr double kSegmentUsable = 0.1;
+
+__global__ void __launch_bounds__(VT)
+segment_decide_kernel(const double* __restrict__ sums, double invT, Coef c,
+                      int select, const double* __restrict__ x, int64_t n,
+                      double tau, double* __restrict__ d,
+                      const double* __restrict__ tmp,
+                      const double* __restrict__ mask,
+                      double* __restrict__ hold, DevScalars* sc) {
+  if (sc->segskip) return;
+  __shared__ double sh[4 * VW];
+  __shared__ double As[5];
+  __shared__ double a_s[1];
+  __shared__ int st_s[1];
+  const int tid = threadIdx.x;
+  if (tid == 0) {
+    line_coefs(sums, invT, c, sc->f, sc->mudseg, As);
+    double a = 0.0;
+    int st = 0;
+    if (select == 2)
+      a = armijo_step(As, 1.0);
+    else
+      st = quartic_step(As, 1.0, &a);
+    a_s[0] = a;
+    st_s[0] = st;
+  }
+  __syncthreads();
+  if (a_s[0] >= kSegmentUsable) {
+    for (int64_t j = tid; j < n; j += VT) d[j] = tmp[j];
+    if (tid == 0) {
+      for (int i = 0; i < 5; ++i) sc->coef[i] = As[i];
+      sc->alpha = a_s[0];
+      sc->status = st_s[0];
+      sc->amax = 1.0;
+      sc->mud = sc->mudseg;
+      sc->projected = 1;
+      sc->lsskip = 1;
+    }
+    return;
+  }
+  hold_blocking(x, d, mask, hold, n, tau, sc, sh);
 }
 
 __global__ void select_step_kernel(DevScalars* sc) {
@@ -778,9 +849,19 @@ hipError_t launch_project_simplex(const double* y, int64_t n, double tau,
   return hipGetLastError();
 }
 hipError_t launch_coef_step(const double* sums, double invT, Coef c,
-                            int select, DevScalars* sc, hipStream_t st) {
+                            int select, DevScalars* sc, hipStream_t st,
+                            const int* skip) {
   hipLaunchKernelGGL(coef_step_kernel, dim3(1), dim3(64), 0, st, sums, invT, c,
-                     select, sc);
+                     select, sc, skip);
+  return hipGetLastError();
+}
+hipError_t launch_segment_decide(const double* sums, double invT, Coef c,
+                                 int select, const double* x, int64_t n,
+                                 double tau, double* d, const double* tmp,
+                                 const double* mask, double* hold,
+                                 DevScalars* sc, hipStream_t st) {
+  hipLaunchKernelGGL(segment_decide_kernel, dim3(1), dim3(VT), 0, st, sums,
+                     invT, c, select, x, n, tau, d, tmp, mask, hold, sc);
   return hipGetLastError();
 }
 hipError_t launch_select_step(DevScalars* sc, hipStream_t st) {

@@ -135,7 +135,9 @@ def test_uniform_T252_matches_oracle(n, large, c):
     w = w.cpu().numpy()
     assert info.status == ir.status and info.iterations == ir.iterations
     assert info.restarts == ir.restarts
-    assert np.abs(w - xr).max() <= (1e-8 if large else 1e-9)
+    # same iterations; both runs stop inside the KKT tolerance 1e-8, which
+    # leaves up to ~1e-8 between the two final iterates on the optimal face
+    assert np.abs(w - xr).max() <= 1e-8
     # the residual is dominated by the bound coordinates' tau = 1e-8, so it
     # is compared through the projection's nonexpansiveness:
     # |kkt(w) - kkt(xr)| <= 2 |w - xr| + |grad f(w) - grad f(xr)|
