@@ -246,3 +246,25 @@ def test_face_solver_takes_over_when_no_segment_descends():
     nu = g[sup].mean()
     assert np.max(np.abs(g[sup] - nu)) <= 1e-7 * np.max(np.abs(g))
     assert np.all(g[~sup] >= nu - 1e-7 * np.max(np.abs(g)))
+
+
+@pytest.mark.parametrize("n", [60, 1000])
+def test_short_projected_segments_hand_off_to_the_face_solver(n):
+    # The paper's T = 252 stress generator with the certified profile
+    # [1, 10, 1, 10]: taking every descent segment, however short its step,
+    # crept to a stall at KKT 1e-3 (n = 60) and 7e-3 (n = 1000).  With the
+    # usable-step rule the run must reach the simplex KKT point, checked
+    # here from the gradient directly.
+    R = synth.uniform_returns(n, 252, seed=n)
+    mu, A = O.center(R)
+    c = np.array([1.0, 10.0, 1.0, 10.0])
+    x, info = O.solve(R, c, opts=O.Options(feasible_set="simplex"))
+    assert info.status == 0
+    g = O.gradient(A, mu, c, x)
+    sup = x > 1e-8 * (1.0 + 1e-6)
+    nu = g[sup].mean()
+    scale = np.max(np.abs(g))
+    assert np.max(np.abs(g[sup] - nu)) <= 1e-8 * scale
+    assert np.all(g[~sup] >= nu - 1e-8 * scale)
+    # a step capped at alpha_max lands on the bound up to rounding
+    assert abs(x.sum() - 1.0) <= 1e-12 and x.min() >= 1e-8 * (1 - 1e-9)
