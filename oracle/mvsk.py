@@ -532,7 +532,8 @@ def _iterate(A, mu, c, x, U, opts: Options, solver, krylov_maxit, max_iter,
         capped raw step is taken; the following iterations run on that
         lower-dimensional face; the holds are dropped once the held face is
         stationary (|reduced gradient| <= eps), which then counts as
-        convergence only without holds;
+        convergence only without holds; an iteration that adds holds does
+        not count toward the stall test;
       * the stopping test also accepts a projected-KKT residual
         (kkt_residual on Delta(tau)) at or below eps.
     With eta = 0 the simplex set only caps the raw step.
@@ -574,6 +575,7 @@ def _iterate(A, mu, c, x, U, opts: Options, solver, krylov_maxit, max_iter,
         d = dr.d
         amax = alpha_max(x, d, opts.tau) if simplex else math.inf
         rule = armijo_step if opts.linesearch == "armijo" else select_step
+        held = int(np.count_nonzero(hold))
         coef = None
         if faces and amax < eta:
             dbar = project_simplex(x + eta * d, opts.tau) - x
@@ -601,7 +603,10 @@ def _iterate(A, mu, c, x, U, opts: Options, solver, krylov_maxit, max_iter,
         info.iterations += 1
         f_new = quartic_value(coef, alpha)
         info.history.append((gn, alpha, f_new))
-        if f_prev - f_new < 1e-14 * abs(f_prev):
+        # a step that changes the face (new holds) is progress of the face
+        # solver even when it moves no weight
+        if (f_prev - f_new < 1e-14 * abs(f_prev)
+                and int(np.count_nonzero(hold)) == held):
             small += 1
             if small >= 3:
                 break

@@ -930,7 +930,9 @@ int after_iteration(Lane& L, const yand_opts& opts, const DirOpts& o) {
   const double a = w.hs.alpha, *A = w.hs.coef;
   const double dec = -(a * (A[1] + a * (A[2] + a * (A[3] + a * A[4]))));
   if (std::isnan(L.f_prev)) L.f_prev = A[0];
-  if (dec < 1e-14 * std::fabs(L.f_prev)) {
+  // an iteration that adds holds changes the face: progress of the face
+  // solver even when no weight moves
+  if (dec < 1e-14 * std::fabs(L.f_prev) && w.hs.nhold <= w.hs.nhold0) {
     if (++L.small >= 3) L.active = false;
   } else {
     L.small = 0;
@@ -1478,7 +1480,7 @@ static int solve_pcg(yand_ctx* ctx, const double c[4], int p0,
       inf.iterations++;
       const double a = w.hs.alpha, *A = w.hs.coef;
       const double dec = -(a * (A[1] + a * (A[2] + a * (A[3] + a * A[4]))));
-      if (dec < 1e-14 * std::fabs(f_prev)) {
+      if (dec < 1e-14 * std::fabs(f_prev) && w.hs.nhold <= w.hs.nhold0) {
         if (++small >= 3) break;
       } else {
         small = 0;

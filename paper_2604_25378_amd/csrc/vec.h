@@ -37,6 +37,8 @@ struct DevScalars {
   int lsskip;        // skip the raw line search (done, or segment taken)
   int segskip;       // skip the projected-segment trial (no candidate)
   double mudseg;     // mu^T dbar of the projected segment
+  int nhold0;        // holds after this iteration's face evaluation
+  int pad4;
 };
 
 // Face masks: mask[j] = 1 for a free coordinate of the current face of

@@ -379,6 +379,7 @@ face_kernel(const double* __restrict__ x, const double* __restrict__ g,
       sc->nhold = 0;
       sc->release = 0;
     }
+    sc->nhold0 = sc->nhold;
   }
 }
 
@@ -387,6 +388,7 @@ reset_hold_kernel(double* __restrict__ hold, int64_t n, DevScalars* sc) {
   for (int64_t j = threadIdx.x; j < n; j += VT) hold[j] = 0.0;
   if (threadIdx.x == 0) {
     sc->nhold = 0;
+    sc->nhold0 = 0;
     sc->release = 0;
   }
 }
