@@ -227,7 +227,7 @@ def _pcg(Bmat, rhs, tol, maxit, precond):
 
 
 def affine_normal(A, mu, c, x, U, *, solver="direct", reg=0.0,
-                  krylov_tol=1e-3, krylov_maxit=15, max_escalations=8):
+                  krylov_tol=1e-3, krylov_maxit=15, max_escalations=16):
     """Exact-trace affine-normal direction in reduced coordinates.
 
     Section 4.2 and Section 4.4: with gbar = U^T g, nu = gbar/|gbar|, the

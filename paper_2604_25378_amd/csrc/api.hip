@@ -385,6 +385,12 @@ int step_line(const Data& D, Work& w, const double c[4], const DirOpts& o,
   return line_at(D, w, c, w.d, o.select, &w.sc->lsskip);
 }
 
+// Regularisation escalations (lambda <- max(10 lambda, 1e-12 scale)) before
+// a direction gives up as indefinite: 16 reach 1e3 times the mean tangent
+// curvature, so an indefinite tangent Hessian outside the convexity
+// certificate still yields a (gradient-like) descent direction.
+constexpr int kMaxEscalations = 16;
+
 struct DirStats {
   int cg = 0;
   int escalations = 0;
@@ -734,7 +740,7 @@ int direction_eager(const Data& D, Work& w, const double c[4], int p0,
     TRY(dir_factor(D, w, p0, nullptr, face_mask(w, o)));
     TRY(sync_scalars(w));
     if (!w.hs.fail) break;
-    if (attempt >= 8) return YAND_ERR_INDEFINITE;
+    if (attempt >= kMaxEscalations) return YAND_ERR_INDEFINITE;
     const double lam = std::max(10.0 * w.hs.lambda, 1e-12 * w.hs.tang_scale);
     hipLaunchKernelGGL(set_lambda_kernel, dim3(1), dim3(64), 0, w.st, w.sc,
                        lam);
