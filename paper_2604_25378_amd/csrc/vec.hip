@@ -450,7 +450,9 @@ boundary_kernel(const double* __restrict__ x, const double* __restrict__ g,
                 double eta, double* __restrict__ d, double* __restrict__ tmp,
                 const double* __restrict__ mask, double* __restrict__ hold,
                 DevScalars* sc) {
-  const bool run = !sc->done && sc->amax < eta;
+  // nothing to do at a stop or after a failed factorisation (the host redoes
+  // the direction): a direction from a failed factor must not set holds
+  const bool run = !sc->done && !sc->fail && sc->amax < eta;
   __shared__ double sh[4 * VW];
   const int tid = threadIdx.x;
   __syncthreads();
