@@ -183,10 +183,15 @@ int yand_affine_normal(yand_ctx* ctx, const double c[4], const double* target,
  * target constraint) and write w_out (device, n).  info (host) is nullable.
  * On YAND_SET_SIMPLEX without a target and with opts->eta > 0 the boundary
  * block of Algorithm 1 runs: the direction lives on the current face of
- * Delta(tau) (bound coordinates with a negative multiplier are released),
+ * Delta(tau) (bound coordinates with a negative multiplier are released);
  * a step capped below eta is replaced by the line search on the corrected
- * segment Pi_{Delta(tau)}(w + eta d) - w when that is a descent direction,
- * and the run also stops when the projected-KKT residual is <= eps. */
+ * segment Pi_{Delta(tau)}(w + eta d) - w when that is a descent direction
+ * whose step covers at least a tenth of it; otherwise the face solver holds
+ * the coordinates that stop the raw step (and released ones the direction
+ * drives down) at the bound and the capped raw step is taken.  The run also
+ * stops when the projected-KKT residual is <= eps.  A failed Cholesky
+ * factorisation escalates lambda tenfold up to 16 times before
+ * YAND_ERR_INDEFINITE. */
 int yand_mvsk_solve(yand_ctx* ctx, const double c[4], const double* target,
                     const double* w0, const yand_opts* opts, double* w_out,
                     yand_info* info);
