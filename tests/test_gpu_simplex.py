@@ -147,3 +147,37 @@ def test_uniform_T252_matches_oracle(n, large, c):
                               - O.gradient(A, mu, np.array(c), xr)))
     assert abs(info.kkt - ir.kkt) <= bound + 1e-12 * ir.kkt + 1e-15
     ctx.close()
+
+
+@pytest.mark.parametrize("n,T,large,c", [
+    (30, 252, False, (1.0, 10.0, 1.0, 10.0)),
+    (120, 252, False, (10.0, 10.0, 10.0, 10.0)),
+    (400, 252, True, (1.0, 10.0, 1.0, 10.0)),
+    (700, 252, True, (10.0, 10.0, 10.0, 10.0)),
+    (1000, 252, False, (1.0, 10.0, 1.0, 10.0)),
+    (150, 2000, True, (1.0, 10.0, 1.0, 10.0)),
+])
+def test_stress_generator_reaches_the_oracle_minimiser(n, T, large, c):
+    """Certified profiles on the uniform stress generator, both
+    configurations, n below and above T: the library reaches the simplex
+    KKT target and the oracle's objective (a unique minimum value)."""
+    print(f"[case] stress n={n} T={T} {'PCG' if large else 'direct'} c={c}",
+          flush=True)
+    R = synth.uniform_returns(n, T, seed=n + T)
+    mu, A = O.center(R)
+    if large:
+        oo = O.Options.large()
+        oo.feasible_set = "simplex"
+    else:
+        oo = O.Options(feasible_set="simplex")
+    xr, ir = O.solve(R, c, opts=oo)
+    ctx = yb.Context(torch.from_numpy(R).cuda())
+    w, info = ctx.solve(c, opts=yb.default_opts(large=large,
+                                                feasible_set="simplex"))
+    ctx.close()
+    w = w.cpu().numpy()
+    print(f"GPU {info.status} {info.iterations} it kkt {info.kkt:.1e}; oracle "
+          f"{ir.status} {ir.iterations} it kkt {ir.kkt:.1e}", flush=True)
+    assert info.kkt <= 1e-6 and ir.kkt <= 1e-6
+    fr, fw = O.objective(A, mu, np.array(c), xr), O.objective(A, mu, np.array(c), w)
+    assert fw == pytest.approx(fr, rel=1e-9, abs=1e-12)
