@@ -116,3 +116,36 @@ def test_frontier_from_given_starts():
         assert np.abs(W3[b].cpu().numpy() - xr).max() <= _kappa_w(R, C4[b], xr, tg[b])
         assert abs(mu @ W3[b].cpu().numpy() - tg[b]) <= 1e-14
     ctx.close()
+
+
+@pytest.mark.parametrize("n", [40, 200])
+def test_simplex_frontier_matches_single_solves(n):
+    """Batched lanes on the simplex: the boundary block (segment trial,
+    face-solver holds, projected-KKT stop) runs inside the graph-replayed
+    iterations and must reproduce each instance's single solve and the
+    oracle's outcome."""
+    print(f"[case] simplex frontier n={n}", flush=True)
+    R = synth.uniform_returns(n, 252, seed=n)
+    mu, A = O.center(R)
+    C4 = np.array([[1.0, 10.0, 1.0, 10.0], [10.0, 10.0, 10.0, 10.0],
+                   [1.0, 5.0, 2.0, 10.0], [2.0, 1.0, 0.5, 4.0],
+                   [1.0, 10.0, 1.0, 10.0]])
+    opts = yb.default_opts(feasible_set="simplex")
+    ctx = yb.Context(torch.from_numpy(R).cuda())
+    W, infos = ctx.frontier(C4, opts=opts)
+    W = W.cpu().numpy()
+    for b, c in enumerate(C4):
+        w1, i1 = ctx.solve(c, opts=opts)
+        xr, ir = O.solve(R, c, opts=O.Options(feasible_set="simplex"))
+        print(f"b={b} batch {infos[b].status} {infos[b].iterations} it kkt "
+              f"{infos[b].kkt:.1e}; single {i1.iterations} it; oracle "
+              f"{ir.iterations} it", flush=True)
+        assert infos[b].iterations == i1.iterations
+        assert infos[b].projected_steps == i1.projected_steps
+        assert np.abs(W[b] - w1.cpu().numpy()).max() <= 1e-12
+        assert infos[b].kkt <= 1e-6
+        assert O.objective(A, mu, c, W[b]) == pytest.approx(
+            O.objective(A, mu, c, xr), rel=1e-9, abs=1e-12)
+    # instances 0 and 4 are the same problem
+    assert np.abs(W[0] - W[4]).max() == 0.0
+    ctx.close()
