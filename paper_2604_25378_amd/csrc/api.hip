@@ -631,117 +631,6 @@ pcg_update_kernel(const double* __restrict__ Hp, const double* __restrict__ B,
   }
 }
 
-// The same step with each thread's K = ceil(n / PT) elements held in
-// registers across the three phases (n <= 8 PT): the same sums in the same
-// order, so bit-identical to pcg_update_kernel, with the E columns, p, Ap and
-// u read or formed once instead of per phase.
-template <int K>
-__global__ void __launch_bounds__(PT)
-pcg_update_reg_kernel(const double* __restrict__ Hp,
-                      const double* __restrict__ B, int64_t bs,
-                      const double* __restrict__ E, int p, int64_t n,
-                      double* s, double* res, double* pv,
-                      DevScalars* sc, const double* __restrict__ mask,
-                      double tol) {
-  if (sc->cgdone) return;
-  __shared__ double sh[8 * 16];
-  const int tid = threadIdx.x;
-  const double lam = sc->lambda;
-  double e[3][K], pr[K], ar[K], mr[K], ur[K];
-  double d1[7] = {0, 0, 0, 0, 0, 0, 0};
-#pragma unroll
-  for (int i = 0; i < K; ++i) {
-    const int64_t j = tid + (int64_t)i * PT;
-    const bool in = j < n;
-    mr[i] = in ? (mask ? mask[j] : 1.0) : 0.0;
-    pr[i] = in ? pv[j] : 0.0;
-    const double a = mr[i] * ((in ? Hp[j] : 0.0) + lam * pr[i]);
-    ar[i] = a;
-#pragma unroll
-    for (int k = 0; k < 3; ++k) e[k][i] = (in && k < p) ? E[k * n + j] : 0.0;
-    for (int k = 0; k < p; ++k) {
-      d1[k] += e[k][i] * a;
-      d1[3 + k] += e[k][i] * pr[i];
-    }
-    d1[6] += pr[i] * a;
-  }
-  bsum(d1, sh);
-  double pap = d1[6];
-  for (int k = 0; k < p; ++k) pap -= d1[3 + k] * d1[k];
-  const double rz = sc->aux[0];
-  const double al = pap > 0.0 ? rz / pap : 0.0;
-  double d2[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-#pragma unroll
-  for (int i = 0; i < K; ++i) {
-    const int64_t j = tid + (int64_t)i * PT;
-    ur[i] = 0.0;
-    if (j < n) {
-      double a = ar[i];
-      for (int k = 0; k < p; ++k) a -= d1[k] * e[k][i];
-      s[j] += al * pr[i];
-      const double rj = res[j] - al * a;
-      res[j] = rj;
-      const double uj = mr[i] * rj / precond_diag(B, bs, j, lam);
-      ur[i] = uj;
-      for (int k = 0; k < p; ++k) {
-        d2[k] += e[k][i] * uj;
-        d2[3 + k] += e[k][i] * rj;
-      }
-      d2[6] += rj * uj;
-      d2[7] += rj * rj;
-    }
-  }
-  bsum(d2, sh);
-  double rzn = d2[6];
-  const double rr = d2[7];
-  for (int k = 0; k < p; ++k) rzn -= d2[3 + k] * d2[k];
-  const double beta = rz > 0.0 ? rzn / rz : 0.0;
-#pragma unroll
-  for (int i = 0; i < K; ++i) {
-    const int64_t j = tid + (int64_t)i * PT;
-    if (j < n) {
-      double uj = ur[i];
-      for (int k = 0; k < p; ++k) uj -= d2[k] * e[k][i];
-      pv[j] = uj + beta * pr[i];
-    }
-  }
-  if (tid == 0) {
-    sc->aux[0] = rzn;
-    sc->aux[1] = rr;
-    if (!(pap > 0.0)) sc->aux[3] = 1.0;  // curvature breakdown
-    sc->cgit += 1;
-    if (sqrt(rr) <= tol * sqrt(sc->aux[2]) || !(pap > 0.0))
-      sc->cgdone = 1;
-  }
-}
-
-void launch_pcg_update(const double* Hp, const double* bd, int64_t bs,
-                       const double* E, int p, int64_t n, double* s,
-                       double* res, double* pv, double* u, double* Ap,
-                       DevScalars* sc, const double* mask, double tol,
-                       hipStream_t st) {
-  const int64_t K = (n + PT - 1) / PT;
-#define YAND_PCG_REG(KK)                                                     \
-  case KK:                                                                   \
-    hipLaunchKernelGGL(pcg_update_reg_kernel<KK>, dim3(1), dim3(PT), 0, st,  \
-                       Hp, bd, bs, E, p, n, s, res, pv, sc, mask, tol);      \
-    return;
-  switch (K) {
-    YAND_PCG_REG(1)
-    YAND_PCG_REG(2)
-    YAND_PCG_REG(3)
-    YAND_PCG_REG(4)
-    YAND_PCG_REG(5)
-    YAND_PCG_REG(6)
-    YAND_PCG_REG(7)
-    YAND_PCG_REG(8)
-    default:
-      hipLaunchKernelGGL(pcg_update_kernel, dim3(1), dim3(PT), 0, st, Hp, bd,
-                         bs, E, p, n, s, res, pv, u, Ap, sc, mask, tol);
-  }
-#undef YAND_PCG_REG
-}
-
 int dir_pcg_solve(const Data& D, Work& w, const double c[4], int p0,
                   const double* x, const DirOpts& o, double* d,
                   DirStats* stats, const double* bd, int64_t bs) {
@@ -756,9 +645,9 @@ int dir_pcg_solve(const Data& D, Work& w, const double c[4], int p0,
   // HVP pass and update returns at once
   for (int it = 0; it < o.krylov_maxit; ++it) {
     TRY(hvp_cached(D, w, c, w.pcg_p, w.hv, nullptr, &w.sc->cgdone));
-    launch_pcg_update(w.hv, bd, bs, w.E, p, n, w.pcg_s, w.pcg_res, w.pcg_p,
-                      w.pcg_u, w.y, w.sc, mask, o.krylov_tol, w.st);
-    HIPTRY(hipGetLastError());
+    hipLaunchKernelGGL(pcg_update_kernel, dim3(1), dim3(PT), 0, w.st, w.hv,
+                       bd, bs, w.E, p, n, w.pcg_s, w.pcg_res, w.pcg_p,
+                       w.pcg_u, w.y, w.sc, mask, o.krylov_tol);
   }
   TRY(sync_scalars(w));
   const int it = w.hs.cgit;
