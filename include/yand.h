@@ -9,7 +9,8 @@
  * Weights satisfy the budget 1^T w = 1 (BUDGET set: its affine hull, the
  * reduced parametrisation of Section 4.2) and optionally a return target
  * mu^T w = r; the SIMPLEX set additionally keeps w_i >= tau through the
- * feasibility cap of Section 4.3.
+ * feasibility cap of Section 4.3 (up to the rounding of a step that ends on
+ * the bound, a few ulps of the largest weight).
  *
  * Conventions for every entry point:
  *  - Scalars and small fixed-size arrays (c[4], coef[5], mom[4], f, target)
@@ -145,9 +146,9 @@ int yand_linesearch_coeffs(yand_ctx* ctx, const double c[4], const double* w,
 /* Exact step (same proposition): the argmin of the quartic over 0, alpha_max
  * (if finite; pass INFINITY for the budget set) and the real roots of its
  * derivative in (0, alpha_max), computed on the device.  Ties go to the
- * smallest step within 1e-15 * sum_{i>=1} |A_i| alpha^i.  Returns
- * YAND_ERR_UNBOUNDED when alpha_max is infinite and the quartic does not grow
- * at infinity. */
+ * smallest step within 1e-15 * sum_{i>=1} |A_i| alpha^i.  A constant model
+ * (A1..A4 zero) gives alpha = 0.  Returns YAND_ERR_UNBOUNDED when alpha_max
+ * is infinite and the quartic does not grow at infinity. */
 int yand_select_step(yand_ctx* ctx, const double coef[5], double alpha_max,
                      double* alpha);
 

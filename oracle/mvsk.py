@@ -408,11 +408,14 @@ def select_step(coef, amax=math.inf):
     candidates are compared on phi(alpha) - A0 = A1 a + A2 a^2 + A3 a^3 + A4 a^4
     so that decreases far below the rounding of A0 still count.  Ties are
     broken toward the smallest step among candidates within
-    1e-15 * sum_{i>=1} |A_i| alpha^i of the minimum.  On an unbounded interval
-    the quartic must grow at infinity (leading nonzero coefficient positive),
-    otherwise ``Unbounded`` is raised.
+    1e-15 * sum_{i>=1} |A_i| alpha^i of the minimum.  A constant model (A1..A4
+    all zero: a zero direction) gives 0.  On an unbounded interval the quartic
+    must grow at infinity (leading nonzero coefficient positive), otherwise
+    ``Unbounded`` is raised.
     """
     coef = np.asarray(coef, dtype=np.float64)
+    if not np.any(coef[1:] != 0.0):
+        return 0.0          # a constant model (zero direction): stay put
     if not math.isfinite(amax):
         lead = next((coef[i] for i in (4, 3, 2, 1) if coef[i] != 0.0), 0.0)
         if lead <= 0.0:

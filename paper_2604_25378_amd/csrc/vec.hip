@@ -522,6 +522,10 @@ __device__ int quartic_step(const double* A, double amax, double* alpha) {
   const bool finite_cap = isfinite(amax);
   double lead_p = A[4] != 0.0 ? A[4] : A[3] != 0.0 ? A[3]
                  : A[2] != 0.0 ? A[2] : 0.0;   // sign of p at +infinity
+  if (A[1] == 0.0 && A[2] == 0.0 && A[3] == 0.0 && A[4] == 0.0) {
+    *alpha = 0.0;  // a constant model (zero direction): stay put
+    return 0;
+  }
   if (!finite_cap) {
     double lead = A[4] != 0.0 ? A[4] : A[3] != 0.0 ? A[3]
                 : A[2] != 0.0 ? A[2] : A[1];
