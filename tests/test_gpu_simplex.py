@@ -181,3 +181,20 @@ def test_stress_generator_reaches_the_oracle_minimiser(n, T, large, c):
     assert info.kkt <= 1e-6 and ir.kkt <= 1e-6
     fr, fw = O.objective(A, mu, np.array(c), xr), O.objective(A, mu, np.array(c), w)
     assert fw == pytest.approx(fr, rel=1e-9, abs=1e-12)
+
+
+def test_single_free_coordinate_face_takes_a_zero_step():
+    """A face with one free coordinate has a zero direction: the step must
+    be 0 (constant quartic model), not an unbounded-model error.  Factor
+    panel n = 2000, T = 500, profile [10,1,10,1] outside the certificate,
+    direct configuration, where such a face occurs on the way."""
+    print("[case] zero-direction face n=2000 T=500", flush=True)
+    R = synth.factor_returns(2000, 500, 3, 2, 4.0, 0.01, 7)
+    ctx = yb.Context(torch.from_numpy(R).cuda())
+    w, info = ctx.solve([10.0, 1.0, 10.0, 1.0],
+                        opts=yb.default_opts(feasible_set="simplex"))
+    ctx.close()
+    w = w.cpu().numpy()
+    assert info.status in (0, 1, 2)
+    assert np.isfinite(w).all() and abs(w.sum() - 1.0) <= 1e-12
+    assert w.min() >= 1e-8 - 1e-15
