@@ -38,7 +38,10 @@ extern "C" {
 enum {
   YAND_OK = 0,
   YAND_WARN_MAXITER = 1,     /* iteration / time budget ended above eps      */
-  YAND_WARN_STALL = 2,       /* still above eps after the stall restarts     */
+  YAND_WARN_STALL = 2,       /* stalled above eps: the objective decreased by
+                                less than 1e-14 of |f| on 3 iterations in a
+                                row, or the stall restarts ran and the solve
+                                is still above eps                           */
   YAND_ERR_ARG = -1,         /* bad size, negative c, infeasible start/target */
   YAND_ERR_NONFINITE = -2,   /* NaN or Inf in R or in an iterate             */
   YAND_ERR_HIP = -3,         /* a HIP runtime call failed                    */
@@ -71,12 +74,19 @@ typedef struct yand_opts {
   int feasible_set;       /* YAND_SET_*                                       */
   double eps;             /* stop when ||reduced gradient||_2 <= eps (1e-8)   */
   int max_iter;           /* outer budget (direct 300, PCG 40)                */
-  double max_elapsed;     /* seconds (PCG 60; <= 0 means unlimited)           */
+  double max_elapsed;     /* seconds per phase (PCG 60; <= 0 means unlimited):
+                             checked before each direction; the direct
+                             configuration and batched solves measure it
+                             from the start of the call                     */
   double regularization;  /* relative lambda (direct 0, PCG 1e-4)             */
-  double krylov_tol;      /* relative PCG residual (1e-3)                     */
+  double krylov_tol;      /* relative PCG residual (1e-3; must be > 0)        */
   int krylov_maxit;       /* PCG iterations (15)                              */
   double tau;             /* interior margin of Delta(tau) (1e-8)             */
-  int stall_recovery;     /* PCG: restart twice when stalled                  */
+  int stall_recovery;     /* PCG: restart twice when a phase ends above eps
+                             (stall test, iteration or time budget): budget
+                             set, twice the Krylov budget, then the direct
+                             solve; simplex boundary block, projected trial
+                             steps 0.045, then 0.02                         */
   int restart_max_iter;   /* outer budget of each restart (120)               */
   double eta;             /* simplex boundary block: nominal projected trial
                              step (0.05; 0 = capped raw steps only).  Active
@@ -105,6 +115,8 @@ typedef struct yand_info {
                              |w - Pi_Delta(tau)(w - grad f(w))|_2 (simplex
                              set; NaN on the budget set)                     */
   int projected_steps;    /* iterations that took the projected trial segment */
+  int phase_iterations[3];/* iterations of the baseline phase and of each
+                             stall-recovery restart                          */
 } yand_info;
 
 /* Fill *opts with the direct configuration (YAND-MVSK small). */

@@ -505,6 +505,7 @@ class SolveInfo:
     kkt: float = math.nan
     projected_steps: int = 0
     history: list = field(default_factory=list)
+    phases: list = field(default_factory=list)
 
 
 # A projected segment whose line search moves less than this fraction of it
@@ -514,7 +515,11 @@ SEGMENT_USABLE = 0.1
 
 def _iterate(A, mu, c, x, U, opts: Options, solver, krylov_maxit, max_iter,
              info: SolveInfo, t0, eta=None):
-    """Run outer iterations from x; return (x, converged, stalled).
+    """Run outer iterations from x; return (x, converged, reason).
+
+    reason: 'converged'; 'stall' when the objective decreased by less than
+    1e-14 of its magnitude on 3 iterations in a row; 'budget' when max_iter
+    iterations ran; 'time' when max_elapsed (seconds, > 0) ran out.
 
     Simplex with eta > 0 runs the boundary block of Algorithm 1 and the
     reduced-simplex wrapper of the implementation appendix:
@@ -545,6 +550,7 @@ def _iterate(A, mu, c, x, U, opts: Options, solver, krylov_maxit, max_iter,
     simplex = opts.feasible_set == "simplex"
     faces = simplex and eta > 0.0
     small = 0
+    reason = "budget"
     f_prev = objective(A, mu, c, x)
     hold = np.zeros(x.size, dtype=bool)
     release = False
@@ -563,13 +569,13 @@ def _iterate(A, mu, c, x, U, opts: Options, solver, krylov_maxit, max_iter,
             info.kkt = float(np.linalg.norm(
                 x - project_simplex(x - g, opts.tau)))
         if simplex and info.kkt <= opts.eps:
-            return x, True, False
+            return x, True, "converged"
         if gn <= opts.eps:
             if not hold.any():
-                return x, True, False
+                return x, True, "converged"
             release = True
-        if time.perf_counter() - t0 > opts.max_elapsed:
-            return x, False, True
+        if opts.max_elapsed > 0.0 and time.perf_counter() - t0 > opts.max_elapsed:
+            return x, False, "time"
         reg = opts.reg if solver == "pcg" else 0.0
         dr = affine_normal(A, mu, c, x, Ui, solver=solver, reg=reg,
                            krylov_tol=opts.krylov_tol,
@@ -612,6 +618,7 @@ def _iterate(A, mu, c, x, U, opts: Options, solver, krylov_maxit, max_iter,
                 and int(np.count_nonzero(hold)) == held):
             small += 1
             if small >= 3:
+                reason = "stall"
                 break
         else:
             small = 0
@@ -624,7 +631,7 @@ def _iterate(A, mu, c, x, U, opts: Options, solver, krylov_maxit, max_iter,
     if simplex:
         info.kkt = float(np.linalg.norm(x - project_simplex(x - g, opts.tau)))
         conv = conv or info.kkt <= opts.eps
-    return x, conv, True
+    return x, conv, "converged" if conv else reason
 
 
 def solve(R, c, target=None, x0=None, opts: Options | None = None):
@@ -637,8 +644,12 @@ def solve(R, c, target=None, x0=None, opts: Options | None = None):
     with twice the Krylov budget, then with the direct solve.  Simplex: with
     the projected trial steps 0.045, then 0.02, of the same table.  The
     boundary block needs the budget hull alone; with a return target it is
-    off (capped steps only).
-    Status: 0 converged, 1 iteration budget exhausted.
+    off (capped steps only).  max_elapsed <= 0 means no time limit.
+    Status: 0 converged; 2 stalled (the last phase ended at the stall test,
+    or restarts ran and the solve is still above eps); 1 the iteration or
+    time budget ended above eps without a restart.
+    info.phases lists each phase as (solver, krylov_maxit, max_iter, eta,
+    iterations, reason).
     """
     opts = opts or Options()
     c = np.asarray(c, dtype=np.float64)
@@ -651,9 +662,12 @@ def solve(R, c, target=None, x0=None, opts: Options | None = None):
     info = SolveInfo()
     eta = opts.eta if target is None else 0.0
     t0 = time.perf_counter()
-    x, conv, stalled = _iterate(A, mu, c, x, U, opts, opts.solver,
-                                opts.krylov_maxit, opts.max_iter, info, t0,
-                                eta)
+    it0 = info.iterations
+    x, conv, reason = _iterate(A, mu, c, x, U, opts, opts.solver,
+                               opts.krylov_maxit, opts.max_iter, info, t0,
+                               eta)
+    info.phases.append((opts.solver, opts.krylov_maxit, opts.max_iter, eta,
+                        info.iterations - it0, reason))
     if not conv and opts.stall_recovery and opts.solver == "pcg":
         if opts.feasible_set == "simplex" and eta > 0.0:
             plan = [("pcg", opts.krylov_maxit, 0.045),
@@ -663,12 +677,20 @@ def solve(R, c, target=None, x0=None, opts: Options | None = None):
         for solver, kmax, e in plan:
             info.restarts += 1
             t0 = time.perf_counter()
-            x, conv, stalled = _iterate(A, mu, c, x, U, opts, solver, kmax,
-                                        opts.restart_max_iter, info, t0, e)
+            it0 = info.iterations
+            x, conv, reason = _iterate(A, mu, c, x, U, opts, solver, kmax,
+                                       opts.restart_max_iter, info, t0, e)
+            info.phases.append((solver, kmax, opts.restart_max_iter, e,
+                                info.iterations - it0, reason))
             if conv:
                 break
     info.f = objective(A, mu, c, x)
-    info.status = 0 if conv else 1
+    if conv:
+        info.status = 0
+    elif info.restarts > 0 or reason == "stall":
+        info.status = 2
+    else:
+        info.status = 1
     return x, info
 
 

@@ -54,7 +54,8 @@ class yand_info(C.Structure):
                 ("oracle_passes", C.c_int64), ("hvp_passes", C.c_int64),
                 ("third_passes", C.c_int64), ("ls_passes", C.c_int64),
                 ("dense_traces", C.c_int64), ("kkt", C.c_double),
-                ("projected_steps", C.c_int)]
+                ("projected_steps", C.c_int),
+                ("phase_iterations", C.c_int * 3)]
 
 
 class yand_mlp_opts(C.Structure):
@@ -223,6 +224,13 @@ class SolveInfo:
     dense_traces: int
     kkt: float
     projected_steps: int
+    phase_iterations: tuple
+
+
+def _info(i) -> SolveInfo:
+    d = {k: getattr(i, k) for k, _ in yand_info._fields_}
+    d["phase_iterations"] = tuple(d["phase_iterations"])
+    return SolveInfo(**d)
 
 
 class Context:
@@ -343,7 +351,7 @@ class Context:
             C.byref(opts) if opts else None, C.c_void_p(out.data_ptr()),
             C.byref(info))
         _check(rc, "yand_mvsk_solve", warn_ok=not raise_on_warning)
-        return out, SolveInfo(**{k: getattr(info, k) for k, _ in yand_info._fields_})
+        return out, _info(info)
 
     def return_floor(self, profile, q: float, opts: yand_opts | None = None,
                      max_rounds: int = 40):
@@ -362,7 +370,7 @@ class Context:
             int(max_rounds), c, C.byref(fl), C.byref(ret),
             C.c_void_p(out.data_ptr()), C.byref(info), C.byref(ns))
         _check(rc, "yand_return_floor", warn_ok=True)
-        si = SolveInfo(**{k: getattr(info, k) for k, _ in yand_info._fields_})
+        si = _info(info)
         return list(c), out, fl.value, ret.value, si, ns.value
 
     def frontier(self, C4, targets=None, opts: yand_opts | None = None,
@@ -389,7 +397,7 @@ class Context:
             C.c_void_p(W0d.data_ptr()) if W0d is not None else None,
             C.byref(opts) if opts else None, C.c_void_p(W.data_ptr()), infos)
         _check(rc, "yand_frontier_solve", warn_ok=True)
-        return W, [SolveInfo(**{k: getattr(i, k) for k, _ in yand_info._fields_})
+        return W, [_info(i)
                    for i in infos]
 
     PASS_KINDS = ("oracle", "value", "hvp", "line", "dot", "third")
@@ -461,7 +469,7 @@ def batch_solve(contexts, C4, targets=None, opts: yand_opts | None = None,
                               C.byref(opts) if opts else None, out_arr, infos,
                               int(max_lanes), int(use_graph))
     _check(rc, "yand_batch_solve", warn_ok=True)
-    return outs, [SolveInfo(**{k: getattr(i, k) for k, _ in yand_info._fields_})
+    return outs, [_info(i)
                   for i in infos]
 
 

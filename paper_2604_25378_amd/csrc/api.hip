@@ -17,6 +17,7 @@
 #include <cstdlib>
 #include <cstring>
 #include <memory>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -93,12 +94,18 @@ struct yand_ctx {
 namespace {
 
 int alloc(void** p, size_t bytes) {
-  if (hipMalloc(p, bytes < 256 ? 256 : bytes) != hipSuccess) {
+  if (bytes < 256) bytes = 256;
+  if (hipMalloc(p, bytes) != hipSuccess) {
     (void)hipGetLastError();
     *p = nullptr;
     return YAND_ERR_OOM;
   }
   return YAND_OK;
+}
+
+// Frees what alloc returned.
+void dfree(void* p) {
+  if (p) (void)hipFree(p);
 }
 
 #define TRY(expr)                   \
@@ -172,9 +179,8 @@ void free_work(Work& w) {
                     w.B,     w.M,      w.X,     w.rn,     w.mask, w.ptmp,
                     w.hold,  w.tGp,    w.tG,    w.tC,     w.tX,   w.bdiag,
                     w.tpart};
-  for (double* p : ptrs)
-    if (p) (void)hipFree(p);
-  if (w.sc && w.own_sc) (void)hipFree(w.sc);
+  for (double* p : ptrs) dfree(p);
+  if (w.sc && w.own_sc) dfree(w.sc);
   if (w.st && w.own_stream) (void)hipStreamDestroy(w.st);
   w = Work{};
 }
@@ -212,8 +218,17 @@ int alloc_work(Work& w, const Data& D, DevScalars* sc_external) {
   } else {
     if ((rc = alloc((void**)&w.sc, sizeof(DevScalars)))) return rc;
     w.own_sc = true;
-    HIPTRY(hipMemsetAsync(w.sc, 0, sizeof(DevScalars), w.st));
   }
+  return YAND_OK;
+}
+
+// First contents of a workspace: zero scalars (when owned) and T-vectors.
+int init_work(Work& w, const Data& D) {
+  const int64_t Tp = D.Tp;
+  static_assert(sizeof(DevScalars) % sizeof(double) == 0, "scalar block");
+  if (w.own_sc)
+    HIPTRY(launch_fill((double*)w.sc, sizeof(DevScalars) / sizeof(double), 0.0,
+                       w.st));
   HIPTRY(launch_fill(w.z, Tp, 0.0, w.st));
   HIPTRY(launch_fill(w.q, Tp, 0.0, w.st));
   HIPTRY(launch_fill(w.AE, 3 * Tp, 0.0, w.st));
@@ -881,6 +896,7 @@ struct Lane {
   int p0 = 1;
   // host state
   bool active = true, converged = false, frozen_set = false;
+  bool stalled = false;  // the stall test ended the run
   int rc = YAND_OK;
   int small = 0;
   double f_prev = NAN;
@@ -939,13 +955,25 @@ int after_iteration(Lane& L, const yand_opts& opts, const DirOpts& o) {
   // an iteration that adds holds changes the face: progress of the face
   // solver even when no weight moves
   if (dec < 1e-14 * std::fabs(L.f_prev) && w.hs.nhold <= w.hs.nhold0) {
-    if (++L.small >= 3) L.active = false;
+    if (++L.small >= 3) {
+      L.active = false;
+      L.stalled = true;
+    }
   } else {
     L.small = 0;
   }
   L.f_prev = A[0] - dec;
+  L.info.phase_iterations[0] = L.info.iterations;
   if (L.info.iterations >= opts.max_iter) L.active = false;
   return YAND_OK;
+}
+
+// Status of a lane that ran without error: converged, stalled (the stall
+// test ended it, or restarts ran and it is still above eps) or the
+// iteration / time budget ended it.
+int finish_status(bool converged, bool stalled, int restarts) {
+  if (converged) return YAND_OK;
+  return (stalled || restarts > 0) ? YAND_WARN_STALL : YAND_WARN_MAXITER;
 }
 
 // Final stationarity check of a lane that stopped without converging.
@@ -966,22 +994,33 @@ int final_check(Lane& L, const yand_opts& opts, const DirOpts& o) {
 
 // Run the direct configuration on a set of lanes until each converges or
 // stops.  Iteration 0 is enqueued eagerly; with use_graph, later iterations
-// replay one captured graph of all lanes.  cs: control stream.
+// replay one captured graph of all lanes.  cs: control stream.  A single lane
+// on the control stream itself needs no fork/join events.  opts.max_elapsed
+// (> 0) stops every lane still running once that many seconds have passed
+// since the call began, checked before each iteration.
 int run_lanes(std::vector<Lane>& lanes, const yand_opts& opts,
               const DirOpts& o, hipStream_t cs, bool use_graph,
               DevScalars* host_sc, DevScalars* dev_sc) {
   const size_t nl = lanes.size();
+  const auto t_start = std::chrono::steady_clock::now();
   HIPTRY(prepare_dense_kernels());
+  const bool inline_lane = nl == 1 && lanes[0].w->st == cs && !use_graph;
   hipEvent_t ev_fork = nullptr;
-  std::vector<hipEvent_t> ev_join(nl, nullptr);
-  HIPTRY(hipEventCreateWithFlags(&ev_fork, hipEventDisableTiming));
-  for (auto& e : ev_join)
-    HIPTRY(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+  std::vector<hipEvent_t> ev_join(inline_lane ? 0 : nl, nullptr);
+  if (!inline_lane) {
+    HIPTRY(hipEventCreateWithFlags(&ev_fork, hipEventDisableTiming));
+    for (auto& e : ev_join)
+      HIPTRY(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+  }
   auto cleanup = [&]() {
-    (void)hipEventDestroy(ev_fork);
+    if (ev_fork) (void)hipEventDestroy(ev_fork);
     for (auto& e : ev_join) (void)hipEventDestroy(e);
   };
   auto enqueue_all = [&]() -> int {
+    if (inline_lane) {
+      Lane& L = lanes[0];
+      return enqueue_iteration(*L.D, *L.w, L.c, L.p0, o, opts.eps);
+    }
     HIPTRY(hipEventRecord(ev_fork, cs));
     for (size_t i = 0; i < nl; ++i) {
       Lane& L = lanes[i];
@@ -1008,6 +1047,11 @@ int run_lanes(std::vector<Lane>& lanes, const yand_opts& opts,
   hipGraphExec_t exec = nullptr;
   int rc = YAND_OK;
   for (int it = 0;; ++it) {
+    if (opts.max_elapsed > 0.0 &&
+        std::chrono::duration<double>(std::chrono::steady_clock::now() -
+                                      t_start)
+                .count() > opts.max_elapsed)
+      for (auto& L : lanes) L.active = false;
     bool any = false;
     for (auto& L : lanes) any |= L.active;
     if (!any) break;
@@ -1208,14 +1252,20 @@ int yand_destroy(yand_ctx* ctx) {
   flush_timed(ctx->prof, ctx->w.st);
   free_work(ctx->w);
   void* ptrs[] = {ctx->d.A, ctx->d.mu, ctx->d.Efix, ctx->d.AEfix};
-  for (void* p : ptrs)
-    if (p) (void)hipFree(p);
+  for (void* p : ptrs) dfree(p);
   delete ctx;
   return YAND_OK;
 }
 
-int yand_create(const double* R, int64_t T, int64_t n, int64_t ldr,
-                int precision, void* hip_stream, yand_ctx** out) {
+}  // extern "C"
+
+// Context creation.  All device memory is taken before the first kernel, so
+// an allocation failure leaves nothing enqueued; with dense_upfront the n x n
+// buffers of the direct configuration are taken here too instead of at the
+// first direction.
+static int create_ctx(const double* R, int64_t T, int64_t n, int64_t ldr,
+                      int precision, void* hip_stream, bool dense_upfront,
+                      yand_ctx** out) {
   if (!out) return YAND_ERR_ARG;
   *out = nullptr;
   if (!R || T < 2 || n < 2 || ldr < n) return YAND_ERR_ARG;
@@ -1253,6 +1303,8 @@ int yand_create(const double* R, int64_t T, int64_t n, int64_t ldr,
   const int64_t nchunks = (T + 255) / 256;
   if ((rc = alloc((void**)&colpart, (size_t)nchunks * n * sizeof(double))))
     return fail(rc);
+  if (dense_upfront && (rc = ensure_dense(w, D))) return fail(rc);
+  if (init_work(w, D) != YAND_OK) return fail(YAND_ERR_HIP);
   hipError_t e = launch_center(R, T, n, ldr, precision, D.A, D.Tp, D.lda,
                                D.mu, colpart, &w.sc->nonfinite, st);
   if (e == hipSuccess) {
@@ -1274,7 +1326,7 @@ int yand_create(const double* R, int64_t T, int64_t n, int64_t ldr,
     e = hipMemcpyAsync(&w.hs, w.sc, sizeof(DevScalars), hipMemcpyDeviceToHost,
                        st);
   if (e == hipSuccess) e = hipStreamSynchronize(st);
-  (void)hipFree(colpart);
+  dfree(colpart);
   if (e != hipSuccess) return fail(YAND_ERR_HIP);
   if (w.hs.nonfinite) return fail(YAND_ERR_NONFINITE);
   D.mbar = stats[0];
@@ -1282,6 +1334,13 @@ int yand_create(const double* R, int64_t T, int64_t n, int64_t ldr,
   D.have_e2 = stats[1] > 1e-300;
   *out = ctx;
   return YAND_OK;
+}
+
+extern "C" {
+
+int yand_create(const double* R, int64_t T, int64_t n, int64_t ldr,
+                int precision, void* hip_stream, yand_ctx** out) {
+  return create_ctx(R, T, n, ldr, precision, hip_stream, false, out);
 }
 
 int yand_shape(yand_ctx* ctx, int64_t* T, int64_t* n, int* precision) {
@@ -1409,10 +1468,12 @@ int yand_kkt_residual(yand_ctx* ctx, const double c[4], const double* w,
 
 // PCG configuration with stall recovery (eager; the Krylov test is on the host).
 static int solve_pcg(yand_ctx* ctx, const double c[4], int p0,
-                     const yand_opts& opts, yand_info& inf, bool* converged) {
+                     const yand_opts& opts, yand_info& inf, bool* converged,
+                     bool* stalled) {
   const Data& D = ctx->d;
   Work& w = ctx->w;
   DirOpts o;
+  o.krylov_tol = opts.krylov_tol;
   o.tau = opts.tau;
   o.simplex = opts.feasible_set == YAND_SET_SIMPLEX;
   o.faces = o.simplex && opts.eta > 0.0 && p0 == 1;
@@ -1443,6 +1504,8 @@ static int solve_pcg(yand_ctx* ctx, const double c[4], int p0,
   *converged = false;
   for (size_t ph = 0; ph < phases.size() && !*converged; ++ph) {
     if (ph > 0) inf.restarts++;
+    *stalled = false;
+    const int it_phase0 = inf.iterations;
     o.solver = phases[ph].solver;
     o.krylov_maxit = phases[ph].kmax;
     o.reg = phases[ph].reg;
@@ -1486,8 +1549,12 @@ static int solve_pcg(yand_ctx* ctx, const double c[4], int p0,
       inf.iterations++;
       const double a = w.hs.alpha, *A = w.hs.coef;
       const double dec = -(a * (A[1] + a * (A[2] + a * (A[3] + a * A[4]))));
+      inf.phase_iterations[ph] = inf.iterations - it_phase0;
       if (dec < 1e-14 * std::fabs(f_prev) && w.hs.nhold <= w.hs.nhold0) {
-        if (++small >= 3) break;
+        if (++small >= 3) {
+          *stalled = true;
+          break;
+        }
       } else {
         small = 0;
       }
@@ -1513,6 +1580,8 @@ static int solve_pcg(yand_ctx* ctx, const double c[4], int p0,
 
 static bool valid_opts(const yand_opts& o) {
   return o.eps >= 0.0 && o.max_iter >= 0 && o.tau >= 0.0 &&
+         o.krylov_tol > 0.0 && std::isfinite(o.krylov_tol) &&
+         !std::isnan(o.max_elapsed) &&
          (o.solver == YAND_SOLVER_DIRECT || o.solver == YAND_SOLVER_PCG) &&
          (o.feasible_set == YAND_SET_BUDGET ||
           o.feasible_set == YAND_SET_SIMPLEX) &&
@@ -1541,9 +1610,9 @@ int yand_mvsk_solve(yand_ctx* ctx, const double c[4], const double* target,
     TRY(check_simplex_start(D, w, opts.tau));
   yand_info inf{};
   int rc = YAND_OK;
-  bool converged = false;
+  bool converged = false, stalled = false;
   if (opts.solver == YAND_SOLVER_PCG) {
-    rc = solve_pcg(ctx, c, p0, opts, inf, &converged);
+    rc = solve_pcg(ctx, c, p0, opts, inf, &converged, &stalled);
   } else {
     DirOpts o;
     o.tau = opts.tau;
@@ -1562,13 +1631,13 @@ int yand_mvsk_solve(yand_ctx* ctx, const double c[4], const double* target,
     if (rc == YAND_OK) {
       inf = L.info;
       converged = L.converged;
+      stalled = L.stalled;
       if (L.rc != YAND_OK) rc = L.rc;
     }
   }
   int status;
   if (rc == YAND_OK) {
-    status = converged ? YAND_OK
-                       : (inf.restarts > 0 ? YAND_WARN_STALL : YAND_WARN_MAXITER);
+    status = finish_status(converged, stalled, inf.restarts);
     HIPTRY(hipMemcpyAsync(w_out, w.x, D.n * sizeof(double),
                           hipMemcpyDeviceToDevice, w.st));
     HIPTRY(hipStreamSynchronize(w.st));
@@ -1669,6 +1738,7 @@ static int batch_solve(int64_t B, yand_ctx* const* ctxs, const double* C4,
     }
     rc = alloc_work(w, big, dev_sc + i);
     if (rc == YAND_OK) rc = ensure_dense(w, big);
+    if (rc == YAND_OK) rc = init_work(w, big);
   }
   for (int64_t start = 0; start < B && rc == YAND_OK; start += nl) {
     const int64_t cnt = std::min(nl, B - start);
@@ -1699,8 +1769,9 @@ static int batch_solve(int64_t B, yand_ctx* const* ctxs, const double* C4,
     for (int64_t i = 0; i < cnt && rc == YAND_OK; ++i) {
       Lane& L = lanes[i];
       const int64_t b = start + i;
-      int st = L.rc != YAND_OK ? L.rc
-                               : (L.converged ? YAND_OK : YAND_WARN_MAXITER);
+      int st = L.rc != YAND_OK
+                   ? L.rc
+                   : finish_status(L.converged, L.stalled, L.info.restarts);
       L.info.status = st;
       if (hipMemcpyAsync(L.w_out, L.w->x, L.D->n * sizeof(double),
                          hipMemcpyDeviceToDevice, cs) != hipSuccess)

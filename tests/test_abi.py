@@ -108,3 +108,4 @@ def test_mlp_entry_points_reject_bad_arguments_without_device(lib):
 def test_autotune_rejects_null_context(lib):
     assert lib.yand_autotune(None, None) == -1
     assert lib.yand_tuning(None, None, None) == -1
+

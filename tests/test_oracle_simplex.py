@@ -162,7 +162,9 @@ def test_eta_zero_keeps_capped_steps():
     R = synth.workload_returns("n12_T500")
     x, info = O.solve(R, [1.0, 1.0, 1.0, 1.0],
                       opts=O.Options(feasible_set="simplex", eta=0.0, max_iter=50))
-    assert info.projected_steps == 0 and info.status == 1
+    # the cap-only run ends at the stall test (three steps without decrease)
+    assert info.projected_steps == 0 and info.status == 2
+    assert info.phases[0][5] == "stall"
 
 
 def test_armijo_step_conditions():
