@@ -47,7 +47,9 @@ enum {
   YAND_ERR_HIP = -3,         /* a HIP runtime call failed                    */
   YAND_ERR_OOM = -4,         /* device allocation failed                     */
   YAND_ERR_INDEFINITE = -5,  /* tangent Hessian indefinite after escalation  */
-  YAND_ERR_UNBOUNDED = -6    /* quartic line model unbounded below           */
+  YAND_ERR_UNBOUNDED = -6,   /* quartic line model unbounded below           */
+  YAND_ERR_TOO_LARGE = -7    /* instance exceeds the fixed scratch array of
+                                yand_mvsk_solve_R_noalloc                    */
 };
 
 /* Storage precision of the centered matrix A inside the context. */
@@ -296,6 +298,25 @@ int yand_tuning(yand_ctx* ctx, const int* set, int* get);
 int yand_mvsk_solve_R(const double* R, int64_t T, int64_t n, double c1,
                       double c2, double c3, double c4, const double* target,
                       double* w_out);
+
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * stateless solve of yand_mvsk_solve_R (same arguments, same kernels, same
+ * results), with every workspace -- the centered copy of A, mu, the pass
+ * partials, the n x n factor buffers -- carved from one fixed 256 MiB device
+ * array that the library holds on each device it runs on until the process
+ * ends.  It calls no hipMalloc, hipFree or other allocating routine and uses
+ * the null stream.  The instance needs about 8 (T n + 3 n^2) bytes plus
+ * 8 MiB per 1024 columns of pass partials (padded to multiples of 128);
+ * larger instances (for example n = 2000 at T = 12000) return
+ * YAND_ERR_TOO_LARGE with a message on stderr, before any device work.
+ * The array keeps the last call's contents and every call clears the part it
+ * uses; calls that overlap on one device (several host threads) race on it
+ * and must be serialised by the caller.  Errors otherwise as
+ * yand_mvsk_solve_R. */
+int yand_mvsk_solve_R_noalloc(const double* R, int64_t T, int64_t n,
+                              double c1, double c2, double c3, double c4,
+                              const double* target, double* w_out);
 
 /* Corollary "coefficient-only convexity certificate": 1 if c4 > 0 and
  * 8 c2 c4 > 3 c3^2, else 0. */

@@ -23,6 +23,7 @@ YAND_WARN_STALL = 2
 ERRORS = {
     -1: "YAND_ERR_ARG", -2: "YAND_ERR_NONFINITE", -3: "YAND_ERR_HIP",
     -4: "YAND_ERR_OOM", -5: "YAND_ERR_INDEFINITE", -6: "YAND_ERR_UNBOUNDED",
+    -7: "YAND_ERR_TOO_LARGE",
 }
 PRECISIONS = {"fp64": 0, "fp32": 1, "bf16": 2}
 SOLVERS = {"direct": 0, "pcg": 1}
@@ -98,6 +99,10 @@ def load(path: str = LIB_PATH):
         "yand_mvsk_solve_R": (C.c_int, [vp, C.c_int64, C.c_int64, C.c_double,
                                         C.c_double, C.c_double, C.c_double,
                                         _D, vp]),
+        "yand_mvsk_solve_R_noalloc": (C.c_int, [vp, C.c_int64, C.c_int64,
+                                                C.c_double, C.c_double,
+                                                C.c_double, C.c_double, _D,
+                                                vp]),
         "yand_is_certified_convex": (C.c_int, [_D]),
         "yand_shape": (C.c_int, [vp, C.POINTER(C.c_int64),
                                  C.POINTER(C.c_int64), C.POINTER(C.c_int)]),
@@ -484,6 +489,24 @@ def solve_R(R, c, target=None):
     rc = lib.yand_mvsk_solve_R(C.c_void_p(R.data_ptr()), T, n, *map(float, c),
                                tg, C.c_void_p(out.data_ptr()))
     _check(rc, "yand_mvsk_solve_R", warn_ok=True)
+    return out
+
+
+def solve_R_noalloc(R, c, target=None, out=None):
+    """yand_mvsk_solve_R_noalloc: the stateless solve with every workspace
+    taken from the library's fixed device array.  R (T x n) and out (n) are
+    the caller's device buffers; out is allocated here only when None."""
+    torch = _torch()
+    lib = load()
+    R = _dev(R)
+    T, n = R.shape
+    if out is None:
+        out = torch.empty(n, dtype=torch.float64, device="cuda")
+    tg = C.byref(C.c_double(float(target))) if target is not None else None
+    rc = lib.yand_mvsk_solve_R_noalloc(C.c_void_p(R.data_ptr()), T, n,
+                                       *map(float, c), tg,
+                                       C.c_void_p(out.data_ptr()))
+    _check(rc, "yand_mvsk_solve_R_noalloc", warn_ok=True)
     return out
 
 

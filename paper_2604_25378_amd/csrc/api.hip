@@ -93,8 +93,28 @@ struct yand_ctx {
 
 namespace {
 
+// Device memory comes from hipMalloc, or, while an Arena is installed on the
+// calling thread (the allocation-free entry point), from a bump allocator
+// over the library's fixed scratch array: 256-byte aligned, never freed
+// individually, YAND_ERR_TOO_LARGE once the array is exhausted.
+struct Arena {
+  char* base = nullptr;
+  size_t cap = 0, used = 0;
+};
+thread_local Arena* g_arena = nullptr;
+
 int alloc(void** p, size_t bytes) {
   if (bytes < 256) bytes = 256;
+  if (g_arena) {
+    const size_t off = (g_arena->used + 255) & ~(size_t)255;
+    if (off > g_arena->cap || bytes > g_arena->cap - off) {
+      *p = nullptr;
+      return YAND_ERR_TOO_LARGE;
+    }
+    *p = g_arena->base + off;
+    g_arena->used = off + bytes;
+    return YAND_OK;
+  }
   if (hipMalloc(p, bytes) != hipSuccess) {
     (void)hipGetLastError();
     *p = nullptr;
@@ -103,9 +123,13 @@ int alloc(void** p, size_t bytes) {
   return YAND_OK;
 }
 
-// Frees what alloc returned.
+// Frees what alloc returned (arena memory is left to the arena).
 void dfree(void* p) {
-  if (p) (void)hipFree(p);
+  if (!p) return;
+  if (g_arena && (char*)p >= g_arena->base &&
+      (char*)p < g_arena->base + g_arena->cap)
+    return;
+  (void)hipFree(p);
 }
 
 #define TRY(expr)                   \
@@ -1262,7 +1286,8 @@ int yand_destroy(yand_ctx* ctx) {
 // Context creation.  All device memory is taken before the first kernel, so
 // an allocation failure leaves nothing enqueued; with dense_upfront the n x n
 // buffers of the direct configuration are taken here too instead of at the
-// first direction.
+// first direction.  Memory taken from an arena is cleared first (it holds
+// the previous call's contents).
 static int create_ctx(const double* R, int64_t T, int64_t n, int64_t ldr,
                       int precision, void* hip_stream, bool dense_upfront,
                       yand_ctx** out) {
@@ -1304,6 +1329,10 @@ static int create_ctx(const double* R, int64_t T, int64_t n, int64_t ldr,
   if ((rc = alloc((void**)&colpart, (size_t)nchunks * n * sizeof(double))))
     return fail(rc);
   if (dense_upfront && (rc = ensure_dense(w, D))) return fail(rc);
+  if (g_arena &&
+      launch_fill((double*)g_arena->base, (int64_t)(g_arena->used / 8), 0.0,
+                  st) != hipSuccess)
+    return fail(YAND_ERR_HIP);
   if (init_work(w, D) != YAND_OK) return fail(YAND_ERR_HIP);
   hipError_t e = launch_center(R, T, n, ldr, precision, D.A, D.Tp, D.lda,
                                D.mu, colpart, &w.sc->nonfinite, st);
@@ -2197,6 +2226,109 @@ int yand_tuning(yand_ctx* ctx, const int* set, int* get) {
     get[6] = D.chol_group;
   }
   return YAND_OK;
+}
+
+// ------------------------------------------------ allocation-free solve --
+
+}  // extern "C"
+
+namespace {
+
+// Device workspace of yand_mvsk_solve_R_noalloc: one fixed array per device,
+// held until the process ends.  Host code never uses the array's name as an
+// address: each device's copy is looked up once with hipGetSymbolAddress.
+constexpr size_t kScratchBytes = (size_t)256 << 20;
+__device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+int scratch_ptr(void** out) {
+  int dev = 0;
+  HIPTRY(hipGetDevice(&dev));
+  if (dev < 0 || dev >= kMaxDevices) return YAND_ERR_ARG;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    HIPTRY(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+    if (!p) return YAND_ERR_HIP;
+    g_scratch_ptr[dev] = p;
+  }
+  *out = g_scratch_ptr[dev];
+  return YAND_OK;
+}
+
+// Bytes create_ctx (FP64, n x n buffers up front) takes from an arena: the
+// same requests in the same order, each rounded up to 256 bytes.
+size_t noalloc_need(int64_t T, int64_t n) {
+  const size_t Tp = (size_t)round_up(T, kRowPad),
+               lda = (size_t)round_up(n, kColPad), nt = lda / kTile;
+  const size_t nb = lda * 8, tb = Tp * 8;
+  size_t used = 0;
+  auto take = [&](size_t b, int k = 1) {
+    for (int i = 0; i < k; ++i)
+      used = ((used + 255) & ~(size_t)255) + (b < 256 ? 256 : b);
+  };
+  take(Tp * lda * 8);                    // A
+  take(nb);                              // mu
+  take(2 * nb);                          // Efix
+  take(2 * tb);                          // AEfix
+  take(nb, 3);                           // x, g, d
+  take(tb, 3);                           // z, wv, q
+  take(3 * tb);                          // AE
+  take(3 * nb, 2);                       // E, W
+  take(nb, 5);                           // t3, r, y, y2, hv
+  take(tb);                              // s_t
+  take(nb, 4);                           // PCG vectors
+  take(nb, 3);                           // mask, ptmp, hold
+  take((size_t)kMaxPassGroups * lda * 8);       // pass partials
+  take((size_t)kMaxPassGroups * kMaxSums * 8);  // scalar partials
+  take((size_t)kMaxSums * 8);                   // sums
+  take((size_t)((n + 63) / 64) * n * 8);        // trmv partials
+  take(sizeof(DevScalars));
+  take((size_t)((T + 255) / 256) * n * 8);      // column-sum partials
+  take(lda * lda * 8, 3);                       // B, M, X
+  take(nt * Tp * 8);                            // trace row norms
+  return used;
+}
+
+struct ArenaScope {
+  explicit ArenaScope(Arena* a) { g_arena = a; }
+  ~ArenaScope() { g_arena = nullptr; }
+};
+
+}  // namespace
+
+extern "C" {
+
+int yand_mvsk_solve_R_noalloc(const double* R, int64_t T, int64_t n,
+                              double c1, double c2, double c3, double c4,
+                              const double* target, double* w_out) {
+  if (!R || !w_out || T < 2 || n < 2) return YAND_ERR_ARG;
+  if (n > max_pass_columns(YAND_FP64) ||
+      noalloc_need(T, n) > kScratchBytes) {
+    fprintf(stderr,
+            "libyand: yand_mvsk_solve_R_noalloc: T=%lld n=%lld needs %zu "
+            "bytes of workspace; the scratch array holds %zu\n",
+            (long long)T, (long long)n,
+            n > max_pass_columns(YAND_FP64) ? (size_t)0 : noalloc_need(T, n),
+            kScratchBytes);
+    return YAND_ERR_TOO_LARGE;
+  }
+  void* base = nullptr;
+  TRY(scratch_ptr(&base));
+  Arena arena;
+  arena.base = (char*)base;
+  arena.cap = kScratchBytes;
+  ArenaScope scope(&arena);
+  yand_ctx* ctx = nullptr;
+  int rc = create_ctx(R, T, n, n, YAND_FP64, nullptr, true, &ctx);
+  if (rc) return rc;
+  const double c[4] = {c1, c2, c3, c4};
+  rc = yand_mvsk_solve(ctx, c, target, nullptr, nullptr, w_out, nullptr);
+  yand_destroy(ctx);
+  return rc;
 }
 
 int yand_profile_enable(yand_ctx* ctx, int enable) {

@@ -109,3 +109,14 @@ def test_autotune_rejects_null_context(lib):
     assert lib.yand_autotune(None, None) == -1
     assert lib.yand_tuning(None, None, None) == -1
 
+
+def test_noalloc_refuses_oversized_instances_without_device(lib):
+    """The allocation-free solve checks the instance against its fixed
+    scratch array before any device call or read of R."""
+    out = C.c_void_p(16)
+    R = C.c_void_p(16)
+    rc = lib.yand_mvsk_solve_R_noalloc(R, 12000, 2000, 1.0, 1.0, 1.0, 1.0,
+                                       None, out)
+    assert rc == -7
+    assert lib.yand_mvsk_solve_R_noalloc(None, 500, 12, 1.0, 1.0, 1.0, 1.0,
+                                         None, out) == -1
