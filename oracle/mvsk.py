@@ -39,7 +39,7 @@ __all__ = [
     "linesearch_coeffs", "alpha_max", "quartic_value", "select_step",
     "Options", "SolveInfo", "solve", "certified_convex", "Unbounded",
     "Indefinite", "project_simplex", "kkt_residual", "face_free",
-    "face_basis", "armijo_step", "return_floor",
+    "face_basis", "armijo_step", "return_floor", "splitmix64", "rademacher",
 ]
 
 
@@ -192,6 +192,42 @@ class Direction:
     a: np.ndarray            # log-det correction (reduced, length m-1)
     u: np.ndarray            # tangential coefficients
     cg_iters: int = 0
+    q: np.ndarray | None = None   # q_t (exact, or the probe estimate)
+    probe_iters: int = 0          # CG iterations of the probe solves
+
+
+# ---------------------------------------------------------------------------
+# Counter-based random signs for the probe estimate of the trace.
+# ---------------------------------------------------------------------------
+
+_SM_GAMMA = 0x9E3779B97F4A7C15
+_SM_M1 = 0xBF58476D1CE4E5B9
+_SM_M2 = 0x94D049BB133111EB
+
+
+def splitmix64(state):
+    """Output of the SplitMix64 generator (Steele, Lea and Flood, 2014) for
+    Weyl states ``state`` (uint64 array): the state advanced by the golden
+    gamma and passed through the variant-13 finaliser."""
+    z = np.asarray(state, dtype=np.uint64) + np.uint64(_SM_GAMMA)
+    z = (z ^ (z >> np.uint64(30))) * np.uint64(_SM_M1)
+    z = (z ^ (z >> np.uint64(27))) * np.uint64(_SM_M2)
+    return z ^ (z >> np.uint64(31))
+
+
+def rademacher(seed, draw, T, k):
+    """T x k matrix of independent signs xi_tj = +-1 for the draw-th probe
+    block of a solve: the sign bit of SplitMix64 at the counter
+    seed + gamma * (draw 2^42 + t 2^10 + j), t < 2^32, j < 2^10."""
+    if not (0 < k <= 1024 and T < (1 << 32) and 0 <= draw < (1 << 22)):
+        raise ValueError("probe counter out of range")
+    t = np.arange(T, dtype=np.uint64)[:, None]
+    j = np.arange(k, dtype=np.uint64)[None, :]
+    ctr = (np.uint64(draw) << np.uint64(42)) | (t << np.uint64(10)) | j
+    with np.errstate(over="ignore"):
+        st = np.uint64(seed) + ctr * np.uint64(_SM_GAMMA)
+        bits = splitmix64(st) >> np.uint64(63)
+    return 1.0 - 2.0 * bits.astype(np.float64)
 
 
 def _pcg(Bmat, rhs, tol, maxit, precond):
@@ -213,10 +249,15 @@ def _pcg(Bmat, rhs, tol, maxit, precond):
     it = 0
     while it < maxit:
         Bp = Bmat @ p
-        alpha = rz / (p @ Bp)
+        pBp = p @ Bp
+        it += 1
+        if not pBp > 0.0:
+            # a direction of non-positive curvature ends the iteration
+            # without a step along it (truncated CG, Steihaug 1983)
+            break
+        alpha = rz / pBp
         u += alpha * p
         r -= alpha * Bp
-        it += 1
         if np.linalg.norm(r) <= tol * r0:
             break
         zv = precond(r)
@@ -227,7 +268,8 @@ def _pcg(Bmat, rhs, tol, maxit, precond):
 
 
 def affine_normal(A, mu, c, x, U, *, solver="direct", reg=0.0,
-                  krylov_tol=1e-3, krylov_maxit=15, max_escalations=16):
+                  krylov_tol=1e-3, krylov_maxit=15, max_escalations=16,
+                  trace="exact", probes=64, seed=0, draw=0):
     """Exact-trace affine-normal direction in reduced coordinates.
 
     Section 4.2 and Section 4.4: with gbar = U^T g, nu = gbar/|gbar|, the
@@ -248,6 +290,13 @@ def affine_normal(A, mu, c, x, U, *, solver="direct", reg=0.0,
     trace and solves for u by ``_pcg``, preconditioned by the Jacobi inverse
     of the ambient Hessian diagonal (plus lam) restricted to the reduced
     space.
+
+    trace = "probe" (PCG solver only) replaces the exact q by Hutchinson's
+    estimate of the diagonal of P H_{T,lam}^{-1} P^T (Appendix C, the
+    Krylov reduced solve): with the T x k sign matrix Xi = rademacher(seed,
+    draw, T, k), y_j solves H_{T,lam} y_j = P^T xi_j by the same PCG
+    (tolerance, budget, preconditioner) and q_t = k^-1 sum_j xi_tj (P y_j)_t.
+    No factorisation is formed.
     """
     T = A.shape[0]
     m = U.shape[1]
@@ -266,6 +315,30 @@ def affine_normal(A, mu, c, x, U, *, solver="direct", reg=0.0,
     B0 = P.T @ (D2[:, None] * P) / T
     scale = np.trace(B0) / (m - 1)
     lam = reg * scale
+    if trace == "probe":
+        if solver != "pcg":
+            raise ValueError("the probe trace needs the PCG solver")
+        Bm = B0 + lam * np.eye(m - 1)
+        dj = np.sum(A * A * (D2 / T)[:, None], axis=0) + lam
+        dj = np.where(dj > 0.0, dj, 1.0)
+        prec = lambda r: V.T @ ((V @ r) / dj)  # noqa: E731
+        Xi = rademacher(seed, draw, T, probes)
+        Yp = np.empty((m - 1, probes))
+        pit = 0
+        for j in range(probes):
+            Yp[:, j], it_j = _pcg(Bm, P.T @ Xi[:, j], krylov_tol,
+                                  krylov_maxit, prec)
+            pit += it_j
+        q = np.mean(Xi * (P @ Yp), axis=1)
+        a = P.T @ (d3psi(c, z) * q) / T
+        h = V.T @ hvp(A, c, x, U @ nu)
+        rhs = h - gn / (m + 1) * a
+        u, cg_iters = _pcg(Bm, rhs, krylov_tol, krylov_maxit, prec)
+        dy = Q @ u - nu
+        return Direction(d=U @ dy, gnorm=gn, lam=lam, a=a, u=u,
+                         cg_iters=cg_iters, q=q, probe_iters=pit)
+    elif trace != "exact":
+        raise ValueError(trace)
     for _ in range(max_escalations + 1):
         Bm = B0 + lam * np.eye(m - 1)
         try:
@@ -293,7 +366,8 @@ def affine_normal(A, mu, c, x, U, *, solver="direct", reg=0.0,
     else:
         raise ValueError(solver)
     dy = Q @ u - nu
-    return Direction(d=U @ dy, gnorm=gn, lam=lam, a=a, u=u, cg_iters=cg_iters)
+    return Direction(d=U @ dy, gnorm=gn, lam=lam, a=a, u=u, cg_iters=cg_iters,
+                     q=q)
 
 
 # ---------------------------------------------------------------------------
@@ -471,6 +545,9 @@ class Options:
     eta: nominal projected trial step of the boundary block (0.05 in Table
     'YAND-MVSK parameter settings'); 0 keeps the capped raw step only.
     linesearch: 'exact' (quartic exact rule) or 'armijo' (armijo_step).
+    trace: 'exact' or 'probe' (PCG phases only: Hutchinson's estimate of q
+    from ``probes`` random sign vectors per direction, drawn from
+    rademacher(probe_seed, direction index of the solve, ...)).
     """
     solver: str = "direct"
     feasible_set: str = "budget"
@@ -485,6 +562,9 @@ class Options:
     linesearch: str = "exact"
     stall_recovery: bool = True
     restart_max_iter: int = 120
+    trace: str = "exact"
+    probes: int = 64
+    probe_seed: int = 0
 
     @staticmethod
     def large():
@@ -506,6 +586,8 @@ class SolveInfo:
     projected_steps: int = 0
     history: list = field(default_factory=list)
     phases: list = field(default_factory=list)
+    directions: int = 0
+    probe_iters: int = 0
 
 
 # A projected segment whose line search moves less than this fraction of it
@@ -579,8 +661,13 @@ def _iterate(A, mu, c, x, U, opts: Options, solver, krylov_maxit, max_iter,
         reg = opts.reg if solver == "pcg" else 0.0
         dr = affine_normal(A, mu, c, x, Ui, solver=solver, reg=reg,
                            krylov_tol=opts.krylov_tol,
-                           krylov_maxit=krylov_maxit)
+                           krylov_maxit=krylov_maxit,
+                           trace=opts.trace if solver == "pcg" else "exact",
+                           probes=opts.probes, seed=opts.probe_seed,
+                           draw=info.directions)
+        info.directions += 1
         info.cg_iters += dr.cg_iters
+        info.probe_iters += dr.probe_iters
         d = dr.d
         amax = alpha_max(x, d, opts.tau) if simplex else math.inf
         rule = armijo_step if opts.linesearch == "armijo" else select_step
@@ -634,7 +721,8 @@ def _iterate(A, mu, c, x, U, opts: Options, solver, krylov_maxit, max_iter,
     return x, conv, "converged" if conv else reason
 
 
-def solve(R, c, target=None, x0=None, opts: Options | None = None):
+def solve(R, c, target=None, x0=None, opts: Options | None = None,
+          centered=None):
     """Algorithm 1 (YAND-MVSK) in FP64 with explicit reduced bases.
 
     Stall recovery (reading of the 'stall-recovery restarts' of Table
@@ -650,10 +738,12 @@ def solve(R, c, target=None, x0=None, opts: Options | None = None):
     time budget ended above eps without a restart.
     info.phases lists each phase as (solver, krylov_maxit, max_iter, eta,
     iterations, reason).
+    centered: an optional (mu, A) used in place of center(R), for instance A
+    rounded to a storage precision (the problem such a store defines).
     """
     opts = opts or Options()
     c = np.asarray(c, dtype=np.float64)
-    mu, A = center(R)
+    mu, A = center(R) if centered is None else centered
     C, b = constraints(mu, target)
     x = feasible_start(C, b, x0)
     if opts.feasible_set == "simplex" and np.any(x < opts.tau):
