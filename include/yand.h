@@ -94,6 +94,13 @@ typedef struct yand_opts {
                              step (0.05; 0 = capped raw steps only).  Active
                              on YAND_SET_SIMPLEX without a return target.    */
   int linesearch;         /* YAND_LS_EXACT (default) or YAND_LS_ARMIJO        */
+  int dense_fp64;         /* FP32 / BF16 storage of A: 0 (default) forms the
+                             exact trace's products (B = A^T diag(psi'') A / T
+                             and the rows of L^-1 A^T) on the matrix cores
+                             with FP32 / BF16 inputs and FP32 accumulation;
+                             1 forms them in FP64.  The factorisation, the
+                             passes' reductions, the line-search sums and
+                             the PCG inner products are FP64 either way.     */
 } yand_opts;
 
 /* Per-solve report: counters follow the oracle-query accounting of the

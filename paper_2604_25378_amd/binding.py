@@ -44,7 +44,7 @@ class yand_opts(C.Structure):
                 ("krylov_tol", C.c_double), ("krylov_maxit", C.c_int),
                 ("tau", C.c_double), ("stall_recovery", C.c_int),
                 ("restart_max_iter", C.c_int), ("eta", C.c_double),
-                ("linesearch", C.c_int)]
+                ("linesearch", C.c_int), ("dense_fp64", C.c_int)]
 
 
 class yand_info(C.Structure):

@@ -48,6 +48,7 @@ struct Data {
   int64_t T = 0, n = 0, Tp = 0, lda = 0, nt = 0;
   size_t esize = 8;
   void* A = nullptr;
+  void* At = nullptr;       // A^T at the storage precision (FP32 / BF16 only)
   double* mu = nullptr;
   double* Efix = nullptr;   // 2 x n: e1 = 1/sqrt(n), e2 = unit centred mu
   double* AEfix = nullptr;  // 2 x Tp: A e1, A e2
@@ -70,6 +71,8 @@ struct Work {
   double *part = nullptr, *psums = nullptr, *sums = nullptr,
          *trpart = nullptr;
   double *B = nullptr, *M = nullptr, *X = nullptr, *rn = nullptr;
+  // FP32 / BF16 storage: s-scaled A^T and X rounded for the matrix cores
+  void *SAt = nullptr, *Xl = nullptr;
   double *mask = nullptr, *ptmp = nullptr;  // face mask, projection scratch
   double* hold = nullptr;  // coordinates the face solver holds at the bound
   // T < n push-through trace: Gram partials, G, C, L^-1 of C, diag(B)
@@ -204,6 +207,8 @@ void free_work(Work& w) {
                     w.hold,  w.tGp,    w.tG,    w.tC,     w.tX,   w.bdiag,
                     w.tpart};
   for (double* p : ptrs) dfree(p);
+  dfree(w.SAt);
+  dfree(w.Xl);
   if (w.sc && w.own_sc) dfree(w.sc);
   if (w.st && w.own_stream) (void)hipStreamDestroy(w.st);
   w = Work{};
@@ -283,6 +288,11 @@ int ensure_dense(Work& w, const Data& D) {
   TRY(alloc((void**)&w.M, nn));
   TRY(alloc((void**)&w.X, nn));
   TRY(alloc((void**)&w.rn, (size_t)D.nt * D.Tp * sizeof(double)));
+  if (D.precision != YAND_FP64) {
+    // FP32: one rounded copy; BF16: high and low parts (4 bytes either way)
+    TRY(alloc(&w.SAt, (size_t)D.lda * D.Tp * 4));
+    TRY(alloc(&w.Xl, (size_t)D.lda * D.lda * 4));
+  }
   return YAND_OK;
 }
 
@@ -396,6 +406,9 @@ struct DirOpts {
   bool faces = false;
   double eta = 0.0;
   int select = 1;  // step rule for line_at: 1 exact quartic, 2 Armijo
+  // FP32 / BF16 storage: products of the exact trace in FP64 instead of on
+  // the storage precision's matrix cores
+  bool dense64 = false;
 };
 
 const double* face_mask(const Work& w, const DirOpts& o) {
@@ -453,9 +466,15 @@ int dir_front(const Data& D, Work& w, const double c[4], int p0,
   hipLaunchKernelGGL(psi2_weight_kernel, dim3((unsigned)((Tp + 255) / 256)),
                      dim3(256), 0, w.st, w.z, Tp, to_coef(c),
                      1.0 / (double)D.T, w.s_t, skip);
-  HIPTRY(timed(w, "syrk", [&] {
-    return launch_syrk(D.precision, D.A, D.lda, Tp, w.s_t, w.B, w.st, skip);
-  }));
+  if (D.precision != YAND_FP64 && !o.dense64)
+    HIPTRY(timed(w, "syrk", [&] {
+      return launch_syrk_lp(D.precision, D.At, w.SAt, np, Tp, w.s_t, w.B,
+                            w.st, skip);
+    }));
+  else
+    HIPTRY(timed(w, "syrk", [&] {
+      return launch_syrk(D.precision, D.A, D.lda, Tp, w.s_t, w.B, w.st, skip);
+    }));
   HIPTRY(launch_symm_multi(w.B, np, n, w.E, p, w.W, w.st, skip));
   HIPTRY(launch_trace_scale(w.B, np, n, w.E, w.W, p, o.reg, w.sc, w.st,
                             face_mask(w, o)));
@@ -477,13 +496,20 @@ int dir_factor(const Data& D, Work& w, int p0, const int* skip,
 
 // Exact trace q, third-order back-projection t3 and r = P_S(B nu - |G|/(m+1) t3).
 int dir_trace(const Data& D, Work& w, const double c[4], int p0,
-              const int* skip, const double* mask = nullptr) {
+              const DirOpts& o, const int* skip,
+              const double* mask = nullptr) {
   const int64_t n = D.n, np = D.lda, Tp = D.Tp;
   const int p = p0 + 1;
-  HIPTRY(timed(w, "trace_gemm", [&] {
-    return launch_trace_gemm(D.precision, D.A, D.lda, Tp, w.X, np, w.rn, w.st,
-                             skip);
-  }));
+  if (D.precision != YAND_FP64 && !o.dense64)
+    HIPTRY(timed(w, "trace_gemm", [&] {
+      return launch_trace_lp(D.precision, D.A, D.lda, Tp, w.X, np, w.Xl, w.rn,
+                             w.st, skip);
+    }));
+  else
+    HIPTRY(timed(w, "trace_gemm", [&] {
+      return launch_trace_gemm(D.precision, D.A, D.lda, Tp, w.X, np, w.rn,
+                               w.st, skip);
+    }));
   if (mask) {
     // the face's frame column E[0] = mask / sqrt(nfree): A E[0] afresh
     PassArgs a = pass_args(D, w, c);
@@ -785,7 +811,7 @@ int direction_eager(const Data& D, Work& w, const double c[4], int p0,
                        lam);
     if (stats) stats->escalations++;
   }
-  TRY(dir_trace(D, w, c, p0, nullptr, face_mask(w, o)));
+  TRY(dir_trace(D, w, c, p0, o, nullptr, face_mask(w, o)));
   if (o.solver == YAND_SOLVER_DIRECT)
     return dir_direct_solve(D, w, p0, x, o, d, nullptr);
   return dir_pcg_solve(D, w, c, p0, x, o, d, stats, w.B, D.lda + 1);
@@ -816,7 +842,7 @@ int enqueue_iteration(const Data& D, Work& w, const double c[4], int p0,
   TRY(stationarity(D, w, o, p0, eps));
   TRY(dir_front(D, w, c, p0, o, skip));
   TRY(dir_factor(D, w, p0, skip, face_mask(w, o)));
-  TRY(dir_trace(D, w, c, p0, skip, face_mask(w, o)));
+  TRY(dir_trace(D, w, c, p0, o, skip, face_mask(w, o)));
   TRY(dir_direct_solve(D, w, p0, w.x, o, w.d, skip));
   TRY(step_line(D, w, c, o, skip));
   HIPTRY(launch_axpy(w.x, w.d, D.n, w.sc, w.st));
@@ -1255,6 +1281,7 @@ void yand_default_opts(yand_opts* o) {
   o->restart_max_iter = 120;
   o->eta = 0.05;
   o->linesearch = YAND_LS_EXACT;
+  o->dense_fp64 = 0;
 }
 
 void yand_large_opts(yand_opts* o) {
@@ -1275,7 +1302,7 @@ int yand_destroy(yand_ctx* ctx) {
   if (!ctx) return YAND_OK;
   flush_timed(ctx->prof, ctx->w.st);
   free_work(ctx->w);
-  void* ptrs[] = {ctx->d.A, ctx->d.mu, ctx->d.Efix, ctx->d.AEfix};
+  void* ptrs[] = {ctx->d.A, ctx->d.At, ctx->d.mu, ctx->d.Efix, ctx->d.AEfix};
   for (void* p : ptrs) dfree(p);
   delete ctx;
   return YAND_OK;
@@ -1318,6 +1345,8 @@ static int create_ctx(const double* R, int64_t T, int64_t n, int64_t ldr,
   const size_t nb = (size_t)D.lda * sizeof(double),
                tb = (size_t)D.Tp * sizeof(double);
   if ((rc = alloc(&D.A, (size_t)D.Tp * D.lda * D.esize)) ||
+      (precision != YAND_FP64 &&
+       (rc = alloc(&D.At, (size_t)D.Tp * D.lda * D.esize))) ||
       (rc = alloc((void**)&D.mu, nb)) ||
       (rc = alloc((void**)&D.Efix, 2 * nb)) ||
       (rc = alloc((void**)&D.AEfix, 2 * tb)))
@@ -1336,6 +1365,8 @@ static int create_ctx(const double* R, int64_t T, int64_t n, int64_t ldr,
   if (init_work(w, D) != YAND_OK) return fail(YAND_ERR_HIP);
   hipError_t e = launch_center(R, T, n, ldr, precision, D.A, D.Tp, D.lda,
                                D.mu, colpart, &w.sc->nonfinite, st);
+  if (e == hipSuccess && precision != YAND_FP64)
+    e = launch_transpose_lp(precision, D.A, D.lda, D.Tp, D.At, st);
   if (e == hipSuccess) {
     hipLaunchKernelGGL(efix_kernel, dim3(1), dim3(PT), 0, st, D.mu, n, D.Efix,
                        w.sums);
@@ -1463,6 +1494,7 @@ int yand_affine_normal(yand_ctx* ctx, const double c[4], const double* target,
     o.krylov_tol = opts->krylov_tol;
     o.krylov_maxit = opts->krylov_maxit;
     o.tau = opts->tau;
+    o.dense64 = opts->dense_fp64 != 0;
   }
   TRY(oracle_at(ctx->d, W, c, w, true));
   HIPTRY(launch_grad_project(W.g, W.E, p0, ctx->d.n, W.sc, W.st));
@@ -1504,6 +1536,7 @@ static int solve_pcg(yand_ctx* ctx, const double c[4], int p0,
   DirOpts o;
   o.krylov_tol = opts.krylov_tol;
   o.tau = opts.tau;
+  o.dense64 = opts.dense_fp64 != 0;
   o.simplex = opts.feasible_set == YAND_SET_SIMPLEX;
   o.faces = o.simplex && opts.eta > 0.0 && p0 == 1;
   o.select = opts.linesearch == YAND_LS_ARMIJO ? 2 : 1;
@@ -1645,6 +1678,7 @@ int yand_mvsk_solve(yand_ctx* ctx, const double c[4], const double* target,
   } else {
     DirOpts o;
     o.tau = opts.tau;
+    o.dense64 = opts.dense_fp64 != 0;
     o.simplex = opts.feasible_set == YAND_SET_SIMPLEX;
     o.faces = o.simplex && opts.eta > 0.0 && p0 == 1;
     o.eta = opts.eta;
@@ -1715,6 +1749,7 @@ static int batch_solve(int64_t B, yand_ctx* const* ctxs, const double* C4,
   HIPTRY(hipStreamWaitEvent(cs, ev_in, 0));
   DirOpts o;
   o.tau = opts.tau;
+  o.dense64 = opts.dense_fp64 != 0;
   o.simplex = opts.feasible_set == YAND_SET_SIMPLEX;
   o.faces = o.simplex && opts.eta > 0.0 && !targets;
   o.eta = opts.eta;
@@ -1728,6 +1763,8 @@ static int batch_solve(int64_t B, yand_ctx* const* ctxs, const double* C4,
     size_t need = 3 * (size_t)D.lda * D.lda * 8 + (size_t)D.nt * D.Tp * 8 +
                   (size_t)kMaxPassGroups * D.lda * 8 + 12 * (size_t)D.Tp * 8 +
                   24 * (size_t)D.lda * 8 + (size_t)((D.n + 63) / 64) * D.n * 8;
+    if (D.precision != YAND_FP64)
+      need += ((size_t)D.Tp + D.lda) * D.lda * 4;
     per_lane = std::max(per_lane, need);
   }
   int64_t nl = std::min<int64_t>(B, max_lanes > 0 ? max_lanes : 64);
@@ -1752,6 +1789,12 @@ static int batch_solve(int64_t B, yand_ctx* const* ctxs, const double* C4,
     big.lda = std::max(big.lda, D.lda);
     big.Tp = std::max(big.Tp, D.Tp);
     big.nt = std::max(big.nt, D.nt);
+    // matrix-core scratch for any FP32 / BF16 context, sized for the widest
+    if (D.precision != YAND_FP64 &&
+        (big.precision == YAND_FP64 || D.esize > big.esize)) {
+      big.precision = D.precision;
+      big.esize = D.esize;
+    }
   }
   int rc = YAND_OK;
   for (int64_t i = 0; i < nl && rc == YAND_OK; ++i) {

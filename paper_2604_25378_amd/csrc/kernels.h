@@ -101,6 +101,37 @@ hipError_t launch_trace_gemm(int precision, const void* A, int64_t lda,
                              int64_t Tp, const double* X, int64_t np,
                              double* rn, hipStream_t st,
                              const int* skip = nullptr);
+// ---- FP32 / BF16 matrix-core variants (lowp.hip), precision 1 or 2 ------
+// At (lda x Tp) = A^T at the storage precision.
+hipError_t launch_transpose_lp(int precision, const void* A, int64_t lda,
+                               int64_t Tp, void* At, hipStream_t st);
+// B = A^T diag(s) A from At: SAt (np x Tp x 4 bytes scratch) = s-scaled At
+// (BF16: high and low parts), then FP32-accumulated products; B (np x np,
+// FP64) exactly symmetric.
+hipError_t launch_syrk_lp(int precision, const void* At, void* SAt,
+                          int64_t np, int64_t Tp, const double* s, double* B,
+                          hipStream_t st, const int* skip = nullptr);
+// rn as launch_trace_gemm from X rounded into Xl (np x np x 4 bytes
+// scratch; BF16: high and low parts).
+hipError_t launch_trace_lp(int precision, const void* A, int64_t lda,
+                           int64_t Tp, const double* X, int64_t np, void* Xl,
+                           double* rn, hipStream_t st,
+                           const int* skip = nullptr);
+// ---- block passes (dense.hip): kb <= 64 vectors at once -----------------
+constexpr int kBlockWidth = 64;
+// Split counts of the two block products for this shape: *sv splits of the
+// n-side reduction of Z = A V, *sz of the T-side one of A^T Z.  Partial
+// slabs: sv x Tp x 64 and sz x 64 x lda doubles.
+int block_splits(int64_t Tp, int64_t lda, int* sv, int* sz);
+// Z (Tp x 64, row-major) = A V, V 64 x lda (row j = vector j); Zp partials.
+hipError_t launch_block_av(int precision, const void* A, int64_t lda,
+                           int64_t Tp, const double* V, double* Zp, double* Z,
+                           hipStream_t st, const int* skip = nullptr);
+// Y (64 x lda, row j = vector j) = (A^T diag(s) Z)^T (s nullable = 1).
+hipError_t launch_block_atz(int precision, const void* A, int64_t lda,
+                            int64_t Tp, const double* Z, const double* s,
+                            double* Yp, double* Y, hipStream_t st,
+                            const int* skip = nullptr);
 // y = X v (lower), y = X^T v (transposed); X is np x np.  part holds
 // ceil(n/64) * n doubles of partial sums for the transposed product.
 hipError_t launch_trmv(const double* X, int64_t np, int64_t n,
