@@ -174,6 +174,51 @@ def ragged_bench(count=32, T=6000, precision="fp64", autotune=True):
 OUTCOME = {0: "converged", 1: "iteration budget", 2: "stalled"}
 
 
+def probe_bench(workload="n5440_T12000", probes=64, seed=0):
+    """PCG configuration (budget set, from equal weights) with the exact
+    trace against the probe estimate (k sign vectors per direction, block
+    PCG on the matrix cores): seconds per solve and per outer iteration,
+    iterations, Krylov counts and the objective gap between the two
+    minimisers."""
+    import torch
+
+    import synth
+    from paper_2604_25378_amd import binding as yb
+
+    log(f"probe trace: {workload}")
+    R = synth.workload_returns(workload)
+    T, n = R.shape
+    c = np.array(synth.WORKLOADS[workload]["c"])
+    ctx = yb.Context(torch.from_numpy(R).cuda(), "fp64")
+    rows = {}
+    res = {}
+    for mode in ("exact", "probe"):
+        opts = yb.default_opts(large=True, trace_mode=mode, probes=probes,
+                               probe_seed=seed)
+        ctx.solve(c, opts=yb.default_opts(large=True, trace_mode=mode,
+                                          probes=probes, max_iter=1))
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        w, info = ctx.solve(c, opts=opts)
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        f, _, _ = ctx.eval(c, w, grad=False)
+        res[mode] = f
+        rows[mode] = {"solve_s": el, "iterations": info.iterations,
+                      "ms_per_iteration": 1e3 * el / max(info.iterations, 1),
+                      "cg_iters": info.cg_iters,
+                      "probe_cg_iters": info.probe_cg_iters,
+                      "outcome": OUTCOME.get(info.status, str(info.status)),
+                      "gnorm": info.gnorm, "f": f}
+    ctx.close()
+    return {"workload": f"{workload}: n={n} T={T}, c={tuple(c)}, budget set, "
+                        f"PCG configuration, {probes} probes",
+            **rows,
+            "objective_rel_gap": abs(res["probe"] - res["exact"]) / abs(res["exact"]),
+            "iteration_speedup": rows["exact"]["ms_per_iteration"]
+                                 / rows["probe"]["ms_per_iteration"]}
+
+
 def precision_bench(reps=3):
     """Single solves on the two single-solve workloads in each storage
     precision of A (FP32 and BF16 form the exact trace's products on the
@@ -637,6 +682,10 @@ def main():
     ap.add_argument("--frontier-points", type=int, default=256)
     ap.add_argument("--no-autotune", action="store_true",
                     help="keep the built-in launch shapes")
+    ap.add_argument("--only", default=None,
+                    help="run the headline step and this one block only "
+                         "(frontier, simplex, conditioning, line_search, "
+                         "return_floor, regime, precision, probe)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="end with one 1 GiB device copy (PMC scale reference)")
     args = ap.parse_args()
@@ -807,7 +856,15 @@ def main():
     }
     ctx.close()
     del ctx
-    if not args.no_frontier:
+    blocks = {"precision": precision_bench, "probe": probe_bench,
+              "simplex": lambda: simplex_bench(args.precision),
+              "conditioning": lambda: conditioning_bench(args.precision),
+              "line_search": lambda: line_search_bench(args.precision),
+              "return_floor": lambda: return_floor_bench(args.precision),
+              "regime": lambda: regime_bench(args.precision)}
+    if args.only and args.only != "frontier":
+        out[args.only] = blocks[args.only]()
+    elif not args.no_frontier:
         tune = not args.no_autotune
         fr = {"n1000_T12000": frontier_bench("n1000_T12000_frontier", 16, 8,
                                              args.precision, tune),
@@ -822,6 +879,7 @@ def main():
         out["return_floor"] = return_floor_bench(args.precision)
         out["regime"] = regime_bench(args.precision)
         out["precision"] = precision_bench()
+        out["probe"] = probe_bench()
         out["frontier_solves_per_s"] = fr["n5440_T12000"]["warm_batched_solves_per_s"]
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(R, c)

@@ -59,6 +59,11 @@ enum { YAND_FP64 = 0, YAND_FP32 = 1, YAND_BF16 = 2 };
 enum { YAND_SOLVER_DIRECT = 0, YAND_SOLVER_PCG = 1 };
 /* Feasible set: affine budget hull (no cap) or the slice Delta(tau). */
 enum { YAND_SET_BUDGET = 0, YAND_SET_SIMPLEX = 1 };
+/* Trace of the affine-normal correction in the PCG configuration: exact
+ * (the dense route, or the T x T push-through when 2 T <= n) or estimated
+ * from random sign probes (Hutchinson's diagonal estimator with the probe
+ * solves by the same PCG: the Krylov reduced solve of Appendix C). */
+enum { YAND_TRACE_EXACT = 0, YAND_TRACE_PROBE = 1 };
 /* Step rule on the quartic line model: the exact rule (Proposition "Quartic
  * exact line search from sample power sums") or Armijo backtracking (the
  * rule of the convergence theory; sigma = 1e-4, halving from min(1,
@@ -101,6 +106,18 @@ typedef struct yand_opts {
                              1 forms them in FP64.  The factorisation, the
                              passes' reductions, the line-search sums and
                              the PCG inner products are FP64 either way.     */
+  int trace_mode;         /* YAND_TRACE_EXACT (default) or YAND_TRACE_PROBE;
+                             the probe estimate applies to PCG phases only:
+                             q_t = k^-1 sum_j xi_tj (A K A^T xi_j)_t with
+                             K = P_S (H + lambda)^-1 P_S applied by k PCG
+                             solves (krylov_tol, krylov_maxit) whose
+                             products with A run as block passes on the
+                             matrix cores; no n x n matrix is formed        */
+  int probes;             /* k, sign vectors per direction (1..64; 64)        */
+  uint64_t probe_seed;    /* xi_tj = sign bit of SplitMix64 at the Weyl state
+                             probe_seed + gamma (d 2^42 + t 2^10 + j), d the
+                             direction count of the solve (0 for
+                             yand_affine_normal), gamma = 0x9E3779B97F4A7C15 */
 } yand_opts;
 
 /* Per-solve report: counters follow the oracle-query accounting of the
@@ -126,6 +143,8 @@ typedef struct yand_info {
   int projected_steps;    /* iterations that took the projected trial segment */
   int phase_iterations[3];/* iterations of the baseline phase and of each
                              stall-recovery restart                          */
+  int64_t probe_traces;   /* directions whose trace came from probes          */
+  int64_t probe_cg_iters; /* PCG iterations of the probe solves (all columns) */
 } yand_info;
 
 /* Fill *opts with the direct configuration (YAND-MVSK small). */

@@ -29,6 +29,7 @@ PRECISIONS = {"fp64": 0, "fp32": 1, "bf16": 2}
 SOLVERS = {"direct": 0, "pcg": 1}
 SETS = {"budget": 0, "simplex": 1}
 LINESEARCH = {"exact": 0, "armijo": 1}
+TRACE = {"exact": 0, "probe": 1}
 
 
 class YandError(RuntimeError):
@@ -44,7 +45,9 @@ class yand_opts(C.Structure):
                 ("krylov_tol", C.c_double), ("krylov_maxit", C.c_int),
                 ("tau", C.c_double), ("stall_recovery", C.c_int),
                 ("restart_max_iter", C.c_int), ("eta", C.c_double),
-                ("linesearch", C.c_int), ("dense_fp64", C.c_int)]
+                ("linesearch", C.c_int), ("dense_fp64", C.c_int),
+                ("trace_mode", C.c_int), ("probes", C.c_int),
+                ("probe_seed", C.c_uint64)]
 
 
 class yand_info(C.Structure):
@@ -56,7 +59,8 @@ class yand_info(C.Structure):
                 ("third_passes", C.c_int64), ("ls_passes", C.c_int64),
                 ("dense_traces", C.c_int64), ("kkt", C.c_double),
                 ("projected_steps", C.c_int),
-                ("phase_iterations", C.c_int * 3)]
+                ("phase_iterations", C.c_int * 3),
+                ("probe_traces", C.c_int64), ("probe_cg_iters", C.c_int64)]
 
 
 class yand_mlp_opts(C.Structure):
@@ -193,6 +197,8 @@ def default_opts(**kw) -> yand_opts:
             v = SETS[v] if isinstance(v, str) else v
         if k == "linesearch":
             v = LINESEARCH[v] if isinstance(v, str) else v
+        if k == "trace_mode":
+            v = TRACE[v] if isinstance(v, str) else v
         setattr(o, k, v)
     return o
 
@@ -230,6 +236,8 @@ class SolveInfo:
     kkt: float
     projected_steps: int
     phase_iterations: tuple
+    probe_traces: int
+    probe_cg_iters: int
 
 
 def _info(i) -> SolveInfo:

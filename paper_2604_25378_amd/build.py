@@ -15,8 +15,8 @@ CSRC = os.path.join(PKG, "csrc")
 ROOT = os.path.dirname(PKG)
 OBJ = os.path.join(ROOT, "_build")
 LIB = os.path.join(PKG, "libyand.so")
-SOURCES = ["pass.hip", "dense.hip", "lowp.hip", "thin.hip", "vec.hip", "mlp.hip",
-           "api.hip"]
+SOURCES = ["pass.hip", "dense.hip", "lowp.hip", "thin.hip", "probe.hip",
+           "vec.hip", "mlp.hip", "api.hip"]
 ARCH = os.environ.get("YAND_OFFLOAD_ARCH", "gfx950")
 FLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",

@@ -78,6 +78,13 @@ struct Work {
   // T < n push-through trace: Gram partials, G, C, L^-1 of C, diag(B)
   double *tGp = nullptr, *tG = nullptr, *tC = nullptr, *tX = nullptr,
          *bdiag = nullptr, *tpart = nullptr;
+  // probe estimate of the trace: signs and block products (Tp x 64), their
+  // split partials, the block PCG vectors (64 x lda each) and per-column
+  // scalars and flags
+  double *pXi = nullptr, *pZ = nullptr, *pZp = nullptr, *pYp = nullptr,
+         *pU = nullptr, *pY = nullptr, *pR = nullptr, *pW = nullptr,
+         *pP = nullptr, *pHP = nullptr, *pAP = nullptr, *pcs = nullptr;
+  int* pflags = nullptr;
   int tK = 0;
   int64_t tld = 0;
   DevScalars* sc = nullptr;
@@ -209,6 +216,10 @@ void free_work(Work& w) {
   for (double* p : ptrs) dfree(p);
   dfree(w.SAt);
   dfree(w.Xl);
+  double* pp[] = {w.pXi, w.pZ, w.pZp, w.pYp, w.pU, w.pY, w.pR, w.pW, w.pP,
+                  w.pHP, w.pAP, w.pcs};
+  for (double* q : pp) dfree(q);
+  dfree(w.pflags);
   if (w.sc && w.own_sc) dfree(w.sc);
   if (w.st && w.own_stream) (void)hipStreamDestroy(w.st);
   w = Work{};
@@ -265,6 +276,8 @@ int init_work(Work& w, const Data& D) {
   return YAND_OK;
 }
 
+int ensure_bdiag(Work& w, const Data& D);
+
 int ensure_thin(Work& w, const Data& D) {
   if (w.tG) return YAND_OK;
   w.tld = round_up(D.T, 128);
@@ -274,10 +287,36 @@ int ensure_thin(Work& w, const Data& D) {
   TRY(alloc((void**)&w.tG, mm));
   TRY(alloc((void**)&w.tC, mm));
   TRY(alloc((void**)&w.tX, mm));
-  TRY(alloc((void**)&w.bdiag, (size_t)D.lda * sizeof(double)));
-  const int64_t ldp = D.lda > w.tld ? D.lda : w.tld;
-  TRY(alloc((void**)&w.tpart,
-            (size_t)thin_part_rows(D.T) * ldp * sizeof(double)));
+  return ensure_bdiag(w, D);
+}
+
+// bdiag and its partial rows (shared by the T < n and the probe routes)
+int ensure_bdiag(Work& w, const Data& D) {
+  if (!w.bdiag) TRY(alloc((void**)&w.bdiag, (size_t)D.lda * sizeof(double)));
+  if (!w.tpart) {
+    const int64_t tld = round_up(D.T, 128);
+    const int64_t ldp = D.lda > tld ? D.lda : tld;
+    TRY(alloc((void**)&w.tpart,
+              (size_t)thin_part_rows(D.T) * ldp * sizeof(double)));
+  }
+  return YAND_OK;
+}
+
+int ensure_probe(Work& w, const Data& D) {
+  if (w.pXi) return YAND_OK;
+  TRY(ensure_bdiag(w, D));
+  int sv = 1, sz = 1;
+  block_splits(D.Tp, D.lda, &sv, &sz);
+  const size_t tb = (size_t)D.Tp * kBlockWidth * sizeof(double);
+  const size_t nb = (size_t)D.lda * kBlockWidth * sizeof(double);
+  TRY(alloc((void**)&w.pXi, tb));
+  TRY(alloc((void**)&w.pZ, tb));
+  TRY(alloc((void**)&w.pZp, tb * sv));
+  TRY(alloc((void**)&w.pYp, nb * sz));
+  double** vecs[] = {&w.pU, &w.pY, &w.pR, &w.pW, &w.pP, &w.pHP, &w.pAP};
+  for (double** v : vecs) TRY(alloc((void**)v, nb));
+  TRY(alloc((void**)&w.pcs, (size_t)8 * kBlockWidth * sizeof(double)));
+  TRY(alloc((void**)&w.pflags, 160 * sizeof(int)));
   return YAND_OK;
 }
 
@@ -409,6 +448,11 @@ struct DirOpts {
   // FP32 / BF16 storage: products of the exact trace in FP64 instead of on
   // the storage precision's matrix cores
   bool dense64 = false;
+  // PCG solver: probe estimate of the trace with `probes` sign vectors from
+  // block `draw` of the counter stream keyed by `seed`
+  bool probe = false;
+  int probes = 64;
+  uint64_t seed = 0, draw = 0;
 };
 
 const double* face_mask(const Work& w, const DirOpts& o) {
@@ -446,6 +490,7 @@ constexpr int kMaxEscalations = 16;
 struct DirStats {
   int cg = 0;
   int escalations = 0;
+  int probe_cg = 0;  // CG iterations of the probe solves (all columns)
 };
 
 // Direction, first part: nu-projection (Aν), B = A^T diag(psi''/T) A,
@@ -788,6 +833,83 @@ int dir_thin(const Data& D, Work& w, const double c[4], int p0,
   return YAND_OK;
 }
 
+// Probe estimate of the trace (probe.hip): frame products A e_a and one HVP
+// pass (B nu, A nu), the Jacobi diagonal diag(B) and lambda, then k sign
+// vectors Xi, U = A^T Xi, k projected PCG solves side by side whose Hessian
+// products are block passes over A, Q = A Y, q_t = k^-1 sum_j Xi_tj Q_tj,
+// the third-order pass and the right-hand side of the tangent solve.
+int dir_probe(const Data& D, Work& w, const double c[4], int p0,
+              const DirOpts& o, DirStats* stats) {
+  TRY(ensure_probe(w, D));
+  const int64_t n = D.n, Tp = D.Tp, ld = D.lda;
+  const int p = p0 + 1;
+  const double* mask = face_mask(w, o);
+  hipLaunchKernelGGL(psi2_weight_kernel, dim3((unsigned)((Tp + 255) / 256)),
+                     dim3(256), 0, w.st, w.z, Tp, to_coef(c),
+                     1.0 / (double)D.T, w.s_t, nullptr);
+  if (mask) {
+    PassArgs a = pass_args(D, w, c);
+    a.v = w.E;
+    a.tout = w.AE;
+    int nwg;
+    TRY(run_pass(D, w, PassKind::Dot, a, &nwg, "dot_pass"));
+  } else {
+    HIPTRY(launch_copy(w.AE, D.AEfix, (int64_t)p0 * Tp, w.st));
+  }
+  TRY(hvp_cached(D, w, c, w.E + (int64_t)p0 * n, w.W + (int64_t)p0 * n,
+                 w.AE + (int64_t)p0 * Tp));
+  HIPTRY(launch_bdiag(D.precision, D.A, D.lda, D.T, n, w.s_t, w.tpart,
+                      w.bdiag, w.st));
+  HIPTRY(launch_probe_scale(w.bdiag, n, w.s_t, w.AE, D.T, Tp, p, o.reg, mask,
+                            w.sc, w.st));
+  const int k = o.probes;
+  HIPTRY(launch_rademacher(o.seed, o.draw, D.T, Tp, k, w.pXi, w.st));
+  HIPTRY(timed(w, "probe_block", [&] {
+    return launch_block_atz(D.precision, D.A, ld, Tp, w.pXi, nullptr, w.pYp,
+                            w.pU, w.st);
+  }));
+  HIPTRY(launch_bpcg_init(w.pU, w.bdiag, w.E, p, n, ld, k, w.pY, w.pR, w.pW,
+                          w.pP, w.pcs, w.pflags, w.sc, mask, w.st));
+  const int* alldone = w.pflags;
+  for (int it = 0; it < o.krylov_maxit; ++it) {
+    HIPTRY(timed(w, "probe_block", [&] {
+      return launch_block_av(D.precision, D.A, ld, Tp, w.pP, w.pZp, w.pZ,
+                             w.st, alldone);
+    }));
+    HIPTRY(timed(w, "probe_block", [&] {
+      return launch_block_atz(D.precision, D.A, ld, Tp, w.pZ, w.s_t, w.pYp,
+                              w.pHP, w.st, alldone);
+    }));
+    HIPTRY(launch_bpcg_update(w.pHP, w.bdiag, w.E, p, n, ld, w.pY, w.pR, w.pW,
+                              w.pP, w.pAP, w.pcs, w.pflags, w.sc, mask,
+                              o.krylov_tol, w.st));
+  }
+  HIPTRY(timed(w, "probe_block", [&] {
+    return launch_block_av(D.precision, D.A, ld, Tp, w.pY, w.pZp, w.pZ, w.st);
+  }));
+  HIPTRY(launch_probe_q(w.pXi, w.pZ, D.T, Tp, k, w.q, w.st));
+  if (stats) {
+    int tot = 0;
+    HIPTRY(hipMemcpyAsync(&tot, w.pflags + 129, sizeof(int),
+                          hipMemcpyDeviceToHost, w.st));
+    HIPTRY(hipStreamSynchronize(w.st));
+    stats->probe_cg += tot;
+  }
+  {
+    PassArgs a = pass_args(D, w, c);
+    a.zc = w.z;
+    a.q = w.q;
+    int nwg;
+    TRY(run_pass(D, w, PassKind::Third, a, &nwg, "third_pass"));
+    HIPTRY(launch_reduce_partials(w.part, nwg, D.lda, n, 1.0, 0.0, nullptr,
+                                  w.t3, w.st));
+  }
+  const double mp1 = mask ? -1.0 : (double)(n - p0 + 1);
+  HIPTRY(launch_rhs(w.W + (int64_t)p0 * n, w.t3, w.E, p, n, mp1, w.sc, w.r,
+                    w.st, mask));
+  return YAND_OK;
+}
+
 // Eager direction with regularisation escalation (host reads the Cholesky
 // flag) and either solver.  The oracle pass and the gradient projection must
 // already have run at x with the done flag clear.  The PCG configuration
@@ -795,6 +917,10 @@ int dir_thin(const Data& D, Work& w, const double c[4], int p0,
 int direction_eager(const Data& D, Work& w, const double c[4], int p0,
                     const double* x, const DirOpts& o, double* d,
                     DirStats* stats) {
+  if (o.solver == YAND_SOLVER_PCG && o.probe) {
+    TRY(dir_probe(D, w, c, p0, o, stats));
+    return dir_pcg_solve(D, w, c, p0, x, o, d, stats, w.bdiag, 1);
+  }
   if (o.solver == YAND_SOLVER_PCG && o.reg > 0.0 && 2 * D.T <= D.n) {
     bool ok = false;
     TRY(dir_thin(D, w, c, p0, o, &ok));
@@ -1282,6 +1408,9 @@ void yand_default_opts(yand_opts* o) {
   o->eta = 0.05;
   o->linesearch = YAND_LS_EXACT;
   o->dense_fp64 = 0;
+  o->trace_mode = YAND_TRACE_EXACT;
+  o->probes = 64;
+  o->probe_seed = 0;
 }
 
 void yand_large_opts(yand_opts* o) {
@@ -1487,6 +1616,10 @@ int yand_affine_normal(yand_ctx* ctx, const double c[4], const double* target,
   int p0 = target ? 2 : 1;
   if (target && (!ctx->d.have_e2 || !std::isfinite(*target))) return YAND_ERR_ARG;
   HIPTRY(launch_copy(W.E, ctx->d.Efix, (int64_t)p0 * ctx->d.n, W.st));
+  if (opts && (opts->trace_mode < YAND_TRACE_EXACT ||
+               opts->trace_mode > YAND_TRACE_PROBE || opts->probes < 1 ||
+               opts->probes > kBlockWidth || !(opts->krylov_tol > 0.0)))
+    return YAND_ERR_ARG;
   DirOpts o;
   if (opts) {
     o.solver = opts->solver;
@@ -1495,6 +1628,9 @@ int yand_affine_normal(yand_ctx* ctx, const double c[4], const double* target,
     o.krylov_maxit = opts->krylov_maxit;
     o.tau = opts->tau;
     o.dense64 = opts->dense_fp64 != 0;
+    o.probe = opts->trace_mode == YAND_TRACE_PROBE;
+    o.probes = opts->probes;
+    o.seed = opts->probe_seed;
   }
   TRY(oracle_at(ctx->d, W, c, w, true));
   HIPTRY(launch_grad_project(W.g, W.E, p0, ctx->d.n, W.sc, W.st));
@@ -1535,6 +1671,9 @@ static int solve_pcg(yand_ctx* ctx, const double c[4], int p0,
   Work& w = ctx->w;
   DirOpts o;
   o.krylov_tol = opts.krylov_tol;
+  o.probe = opts.trace_mode == YAND_TRACE_PROBE;
+  o.probes = opts.probes;
+  o.seed = opts.probe_seed;
   o.tau = opts.tau;
   o.dense64 = opts.dense_fp64 != 0;
   o.simplex = opts.feasible_set == YAND_SET_SIMPLEX;
@@ -1596,11 +1735,17 @@ static int solve_pcg(yand_ctx* ctx, const double c[4], int p0,
                             .count();
       if (opts.max_elapsed > 0.0 && el > opts.max_elapsed) break;
       DirStats ds;
+      // the probe block of this direction: the solve's direction count
+      o.draw = (uint64_t)(inf.dense_traces + inf.probe_traces);
       TRY(direction_eager(D, w, c, p0, w.x, o, w.d, &ds));
-      inf.dense_traces++;
+      if (o.probe && o.solver == YAND_SOLVER_PCG)
+        inf.probe_traces++;
+      else
+        inf.dense_traces++;
       inf.third_passes++;
       inf.cg_iters += ds.cg;
       inf.hvp_passes += ds.cg;
+      inf.probe_cg_iters += ds.probe_cg;
       TRY(step_line(D, w, c, o, nullptr));
       inf.ls_passes++;
       TRY(sync_scalars(w));
@@ -1642,6 +1787,9 @@ static int solve_pcg(yand_ctx* ctx, const double c[4], int p0,
 
 static bool valid_opts(const yand_opts& o) {
   return o.eps >= 0.0 && o.max_iter >= 0 && o.tau >= 0.0 &&
+         (o.trace_mode == YAND_TRACE_EXACT ||
+          o.trace_mode == YAND_TRACE_PROBE) &&
+         o.probes >= 1 && o.probes <= kBlockWidth &&
          o.krylov_tol > 0.0 && std::isfinite(o.krylov_tol) &&
          !std::isnan(o.max_elapsed) &&
          (o.solver == YAND_SOLVER_DIRECT || o.solver == YAND_SOLVER_PCG) &&

@@ -9,6 +9,8 @@
 // the FP64 matrix cores (v_mfma_f64_16x16x4f64) in 128 x 128 output tiles:
 // 256 threads = 4 waves in a 2 x 2 grid, each wave 64 x 64 = 4 x 4 MFMA
 // blocks; operands are staged through LDS k-major (contiguous along m / n).
+#include <algorithm>
+
 #include "common.h"
 #include "kernels.h"
 
@@ -353,6 +355,70 @@ trace_gemm_kernel(const S* __restrict__ A, int64_t lda, int64_t Tp,
     }
   __syncthreads();
   if (tid < BM) rn[(int64_t)J * Tp + t0 + tid] = rows[0][tid] + rows[1][tid];
+}
+
+// ------------------------------------------------- block passes over A --
+// Products of A with a block of kb <= 64 vectors at once (the probe solves
+// of the trace estimate): Z = A V and Y = A^T diag(s) Z as two FP64 MFMA
+// GEMMs with 128 x 64 output tiles.  A has few 128-row tiles along the output
+// side of each product, so the reduction dimension is split over
+// workgroups; every split writes its own partial slab and a second kernel
+// sums the slabs in split order (deterministic).
+//  V and Y: 64 x lda, column j of the block contiguous (row j of the array);
+//  Z: Tp x 64 row-major (bar t's 64 values contiguous).
+constexpr int BW = 64;  // block width
+
+template <typename S>
+__global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2, 2)))
+block_av_kernel(const S* __restrict__ A, int64_t lda, const double* __restrict__ V,
+                int64_t kchunk, double* __restrict__ Zp, int64_t Tp,
+                const int* skip) {
+  if (skip && *skip) return;
+  __shared__ double sA[2 * stage_size<BM>()], sB[2 * stage_size<BW>()];
+  const int ntt = (int)(Tp / BM);
+  const int ti = (int)blockIdx.x % ntt, sp = (int)blockIdx.x / ntt;
+  const int64_t t0 = (int64_t)ti * BM, k0 = (int64_t)sp * kchunk;
+  const int64_t k1 = k0 + kchunk < lda ? k0 + kchunk : lda;
+  f64x4 acc[BM / 32][BW / 32];
+  gemm_core<S, true, double, true, BM, BW>(A + t0 * lda, lda, V, lda, nullptr,
+                                           k0, k1, acc, sA, sB);
+  double* out = Zp + (int64_t)sp * Tp * BW + t0 * BW;
+  for_each_acc<BM, BW>(acc, [&](int r, int c, double v) {
+    out[(int64_t)r * BW + c] = v;
+  });
+}
+
+template <typename S, bool SCALE>
+__global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2, 2)))
+block_atz_kernel(const S* __restrict__ A, int64_t lda, int64_t Tp,
+                 const double* __restrict__ Z, const double* __restrict__ s,
+                 int64_t tchunk, double* __restrict__ Yp, const int* skip) {
+  if (skip && *skip) return;
+  __shared__ double sA[2 * stage_size<BM>()], sB[2 * stage_size<BW>()];
+  const int njt = (int)(lda / BM);
+  const int jt = (int)blockIdx.x % njt, sp = (int)blockIdx.x / njt;
+  const int64_t j0 = (int64_t)jt * BM, k0 = (int64_t)sp * tchunk;
+  const int64_t k1 = k0 + tchunk < Tp ? k0 + tchunk : Tp;
+  f64x4 acc[BM / 32][BW / 32];
+  gemm_core<S, false, double, false, BM, BW, SCALE>(A + j0, lda, Z, BW, s, k0,
+                                                    k1, acc, sA, sB);
+  double* out = Yp + (int64_t)sp * BW * lda + j0;
+  for_each_acc<BM, BW>(acc, [&](int r, int c, double v) {
+    out[(int64_t)c * lda + r] = v;
+  });
+}
+
+// out[i] = sum_{p < parts} part[p * len + i], parts summed in order.
+__global__ void sum_slabs_kernel(const double* __restrict__ part, int parts,
+                                 int64_t len, double* __restrict__ out,
+                                 const int* skip) {
+  if (skip && *skip) return;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < len;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    double v = 0.0;
+    for (int p = 0; p < parts; ++p) v += part[(int64_t)p * len + i];
+    out[i] = v;
+  }
 }
 
 // ------------------------------------------------------ blocked Cholesky --
@@ -885,8 +951,8 @@ __global__ void symm_multi_kernel(const double* __restrict__ B, int64_t ld,
 hipError_t launch_syrk(int precision, const void* A, int64_t lda, int64_t Tp,
                        const double* s, double* B, hipStream_t st,
                        const int* skip) {
-  const int64_t nt = lda / BM;
-  dim3 g((unsigned)(nt * (nt + 1) / 2)), b(NT);
+  const int64_t nt = lda / BM, ntiles = nt * (nt + 1) / 2;
+  dim3 g((unsigned)ntiles), b(NT);
   switch (precision) {
     case 0:
       hipLaunchKernelGGL(syrk_kernel<double>, g, b, 0, st, (const double*)A,
@@ -985,6 +1051,83 @@ hipError_t launch_trace_gemm(int precision, const void* A, int64_t lda,
     default:
       return hipErrorInvalidValue;
   }
+  return hipGetLastError();
+}
+
+// Split counts: about 768 workgroups, every split a multiple of 16 long.
+static int64_t block_chunk(int64_t len, int tiles) {
+  int64_t parts = std::max<int64_t>(1, std::min<int64_t>(len / 16, 768 / tiles));
+  return (len / 16 + parts - 1) / parts * 16;
+}
+
+int block_splits(int64_t Tp, int64_t lda, int* sv, int* sz) {
+  const int64_t kc = block_chunk(lda, (int)(Tp / BM));
+  const int64_t tc = block_chunk(Tp, (int)(lda / BM));
+  *sv = (int)((lda + kc - 1) / kc);
+  *sz = (int)((Tp + tc - 1) / tc);
+  return 0;
+}
+
+hipError_t launch_block_av(int precision, const void* A, int64_t lda,
+                           int64_t Tp, const double* V, double* Zp, double* Z,
+                           hipStream_t st, const int* skip) {
+  const int ntt = (int)(Tp / BM);
+  const int64_t kc = block_chunk(lda, ntt);
+  const int parts = (int)((lda + kc - 1) / kc);
+  dim3 g((unsigned)(ntt * parts)), b(NT);
+  switch (precision) {
+    case 0:
+      hipLaunchKernelGGL(block_av_kernel<double>, g, b, 0, st,
+                         (const double*)A, lda, V, kc, Zp, Tp, skip);
+      break;
+    case 1:
+      hipLaunchKernelGGL(block_av_kernel<float>, g, b, 0, st, (const float*)A,
+                         lda, V, kc, Zp, Tp, skip);
+      break;
+    case 2:
+      hipLaunchKernelGGL(block_av_kernel<bf16_t>, g, b, 0, st,
+                         (const bf16_t*)A, lda, V, kc, Zp, Tp, skip);
+      break;
+    default:
+      return hipErrorInvalidValue;
+  }
+  hipLaunchKernelGGL(sum_slabs_kernel, dim3(1024), dim3(256), 0, st, Zp, parts,
+                     Tp * BW, Z, skip);
+  return hipGetLastError();
+}
+
+template <bool SC>
+static void launch_atz_t(int precision, const void* A, int64_t lda,
+                         int64_t Tp, const double* Z, const double* s,
+                         int64_t tc, double* Yp, dim3 g, hipStream_t st,
+                         const int* skip) {
+  dim3 b(NT);
+  if (precision == 0)
+    hipLaunchKernelGGL((block_atz_kernel<double, SC>), g, b, 0, st,
+                       (const double*)A, lda, Tp, Z, s, tc, Yp, skip);
+  else if (precision == 1)
+    hipLaunchKernelGGL((block_atz_kernel<float, SC>), g, b, 0, st,
+                       (const float*)A, lda, Tp, Z, s, tc, Yp, skip);
+  else
+    hipLaunchKernelGGL((block_atz_kernel<bf16_t, SC>), g, b, 0, st,
+                       (const bf16_t*)A, lda, Tp, Z, s, tc, Yp, skip);
+}
+
+hipError_t launch_block_atz(int precision, const void* A, int64_t lda,
+                            int64_t Tp, const double* Z, const double* s,
+                            double* Yp, double* Y, hipStream_t st,
+                            const int* skip) {
+  if (precision < 0 || precision > 2) return hipErrorInvalidValue;
+  const int njt = (int)(lda / BM);
+  const int64_t tc = block_chunk(Tp, njt);
+  const int parts = (int)((Tp + tc - 1) / tc);
+  dim3 g((unsigned)(njt * parts));
+  if (s)
+    launch_atz_t<true>(precision, A, lda, Tp, Z, s, tc, Yp, g, st, skip);
+  else
+    launch_atz_t<false>(precision, A, lda, Tp, Z, s, tc, Yp, g, st, skip);
+  hipLaunchKernelGGL(sum_slabs_kernel, dim3(1024), dim3(256), 0, st, Yp, parts,
+                     lda * BW, Y, skip);
   return hipGetLastError();
 }
 

@@ -132,6 +132,33 @@ hipError_t launch_block_atz(int precision, const void* A, int64_t lda,
                             int64_t Tp, const double* Z, const double* s,
                             double* Yp, double* Y, hipStream_t st,
                             const int* skip = nullptr);
+// ---- probe estimate of the trace (probe.hip) -----------------------------
+struct DevScalars;
+// Xi (Tp x 64): SplitMix64 signs for t < T, j < k; zero elsewhere.
+hipError_t launch_rademacher(uint64_t seed, uint64_t draw, int64_t T,
+                             int64_t Tp, int k, double* Xi, hipStream_t st);
+// sc->lambda = reg * tangent trace of B / (free coordinates - p).
+hipError_t launch_probe_scale(const double* bd, int64_t n, const double* s,
+                              const double* AE, int64_t T, int64_t Tp, int p,
+                              double reg, const double* mask, DevScalars* sc,
+                              hipStream_t st);
+// Block PCG over the 64 columns (rows of the 64 x ld arrays); columns >= k
+// are done at once.  flags: [0] all done, [1 + j] done, [65 + j]
+// iterations, [129] total iterations; cs: 8 doubles per column.
+hipError_t launch_bpcg_init(const double* U, const double* bd, const double* E,
+                            int p, int64_t n, int64_t ld, int k, double* Y,
+                            double* Rr, double* Z, double* P, double* cs,
+                            int* flags, const DevScalars* sc,
+                            const double* mask, hipStream_t st);
+hipError_t launch_bpcg_update(const double* HP, const double* bd,
+                              const double* E, int p, int64_t n, int64_t ld,
+                              double* Y, double* Rr, double* Z, double* P,
+                              double* AP, double* cs, int* flags,
+                              const DevScalars* sc, const double* mask,
+                              double tol, hipStream_t st);
+// q_t = k^-1 sum_j Xi_tj Q_tj (zero for t >= T).
+hipError_t launch_probe_q(const double* Xi, const double* Q, int64_t T,
+                          int64_t Tp, int k, double* q, hipStream_t st);
 // y = X v (lower), y = X^T v (transposed); X is np x np.  part holds
 // ceil(n/64) * n doubles of partial sums for the transposed product.
 hipError_t launch_trmv(const double* X, int64_t np, int64_t n,
