@@ -684,8 +684,9 @@ def main():
                     help="keep the built-in launch shapes")
     ap.add_argument("--only", default=None,
                     help="run the headline step and this one block only "
-                         "(frontier, simplex, conditioning, line_search, "
-                         "return_floor, regime, precision, probe)")
+                         "(frontier_n1000, ragged, warmstart, simplex, "
+                         "conditioning, line_search, return_floor, regime, "
+                         "precision, probe)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="end with one 1 GiB device copy (PMC scale reference)")
     args = ap.parse_args()
@@ -857,12 +858,20 @@ def main():
     ctx.close()
     del ctx
     blocks = {"precision": precision_bench, "probe": probe_bench,
+              "frontier_n1000": lambda: frontier_bench(
+                  "n1000_T12000_frontier", 16, 8, args.precision,
+                  not args.no_autotune),
+              "ragged": lambda: ragged_bench(32, 6000, args.precision,
+                                             not args.no_autotune),
+              "warmstart": lambda: warmstart_bench(
+                  args.workload, 16, args.frontier_points, 16, args.precision,
+                  not args.no_autotune),
               "simplex": lambda: simplex_bench(args.precision),
               "conditioning": lambda: conditioning_bench(args.precision),
               "line_search": lambda: line_search_bench(args.precision),
               "return_floor": lambda: return_floor_bench(args.precision),
               "regime": lambda: regime_bench(args.precision)}
-    if args.only and args.only != "frontier":
+    if args.only:
         out[args.only] = blocks[args.only]()
     elif not args.no_frontier:
         tune = not args.no_autotune

@@ -287,8 +287,13 @@ int yand_frontier_solve(yand_ctx* ctx, int64_t B, const double* C4,
  * instance b runs on ctxs[b] (host array of B contexts on one device) and
  * writes W_out[b] (host array of B device pointers, each n_b long); W0
  * (nullable host array of B device pointers, entries nullable) gives starts.
- * max_lanes bounds the solves advancing together (<= 0: 64); use_graph != 0
- * replays captured iterations. */
+ * max_lanes bounds the solves advancing together (<= 0: 64).  use_graph:
+ * bit 0 replays captured iterations; bit 1 keeps the lanes on separate
+ * streams.  Without bit 1, instances that all run on one context with the
+ * exact trace's products in FP64 advance in lockstep on one stream: the
+ * SYRK, the factorisation with its inverse and the trace GEMM of all lanes
+ * run as single grouped launches (the same kernels and tile order per lane,
+ * so the results are those of separate lanes bit for bit). */
 int yand_batch_solve(int64_t B, yand_ctx* const* ctxs, const double* C4,
                      const double* targets, const double* const* W0,
                      const yand_opts* opts, double* const* W_out,

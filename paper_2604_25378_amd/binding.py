@@ -453,8 +453,11 @@ class Context:
 
 
 def batch_solve(contexts, C4, targets=None, opts: yand_opts | None = None,
-                max_lanes: int = 64, use_graph: bool = True, W0=None):
+                max_lanes: int = 64, use_graph: bool = True, W0=None,
+                grouped: bool = True):
     """Batched solve where instance b runs on contexts[b] (uneven universes).
+    grouped=False keeps lanes of one context on separate streams instead of
+    grouped lockstep launches.
 
     Returns ([w_b device tensors], [SolveInfo])."""
     torch = _torch()
@@ -480,7 +483,8 @@ def batch_solve(contexts, C4, targets=None, opts: yand_opts | None = None,
                                     for w in starts])
     rc = lib.yand_batch_solve(B, ctx_arr, C4.ctypes.data_as(_D), tg, w0_arr,
                               C.byref(opts) if opts else None, out_arr, infos,
-                              int(max_lanes), int(use_graph))
+                              int(max_lanes),
+                              int(bool(use_graph)) | (0 if grouped else 2))
     _check(rc, "yand_batch_solve", warn_ok=True)
     return outs, [_info(i)
                   for i in infos]

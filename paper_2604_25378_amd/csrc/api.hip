@@ -89,6 +89,9 @@ struct Work {
   int64_t tld = 0;
   DevScalars* sc = nullptr;
   bool own_sc = true;
+  // lockstep lanes: B, M, X, rn and s_t point into the batch's strided
+  // blocks (freed by the batch, not by the lane)
+  bool shared_dense = false;
   DevScalars hs{};
   Prof* prof = nullptr;
 };
@@ -206,6 +209,7 @@ void flush_timed(Prof& p, hipStream_t st) {
 // ------------------------------------------------------------ workspaces --
 
 void free_work(Work& w) {
+  if (w.shared_dense) w.B = w.M = w.X = w.rn = w.s_t = nullptr;
   double* ptrs[] = {w.x,     w.g,      w.d,     w.z,      w.wv,   w.q,
                     w.AE,    w.E,      w.W,     w.t3,     w.r,    w.y,
                     w.y2,    w.hv,     w.s_t,   w.pcg_s,  w.pcg_res,
@@ -495,11 +499,10 @@ struct DirStats {
 
 // Direction, first part: nu-projection (Aν), B = A^T diag(psi''/T) A,
 // W_E = B E and the scales gamma, lambda.  Needs z, g and E[p0] = nu.
-int dir_front(const Data& D, Work& w, const double c[4], int p0,
-              const DirOpts& o, const int* skip) {
-  TRY(ensure_dense(w, D));
-  const int64_t n = D.n, np = D.lda, Tp = D.Tp;
-  const int p = p0 + 1;
+// A nu and the weights s_t = psi''(z_t) / T of the SYRK.
+int dir_front_pre(const Data& D, Work& w, const double c[4], int p0,
+                  const int* skip) {
+  const int64_t n = D.n, Tp = D.Tp;
   {
     PassArgs a = pass_args(D, w, c);
     a.v = w.E + (int64_t)p0 * n;
@@ -511,6 +514,25 @@ int dir_front(const Data& D, Work& w, const double c[4], int p0,
   hipLaunchKernelGGL(psi2_weight_kernel, dim3((unsigned)((Tp + 255) / 256)),
                      dim3(256), 0, w.st, w.z, Tp, to_coef(c),
                      1.0 / (double)D.T, w.s_t, skip);
+  return YAND_OK;
+}
+
+// W_E = B E and the scales gamma, lambda (after the SYRK).
+int dir_front_post(const Data& D, Work& w, int p0, const DirOpts& o,
+                   const int* skip) {
+  const int64_t n = D.n, np = D.lda;
+  const int p = p0 + 1;
+  HIPTRY(launch_symm_multi(w.B, np, n, w.E, p, w.W, w.st, skip));
+  HIPTRY(launch_trace_scale(w.B, np, n, w.E, w.W, p, o.reg, w.sc, w.st,
+                            face_mask(w, o)));
+  return YAND_OK;
+}
+
+int dir_front(const Data& D, Work& w, const double c[4], int p0,
+              const DirOpts& o, const int* skip) {
+  TRY(ensure_dense(w, D));
+  const int64_t np = D.lda, Tp = D.Tp;
+  TRY(dir_front_pre(D, w, c, p0, skip));
   if (D.precision != YAND_FP64 && !o.dense64)
     HIPTRY(timed(w, "syrk", [&] {
       return launch_syrk_lp(D.precision, D.At, w.SAt, np, Tp, w.s_t, w.B,
@@ -520,10 +542,7 @@ int dir_front(const Data& D, Work& w, const double c[4], int p0,
     HIPTRY(timed(w, "syrk", [&] {
       return launch_syrk(D.precision, D.A, D.lda, Tp, w.s_t, w.B, w.st, skip);
     }));
-  HIPTRY(launch_symm_multi(w.B, np, n, w.E, p, w.W, w.st, skip));
-  HIPTRY(launch_trace_scale(w.B, np, n, w.E, w.W, p, o.reg, w.sc, w.st,
-                            face_mask(w, o)));
-  return YAND_OK;
+  return dir_front_post(D, w, p0, o, skip);
 }
 
 // Projection of B into M and the factorisation M = L L^T, X = L^-1.
@@ -538,6 +557,9 @@ int dir_factor(const Data& D, Work& w, int p0, const int* skip,
   }));
   return YAND_OK;
 }
+
+int dir_trace_post(const Data& D, Work& w, const double c[4], int p0,
+                   const int* skip, const double* mask);
 
 // Exact trace q, third-order back-projection t3 and r = P_S(B nu - |G|/(m+1) t3).
 int dir_trace(const Data& D, Work& w, const double c[4], int p0,
@@ -555,6 +577,15 @@ int dir_trace(const Data& D, Work& w, const double c[4], int p0,
       return launch_trace_gemm(D.precision, D.A, D.lda, Tp, w.X, np, w.rn,
                                w.st, skip);
     }));
+  return dir_trace_post(D, w, c, p0, skip, mask);
+}
+
+// After the trace GEMM: the frame's A e_a, q, the third-order pass and the
+// right-hand side r = P_S(B nu - |G|/(m+1) t3).
+int dir_trace_post(const Data& D, Work& w, const double c[4], int p0,
+                   const int* skip, const double* mask) {
+  const int64_t n = D.n, Tp = D.Tp;
+  const int p = p0 + 1;
   if (mask) {
     // the face's frame column E[0] = mask / sqrt(nfree): A E[0] afresh
     PassArgs a = pass_args(D, w, c);
@@ -975,6 +1006,59 @@ int enqueue_iteration(const Data& D, Work& w, const double c[4], int p0,
   return YAND_OK;
 }
 
+// Lanes advancing in lockstep on one stream (a frontier on one context):
+// the SYRK, the factorisation with its inverse and the trace GEMM of all
+// lanes run as single grouped launches (blockIdx.y = lane) over strided
+// per-lane blocks, so the lanes' tiles fill the GPU together; the passes
+// and vector kernels run per lane in between.
+struct Group {
+  int nl = 0;
+  Lanes ls;
+  double *s = nullptr, *B = nullptr, *M = nullptr, *X = nullptr,
+         *rn = nullptr;
+  int *skip = nullptr, *fail = nullptr;
+};
+
+struct LaneRef {
+  const Data* D;
+  Work* w;
+  const double* c;
+  int p0;
+};
+
+int enqueue_group(const std::vector<LaneRef>& lanes, const DirOpts& o,
+                  double eps, const Group& G, hipStream_t st) {
+  const Data& D = *lanes[0].D;
+  const int64_t np = D.lda, Tp = D.Tp;
+  for (const auto& L : lanes) {
+    Work& w = *L.w;
+    TRY(oracle_at(D, w, L.c, w.x, true, &w.sc->frozen));
+    TRY(stationarity(D, w, o, L.p0, eps));
+    TRY(dir_front_pre(D, w, L.c, L.p0, &w.sc->done));
+  }
+  HIPTRY(launch_syrk(D.precision, D.A, D.lda, Tp, G.s, G.B, st, G.skip, G.ls,
+                     G.nl));
+  for (const auto& L : lanes) {
+    Work& w = *L.w;
+    TRY(dir_front_post(D, w, L.p0, o, &w.sc->done));
+    HIPTRY(launch_project(w.B, w.M, np, D.n, np, w.E, w.W, L.p0 + 1, w.sc,
+                          w.st, face_mask(w, o)));
+  }
+  HIPTRY(launch_potrf_trtri(G.M, G.X, np, G.fail, st, G.skip, D.chol_group,
+                            G.ls, G.nl));
+  HIPTRY(launch_trace_gemm(D.precision, D.A, D.lda, Tp, G.X, np, G.rn, st,
+                           G.skip, G.ls, G.nl));
+  for (const auto& L : lanes) {
+    Work& w = *L.w;
+    const int* skip = &w.sc->done;
+    TRY(dir_trace_post(D, w, L.c, L.p0, skip, face_mask(w, o)));
+    TRY(dir_direct_solve(D, w, L.p0, w.x, o, w.d, skip));
+    TRY(step_line(D, w, L.c, o, skip));
+    HIPTRY(launch_axpy(w.x, w.d, D.n, w.sc, w.st));
+  }
+  return YAND_OK;
+}
+
 // ------------------------------------------------- constraints and start --
 
 // x <- x + sum_a e_a (b_a - e_a^T x): minimum-norm move onto the budget (and
@@ -1176,11 +1260,13 @@ int final_check(Lane& L, const yand_opts& opts, const DirOpts& o) {
 // since the call began, checked before each iteration.
 int run_lanes(std::vector<Lane>& lanes, const yand_opts& opts,
               const DirOpts& o, hipStream_t cs, bool use_graph,
-              DevScalars* host_sc, DevScalars* dev_sc) {
+              DevScalars* host_sc, DevScalars* dev_sc,
+              const Group* grp = nullptr) {
   const size_t nl = lanes.size();
   const auto t_start = std::chrono::steady_clock::now();
   HIPTRY(prepare_dense_kernels());
-  const bool inline_lane = nl == 1 && lanes[0].w->st == cs && !use_graph;
+  const bool inline_lane =
+      grp != nullptr || (nl == 1 && lanes[0].w->st == cs && !use_graph);
   hipEvent_t ev_fork = nullptr;
   std::vector<hipEvent_t> ev_join(inline_lane ? 0 : nl, nullptr);
   if (!inline_lane) {
@@ -1193,6 +1279,13 @@ int run_lanes(std::vector<Lane>& lanes, const yand_opts& opts,
     for (auto& e : ev_join) (void)hipEventDestroy(e);
   };
   auto enqueue_all = [&]() -> int {
+    if (grp) {
+      std::vector<LaneRef> refs;
+      for (auto& L : lanes) refs.push_back(LaneRef{L.D, L.w, L.c, L.p0});
+      Group g = *grp;
+      g.nl = (int)nl;
+      return enqueue_group(refs, o, opts.eps, g, cs);
+    }
     if (inline_lane) {
       Lane& L = lanes[0];
       return enqueue_iteration(*L.D, *L.w, L.c, L.p0, o, opts.eps);
@@ -1870,7 +1963,8 @@ int yand_mvsk_solve(yand_ctx* ctx, const double c[4], const double* target,
 static int batch_solve(int64_t B, yand_ctx* const* ctxs, const double* C4,
                        const double* targets, const double* const* W0,
                        const yand_opts* opts_in, double* const* W_out,
-                       yand_info* infos, int max_lanes, int use_graph) {
+                       yand_info* infos, int max_lanes, int use_graph,
+                       bool group_lanes) {
   if (B <= 0 || !ctxs || !C4 || !W_out) return YAND_ERR_ARG;
   yand_opts opts;
   if (opts_in)
@@ -1945,18 +2039,58 @@ static int batch_solve(int64_t B, yand_ctx* const* ctxs, const double* C4,
     }
   }
   int rc = YAND_OK;
+  // lockstep lanes: instances on one context whose exact-trace products are
+  // FP64 share grouped launches; their dense buffers live in strided blocks
+  bool lockstep = nl > 1 && group_lanes;
+  for (int64_t b = 1; b < B && lockstep; ++b)
+    lockstep = ctxs[b] == ctxs[0];
+  lockstep = lockstep && (big.precision == YAND_FP64 || opts.dense_fp64);
+  Group grp;
+  double* gblk[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
+  if (lockstep) {
+    const int64_t mat = big.lda * big.lda, rnl = big.nt * big.Tp;
+    const int64_t sizes[5] = {mat, mat, mat, rnl, big.Tp};
+    for (int q = 0; q < 5 && rc == YAND_OK; ++q)
+      rc = alloc((void**)&gblk[q], (size_t)sizes[q] * nl * sizeof(double));
+    grp.B = gblk[0];
+    grp.M = gblk[1];
+    grp.X = gblk[2];
+    grp.rn = gblk[3];
+    grp.s = gblk[4];
+    grp.ls.mat = mat;
+    grp.ls.rn = rnl;
+    grp.ls.vec = big.Tp;
+    grp.ls.flag = (int64_t)(sizeof(DevScalars) / sizeof(int));
+    grp.skip = &dev_sc[0].done;
+    grp.fail = &dev_sc[0].fail;
+  }
   for (int64_t i = 0; i < nl && rc == YAND_OK; ++i) {
     Work& w = works[i];
-    if (hipStreamCreateWithFlags(&w.st, hipStreamNonBlocking) != hipSuccess) {
-      rc = YAND_ERR_HIP;
-      break;
-    }
-    w.own_stream = true;
-    if (hipStreamWaitEvent(w.st, ev_in, 0) != hipSuccess) {
-      rc = YAND_ERR_HIP;
-      break;
+    if (lockstep) {
+      w.st = cs;
+      w.own_stream = false;
+    } else {
+      if (hipStreamCreateWithFlags(&w.st, hipStreamNonBlocking) !=
+          hipSuccess) {
+        rc = YAND_ERR_HIP;
+        break;
+      }
+      w.own_stream = true;
+      if (hipStreamWaitEvent(w.st, ev_in, 0) != hipSuccess) {
+        rc = YAND_ERR_HIP;
+        break;
+      }
     }
     rc = alloc_work(w, big, dev_sc + i);
+    if (rc == YAND_OK && lockstep) {
+      dfree(w.s_t);
+      w.s_t = grp.s + i * grp.ls.vec;
+      w.B = grp.B + i * grp.ls.mat;
+      w.M = grp.M + i * grp.ls.mat;
+      w.X = grp.X + i * grp.ls.mat;
+      w.rn = grp.rn + i * grp.ls.rn;
+      w.shared_dense = true;
+    }
     if (rc == YAND_OK) rc = ensure_dense(w, big);
     if (rc == YAND_OK) rc = init_work(w, big);
   }
@@ -1985,7 +2119,7 @@ static int batch_solve(int64_t B, yand_ctx* const* ctxs, const double* C4,
     }
     if (rc != YAND_OK) break;
     rc = run_lanes(lanes, opts, o, cs, use_graph != 0, host_sc.data(),
-                   dev_sc);
+                   dev_sc, lockstep ? &grp : nullptr);
     for (int64_t i = 0; i < cnt && rc == YAND_OK; ++i) {
       Lane& L = lanes[i];
       const int64_t b = start + i;
@@ -2005,6 +2139,7 @@ static int batch_solve(int64_t B, yand_ctx* const* ctxs, const double* C4,
   if (hipStreamSynchronize(cs) != hipSuccess && rc == YAND_OK)
     rc = YAND_ERR_HIP;
   for (auto& w : works) free_work(w);
+  for (double* q : gblk) dfree(q);
   (void)hipFree(dev_sc);
   (void)hipEventRecord(ev_out, cs);
   (void)hipStreamWaitEvent(caller, ev_out, 0);
@@ -2028,7 +2163,7 @@ int yand_frontier_solve(yand_ctx* ctx, int64_t B, const double* C4,
     starts[b] = W0 ? W0 + b * ctx->d.n : nullptr;
   }
   return batch_solve(B, ctxs.data(), C4, targets, W0 ? starts.data() : nullptr,
-                     opts, outs.data(), infos, 64, 1);
+                     opts, outs.data(), infos, 64, 1, true);
 }
 
 int yand_batch_solve(int64_t B, yand_ctx* const* ctxs, const double* C4,
@@ -2036,7 +2171,7 @@ int yand_batch_solve(int64_t B, yand_ctx* const* ctxs, const double* C4,
                      const yand_opts* opts, double* const* W_out,
                      yand_info* infos, int max_lanes, int use_graph) {
   return batch_solve(B, ctxs, C4, targets, W0, opts, W_out, infos, max_lanes,
-                     use_graph);
+                     use_graph & 1, (use_graph & 2) == 0);
 }
 
 int yand_warmstart_features(yand_ctx* ctx, int64_t N, const double* C4,

@@ -293,11 +293,13 @@ __device__ __forceinline__ void lower_tile(int64_t b, int* I, int* J) {
 // B = A^T diag(s) A, lower tiles computed, written to both triangles.
 template <typename S>
 __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2, 2)))
-syrk_kernel(const S* __restrict__ A,
-                                                  int64_t lda, int64_t Tp,
-                                                  const double* __restrict__ s,
-                                                  double* __restrict__ B,
-                                                  const int* skip) {
+syrk_kernel(const S* __restrict__ A, int64_t lda, int64_t Tp,
+            const double* __restrict__ s, double* __restrict__ B,
+            const int* skip, Lanes ls) {
+  const int ln = blockIdx.y;
+  s += ln * ls.vec;
+  B += ln * ls.mat;
+  if (skip) skip += ln * ls.flag;
   if (skip && *skip) return;
   __shared__ double sA[2 * kStage], sB[2 * kStage];
   int I, J;
@@ -320,7 +322,11 @@ template <typename S>
 __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2, 2)))
 trace_gemm_kernel(const S* __restrict__ A, int64_t lda, int64_t Tp,
                   const double* __restrict__ X, int64_t ldx,
-                  double* __restrict__ rn, const int* skip) {
+                  double* __restrict__ rn, const int* skip, Lanes ls) {
+  const int ln = blockIdx.y;
+  X += ln * ls.mat;
+  rn += ln * ls.rn;
+  if (skip) skip += ln * ls.flag;
   if (skip && *skip) return;
   __shared__ double sA[2 * kStage], sB[2 * kStage];
   __shared__ double rows[2][BM];
@@ -672,7 +678,13 @@ __device__ __forceinline__ void leaf_inv(double* S, const double* rd, int c0,
 __global__ void __launch_bounds__(DT) diag_block_kernel(double* M, double* X,
                                                         int64_t ld, int k,
                                                         int* fail,
-                                                        const int* skip) {
+                                                        const int* skip,
+                                                        Lanes ls) {
+  const int ln = blockIdx.y;
+  M += ln * ls.mat;
+  X += ln * ls.mat;
+  fail += ln * ls.flag;
+  if (skip) skip += ln * ls.flag;
   if (skip && *skip) return;
   extern __shared__ double S[];  // BM x LDD, then rdiag (BM)
   double* rd = S + BM * LDD;
@@ -803,7 +815,11 @@ __global__ void __launch_bounds__(DT) diag_block_kernel(double* M, double* X,
 //                          on the same columns of S[k, j].
 __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2, 2)))
 panel_finalize_kernel(double* M, double* X, int64_t ld, int k, int rem,
-                      const int* skip) {
+                      const int* skip, Lanes ls) {
+  const int ln = blockIdx.y;
+  M += ln * ls.mat;
+  X += ln * ls.mat;
+  if (skip) skip += ln * ls.flag;
   if (skip && *skip) return;
   constexpr int H = BM / 2;
   __shared__ double sA[2 * stage_size<BM>()], sB[2 * stage_size<BM>()];
@@ -853,7 +869,11 @@ __device__ __forceinline__ void sub_block(int b, int* tile, int* so, int* sc) {
 template <int TM>
 __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2, 2)))
 update_kernel(double* M, double* X, int64_t ld, int nt, int kA, int kB,
-              int jlo, int jhi, int ilo, int nu, const int* skip) {
+              int jlo, int jhi, int ilo, int nu, const int* skip, Lanes ls) {
+  const int ln = blockIdx.y;
+  M += ln * ls.mat;
+  X += ln * ls.mat;
+  if (skip) skip += ln * ls.flag;
   if (skip && *skip) return;
   __shared__ double sA[2 * stage_size<TM>()], sB[2 * stage_size<TM>()];
   int b, so, sc;
@@ -950,21 +970,21 @@ __global__ void symm_multi_kernel(const double* __restrict__ B, int64_t ld,
 
 hipError_t launch_syrk(int precision, const void* A, int64_t lda, int64_t Tp,
                        const double* s, double* B, hipStream_t st,
-                       const int* skip) {
+                       const int* skip, Lanes ls, int nlanes) {
   const int64_t nt = lda / BM, ntiles = nt * (nt + 1) / 2;
-  dim3 g((unsigned)ntiles), b(NT);
+  dim3 g((unsigned)ntiles, (unsigned)nlanes), b(NT);
   switch (precision) {
     case 0:
       hipLaunchKernelGGL(syrk_kernel<double>, g, b, 0, st, (const double*)A,
-                         lda, Tp, s, B, skip);
+                         lda, Tp, s, B, skip, ls);
       break;
     case 1:
       hipLaunchKernelGGL(syrk_kernel<float>, g, b, 0, st, (const float*)A, lda,
-                         Tp, s, B, skip);
+                         Tp, s, B, skip, ls);
       break;
     case 2:
       hipLaunchKernelGGL(syrk_kernel<bf16_t>, g, b, 0, st, (const bf16_t*)A,
-                         lda, Tp, s, B, skip);
+                         lda, Tp, s, B, skip, ls);
       break;
     default:
       return hipErrorInvalidValue;
@@ -995,7 +1015,9 @@ hipError_t prepare_dense_kernels() {
 constexpr int kDefaultGroup = 4;
 
 hipError_t launch_potrf_trtri(double* M, double* X, int64_t np, int* fail,
-                              hipStream_t st, const int* skip, int group) {
+                              hipStream_t st, const int* skip, int group,
+                              Lanes ls, int nlanes) {
+  const unsigned L = (unsigned)nlanes;
   const int kGroup = group > 0 ? group : kDefaultGroup;
   const int nt = (int)(np / BM);
   const size_t lds = kDiagLds;
@@ -1009,21 +1031,22 @@ hipError_t launch_potrf_trtri(double* M, double* X, int64_t np, int* fail,
     const int ni = (ihi - ilo) * kB;
     if (nu + ni == 0) return;
     if (small)
-      hipLaunchKernelGGL(update_kernel<64>, dim3((nu + ni) * Q64), dim3(NT), 0,
-                         st, M, X, np, nt, kA, kB, jlo, jhi, ilo, nu, skip);
+      hipLaunchKernelGGL(update_kernel<64>, dim3((nu + ni) * Q64, L), dim3(NT),
+                         0, st, M, X, np, nt, kA, kB, jlo, jhi, ilo, nu, skip,
+                         ls);
     else
-      hipLaunchKernelGGL(update_kernel<BM>, dim3(nu + ni), dim3(NT), 0, st, M,
-                         X, np, nt, kA, kB, jlo, jhi, ilo, nu, skip);
+      hipLaunchKernelGGL(update_kernel<BM>, dim3(nu + ni, L), dim3(NT), 0, st,
+                         M, X, np, nt, kA, kB, jlo, jhi, ilo, nu, skip, ls);
   };
   for (int g0 = 0; g0 < nt; g0 += kGroup) {
     const int g1 = g0 + kGroup < nt ? g0 + kGroup : nt;
     for (int k = g0; k < g1; ++k) {
-      hipLaunchKernelGGL(diag_block_kernel, dim3(1), dim3(DT), lds, st, M, X,
-                         np, k, fail, skip);
+      hipLaunchKernelGGL(diag_block_kernel, dim3(1, L), dim3(DT), lds, st, M,
+                         X, np, k, fail, skip, ls);
       const int rem = nt - k - 1;
       if (rem + k > 0)
-        hipLaunchKernelGGL(panel_finalize_kernel, dim3((rem + k) * 2),
-                           dim3(NT), 0, st, M, X, np, k, rem, skip);
+        hipLaunchKernelGGL(panel_finalize_kernel, dim3((rem + k) * 2, L),
+                           dim3(NT), 0, st, M, X, np, k, rem, skip, ls);
       if (k + 1 < g1) update(k, k + 1, k + 1, g1, k + 1, g1, true);
     }
     if (g1 < nt) update(g0, g1, g1, nt, g1, nt, false);
@@ -1033,20 +1056,22 @@ hipError_t launch_potrf_trtri(double* M, double* X, int64_t np, int* fail,
 
 hipError_t launch_trace_gemm(int precision, const void* A, int64_t lda,
                              int64_t Tp, const double* X, int64_t np,
-                             double* rn, hipStream_t st, const int* skip) {
-  dim3 g((unsigned)((np / BM) * ((Tp / BM + 7) / 8 * 8))), b(NT);
+                             double* rn, hipStream_t st, const int* skip,
+                             Lanes ls, int nlanes) {
+  dim3 g((unsigned)((np / BM) * ((Tp / BM + 7) / 8 * 8)), (unsigned)nlanes),
+      b(NT);
   switch (precision) {
     case 0:
       hipLaunchKernelGGL(trace_gemm_kernel<double>, g, b, 0, st,
-                         (const double*)A, lda, Tp, X, np, rn, skip);
+                         (const double*)A, lda, Tp, X, np, rn, skip, ls);
       break;
     case 1:
       hipLaunchKernelGGL(trace_gemm_kernel<float>, g, b, 0, st,
-                         (const float*)A, lda, Tp, X, np, rn, skip);
+                         (const float*)A, lda, Tp, X, np, rn, skip, ls);
       break;
     case 2:
       hipLaunchKernelGGL(trace_gemm_kernel<bf16_t>, g, b, 0, st,
-                         (const bf16_t*)A, lda, Tp, X, np, rn, skip);
+                         (const bf16_t*)A, lda, Tp, X, np, rn, skip, ls);
       break;
     default:
       return hipErrorInvalidValue;

@@ -83,24 +83,34 @@ hipError_t launch_center(const double* R, int64_t T, int64_t n, int64_t ldr,
 // ---- dense FP64 MFMA kernels (dense.hip) ----------------------------------
 constexpr int kTile = 128;  // output tile and Cholesky block size
 
+// Lanes of a grouped launch (blockIdx.y = lane): element strides between
+// the lanes' n x n matrices (B, M, X), T-vectors (s), row-norm arrays (rn)
+// and int strides between their flags (skip, fail).  All zero with one lane.
+struct Lanes {
+  int64_t mat = 0, vec = 0, rn = 0, flag = 0;
+};
+
 // B = A^T diag(s) A (full symmetric n x n, ldb = lda), s length Tp, non-null.
 hipError_t launch_syrk(int precision, const void* A, int64_t lda, int64_t Tp,
                        const double* s, double* B, hipStream_t st,
-                       const int* skip = nullptr);
+                       const int* skip = nullptr, Lanes ls = Lanes{},
+                       int nlanes = 1);
 // In-place Cholesky of the lower triangle of M (np x np, np multiple of
 // kTile) and X = L^-1 (lower triangle and the diagonal blocks' upper zeros;
 // the tiles above the diagonal blocks are left untouched).  *fail != 0 on exit
 // when a pivot was not positive.
 hipError_t launch_potrf_trtri(double* M, double* X, int64_t np, int* fail,
                               hipStream_t st, const int* skip = nullptr,
-                              int group = 0);
+                              int group = 0, Lanes ls = Lanes{},
+                              int nlanes = 1);
 // Sets the LDS attribute of the diagonal-block kernel (call before capture).
 hipError_t prepare_dense_kernels();
 // rn[J][t] = sum_{j in tile J} (sum_k A[t][k] X[j][k])^2  (X lower)
 hipError_t launch_trace_gemm(int precision, const void* A, int64_t lda,
                              int64_t Tp, const double* X, int64_t np,
                              double* rn, hipStream_t st,
-                             const int* skip = nullptr);
+                             const int* skip = nullptr, Lanes ls = Lanes{},
+                             int nlanes = 1);
 // ---- FP32 / BF16 matrix-core variants (lowp.hip), precision 1 or 2 ------
 // At (lda x Tp) = A^T at the storage precision.
 hipError_t launch_transpose_lp(int precision, const void* A, int64_t lda,

@@ -75,6 +75,29 @@ def test_frontier_budget_only_and_waves():
     ctx.close()
 
 
+@pytest.mark.parametrize("n,T", [(300, 1000), (520, 600)])
+def test_grouped_lanes_match_separate_streams(n, T):
+    """Lanes of one context advance in lockstep with grouped launches (the
+    SYRK, the factorisation and the trace GEMM of all lanes in one launch
+    each); the per-lane arithmetic is unchanged, so the weights equal those
+    of lanes on separate streams bit for bit, in waves, with graph replay or
+    eager, with and without return targets."""
+    print(f"[case] grouped lanes n={n} T={T}", flush=True)
+    R = synth.factor_returns(n, T, 3, 0, 5.0, 0.0, 11)
+    C4, tg = _frontier_instances(R, 3)
+    ctx = yb.Context(torch.from_numpy(R).cuda())
+    for targets in (tg, None):
+        Wsep, isep = yb.batch_solve([ctx] * len(C4), C4, targets, max_lanes=4,
+                                    grouped=False)
+        for use_graph in (True, False):
+            Wg, ig = yb.batch_solve([ctx] * len(C4), C4, targets, max_lanes=4,
+                                    use_graph=use_graph, grouped=True)
+            for b in range(len(C4)):
+                assert ig[b].status == 0 and ig[b].iterations == isep[b].iterations
+                assert np.array_equal(Wg[b].cpu().numpy(), Wsep[b].cpu().numpy())
+    ctx.close()
+
+
 def test_ragged_universes_batch():
     sizes = [17, 130, 257, 90]
     ctxs, Rs = [], []
