@@ -105,6 +105,25 @@ def test_fullscale_solve_certified_by_oracle(full):
     assert O.objective(A, mu, c, w) < O.objective(A, mu, c, x0)
 
 
+def test_fullscale_solve_objective_matches_oracle_solve(full):
+    """The full-scale solve against the oracle's own solve of the same
+    instance: the same iterations and the objective to a relative error of
+    1e-10 (FP64); the weights are certified separately by the oracle's
+    reduced gradient."""
+    R, A, mu, c, ctx = full["R"], full["A"], full["mu"], full["c"], full["ctx"]
+    w, info = ctx.solve(c)
+    w = w.cpu().numpy()
+    xr, ir = O.solve(R, c)
+    print(f"oracle: {ir.iterations} iterations, f {ir.f:.12e}; GPU: "
+          f"{info.iterations} iterations, f {info.f:.12e}", flush=True)
+    assert ir.status == 0 and info.status == 0
+    assert info.iterations == ir.iterations
+    f = O.objective(A, mu, c, w)
+    assert abs(f - ir.f) <= 1e-10 * abs(ir.f)
+    assert abs(info.f - ir.f) <= 1e-10 * abs(ir.f)
+    assert _oracle_gnorm(A, mu, c, w, None) <= 2e-8
+
+
 def test_fullscale_frontier_certified_by_oracle(full):
     R, A, mu, ctx = full["R"], full["A"], full["mu"], full["ctx"]
     targets = synth.frontier_targets(R, 5)[1:4:2]
