@@ -435,11 +435,12 @@ __global__ void sum_slabs_kernel(const double* __restrict__ part, int parts,
 // included); the strictly lower part of X stored transposed in the strict
 // upper triangle (X[i][j], i > j, at row j, column i); 1/L_ii in rdiag.
 //
-// Factorisation: right-looking in 16-column steps.  Wave 0 factors each
-// panel (the 16 columns from the diagonal down) in registers, the leaf's
-// values moving between lanes by DPP row broadcasts.  The trailing update A22 -= L21 L21^T
-// runs on the FP64 matrix cores: first the next panel's blocks, one per wave,
-// then the rest on waves 1-7 while wave 0 factors that panel.
+// Factorisation: right-looking in 16-column steps.  Waves 0 and 1 factor
+// each panel (the 16 columns from the diagonal down) in registers, 64 rows
+// below the leaf each, the leaf's values moving between lanes by DPP row
+// broadcasts.  The trailing update A22 -= L21 L21^T runs on the FP64 matrix
+// cores: first the next panel's blocks, one per wave, then the rest on the
+// other waves while the panel is factored.
 // Inverse: the eight leaves in parallel (one wave each), then recursive
 // doubling, X21 = -X22 (L21 X11), for half sizes 16, 32 and 64 on the matrix
 // cores.
@@ -449,7 +450,8 @@ constexpr int SB = 16;       // leaf width
 // MFMA operand read (16 lanes down a column, 4 k across) hit 64 distinct
 // banks
 constexpr int LDD = BM + 2;
-constexpr size_t kDiagLds = ((size_t)BM * LDD + BM) * sizeof(double);
+// BM x LDD tile, rdiag (BM), a zero (padded to 16 bytes)
+constexpr size_t kDiagLds = ((size_t)BM * LDD + BM + 2) * sizeof(double);
 
 __device__ __forceinline__ void wave_sync() {
   __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
@@ -490,14 +492,6 @@ __device__ __forceinline__ f64x4 mfma_block(FA fa, FB fb, int r0, int c0,
   }
 }
 
-// Value of v in lane l (l uniform), read through the scalar unit.
-__device__ __forceinline__ double bcast(double v, int l) {
-  const long long b = __double_as_longlong(v);
-  const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)b, l);
-  const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(b >> 32), l);
-  return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
-}
-
 // 1 / sqrt(p) for p > 0: hardware estimate refined by one Newton-Raphson
 // step y <- y + y (1 - p y^2) / 2 (relative error of the estimate squares).
 __device__ __forceinline__ double rsqrt_nr(double p) {
@@ -513,27 +507,45 @@ __device__ __forceinline__ double rcp_nr(double p) {
   return fma(r, fma(-p, r, 1.0), r);
 }
 
-// Value of v in lane n of this lane's row of 16 (DPP row broadcast).
+// Value of v in lane n of this lane's row of 16 (DPP row broadcast).  Every
+// lane has a valid source lane, so bound_ctrl changes no value; it lets the
+// compiler drop the initialisation of the destination.
 template <int N>
 __device__ __forceinline__ double row_bcast(double v) {
-  return __builtin_amdgcn_update_dpp(0.0, v, 0x150 + N, 0xF, 0xF, false);
+  return __builtin_amdgcn_update_dpp(0.0, v, 0x150 + N, 0xF, 0xF, true);
 }
 
-// Columns C >= J + 2 of every slot: A[r][C] -= u_r A[C][J] + v_r A[C][J+1].
+// Columns C >= J + 2 of every slot: A[r][C] -= u_r A[C][J] + v_r A[C][J+1],
+// two columns at a time so that four independent FMA chains interleave.
 template <int J, int C, int NS>
-__device__ __forceinline__ void panel_update(double (&a)[3][SB],
+__device__ __forceinline__ void panel_update(double (&a)[2][SB],
                                              const double (&u)[NS],
                                              const double (&v)[NS]) {
-  if constexpr (C < SB) {
+  if constexpr (C + 1 < SB) {
+    const double l0 = row_bcast<C>(a[0][J]), l1 = row_bcast<C>(a[0][J + 1]);
+    const double m0 = row_bcast<C + 1>(a[0][J]);
+    const double m1 = row_bcast<C + 1>(a[0][J + 1]);
+#pragma unroll
+    for (int s = 0; s < NS; ++s) {
+      a[s][C] = fma(-u[s], l0, a[s][C]);
+      a[s][C + 1] = fma(-u[s], m0, a[s][C + 1]);
+    }
+#pragma unroll
+    for (int s = 0; s < NS; ++s) {
+      a[s][C] = fma(-v[s], l1, a[s][C]);
+      a[s][C + 1] = fma(-v[s], m1, a[s][C + 1]);
+      // keep the update here: sunk to its first use it would hold every
+      // broadcast value live until the end of the panel
+      asm volatile("" : "+v"(a[s][C]), "+v"(a[s][C + 1]));
+    }
+    panel_update<J, C + 2, NS>(a, u, v);
+  } else if constexpr (C < SB) {
     const double l0 = row_bcast<C>(a[0][J]), l1 = row_bcast<C>(a[0][J + 1]);
 #pragma unroll
     for (int s = 0; s < NS; ++s) {
       a[s][C] = fma(-v[s], l1, fma(-u[s], l0, a[s][C]));
-      // keep the update here: sunk to its first use it would hold every
-      // broadcast value live until the end of the panel
       asm volatile("" : "+v"(a[s][C]));
     }
-    panel_update<J, C + 1, NS>(a, u, v);
   }
 }
 
@@ -543,7 +555,7 @@ __device__ __forceinline__ void panel_update(double (&a)[3][SB],
 // are; the columns after the pair lose P B^-1 P^T.  B^-1 comes from the
 // determinant in closed form, one reciprocal per pair on the serial chain.
 template <int J, int NS>
-__device__ __forceinline__ void panel_pairs(double (&a)[3][SB],
+__device__ __forceinline__ void panel_pairs(double (&a)[2][SB],
                                             double (&bb)[SB / 2][3],
                                             bool& bad) {
   if constexpr (J < SB) {
@@ -573,35 +585,45 @@ __device__ __forceinline__ void panel_pairs(double (&a)[3][SB],
   }
 }
 
+// Rows of the panel at c0 into a (see panel_chol); rows past the block read
+// the zero *zs.  Selecting the address rather than the value keeps every
+// read unconditional: a select of loaded values is turned into branches,
+// each paying a full LDS round trip.
+template <int NS>
+__device__ __forceinline__ void panel_load(const double* S, const double* zs,
+                                           int c0, int r1, int lane,
+                                           double (&a)[2][SB]) {
+  const int row[2] = {c0 + (lane & 15), r1 + lane};
+#pragma unroll
+  for (int s = 0; s < NS; ++s) {
+    const bool in = row[s] < BM;
+#pragma unroll
+    for (int j = 0; j < SB; ++j)
+      a[s][j] = *(in ? S + row[s] * LDD + c0 + j : zs);
+  }
+}
+
 // One wave: Cholesky factor of the panel S[c0:BM, c0:c0+SB], whose trailing
 // updates are complete.  Slot 0 of lane l holds leaf row c0 + l % 16 (each
 // row of 16 lanes a copy of the leaf, so that the leaf's entries reach every
-// lane by a row broadcast); slots 1 and 2 hold rows c0 + 16 + l and
-// c0 + 80 + l below the leaf (NS slots in use).  Block elimination with 2 x 2
-// pivots leaves, per column pair, the pair entries P of each row and the
-// pivot block B (kept as b11, b21, det); afterwards L_B = chol(B) and the
-// rows' factor entries P L_B^-T are formed off the serial chain.  Stores L (on and below the
+// lane by a row broadcast); slot 1 holds row r1 + l below the leaf (NS slots
+// in use).  Two waves may share a panel, each with its own rows below and its
+// own copy of the leaf's elimination; only the leaf owner stores the leaf and
+// reports a failed pivot.  Block elimination with 2 x 2 pivots leaves, per
+// column pair, the pair entries P of each row and the pivot block B (kept as
+// b11, b21, det); afterwards L_B = chol(B) and the rows' factor entries
+// P L_B^-T are formed off the serial chain.  Stores L (on and below the
 // diagonal) and 1 / L_jj in rd.  Leaf entries right of the diagonal are
 // updated too but never broadcast nor stored.
 template <int NS>
 __device__ __forceinline__ void panel_chol(double* S, double* rd, int c0,
-                                           int lane, int* fail) {
-  const int row[3] = {c0 + (lane & 15), c0 + 16 + lane, c0 + 80 + lane};
-  double a[3][SB], bb[SB / 2][3];
-#pragma unroll
-  for (int s = 0; s < 3; ++s) {
-    // rows past the block read row BM - 1 and are zeroed (no divergence)
-    const int rr = row[s] < BM ? row[s] : BM - 1;
-    const bool in = row[s] < BM;
-#pragma unroll
-    for (int j = 0; j < SB; ++j) {
-      const double v = s < NS ? S[rr * LDD + c0 + j] : 0.0;
-      a[s][j] = in ? v : 0.0;
-    }
-  }
+                                           int r1, bool owner, int lane,
+                                           int* fail, double (&a)[2][SB]) {
+  const int row[2] = {c0 + (lane & 15), r1 + lane};
+  double bb[SB / 2][3];
   bool bad = false;
   panel_pairs<0, NS>(a, bb, bad);
-  if (bad && lane == 0) atomicOr(fail, 1);
+  if (bad && owner && lane == 0) atomicOr(fail, 1);
   double rpr = 0.0;
 #pragma unroll
   for (int q = 0; q < SB / 2; ++q) {
@@ -620,51 +642,79 @@ __device__ __forceinline__ void panel_chol(double* S, double* rd, int c0,
   }
 #pragma unroll
   for (int j = 0; j < SB; ++j) {
-    if (lane < SB && j <= lane) S[row[0] * LDD + c0 + j] = a[0][j];
+    if (owner && lane < SB && j <= lane) S[row[0] * LDD + c0 + j] = a[0][j];
 #pragma unroll
     for (int s = 1; s < NS; ++s)
       if (row[s] < BM) S[row[s] * LDD + c0 + j] = a[s][j];
   }
-  if (lane < SB) rd[c0 + lane] = rpr;
+  if (owner && lane < SB) rd[c0 + lane] = rpr;
 }
 
-// Slots in use for the panel at c0: rows below the leaf, BM - c0 - SB of
-// them, over 64 lanes.
-__device__ __forceinline__ void panel_chol_at(double* S, double* rd, int c0,
-                                              int lane, int* fail) {
-  const int below = BM - c0 - SB;
-  if (below > 64)
-    panel_chol<3>(S, rd, c0, lane, fail);
-  else if (below > 0)
-    panel_chol<2>(S, rd, c0, lane, fail);
-  else
-    panel_chol<1>(S, rd, c0, lane, fail);
+// Waves that factor the panel at c0: the BM - c0 - SB rows below the leaf
+// take one 64-row slot per wave (waves 0 and 1 when there are more than 64).
+__device__ __forceinline__ int panel_waves(int c0) {
+  return BM - c0 - SB > 64 ? 2 : 1;
+}
+
+// The panel at c0 on waves [0, panel_waves(c0)); others(pw) runs on the
+// remaining waves.  Two waves each eliminate their own copy of the leaf, so
+// both read it before either stores (barrier between load and factor).
+template <class F>
+__device__ __forceinline__ void panel_step(double* S, double* rd,
+                                           const double* zs, int c0, int wave,
+                                           int lane, int* fail, F others) {
+  const int pw = panel_waves(c0);
+  double a[2][SB];
+  if (BM - c0 - SB > 0) {
+    const int r1 = c0 + SB + 64 * wave;
+    if (wave < pw) panel_load<2>(S, zs, c0, r1, lane, a);
+    if (pw == 2) __syncthreads();
+    if (wave < pw)
+      panel_chol<2>(S, rd, c0, r1, wave == 0, lane, fail, a);
+    else
+      others(pw);
+  } else if (wave == 0) {
+    panel_load<1>(S, zs, c0, c0 + SB, lane, a);
+    panel_chol<1>(S, rd, c0, c0 + SB, true, lane, fail, a);
+  } else {
+    others(1);
+  }
+}
+
+// Step m of the leaf inverse (see leaf_inv): row m of X, formed in lane m
+// from its accumulator, reaches the lanes of its row of 16 by a row
+// broadcast; lanes of later rows add L[r][m] X[m][c].
+template <int M>
+__device__ __forceinline__ void leaf_inv_step(const double (&a)[SB],
+                                              const double (&rp)[SB],
+                                              double (&x)[SB]) {
+  if constexpr (M + 1 < SB) {
+#pragma unroll
+    for (int c = 0; c <= M; ++c) {
+      const double xmc = ((c == M ? 1.0 : 0.0) - row_bcast<M>(x[c])) * rp[M];
+      x[c] = fma(a[M], xmc, x[c]);
+    }
+    leaf_inv_step<M + 1>(a, rp, x);
+  }
 }
 
 // One wave: inverse X of the factored leaf at (c0, c0), row by row:
-// X[m] = (e_m - sum_{m'<m} L[m][m'] X[m']) / L[m][m].  Lane r holds row r
-// and accumulates sum_{m<r} L[r][m] X[m][:]; row m of X is formed from lane
-// m's accumulator as it is broadcast.  The strict lower part of X is parked
-// transposed in the leaf's strict upper triangle.
-__device__ __forceinline__ void leaf_inv(double* S, const double* rd, int c0,
-                                         int lane) {
+// X[m] = (e_m - sum_{m'<m} L[m][m'] X[m']) / L[m][m].  Lane r holds row
+// r % 16 (each row of 16 lanes a copy) and accumulates
+// sum_{m<r} L[r][m] X[m][:]; row m of X is formed from lane m's accumulator
+// as it is broadcast.  The strict lower part of X is parked transposed in
+// the leaf's strict upper triangle.
+__device__ __forceinline__ void leaf_inv(double* S, const double* rd,
+                                         const double* zs, int c0, int lane) {
   const int r = lane & (SB - 1);
   double a[SB], rp[SB], x[SB];
 #pragma unroll
   for (int j = 0; j < SB; ++j) {
-    const double v = S[(c0 + r) * LDD + c0 + j];
-    a[j] = j < r ? v : 0.0;
+    a[j] = *(j < r ? S + (c0 + r) * LDD + c0 + j : zs);
     rp[j] = rd[c0 + j];
     x[j] = 0.0;
   }
-#pragma unroll
-  for (int m = 0; m + 1 < SB; ++m) {
-#pragma unroll
-    for (int c = 0; c <= m; ++c) {
-      const double xmc = ((c == m ? 1.0 : 0.0) - bcast(x[c], m)) * rp[m];
-      x[c] = fma(a[m], xmc, x[c]);
-    }
-  }
+  leaf_inv_step<0>(a, rp, x);
   const double rpr = rd[c0 + r];
 #pragma unroll
   for (int c = 0; c < SB; ++c) x[c] = ((c == r ? 1.0 : 0.0) - x[c]) * rpr;
@@ -686,40 +736,46 @@ __global__ void __launch_bounds__(DT) diag_block_kernel(double* M, double* X,
   fail += ln * ls.flag;
   if (skip) skip += ln * ls.flag;
   if (skip && *skip) return;
-  extern __shared__ double S[];  // BM x LDD, then rdiag (BM)
+  extern __shared__ double S[];  // BM x LDD, then rdiag (BM), then a zero
   double* rd = S + BM * LDD;
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  double* zs = rd + BM;
+  const int tid = threadIdx.x, lane = tid & 63;
+  // wave-uniform, kept in a scalar register so that branches on it are
+  // scalar branches
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   constexpr int NW = DT / 64;
   double* Mk = M + (int64_t)k * BM * ld + (int64_t)k * BM;
   double* Xk = X + (int64_t)k * BM * ld + (int64_t)k * BM;
   auto Lv = [&](int i, int j) { return S[i * LDD + j]; };  // i >= j only
-  // both candidates are read (in bounds for any i, j < BM) and selected, so
-  // operand reads do not diverge
+  // one unconditional read from the selected address (see panel_load)
   auto Xv = [&](int i, int j) {
-    const double u = S[j * LDD + i], d = rd[i];
-    return i > j ? u : (i == j ? d : 0.0);
+    return *(i > j ? S + j * LDD + i : (i == j ? rd + i : zs));
   };
   auto Xt = [&](int m, int c) { return Xv(c, m); };  // X^T
   {
     constexpr int PER = BM * BM / DT;
     double v[PER];
+    // the whole tile: nothing reads the part above the diagonal as data
+    // (the leaf entries there are updated but never broadcast, and X is
+    // parked there before it is read)
 #pragma unroll
     for (int q = 0; q < PER; ++q) {
       const int idx = tid + q * DT, i = idx / BM, c = idx % BM;
-      v[q] = c <= i ? Mk[(int64_t)i * ld + c] : 0.0;
+      v[q] = Mk[(int64_t)i * ld + c];
     }
 #pragma unroll
     for (int q = 0; q < PER; ++q) {
       const int idx = tid + q * DT, i = idx / BM, c = idx % BM;
       S[i * LDD + c] = v[q];
     }
+    if (tid == 0) *zs = 0.0;
   }
   __syncthreads();
   // ---- factorisation --------------------------------------------------------
-  // Step c0: the sub-panel below leaf c0, then the trailing update.  Wave 0
-  // updates the next leaf's diagonal block first and factors it while the
-  // other waves finish the trailing update (disjoint blocks).
-  if (wave == 0) panel_chol_at(S, rd, 0, lane, fail);
+  // Step c0: the sub-panel below leaf c0, then the trailing update.  The
+  // next panel's blocks are updated first; waves 0 (and 1) factor that panel
+  // while the other waves finish the trailing update (disjoint blocks).
+  panel_step(S, rd, zs, 0, wave, lane, fail, [](int) {});
   __syncthreads();
   auto Lt = [&](int m, int c) { return S[c * LDD + m]; };  // L^T
   for (int c0 = 0; c0 + SB < BM; c0 += SB) {
@@ -736,22 +792,20 @@ __global__ void __launch_bounds__(DT) diag_block_kernel(double* M, double* X,
     // the next panel's blocks first, one per wave
     if (wave < nb) trail(wave, 0);
     __syncthreads();
-    // wave 0 factors the next panel while the others update the rest
-    if (wave == 0) {
-      panel_chol_at(S, rd, r0, lane, fail);
-    } else {
-      for (int b = wave - 1; b < (nb - 1) * nb / 2; b += NW - 1) {
+    // waves 0 (and 1) factor the next panel while the others update the rest
+    panel_step(S, rd, zs, r0, wave, lane, fail, [&](int pw) {
+      for (int b = wave - pw; b < (nb - 1) * nb / 2; b += NW - pw) {
         int bi = 0;
         while ((bi + 1) * (bi + 2) / 2 <= b) ++bi;
         trail(bi + 1, b - bi * (bi + 1) / 2 + 1);
       }
-    }
+    });
     __syncthreads();
   }
   // ---- inverse: the leaves' inverses, one wave each, then
   // X21 = -X22 (L21 X11) at half sizes 16, 32 and 64 --------------------------
   static_assert(BM / SB == NW, "one leaf per wave");
-  leaf_inv(S, rd, wave * SB, lane);
+  leaf_inv(S, rd, zs, wave * SB, lane);
   __syncthreads();
   auto Tv = [&](int m, int c) { return S[c * LDD + m]; };  // parked T / X21
   for (int h = SB; h < BM; h *= 2) {
@@ -800,19 +854,21 @@ __global__ void __launch_bounds__(DT) diag_block_kernel(double* M, double* X,
   for (int idx = tid; idx < BM * BM; idx += DT) {
     const int i = idx / BM, c = idx % BM;
     if (c <= i) Mk[(int64_t)i * ld + c] = S[i * LDD + c];
-    Xk[(int64_t)i * ld + c] = c <= i ? Xv(i, c) : 0.0;
+    Xk[(int64_t)i * ld + c] = Xv(i, c);
   }
 }
 
 // Step k after the diagonal block, first launch (both need only L_kk^-1),
-// each 128 x 128 tile split in two 64-wide halves on separate workgroups:
+// each 128 x 128 tile split in BM / H bands of width H on separate
+// workgroups:
 //   tiles [0, rem):        L[I, k] = M[I, k] L_kk^-T, I = k + 1 + b, in place;
-//                          a half is a band of 64 rows, which depends only on
-//                          the same rows of M[I, k];
+//                          a band of H rows depends only on the same rows of
+//                          M[I, k];
 //   tiles [rem, rem + k):  X[k, j] = -L_kk^-1 S[k, j], j = b - rem, where S
 //                          accumulated sum_{m<k} L[k, m] X[m, j] in place; a
-//                          half is a band of 64 columns, which depends only
-//                          on the same columns of S[k, j].
+//                          band of H columns depends only on the same columns
+//                          of S[k, j].
+template <int H>
 __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2, 2)))
 panel_finalize_kernel(double* M, double* X, int64_t ld, int k, int rem,
                       const int* skip, Lanes ls) {
@@ -821,9 +877,9 @@ panel_finalize_kernel(double* M, double* X, int64_t ld, int k, int rem,
   X += ln * ls.mat;
   if (skip) skip += ln * ls.flag;
   if (skip && *skip) return;
-  constexpr int H = BM / 2;
+  constexpr int NBAND = BM / H;
   __shared__ double sA[2 * stage_size<BM>()], sB[2 * stage_size<BM>()];
-  const int b = blockIdx.x >> 1, half = (blockIdx.x & 1) * H;
+  const int b = blockIdx.x / NBAND, half = (blockIdx.x % NBAND) * H;
   const double* Xkk = X + (int64_t)k * BM * ld + (int64_t)k * BM;
   if (b < rem) {
     const int I = k + 1 + b;
@@ -1013,6 +1069,11 @@ hipError_t prepare_dense_kernels() {
 // later column and inverse row up to date, so the trailing matrix is read
 // and written once per group instead of once per step.
 constexpr int kDefaultGroup = 4;
+// Band width of the panel finalisation and sub-block of the in-group
+// updates: the steps on the factorisation's critical path launch few tiles,
+// so narrower pieces on more workgroups shorten each launch.
+constexpr int kFinBand = 32;
+constexpr int kStepTM = 32;
 
 hipError_t launch_potrf_trtri(double* M, double* X, int64_t np, int* fail,
                               hipStream_t st, const int* skip, int group,
@@ -1023,7 +1084,7 @@ hipError_t launch_potrf_trtri(double* M, double* X, int64_t np, int* fail,
   const size_t lds = kDiagLds;
   hipError_t pe = prepare_dense_kernels();
   if (pe != hipSuccess) return pe;
-  constexpr int Q64 = (BM / 64) * (BM / 64);   // 64 x 64 sub-blocks per tile
+  constexpr int QS = (BM / kStepTM) * (BM / kStepTM);  // sub-blocks per tile
   auto update = [&](int kA, int kB, int jlo, int jhi, int ilo, int ihi,
                     bool small) {
     int nu = 0;
@@ -1031,9 +1092,9 @@ hipError_t launch_potrf_trtri(double* M, double* X, int64_t np, int* fail,
     const int ni = (ihi - ilo) * kB;
     if (nu + ni == 0) return;
     if (small)
-      hipLaunchKernelGGL(update_kernel<64>, dim3((nu + ni) * Q64, L), dim3(NT),
-                         0, st, M, X, np, nt, kA, kB, jlo, jhi, ilo, nu, skip,
-                         ls);
+      hipLaunchKernelGGL(update_kernel<kStepTM>, dim3((nu + ni) * QS, L),
+                         dim3(NT), 0, st, M, X, np, nt, kA, kB, jlo, jhi, ilo,
+                         nu, skip, ls);
     else
       hipLaunchKernelGGL(update_kernel<BM>, dim3(nu + ni, L), dim3(NT), 0, st,
                          M, X, np, nt, kA, kB, jlo, jhi, ilo, nu, skip, ls);
@@ -1045,8 +1106,9 @@ hipError_t launch_potrf_trtri(double* M, double* X, int64_t np, int* fail,
                          X, np, k, fail, skip, ls);
       const int rem = nt - k - 1;
       if (rem + k > 0)
-        hipLaunchKernelGGL(panel_finalize_kernel, dim3((rem + k) * 2, L),
-                           dim3(NT), 0, st, M, X, np, k, rem, skip, ls);
+        hipLaunchKernelGGL(panel_finalize_kernel<kFinBand>,
+                           dim3((rem + k) * (BM / kFinBand), L), dim3(NT), 0,
+                           st, M, X, np, k, rem, skip, ls);
       if (k + 1 < g1) update(k, k + 1, k + 1, g1, k + 1, g1, true);
     }
     if (g1 < nt) update(g0, g1, g1, nt, g1, nt, false);
