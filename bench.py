@@ -84,10 +84,12 @@ def _conv(infos):
 
 
 def frontier_bench(workload, n_targets, n_plain, precision="fp64",
-                   autotune=True):
+                   autotune=True, pcg=False):
     """Frontier solves/s: batched (one call, lanes advancing together with
     graph-replayed iterations) vs plain single-instance solves of the same
-    instances, at ||reduced gradient|| <= 1e-8."""
+    instances, at ||reduced gradient|| <= 1e-8; pcg: the PCG configuration
+    (batched tangent solves: one pair of block products per CG step for all
+    lanes)."""
     import torch
 
     import synth
@@ -103,23 +105,25 @@ def frontier_bench(workload, n_targets, n_plain, precision="fp64",
     ctx = yb.Context(torch.from_numpy(R).cuda(), precision)
     if autotune:
         ctx.autotune()
-    ctx.frontier(C4[:2], tg[:2])            # warm-up (graph path, allocations)
+    opts = yb.default_opts(large=True) if pcg else None
+    ctx.frontier(C4[:2], tg[:2], opts=opts)  # warm-up (graph, allocations)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    W, infos = ctx.frontier(C4, tg)
+    W, infos = ctx.frontier(C4, tg, opts=opts)
     torch.cuda.synchronize()
     el_b = time.perf_counter() - t0
     its = [i.iterations for i in infos]
     t0 = time.perf_counter()
     plain_its = []
     for b in range(n_plain):
-        _, inf = ctx.solve(C4[b], target=tg[b])
+        _, inf = ctx.solve(C4[b], target=tg[b], opts=opts)
         plain_its.append(inf.iterations)
     torch.cuda.synchronize()
     el_p = time.perf_counter() - t0
     ctx.close()
     return {"workload": f"{workload}: n={n} T={T}, {len(tg)} instances "
-                        f"({n_targets} targets x 4 CRRA gamma)",
+                        f"({n_targets} targets x 4 CRRA gamma), "
+                        f"{'PCG' if pcg else 'direct'} configuration",
             "batched_solves_per_s": len(tg) / el_b,
             "plain_solves_per_s": n_plain / el_p,
             "speedup": (len(tg) / el_b) / (n_plain / el_p),
@@ -684,7 +688,7 @@ def main():
                     help="keep the built-in launch shapes")
     ap.add_argument("--only", default=None,
                     help="run the headline step and this one block only "
-                         "(frontier_n1000, ragged, warmstart, simplex, "
+                         "(frontier_n1000, frontier_n1000_pcg, ragged, warmstart, simplex, "
                          "conditioning, line_search, return_floor, regime, "
                          "precision, probe)")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -861,6 +865,9 @@ def main():
               "frontier_n1000": lambda: frontier_bench(
                   "n1000_T12000_frontier", 16, 8, args.precision,
                   not args.no_autotune),
+              "frontier_n1000_pcg": lambda: frontier_bench(
+                  "n1000_T12000_frontier", 16, 8, args.precision,
+                  not args.no_autotune, pcg=True),
               "ragged": lambda: ragged_bench(32, 6000, args.precision,
                                              not args.no_autotune),
               "warmstart": lambda: warmstart_bench(
@@ -877,6 +884,9 @@ def main():
         tune = not args.no_autotune
         fr = {"n1000_T12000": frontier_bench("n1000_T12000_frontier", 16, 8,
                                              args.precision, tune),
+              "n1000_T12000_pcg": frontier_bench("n1000_T12000_frontier", 16,
+                                                 8, args.precision, tune,
+                                                 pcg=True),
               "ragged_T6000": ragged_bench(32, 6000, args.precision, tune),
               "n5440_T12000": warmstart_bench(args.workload, 16,
                                               args.frontier_points, 16,

@@ -275,9 +275,16 @@ int yand_return_floor(yand_ctx* ctx, const double profile[3], double q,
  * row b of W_out (device, B x n row-major); infos (host, length B) is
  * nullable.  Instances advance together in lanes of up to 64 solves; after
  * the first iteration one outer iteration of all lanes is replayed from a
- * captured HIP graph, with one host synchronisation per iteration.  Direct
- * configuration only (opts->solver must be YAND_SOLVER_DIRECT).  Returns the
- * first error; per-instance status is in infos[b].status. */
+ * captured HIP graph, with one host synchronisation per iteration.  Both
+ * configurations: with opts->solver = YAND_SOLVER_PCG (exact trace only;
+ * trace_mode = YAND_TRACE_PROBE is YAND_ERR_ARG) the lanes' tangent solves
+ * advance together too, every CG step one pair of block products over A
+ * for all lanes (the search directions as the 64 columns of one block), and
+ * instances that neither converge nor fail continue through the single
+ * solve's stall recovery (twice the Krylov budget, then the direct solve;
+ * on the simplex face solver the projected trial steps 0.045 then 0.02),
+ * counted in infos[b].restarts and phase_iterations.  Returns the first
+ * error; per-instance status is in infos[b].status. */
 int yand_frontier_solve(yand_ctx* ctx, int64_t B, const double* C4,
                         const double* targets, const double* W0,
                         const yand_opts* opts, double* W_out,
@@ -293,7 +300,10 @@ int yand_frontier_solve(yand_ctx* ctx, int64_t B, const double* C4,
  * exact trace's products in FP64 advance in lockstep on one stream: the
  * SYRK, the factorisation with its inverse and the trace GEMM of all lanes
  * run as single grouped launches (the same kernels and tile order per lane,
- * so the results are those of separate lanes bit for bit). */
+ * so in the direct configuration the results are those of separate lanes
+ * bit for bit; the PCG configuration's batched Hessian products sum in
+ * another order than the per-lane passes, so there they agree to rounding).
+ * The PCG configuration is accepted as in yand_frontier_solve. */
 int yand_batch_solve(int64_t B, yand_ctx* const* ctxs, const double* C4,
                      const double* targets, const double* const* W0,
                      const yand_opts* opts, double* const* W_out,

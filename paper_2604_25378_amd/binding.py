@@ -388,7 +388,7 @@ class Context:
 
     def frontier(self, C4, targets=None, opts: yand_opts | None = None,
                  W0=None):
-        """Batched solve of B instances on this context's A (direct solver).
+        """Batched solve of B instances on this context's A (direct or PCG).
 
         C4: B x 4 preference vectors; targets: B return targets or None;
         W0: B x n starting weights (device) or None.

@@ -90,8 +90,9 @@ struct Work {
   DevScalars* sc = nullptr;
   bool own_sc = true;
   // lockstep lanes: B, M, X, rn and s_t point into the batch's strided
-  // blocks (freed by the batch, not by the lane)
-  bool shared_dense = false;
+  // blocks (freed by the batch, not by the lane); with the PCG
+  // configuration pcg_p and hv are rows of the batch's 64 x lda blocks
+  bool shared_dense = false, shared_pcg = false;
   DevScalars hs{};
   Prof* prof = nullptr;
 };
@@ -210,6 +211,7 @@ void flush_timed(Prof& p, hipStream_t st) {
 
 void free_work(Work& w) {
   if (w.shared_dense) w.B = w.M = w.X = w.rn = w.s_t = nullptr;
+  if (w.shared_pcg) w.pcg_p = w.hv = nullptr;
   double* ptrs[] = {w.x,     w.g,      w.d,     w.z,      w.wv,   w.q,
                     w.AE,    w.E,      w.W,     w.t3,     w.r,    w.y,
                     w.y2,    w.hv,     w.s_t,   w.pcg_s,  w.pcg_res,
@@ -664,21 +666,46 @@ __device__ double precond_diag(const double* bd, int64_t bs, int64_t j,
 // needs two block reductions.  Taking x^T y alone would be exact for x in S
 // but lets the rounding residue of the residual outside S into the products
 // once the residual itself is small.
-__global__ void __launch_bounds__(PT)
-pcg_init_kernel(const double* __restrict__ r, const double* __restrict__ B,
-                int64_t bs, const double* __restrict__ E, int p, int64_t n,
-                double* s, double* res, double* pv, double* u,
-                DevScalars* sc, const double* __restrict__ mask) {
-  __shared__ double sh[8 * 16];
+// Operands of one projected PCG solve: right-hand side r, the diagonal of
+// B at bd[j * bs], the frame E (p rows of n), iterate s, residual res,
+// search direction pv, preconditioned residual u, scratch Ap, the product
+// hp = B pv of the current step, the lane's scalars and face mask.
+struct PcgLane {
+  const double* r;
+  const double* bd;
+  int64_t bs;
+  const double* E;
+  int p;
+  int64_t n;
+  double *s, *res, *pv, *u, *Ap;
+  const double* hp;
+  DevScalars* sc;
+  const double* mask;
+};
+
+// A lane already done at this iteration takes no step (cgdone, 0 steps).
+__device__ void pcg_init_body(const PcgLane& L, double* sh) {
   const int tid = threadIdx.x;
+  DevScalars* sc = L.sc;
+  if (sc->done) {
+    if (tid == 0) {
+      sc->cgit = 0;
+      sc->cgdone = 1;
+    }
+    return;
+  }
   const double lam = sc->lambda;
+  const int p = L.p;
+  const int64_t n = L.n;
+  const double *r = L.r, *E = L.E, *mask = L.mask;
   // E^T u (p), E^T r (p), r^T u, r^T r
   double dt[8] = {0, 0, 0, 0, 0, 0, 0, 0};
   for (int64_t j = tid; j < n; j += PT) {
-    s[j] = 0.0;
+    L.s[j] = 0.0;
     const double rj = r[j];
-    const double uj = (mask ? mask[j] : 1.0) * rj / precond_diag(B, bs, j, lam);
-    u[j] = uj;
+    const double uj =
+        (mask ? mask[j] : 1.0) * rj / precond_diag(L.bd, L.bs, j, lam);
+    L.u[j] = uj;
     for (int a = 0; a < p; ++a) {
       dt[a] += E[a * n + j] * uj;
       dt[3 + a] += E[a * n + j] * rj;
@@ -691,11 +718,11 @@ pcg_init_kernel(const double* __restrict__ r, const double* __restrict__ B,
   const double rr = dt[7];
   for (int a = 0; a < p; ++a) rz -= dt[3 + a] * dt[a];
   for (int64_t j = tid; j < n; j += PT) {
-    double uj = u[j];
+    double uj = L.u[j];
     for (int a = 0; a < p; ++a) uj -= dt[a] * E[a * n + j];
-    u[j] = uj;
-    pv[j] = uj;
-    res[j] = r[j];
+    L.u[j] = uj;
+    L.pv[j] = uj;
+    L.res[j] = r[j];
   }
   if (tid == 0) {
     sc->aux[0] = rz;
@@ -707,16 +734,15 @@ pcg_init_kernel(const double* __restrict__ r, const double* __restrict__ B,
   }
 }
 
-__global__ void __launch_bounds__(PT)
-pcg_update_kernel(const double* __restrict__ Hp, const double* __restrict__ B,
-                  int64_t bs, const double* __restrict__ E, int p, int64_t n,
-                  double* s, double* res, double* pv, double* u, double* Ap,
-                  DevScalars* sc, const double* __restrict__ mask,
-                  double tol) {
+__device__ void pcg_update_body(const PcgLane& L, double tol, double* sh) {
+  DevScalars* sc = L.sc;
   if (sc->cgdone) return;
-  __shared__ double sh[8 * 16];
   const int tid = threadIdx.x;
   const double lam = sc->lambda;
+  const int p = L.p;
+  const int64_t n = L.n;
+  const double *E = L.E, *mask = L.mask, *Hp = L.hp;
+  double *pv = L.pv, *Ap = L.Ap;
   // E^T Ap (p), E^T pv (p), pv^T Ap
   double d1[7] = {0, 0, 0, 0, 0, 0, 0};
   for (int64_t j = tid; j < n; j += PT) {
@@ -738,11 +764,12 @@ pcg_update_kernel(const double* __restrict__ Hp, const double* __restrict__ B,
   for (int64_t j = tid; j < n; j += PT) {
     double a = Ap[j];
     for (int k = 0; k < p; ++k) a -= d1[k] * E[k * n + j];
-    s[j] += al * pv[j];
-    const double rj = res[j] - al * a;
-    res[j] = rj;
-    const double uj = (mask ? mask[j] : 1.0) * rj / precond_diag(B, bs, j, lam);
-    u[j] = uj;
+    L.s[j] += al * pv[j];
+    const double rj = L.res[j] - al * a;
+    L.res[j] = rj;
+    const double uj =
+        (mask ? mask[j] : 1.0) * rj / precond_diag(L.bd, L.bs, j, lam);
+    L.u[j] = uj;
     for (int k = 0; k < p; ++k) {
       d2[k] += E[k * n + j] * uj;
       d2[3 + k] += E[k * n + j] * rj;
@@ -756,9 +783,9 @@ pcg_update_kernel(const double* __restrict__ Hp, const double* __restrict__ B,
   for (int k = 0; k < p; ++k) rzn -= d2[3 + k] * d2[k];
   const double beta = rz > 0.0 ? rzn / rz : 0.0;
   for (int64_t j = tid; j < n; j += PT) {
-    double uj = u[j];
+    double uj = L.u[j];
     for (int k = 0; k < p; ++k) uj -= d2[k] * E[k * n + j];
-    u[j] = uj;
+    L.u[j] = uj;
     pv[j] = uj + beta * pv[j];
   }
   if (tid == 0) {
@@ -772,32 +799,98 @@ pcg_update_kernel(const double* __restrict__ Hp, const double* __restrict__ B,
   }
 }
 
+__global__ void __launch_bounds__(PT) pcg_init_kernel(PcgLane L) {
+  __shared__ double sh[8 * 16];
+  pcg_init_body(L, sh);
+}
+
+__global__ void __launch_bounds__(PT) pcg_update_kernel(PcgLane L,
+                                                        double tol) {
+  __shared__ double sh[8 * 16];
+  pcg_update_body(L, tol, sh);
+}
+
+// Lane-batched forms: workgroup b runs lane b's solve.
+__global__ void __launch_bounds__(PT)
+pcg_init_lanes_kernel(const PcgLane* __restrict__ Ls) {
+  __shared__ double sh[8 * 16];
+  pcg_init_body(Ls[blockIdx.x], sh);
+}
+
+__global__ void __launch_bounds__(PT)
+pcg_update_lanes_kernel(const PcgLane* __restrict__ Ls, double tol) {
+  __shared__ double sh[8 * 16];
+  pcg_update_body(Ls[blockIdx.x], tol, sh);
+}
+
+// *flag = 1 once every lane's solve has stopped (the block products of later
+// steps are skipped).
+__global__ void pcg_alldone_kernel(const PcgLane* __restrict__ Ls, int nl,
+                                   int* flag) {
+  __shared__ int any;
+  if (threadIdx.x == 0) any = 0;
+  __syncthreads();
+  for (int l = threadIdx.x; l < nl; l += blockDim.x)
+    if (!Ls[l].sc->cgdone) atomicOr(&any, 1);
+  __syncthreads();
+  if (threadIdx.x == 0) *flag = any ? 0 : 1;
+}
+
+PcgLane pcg_lane(const Data& D, Work& w, int p0, const DirOpts& o,
+                 const double* bd, int64_t bs) {
+  PcgLane L;
+  L.r = w.r;
+  L.bd = bd;
+  L.bs = bs;
+  L.E = w.E;
+  L.p = p0 + 1;
+  L.n = D.n;
+  L.s = w.pcg_s;
+  L.res = w.pcg_res;
+  L.pv = w.pcg_p;
+  L.u = w.pcg_u;
+  L.Ap = w.y;
+  L.hp = w.hv;
+  L.sc = w.sc;
+  L.mask = face_mask(w, o);
+  return L;
+}
+
+// The direction from the tangent solve s (and the boundary block's first
+// part on a face).
+int dir_from_solve(const Data& D, Work& w, int p0, const double* x,
+                   const DirOpts& o, double* d) {
+  HIPTRY(launch_direction(w.pcg_s, w.E, p0 + 1, D.n, x, D.mu, o.tau,
+                          o.simplex, d, w.sc, w.st, face_mask(w, o)));
+  if (o.faces)
+    HIPTRY(launch_boundary(x, w.g, D.mu, D.n, o.tau, o.eta, d, w.ptmp, w.mask,
+                           w.hold, w.sc, w.st));
+  return YAND_OK;
+}
+
+// Projected PCG for the tangent system, krylov_maxit steps enqueued without
+// host synchronisation: the update kernel raises cgdone at convergence or
+// breakdown, and every later HVP pass and update returns at once.  The step
+// count is left in sc->cgit.
+int dir_pcg_enqueue(const Data& D, Work& w, const double c[4], int p0,
+                    const double* x, const DirOpts& o, double* d,
+                    const double* bd, int64_t bs) {
+  const PcgLane L = pcg_lane(D, w, p0, o, bd, bs);
+  hipLaunchKernelGGL(pcg_init_kernel, dim3(1), dim3(PT), 0, w.st, L);
+  for (int it = 0; it < o.krylov_maxit; ++it) {
+    TRY(hvp_cached(D, w, c, w.pcg_p, w.hv, nullptr, &w.sc->cgdone));
+    hipLaunchKernelGGL(pcg_update_kernel, dim3(1), dim3(PT), 0, w.st, L,
+                       o.krylov_tol);
+  }
+  return dir_from_solve(D, w, p0, x, o, d);
+}
+
 int dir_pcg_solve(const Data& D, Work& w, const double c[4], int p0,
                   const double* x, const DirOpts& o, double* d,
                   DirStats* stats, const double* bd, int64_t bs) {
-  const int64_t n = D.n;
-  const int p = p0 + 1;
-  const double* mask = face_mask(w, o);
-  hipLaunchKernelGGL(pcg_init_kernel, dim3(1), dim3(PT), 0, w.st, w.r, bd, bs,
-                     w.E, p, n, w.pcg_s, w.pcg_res, w.pcg_p, w.pcg_u, w.sc,
-                     mask);
-  // krylov_maxit iterations enqueued without host synchronisation: the
-  // update kernel raises cgdone at convergence or breakdown, and every later
-  // HVP pass and update returns at once
-  for (int it = 0; it < o.krylov_maxit; ++it) {
-    TRY(hvp_cached(D, w, c, w.pcg_p, w.hv, nullptr, &w.sc->cgdone));
-    hipLaunchKernelGGL(pcg_update_kernel, dim3(1), dim3(PT), 0, w.st, w.hv,
-                       bd, bs, w.E, p, n, w.pcg_s, w.pcg_res, w.pcg_p,
-                       w.pcg_u, w.y, w.sc, mask, o.krylov_tol);
-  }
+  TRY(dir_pcg_enqueue(D, w, c, p0, x, o, d, bd, bs));
   TRY(sync_scalars(w));
-  const int it = w.hs.cgit;
-  if (stats) stats->cg += it;
-  HIPTRY(launch_direction(w.pcg_s, w.E, p, n, x, D.mu, o.tau, o.simplex, d,
-                          w.sc, w.st, mask));
-  if (o.faces)
-    HIPTRY(launch_boundary(x, w.g, D.mu, n, o.tau, o.eta, d, w.ptmp, w.mask,
-                           w.hold, w.sc, w.st));
+  if (stats) stats->cg += w.hs.cgit;
   return YAND_OK;
 }
 
@@ -1000,7 +1093,10 @@ int enqueue_iteration(const Data& D, Work& w, const double c[4], int p0,
   TRY(dir_front(D, w, c, p0, o, skip));
   TRY(dir_factor(D, w, p0, skip, face_mask(w, o)));
   TRY(dir_trace(D, w, c, p0, o, skip, face_mask(w, o)));
-  TRY(dir_direct_solve(D, w, p0, w.x, o, w.d, skip));
+  if (o.solver == YAND_SOLVER_PCG)
+    TRY(dir_pcg_enqueue(D, w, c, p0, w.x, o, w.d, w.B, D.lda + 1));
+  else
+    TRY(dir_direct_solve(D, w, p0, w.x, o, w.d, skip));
   TRY(step_line(D, w, c, o, skip));
   HIPTRY(launch_axpy(w.x, w.d, D.n, w.sc, w.st));
   return YAND_OK;
@@ -1010,13 +1106,23 @@ int enqueue_iteration(const Data& D, Work& w, const double c[4], int p0,
 // the SYRK, the factorisation with its inverse and the trace GEMM of all
 // lanes run as single grouped launches (blockIdx.y = lane) over strided
 // per-lane blocks, so the lanes' tiles fill the GPU together; the passes
-// and vector kernels run per lane in between.
+// and vector kernels run per lane in between.  With the PCG configuration
+// the lanes' tangent solves also run together: their search directions are
+// the rows of one 64 x lda block P, so each CG step is one pair of block
+// products over A for every lane, HP = (A^T diag(s_l) A P)^T, between
+// lane-batched init and update kernels.
 struct Group {
   int nl = 0;
   Lanes ls;
   double *s = nullptr, *B = nullptr, *M = nullptr, *X = nullptr,
          *rn = nullptr;
   int *skip = nullptr, *fail = nullptr;
+  // PCG: P and HP (64 x lda), Z and ZS (Tp x 64), split partials, the lanes'
+  // operands (device array) and the all-stopped flag
+  double *P = nullptr, *HP = nullptr, *Z = nullptr, *ZS = nullptr,
+         *Zp = nullptr, *Yp = nullptr;
+  PcgLane* pl = nullptr;
+  int* cgall = nullptr;
 };
 
 struct LaneRef {
@@ -1052,7 +1158,32 @@ int enqueue_group(const std::vector<LaneRef>& lanes, const DirOpts& o,
     Work& w = *L.w;
     const int* skip = &w.sc->done;
     TRY(dir_trace_post(D, w, L.c, L.p0, skip, face_mask(w, o)));
-    TRY(dir_direct_solve(D, w, L.p0, w.x, o, w.d, skip));
+    if (o.solver != YAND_SOLVER_PCG)
+      TRY(dir_direct_solve(D, w, L.p0, w.x, o, w.d, skip));
+  }
+  if (o.solver == YAND_SOLVER_PCG) {
+    const unsigned nl = (unsigned)G.nl;
+    hipLaunchKernelGGL(pcg_init_lanes_kernel, dim3(nl), dim3(PT), 0, st, G.pl);
+    hipLaunchKernelGGL(pcg_alldone_kernel, dim3(1), dim3(64), 0, st, G.pl,
+                       G.nl, G.cgall);
+    for (int it = 0; it < o.krylov_maxit; ++it) {
+      HIPTRY(launch_block_av(D.precision, D.A, D.lda, Tp, G.P, G.Zp, G.Z, st,
+                             G.cgall));
+      HIPTRY(launch_lane_scale(G.Z, G.s, G.ls.vec, G.nl, Tp, G.ZS, st,
+                               G.cgall));
+      HIPTRY(launch_block_atz(D.precision, D.A, D.lda, Tp, G.ZS, nullptr,
+                              G.Yp, G.HP, st, G.cgall));
+      hipLaunchKernelGGL(pcg_update_lanes_kernel, dim3(nl), dim3(PT), 0, st,
+                         G.pl, o.krylov_tol);
+      hipLaunchKernelGGL(pcg_alldone_kernel, dim3(1), dim3(64), 0, st, G.pl,
+                         G.nl, G.cgall);
+    }
+    for (const auto& L : lanes)
+      TRY(dir_from_solve(D, *L.w, L.p0, L.w->x, o, L.w->d));
+  }
+  for (const auto& L : lanes) {
+    Work& w = *L.w;
+    const int* skip = &w.sc->done;
     TRY(step_line(D, w, L.c, o, skip));
     HIPTRY(launch_axpy(w.x, w.d, D.n, w.sc, w.st));
   }
@@ -1160,6 +1291,9 @@ struct Lane {
   int rc = YAND_OK;
   int small = 0;
   double f_prev = NAN;
+  // stall-recovery phase of the lane and its iteration count when the phase
+  // began (the phase's budget counts from there)
+  int phase = 0, it0 = 0;
   yand_info info{};
 };
 
@@ -1201,6 +1335,10 @@ int after_iteration(Lane& L, const yand_opts& opts, const DirOpts& o) {
   L.info.dense_traces++;
   L.info.third_passes++;
   L.info.ls_passes++;
+  if (o.solver == YAND_SOLVER_PCG) {
+    L.info.cg_iters += w.hs.cgit;
+    L.info.hvp_passes += w.hs.cgit;
+  }
   if (w.hs.projected) L.info.projected_steps++;
   L.info.lambda_used = w.hs.lambda;
   if (w.hs.status != 0) {
@@ -1223,8 +1361,9 @@ int after_iteration(Lane& L, const yand_opts& opts, const DirOpts& o) {
     L.small = 0;
   }
   L.f_prev = A[0] - dec;
-  L.info.phase_iterations[0] = L.info.iterations;
-  if (L.info.iterations >= opts.max_iter) L.active = false;
+  const int pit = L.info.iterations - L.it0;
+  L.info.phase_iterations[L.phase] = pit;
+  if (pit >= opts.max_iter) L.active = false;
   return YAND_OK;
 }
 
@@ -1972,7 +2111,9 @@ static int batch_solve(int64_t B, yand_ctx* const* ctxs, const double* C4,
   else
     yand_default_opts(&opts);
   if (!valid_opts(opts)) return YAND_ERR_ARG;
-  if (opts.solver != YAND_SOLVER_DIRECT) return YAND_ERR_ARG;
+  // the probe estimate of the trace runs in single solves only
+  if (opts.solver == YAND_SOLVER_PCG && opts.trace_mode != YAND_TRACE_EXACT)
+    return YAND_ERR_ARG;
   for (int64_t b = 0; b < B; ++b) {
     if (!ctxs[b] || !W_out[b]) return YAND_ERR_ARG;
     TRY(check_c(C4 + 4 * b));
@@ -1996,6 +2137,11 @@ static int batch_solve(int64_t B, yand_ctx* const* ctxs, const double* C4,
   o.faces = o.simplex && opts.eta > 0.0 && !targets;
   o.eta = opts.eta;
   o.select = opts.linesearch == YAND_LS_ARMIJO ? 2 : 1;
+  o.solver = opts.solver;
+  o.krylov_tol = opts.krylov_tol;
+  o.krylov_maxit = opts.krylov_maxit;
+  o.reg = opts.solver == YAND_SOLVER_PCG ? opts.regularization : 0.0;
+  const bool pcg = opts.solver == YAND_SOLVER_PCG;
   // lane count: bounded by max_lanes and by free device memory
   size_t freeb = 0, totalb = 0;
   (void)hipMemGetInfo(&freeb, &totalb);
@@ -2047,6 +2193,32 @@ static int batch_solve(int64_t B, yand_ctx* const* ctxs, const double* C4,
   lockstep = lockstep && (big.precision == YAND_FP64 || opts.dense_fp64);
   Group grp;
   double* gblk[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
+  double* pblk[6] = {nullptr, nullptr, nullptr, nullptr, nullptr, nullptr};
+  if (lockstep && pcg) {
+    // batched tangent solves: P, HP, Z, ZS and the split partials
+    int sv = 1, sz = 1;
+    block_splits(big.Tp, big.lda, &sv, &sz);
+    const int64_t bw = kBlockWidth;
+    const int64_t sizes[6] = {bw * big.lda, bw * big.lda, big.Tp * bw,
+                              big.Tp * bw, sv * big.Tp * bw,
+                              sz * bw * big.lda};
+    for (int q = 0; q < 6 && rc == YAND_OK; ++q)
+      rc = alloc((void**)&pblk[q], (size_t)sizes[q] * sizeof(double));
+    if (rc == YAND_OK)
+      rc = alloc((void**)&grp.pl, kBlockWidth * sizeof(PcgLane));
+    if (rc == YAND_OK) rc = alloc((void**)&grp.cgall, sizeof(int));
+    // rows of P past the lanes (and past n) stay zero for the products
+    if (rc == YAND_OK &&
+        hipMemsetAsync(pblk[0], 0, (size_t)sizes[0] * sizeof(double), cs) !=
+            hipSuccess)
+      rc = YAND_ERR_HIP;
+    grp.P = pblk[0];
+    grp.HP = pblk[1];
+    grp.Z = pblk[2];
+    grp.ZS = pblk[3];
+    grp.Zp = pblk[4];
+    grp.Yp = pblk[5];
+  }
   if (lockstep) {
     const int64_t mat = big.lda * big.lda, rnl = big.nt * big.Tp;
     const int64_t sizes[5] = {mat, mat, mat, rnl, big.Tp};
@@ -2090,6 +2262,13 @@ static int batch_solve(int64_t B, yand_ctx* const* ctxs, const double* C4,
       w.X = grp.X + i * grp.ls.mat;
       w.rn = grp.rn + i * grp.ls.rn;
       w.shared_dense = true;
+      if (pcg) {
+        dfree(w.pcg_p);
+        dfree(w.hv);
+        w.pcg_p = grp.P + i * big.lda;
+        w.hv = grp.HP + i * big.lda;
+        w.shared_pcg = true;
+      }
     }
     if (rc == YAND_OK) rc = ensure_dense(w, big);
     if (rc == YAND_OK) rc = init_work(w, big);
@@ -2118,8 +2297,73 @@ static int batch_solve(int64_t B, yand_ctx* const* ctxs, const double* C4,
       if (hipStreamSynchronize(w.st) != hipSuccess) rc = YAND_ERR_HIP;
     }
     if (rc != YAND_OK) break;
-    rc = run_lanes(lanes, opts, o, cs, use_graph != 0, host_sc.data(),
-                   dev_sc, lockstep ? &grp : nullptr);
+    // the lanes' solve operands for the batched tangent solves (per phase:
+    // the face mask and the preconditioner source depend on it)
+    auto upload_pcg = [&](const DirOpts& od) -> int {
+      if (!(lockstep && od.solver == YAND_SOLVER_PCG)) return YAND_OK;
+      std::vector<PcgLane> pl(cnt);
+      for (int64_t i = 0; i < cnt; ++i)
+        pl[i] = pcg_lane(*lanes[i].D, *lanes[i].w, lanes[i].p0, od,
+                         lanes[i].w->B, lanes[i].D->lda + 1);
+      HIPTRY(hipMemcpyAsync(grp.pl, pl.data(), cnt * sizeof(PcgLane),
+                            hipMemcpyHostToDevice, cs));
+      HIPTRY(hipStreamSynchronize(cs));
+      return YAND_OK;
+    };
+    rc = upload_pcg(o);
+    if (rc == YAND_OK)
+      rc = run_lanes(lanes, opts, o, cs, use_graph != 0, host_sc.data(),
+                     dev_sc, lockstep ? &grp : nullptr);
+    // stall recovery of the PCG configuration, as in a single solve: the
+    // lanes that neither converged nor failed continue from where they
+    // stopped, with twice the Krylov budget, then with the direct solve
+    // (budget set), or with the projected trial steps 0.045 then 0.02 (the
+    // simplex boundary block)
+    if (pcg && opts.stall_recovery) {
+      struct Phase {
+        int solver, kmax;
+        double reg, eta;
+      };
+      std::vector<Phase> phases;
+      if (o.faces) {
+        phases.push_back({YAND_SOLVER_PCG, opts.krylov_maxit,
+                          opts.regularization, 0.045});
+        phases.push_back({YAND_SOLVER_PCG, opts.krylov_maxit,
+                          opts.regularization, 0.02});
+      } else {
+        phases.push_back({YAND_SOLVER_PCG, 2 * opts.krylov_maxit,
+                          opts.regularization, opts.eta});
+        phases.push_back({YAND_SOLVER_DIRECT, 0, 0.0, opts.eta});
+      }
+      for (size_t ph = 0; ph < phases.size() && rc == YAND_OK; ++ph) {
+        bool any = false;
+        for (auto& L : lanes) {
+          L.active = false;
+          if (L.converged || L.rc != YAND_OK) continue;
+          L.active = opts.restart_max_iter > 0;
+          L.stalled = false;
+          L.small = 0;
+          L.f_prev = NAN;
+          L.frozen_set = false;
+          L.info.restarts++;
+          L.phase = (int)ph + 1;
+          L.it0 = L.info.iterations;
+          any = true;
+        }
+        if (!any) break;
+        yand_opts op = opts;
+        op.max_iter = opts.restart_max_iter;
+        DirOpts od = o;
+        od.solver = phases[ph].solver;
+        od.krylov_maxit = phases[ph].kmax;
+        od.reg = phases[ph].reg;
+        od.eta = phases[ph].eta;
+        rc = upload_pcg(od);
+        if (rc == YAND_OK)
+          rc = run_lanes(lanes, op, od, cs, use_graph != 0, host_sc.data(),
+                         dev_sc, lockstep ? &grp : nullptr);
+      }
+    }
     for (int64_t i = 0; i < cnt && rc == YAND_OK; ++i) {
       Lane& L = lanes[i];
       const int64_t b = start + i;
@@ -2140,6 +2384,9 @@ static int batch_solve(int64_t B, yand_ctx* const* ctxs, const double* C4,
     rc = YAND_ERR_HIP;
   for (auto& w : works) free_work(w);
   for (double* q : gblk) dfree(q);
+  for (double* q : pblk) dfree(q);
+  dfree(grp.pl);
+  dfree(grp.cgall);
   (void)hipFree(dev_sc);
   (void)hipEventRecord(ev_out, cs);
   (void)hipStreamWaitEvent(caller, ev_out, 0);

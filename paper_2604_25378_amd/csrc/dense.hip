@@ -427,6 +427,22 @@ __global__ void sum_slabs_kernel(const double* __restrict__ part, int parts,
   }
 }
 
+// ZS[t][l] = Z[t][l] s_l[t] for lanes l < nl (s_l at s + l * vec), 0 for
+// the block's unused columns: the per-lane weights of a batched Hessian
+// product A^T diag(s_l) A v_l.
+__global__ void lane_scale_kernel(const double* __restrict__ Z,
+                                  const double* __restrict__ s, int64_t vec,
+                                  int nl, int64_t Tp, double* __restrict__ ZS,
+                                  const int* skip) {
+  if (skip && *skip) return;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+       i < Tp * BW; i += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t t = i / BW;
+    const int l = (int)(i % BW);
+    ZS[i] = l < nl ? Z[i] * s[(int64_t)l * vec + t] : 0.0;
+  }
+}
+
 // ------------------------------------------------------ blocked Cholesky --
 // Diagonal block k: Cholesky factor L_kk of the 128 x 128 block and its
 // inverse X_kk = L_kk^-1, computed in LDS by one workgroup of 8 waves.
@@ -1215,6 +1231,15 @@ hipError_t launch_block_atz(int precision, const void* A, int64_t lda,
     launch_atz_t<false>(precision, A, lda, Tp, Z, s, tc, Yp, g, st, skip);
   hipLaunchKernelGGL(sum_slabs_kernel, dim3(1024), dim3(256), 0, st, Yp, parts,
                      lda * BW, Y, skip);
+  return hipGetLastError();
+}
+
+hipError_t launch_lane_scale(const double* Z, const double* s, int64_t vec,
+                             int nl, int64_t Tp, double* ZS, hipStream_t st,
+                             const int* skip) {
+  if (nl < 1 || nl > BW) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(lane_scale_kernel, dim3(1024), dim3(256), 0, st, Z, s,
+                     vec, nl, Tp, ZS, skip);
   return hipGetLastError();
 }
 

@@ -166,6 +166,12 @@ hipError_t launch_bpcg_update(const double* HP, const double* bd,
                               double* AP, double* cs, int* flags,
                               const DevScalars* sc, const double* mask,
                               double tol, hipStream_t st);
+// ZS[t][l] = Z[t][l] * s[l * vec + t] for l < nl, 0 for nl <= l < 64
+// (Z, ZS: Tp x 64 row-major): per-lane row weights of a batched Hessian
+// product.  nl outside [1, 64] is an invalid value.
+hipError_t launch_lane_scale(const double* Z, const double* s, int64_t vec,
+                             int nl, int64_t Tp, double* ZS, hipStream_t st,
+                             const int* skip = nullptr);
 // q_t = k^-1 sum_j Xi_tj Q_tj (zero for t >= T).
 hipError_t launch_probe_q(const double* Xi, const double* Q, int64_t T,
                           int64_t Tp, int k, double* q, hipStream_t st);

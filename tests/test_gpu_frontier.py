@@ -172,3 +172,119 @@ def test_simplex_frontier_matches_single_solves(n):
     # instances 0 and 4 are the same problem
     assert np.abs(W[0] - W[4]).max() == 0.0
     ctx.close()
+
+
+def _close(got, ref, rtol):
+    err = np.abs(got - ref).max() / np.abs(ref).max()
+    assert err <= rtol, f"relative error {err:.3e} > {rtol:.1e}"
+
+
+@pytest.mark.parametrize("grouped", [True, False])
+@pytest.mark.parametrize("iters", [1, 4])
+def test_frontier_pcg_iterates_match_single_and_oracle(grouped, iters):
+    """PCG configuration in a batch.  On separate streams each lane runs the
+    single solve's kernels in the same order: weights equal to the single
+    solve's bit for bit.  In lockstep every CG step is one pair of block
+    products for all lanes, which sum in another order: the same CG step
+    counts as the single solve, and iterates as close to the oracle's as the
+    single solve's within a factor 10 (the truncated inner solves amplify
+    rounding differently per instance; the single solve's own iterate test
+    holds c = (1, 5, 2, 10) to 1e-8, checked here too).  Budget hull: with a
+    return target the truncation test of some inner solve falls within
+    rounding of its tolerance for single solves as well."""
+    print(f"[case] frontier PCG iterates grouped={grouped} iters={iters}",
+          flush=True)
+    R = synth.factor_returns(300, 1000, 5, 0, 5.0, 0.0, 7)
+    C4 = np.array([[1.0, 5.0, 2.0, 10.0]] +
+                  [synth.crra_coefficients(g) for g in (2.0, 4.0, 6.0, 10.0)])
+    kw = dict(large=True, max_iter=iters, eps=0.0, stall_recovery=0)
+    ctx = yb.Context(torch.from_numpy(R).cuda())
+    W, infos = yb.batch_solve([ctx] * len(C4), C4,
+                              opts=yb.default_opts(**kw), grouped=grouped)
+    for b in range(len(C4)):
+        w1, i1 = ctx.solve(C4[b], opts=yb.default_opts(**kw))
+        w1 = w1.cpu().numpy()
+        wb = W[b].cpu().numpy()
+        oo = O.Options.large()
+        oo.max_iter, oo.eps, oo.stall_recovery = iters, 0.0, False
+        xr, ir = O.solve(R, C4[b], opts=oo)
+        e1 = np.abs(w1 - xr).max() / np.abs(xr).max()
+        eb = np.abs(wb - xr).max() / np.abs(xr).max()
+        print(f"b={b}: cg {infos[b].cg_iters} single {i1.cg_iters} oracle "
+              f"{ir.cg_iters}; error batch {eb:.2e} single {e1:.2e}",
+              flush=True)
+        assert infos[b].iterations == i1.iterations == iters
+        assert infos[b].cg_iters == i1.cg_iters
+        if grouped:
+            assert eb <= 10.0 * e1 + 1e-9
+        else:
+            assert np.array_equal(wb, w1)
+        if b == 0:
+            assert infos[b].cg_iters == ir.cg_iters and eb <= 1e-8
+    ctx.close()
+
+
+def test_frontier_pcg_solves_match_oracle():
+    """Full frontier solves in the PCG configuration (lockstep, graph
+    replay), return targets: every instance converges to the oracle's
+    minimiser (within kappa_w) in the oracle's number of outer iterations."""
+    print("[case] frontier PCG solves n=300 T=1000", flush=True)
+    R = synth.factor_returns(300, 1000, 5, 0, 5.0, 0.0, 7)
+    C4, tg = _frontier_instances(R, 3)
+    ctx = yb.Context(torch.from_numpy(R).cuda())
+    W, infos = ctx.frontier(C4, tg, opts=yb.default_opts(large=True))
+    W = W.cpu().numpy()
+    for b in range(len(C4)):
+        xr, ir = O.solve(R, C4[b], target=tg[b], opts=O.Options.large())
+        print(f"b={b}: batch {infos[b].status} {infos[b].iterations} it "
+              f"{infos[b].cg_iters} cg; oracle {ir.status} {ir.iterations} it "
+              f"{ir.cg_iters} cg", flush=True)
+        assert infos[b].status == ir.status == 0
+        assert infos[b].iterations == ir.iterations
+        assert np.abs(W[b] - xr).max() <= _kappa_w(R, C4[b], xr, tg[b])
+    ctx.close()
+
+
+@pytest.mark.parametrize("restart_max_iter", [1, 120])
+def test_frontier_pcg_restarts_match_oracle(restart_max_iter):
+    """Stall recovery inside a batch (krylov_maxit = 1, max_iter = 2): the
+    instances that end the baseline phase above eps continue with twice the
+    Krylov budget, then with the direct solve, like the oracle's solve;
+    restarts, the iterations of every phase, status, CG steps and iterates
+    match it per instance."""
+    print(f"[case] frontier PCG restarts restart_max_iter={restart_max_iter}",
+          flush=True)
+    R = synth.workload_returns("n12_T500")
+    C4 = np.array([synth.WORKLOADS["n12_T500"]["c"],
+                   synth.crra_coefficients(4.0), synth.crra_coefficients(8.0)])
+    ctx = yb.Context(torch.from_numpy(R).cuda())
+    W, infos = ctx.frontier(C4, opts=yb.default_opts(
+        large=True, krylov_maxit=1, max_iter=2,
+        restart_max_iter=restart_max_iter))
+    for b in range(len(C4)):
+        oo = O.Options.large()
+        oo.krylov_maxit, oo.max_iter, oo.restart_max_iter = 1, 2, restart_max_iter
+        xr, ir = O.solve(R, C4[b], opts=oo)
+        its = [p[4] for p in ir.phases]
+        its = tuple(its + [0] * (3 - len(its)))
+        print(f"b={b}: batch restarts {infos[b].restarts} phases "
+              f"{infos[b].phase_iterations}; oracle {ir.restarts} {its}",
+              flush=True)
+        assert infos[b].restarts == ir.restarts
+        assert infos[b].phase_iterations == its
+        assert infos[b].iterations == ir.iterations
+        assert infos[b].status == ir.status
+        assert infos[b].cg_iters == ir.cg_iters
+        assert np.abs(W[b].cpu().numpy() - xr).max() <= 1e-9
+    assert any(i.restarts >= 1 for i in infos)
+    ctx.close()
+
+
+def test_frontier_rejects_probe_trace():
+    R = synth.factor_returns(40, 400, 2, 0, 5.0, 0.0, 3)
+    ctx = yb.Context(torch.from_numpy(R).cuda())
+    with pytest.raises(yb.YandError) as e:
+        ctx.frontier(np.array([[1.0, 5.0, 2.0, 10.0]]),
+                     opts=yb.default_opts(large=True, trace_mode="probe"))
+    assert e.value.code == -1
+    ctx.close()
