@@ -1480,6 +1480,7 @@ int run_lanes(std::vector<Lane>& lanes, const yand_opts& opts,
           rc = enqueue_all();
           hipError_t e = hipStreamEndCapture(cs, &graph);
           if (rc != YAND_OK || e != hipSuccess) {
+            if (graph) (void)hipGraphDestroy(graph);
             cleanup();
             return rc != YAND_OK ? rc : YAND_ERR_HIP;
           }
