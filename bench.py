@@ -335,7 +335,10 @@ def simplex_bench(precision="fp64"):
             "projected_steps": [i.projected_steps if i else None for i in infos],
             "restarts": [i.restarts if i else None for i in infos],
             "kkt": [i.kkt if i else None for i in infos],
-            "kkt_hits_1e-6": f"{sum(i.kkt <= 1e-6 for i in ok)}/{len(infos)}"}
+            "kkt_hits_1e-6": f"{sum(i.kkt <= 1e-6 for i in ok)}/{len(infos)}",
+            "traces_dense_thin": [[i.dense_traces - i.thin_traces,
+                                   i.thin_traces] if i else None
+                                  for i in infos]}
     return res
 
 

@@ -145,6 +145,8 @@ typedef struct yand_info {
                              stall-recovery restart                          */
   int64_t probe_traces;   /* directions whose trace came from probes          */
   int64_t probe_cg_iters; /* PCG iterations of the probe solves (all columns) */
+  int64_t thin_traces;    /* exact traces by the T < n push-through (of
+                             dense_traces; no n x n matrix formed)           */
 } yand_info;
 
 /* Fill *opts with the direct configuration (YAND-MVSK small). */

@@ -60,7 +60,8 @@ class yand_info(C.Structure):
                 ("dense_traces", C.c_int64), ("kkt", C.c_double),
                 ("projected_steps", C.c_int),
                 ("phase_iterations", C.c_int * 3),
-                ("probe_traces", C.c_int64), ("probe_cg_iters", C.c_int64)]
+                ("probe_traces", C.c_int64), ("probe_cg_iters", C.c_int64),
+                ("thin_traces", C.c_int64)]
 
 
 class yand_mlp_opts(C.Structure):
@@ -238,6 +239,7 @@ class SolveInfo:
     phase_iterations: tuple
     probe_traces: int
     probe_cg_iters: int
+    thin_traces: int
 
 
 def _info(i) -> SolveInfo:

@@ -78,6 +78,7 @@ struct Work {
   // T < n push-through trace: Gram partials, G, C, L^-1 of C, diag(B)
   double *tGp = nullptr, *tG = nullptr, *tC = nullptr, *tX = nullptr,
          *bdiag = nullptr, *tpart = nullptr;
+  double* tW = nullptr;  // indefinite S: blocks of the signed factorisation
   // probe estimate of the trace: signs and block products (Tp x 64), their
   // split partials, the block PCG vectors (64 x lda each) and per-column
   // scalars and flags
@@ -218,7 +219,7 @@ void free_work(Work& w) {
                     w.pcg_p, w.pcg_u,  w.part,  w.psums,  w.sums, w.trpart,
                     w.B,     w.M,      w.X,     w.rn,     w.mask, w.ptmp,
                     w.hold,  w.tGp,    w.tG,    w.tC,     w.tX,   w.bdiag,
-                    w.tpart};
+                    w.tpart, w.tW};
   for (double* p : ptrs) dfree(p);
   dfree(w.SAt);
   dfree(w.Xl);
@@ -497,6 +498,7 @@ struct DirStats {
   int cg = 0;
   int escalations = 0;
   int probe_cg = 0;  // CG iterations of the probe solves (all columns)
+  bool thin = false;  // the exact trace came from the T < n push-through
 };
 
 // Direction, first part: nu-projection (Aν), B = A^T diag(psi''/T) A,
@@ -895,11 +897,14 @@ int dir_pcg_solve(const Data& D, Work& w, const double c[4], int p0,
 }
 
 // Exact trace by the T < n push-through (thin.hip): the frame's A e_a, the
-// Gram matrix G of the rows of A P_S, C = S^1/2 G S^1/2 + lambda I, its
-// factor and inverse, q, the third-order pass and the right-hand side; also
-// diag(B) for the preconditioner and W[p0] = B nu from one HVP pass.  Returns
-// with *ok = false (and the fail flag clear) when the identity does not
-// apply at this iterate (some psi''(z_t) <= 0) or C's factorisation fails.
+// Gram matrix G of the rows of A P_S, then either (S > 0) C = S^1/2 G S^1/2
+// + lambda I, its factor and inverse, or (some s_t < 0) the signed
+// factorisation of W = lambda S^-1 + G, whose failure raises lambda as the
+// dense route's does; q, the third-order pass and the right-hand side; also
+// diag(B) for the preconditioner and W[p0] = B nu from one HVP pass.
+// Returns with *ok = false (and the fail flag clear) when the identity does
+// not apply at this iterate (some psi''(z_t) = 0) or C's factorisation
+// fails.
 int dir_thin(const Data& D, Work& w, const double c[4], int p0,
              const DirOpts& o, bool* ok) {
   TRY(ensure_thin(w, D));
@@ -927,19 +932,44 @@ int dir_thin(const Data& D, Work& w, const double c[4], int p0,
   }));
   HIPTRY(launch_thin_factor_input(w.tG, w.tld, D.T, w.s_t, w.AE, Tp, p, n,
                                   o.reg, mask, w.sc, w.tC, w.st));
-  HIPTRY(timed(w, "thin_potrf_trtri", [&] {
-    return launch_potrf_trtri(w.tC, w.tX, w.tld, &w.sc->fail, w.st, nullptr,
-                              0);
-  }));
   TRY(sync_scalars(w));
-  *ok = !w.hs.ptbad && !w.hs.fail;
-  if (!*ok) {
+  auto not_applicable = [&]() -> int {
+    *ok = false;
     hipLaunchKernelGGL(set_lambda_kernel, dim3(1), dim3(64), 0, w.st, w.sc,
                        0.0);
     return YAND_OK;
+  };
+  if (w.hs.ptbad) return not_applicable();
+  if (w.hs.sneg == 0) {
+    HIPTRY(timed(w, "thin_potrf_trtri", [&] {
+      return launch_potrf_trtri(w.tC, w.tX, w.tld, &w.sc->fail, w.st, nullptr,
+                                0);
+    }));
+    TRY(sync_scalars(w));
+    if (w.hs.fail) return not_applicable();
+    HIPTRY(launch_thin_q(w.tX, w.tld, D.T, Tp, w.s_t, w.sc, w.tpart, w.q,
+                         w.st));
+  } else {
+    if (!w.tW)
+      TRY(alloc((void**)&w.tW,
+                (size_t)thin_indef_doubles(D.T) * sizeof(double)));
+    const int np_ = (int)D.T - w.hs.sneg;
+    for (int attempt = 0;; ++attempt) {
+      HIPTRY(timed(w, "thin_indef_factor", [&] {
+        return launch_thin_indef_factor(w.tG, w.tld, D.T, w.s_t, np_, 0, w.sc,
+                                        w.tW, w.st);
+      }));
+      TRY(sync_scalars(w));
+      if (!w.hs.fail) break;
+      if (attempt >= kMaxEscalations) return YAND_ERR_INDEFINITE;
+      const double lam = std::max(10.0 * w.hs.lambda,
+                                  1e-12 * w.hs.tang_scale);
+      hipLaunchKernelGGL(set_lambda_kernel, dim3(1), dim3(64), 0, w.st, w.sc,
+                         lam);
+    }
+    HIPTRY(launch_thin_indef_q(D.T, Tp, w.s_t, np_, w.sc, w.tW, w.q, w.st));
   }
-  HIPTRY(launch_thin_q(w.tX, w.tld, D.T, Tp, w.s_t, w.sc, w.tpart, w.q,
-                       w.st));
+  *ok = true;
   {
     PassArgs a = pass_args(D, w, c);
     a.zc = w.z;
@@ -1048,7 +1078,10 @@ int direction_eager(const Data& D, Work& w, const double c[4], int p0,
   if (o.solver == YAND_SOLVER_PCG && o.reg > 0.0 && 2 * D.T <= D.n) {
     bool ok = false;
     TRY(dir_thin(D, w, c, p0, o, &ok));
-    if (ok) return dir_pcg_solve(D, w, c, p0, x, o, d, stats, w.bdiag, 1);
+    if (ok) {
+      if (stats) stats->thin = true;
+      return dir_pcg_solve(D, w, c, p0, x, o, d, stats, w.bdiag, 1);
+    }
   }
   TRY(dir_front(D, w, c, p0, o, nullptr));
   for (int attempt = 0;; ++attempt) {
@@ -1975,6 +2008,7 @@ static int solve_pcg(yand_ctx* ctx, const double c[4], int p0,
         inf.probe_traces++;
       else
         inf.dense_traces++;
+      if (ds.thin) inf.thin_traces++;
       inf.third_passes++;
       inf.cg_iters += ds.cg;
       inf.hvp_passes += ds.cg;

@@ -427,6 +427,29 @@ __global__ void sum_slabs_kernel(const double* __restrict__ part, int parts,
   }
 }
 
+// General FP64 product C = alpha op(A) op(B) + beta C in 128 x 128 tiles
+// (one per workgroup): op(A)(m, k) = A[m * lda + k], or A[k * lda + m] when
+// transposed (AKC false); op(B)(k, n) = B[k * ldb + n], or B[n * ldb + k]
+// when transposed (BKC true).  M, N multiples of 128, K of 16.
+template <bool AKC, bool BKC>
+__global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2, 2)))
+gemm64_kernel(const double* __restrict__ A, int64_t lda,
+              const double* __restrict__ B, int64_t ldb, double* C,
+              int64_t ldc, int64_t K, int ntn, double alpha, double beta) {
+  __shared__ double sA[2 * stage_size<BM>()], sB[2 * stage_size<BM>()];
+  const int64_t m0 = (int64_t)(blockIdx.x / ntn) * BM;
+  const int64_t n0 = (int64_t)(blockIdx.x % ntn) * BM;
+  const double* Ab = AKC ? A + m0 * lda : A + m0;
+  const double* Bb = BKC ? B + n0 * ldb : B + n0;
+  f64x4 acc[BM / 32][BM / 32];
+  gemm_core<double, AKC, double, BKC, BM, BM>(Ab, lda, Bb, ldb, nullptr, 0, K,
+                                              acc, sA, sB);
+  for_each_acc<BM, BM>(acc, [&](int r, int c, double v) {
+    double* p = C + (m0 + r) * ldc + n0 + c;
+    *p = beta != 0.0 ? alpha * v + beta * *p : alpha * v;
+  });
+}
+
 // ZS[t][l] = Z[t][l] s_l[t] for lanes l < nl (s_l at s + l * vec), 0 for
 // the block's unused columns: the per-lane weights of a batched Hessian
 // product A^T diag(s_l) A v_l.
@@ -1231,6 +1254,29 @@ hipError_t launch_block_atz(int precision, const void* A, int64_t lda,
     launch_atz_t<false>(precision, A, lda, Tp, Z, s, tc, Yp, g, st, skip);
   hipLaunchKernelGGL(sum_slabs_kernel, dim3(1024), dim3(256), 0, st, Yp, parts,
                      lda * BW, Y, skip);
+  return hipGetLastError();
+}
+
+hipError_t launch_gemm64(const double* A, int64_t lda, bool at,
+                         const double* B, int64_t ldb, bool bt, double* C,
+                         int64_t ldc, int64_t M, int64_t N, int64_t K,
+                         double alpha, double beta, hipStream_t st) {
+  if (M % BM || N % BM || K % BKK || M <= 0 || N <= 0 || K <= 0)
+    return hipErrorInvalidValue;
+  const int ntn = (int)(N / BM);
+  dim3 g((unsigned)((M / BM) * ntn)), b(NT);
+  if (!at && !bt)
+    hipLaunchKernelGGL((gemm64_kernel<true, false>), g, b, 0, st, A, lda, B,
+                       ldb, C, ldc, K, ntn, alpha, beta);
+  else if (!at && bt)
+    hipLaunchKernelGGL((gemm64_kernel<true, true>), g, b, 0, st, A, lda, B,
+                       ldb, C, ldc, K, ntn, alpha, beta);
+  else if (at && !bt)
+    hipLaunchKernelGGL((gemm64_kernel<false, false>), g, b, 0, st, A, lda, B,
+                       ldb, C, ldc, K, ntn, alpha, beta);
+  else
+    hipLaunchKernelGGL((gemm64_kernel<false, true>), g, b, 0, st, A, lda, B,
+                       ldb, C, ldc, K, ntn, alpha, beta);
   return hipGetLastError();
 }
 

@@ -166,6 +166,15 @@ hipError_t launch_bpcg_update(const double* HP, const double* bd,
                               double* AP, double* cs, int* flags,
                               const DevScalars* sc, const double* mask,
                               double tol, hipStream_t st);
+// C = alpha op(A) op(B) + beta C in FP64 on the matrix cores (C: M x N,
+// row-major, ldc); op(A) is M x K (A row-major, or its transpose when at),
+// op(B) K x N (B row-major, or its transpose when bt).  M and N must be
+// multiples of 128 and K of 16 (invalid value otherwise); beta = 0 does not
+// read C.
+hipError_t launch_gemm64(const double* A, int64_t lda, bool at,
+                         const double* B, int64_t ldb, bool bt, double* C,
+                         int64_t ldc, int64_t M, int64_t N, int64_t K,
+                         double alpha, double beta, hipStream_t st);
 // ZS[t][l] = Z[t][l] * s[l * vec + t] for l < nl, 0 for nl <= l < 64
 // (Z, ZS: Tp x 64 row-major): per-lane row weights of a batched Hessian
 // product.  nl outside [1, 64] is an invalid value.
@@ -190,6 +199,20 @@ hipError_t launch_symm_multi(const double* B, int64_t ldb, int64_t n,
 struct DevScalars;
 // Column splits of the Gram kernel for T rows (1..64, partials <= 64 MiB).
 int thin_splits(int64_t T);
+// Workspace (doubles) of the indefinite push-through factorisation for T.
+int64_t thin_indef_doubles(int64_t T);
+// Indefinite S (np_ bars with s > 0, T - np_ >= 1 with s < 0): the signed
+// factorisation of W = lambda S^-1 + G (G lower, ld ldg) with lambda from
+// sc; sc->fail is raised when it does not exist (B_m not positive
+// definite).  ws: thin_indef_doubles(T) doubles, kept for launch_thin_indef_q.
+hipError_t launch_thin_indef_factor(const double* G, int64_t ldg, int64_t T,
+                                    const double* s, int np_, int chol_group,
+                                    DevScalars* sc, double* ws,
+                                    hipStream_t st);
+// q (Tp, zero padding) from that factorisation.
+hipError_t launch_thin_indef_q(int64_t T, int64_t Tp, const double* s,
+                               int np_, const DevScalars* sc, double* ws,
+                               double* q, hipStream_t st);
 // Rows of the partial-sum scratch (each ld long) that launch_thin_q
 // (ld = ldg) and launch_bdiag (ld = lda) need for T rows.
 int64_t thin_part_rows(int64_t T);

@@ -11,6 +11,23 @@
 // inverse T^3 / 2, instead of the n^2 T SYRK, the n^3 factorisation and the
 // n^2 T trace GEMM.  The PCG solve for u never needed the factor; its
 // Jacobi preconditioner takes diag(A^T S A) from one pass over A.
+//
+// Indefinite S (some psi'' < 0, none zero).  By Woodbury, for any
+// invertible S, P B_m^-1 P^T = S^-1 - lambda S^-1 W^-1 S^-1 with
+// W = lambda S^-1 + G, so q_t = (1 - lambda (W^-1)_tt / s_t) / s_t (C above
+// is S^1/2 W S^1/2).  W is indefinite; with the bars of positive s first,
+//   W = [[W_PP, W_PN], [W_NP, W_NN]],  W_PP = L1 L1^T,
+//   Sigma = W_NN - W_NP W_PP^-1 W_PN = -L2 L2^T,
+// a signed factorisation W = L diag(I, -I) L^T that exists exactly when
+// B_m is positive definite: by Haynsworth's inertia additivity applied to
+// [[lambda I, P^T], [P, -S^-1]], nu_-(B_m) = nu_+(W) - nu_+(S), and
+// nu_+(W) = nu_+(W_PP) + nu_+(Sigma) = |P| + nu_+(Sigma), so B_m > 0 iff
+// -Sigma > 0.  Both factors are Cholesky factors (the blocked kernels of
+// the dense route); a failed one means B_m is not positive definite and the
+// caller raises lambda, as the dense route does.  With X1 = L1^-1,
+// M^T = X1 W_PN, X2 = L2^-1 and Y = X2 M X1,
+//   (W^-1)_tt = |X1 e_t|^2 - |Y e_t|^2  (t among the positive bars),
+//   (W^-1)_tt = -|X2 e_t|^2              (t among the negative bars).
 #include "common.h"
 #include "kernels.h"
 #include "vec.h"
@@ -121,25 +138,27 @@ __global__ void gram_finish_kernel(const double* __restrict__ Gp, int K,
 
 // Scales from G and s: the tangent-Hessian trace sum_t s_t G_tt, its mean
 // over the tangent dimension (nfree - p), lambda = reg * mean, gamma and
-// trace(B); ptbad when some s_t <= 0 or lambda <= 0 (the identity needs both
-// positive).
+// trace(B); sneg, the bars with s_t < 0; ptbad when some s_t is zero or not
+// finite, or lambda <= 0 (the identity needs S invertible and lambda > 0).
 __global__ void __launch_bounds__(RT)
 thin_scale_kernel(const double* __restrict__ G, int64_t ldg, int64_t T,
                   const double* __restrict__ s, const double* __restrict__ AE,
                   int64_t Tp, int p, int64_t n, double reg,
                   const double* __restrict__ mask, DevScalars* sc) {
   __shared__ double sh[RT / 64];
-  double tg = 0.0, tb = 0.0, smin = INFINITY;
+  double tg = 0.0, tb = 0.0, nneg = 0.0, nbad = 0.0;
   for (int64_t t = threadIdx.x; t < T; t += RT) {
     double e = 0.0;
     for (int a = 0; a < p; ++a) e += AE[a * Tp + t] * AE[a * Tp + t];
     tg += s[t] * G[t * ldg + t];
     tb += s[t] * (G[t * ldg + t] + e);
-    smin = fmin(smin, s[t]);
+    nneg += s[t] < 0.0 ? 1.0 : 0.0;
+    nbad += (s[t] != 0.0 && isfinite(s[t])) ? 0.0 : 1.0;
   }
   tg = rt_sum(tg, sh);
   tb = rt_sum(tb, sh);
-  smin = rt_min(smin, sh);
+  nneg = rt_sum(nneg, sh);
+  nbad = rt_sum(nbad, sh);
   if (threadIdx.x == 0) {
     const double neff = mask ? sc->nfree : (double)n;
     double gam = tb / neff;
@@ -150,13 +169,14 @@ thin_scale_kernel(const double* __restrict__ G, int64_t ldg, int64_t T,
     sc->gamma = gam;
     sc->tang_scale = tang;
     sc->lambda = reg * tang;
-    sc->ptbad = (smin > 0.0 && sc->lambda > 0.0) ? 0 : 1;
+    sc->sneg = (int)nneg;
+    sc->ptbad = (nbad == 0.0 && sc->lambda > 0.0) ? 0 : 1;
     sc->fail = 0;
   }
 }
 
 // Lower triangle of C = S^1/2 G S^1/2 + lambda I (T x T), identity on the
-// padding up to ldg; the identity throughout when ptbad.
+// padding up to ldg; the identity throughout when ptbad or S is indefinite.
 __global__ void thin_build_kernel(const double* __restrict__ G, int64_t ldg,
                                   int64_t T, const double* __restrict__ s,
                                   const DevScalars* __restrict__ sc,
@@ -165,7 +185,7 @@ __global__ void thin_build_kernel(const double* __restrict__ G, int64_t ldg,
   const int64_t u = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (u > t || t >= ldg) return;
   double v = t == u ? 1.0 : 0.0;
-  if (!sc->ptbad && t < T)
+  if (!sc->ptbad && !sc->sneg && t < T)
     v = sqrt(s[t]) * G[t * ldg + u] * sqrt(s[u]) + (t == u ? sc->lambda : 0.0);
   C[t * ldg + u] = v;
 }
@@ -209,6 +229,116 @@ __global__ void thin_q_kernel(const double* __restrict__ part, int nb,
   double c = 0.0;
   for (int b = 0; b < nb; ++b) c += part[(int64_t)b * ldg + t];
   q[t] = (1.0 - sc->lambda * c) / s[t];
+}
+
+// Indefinite S: bars of positive s_t first, each set in bar order
+// (perm[i] = bar at position i, pos[t] = position of bar t).
+__global__ void thin_perm_kernel(const double* __restrict__ s, int64_t T,
+                                 int* __restrict__ perm, int* __restrict__ pos) {
+  if (threadIdx.x != 0) return;
+  int k = 0;
+  for (int64_t t = 0; t < T; ++t)
+    if (s[t] > 0.0) {
+      perm[k] = (int)t;
+      pos[t] = k++;
+    }
+  for (int64_t t = 0; t < T; ++t)
+    if (!(s[t] > 0.0)) {
+      perm[k] = (int)t;
+      pos[t] = k++;
+    }
+}
+
+__device__ __forceinline__ double gsym(const double* G, int64_t ldg, int a,
+                                       int b) {
+  return a >= b ? G[(int64_t)a * ldg + b] : G[(int64_t)b * ldg + a];
+}
+
+// The blocks of the permuted W = lambda S^-1 + G: W_PP (ldp x ldp, the
+// identity on its padding), W_PN (ldp x ldn, zero padding) and W_NN
+// (ldn x ldn, minus the identity on its padding, so that
+// M M^T - W_NN is the identity there).  Row i of the grid block (y) and
+// column j (x) index the largest of the three shapes.
+__global__ void thin_split_kernel(const double* __restrict__ G, int64_t ldg,
+                                  const double* __restrict__ s,
+                                  const int* __restrict__ perm, int np_,
+                                  int nn, int64_t ldp, int64_t ldn,
+                                  const DevScalars* __restrict__ sc,
+                                  double* __restrict__ Wpp,
+                                  double* __restrict__ Wpn,
+                                  double* __restrict__ Wnn) {
+  const int64_t i = blockIdx.y;
+  const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const double lam = sc->lambda;
+  if (i < ldp && j < ldp) {
+    double v = i == j ? 1.0 : 0.0;
+    if (i < np_ && j < np_) {
+      v = gsym(G, ldg, perm[i], perm[j]);
+      if (i == j) v += lam / s[perm[i]];
+    }
+    Wpp[i * ldp + j] = v;
+  }
+  if (i < ldp && j < ldn)
+    Wpn[i * ldn + j] =
+        (i < np_ && j < nn) ? gsym(G, ldg, perm[i], perm[np_ + j]) : 0.0;
+  if (i < ldn && j < ldn) {
+    double v = i == j ? -1.0 : 0.0;
+    if (i < nn && j < nn) {
+      v = gsym(G, ldg, perm[np_ + i], perm[np_ + j]);
+      if (i == j) v += lam / s[perm[np_ + i]];
+    }
+    Wnn[i * ldn + j] = v;
+  }
+}
+
+__global__ void fill_kernel(double* __restrict__ x, int64_t len, double v) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < len;
+       i += (int64_t)gridDim.x * blockDim.x)
+    x[i] = v;
+}
+
+__global__ void negate_kernel(double* __restrict__ x, int64_t len) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < len;
+       i += (int64_t)gridDim.x * blockDim.x)
+    x[i] = -x[i];
+}
+
+// q_t = (1 - lambda (W^-1)_tt / s_t) / s_t from the signed factorisation
+// (see the head of this file); 0 on the padding rows.
+__global__ void thin_q_indef_kernel(const double* __restrict__ X1,
+                                    const double* __restrict__ X2,
+                                    const double* __restrict__ Y,
+                                    const int* __restrict__ pos, int np_,
+                                    int nn, int64_t ldp, int64_t ldn,
+                                    int64_t T, int64_t Tp,
+                                    const double* __restrict__ s,
+                                    const DevScalars* __restrict__ sc,
+                                    double* __restrict__ q) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= Tp) return;
+  if (t >= T) {
+    q[t] = 0.0;
+    return;
+  }
+  const int i = pos[t];
+  double w = 0.0;
+  if (i < np_) {
+    for (int k = i; k < np_; ++k) {
+      const double x = X1[(int64_t)k * ldp + i];
+      w += x * x;
+    }
+    for (int k = 0; k < nn; ++k) {
+      const double y = Y[(int64_t)k * ldp + i];
+      w -= y * y;
+    }
+  } else {
+    const int j = i - np_;
+    for (int k = j; k < nn; ++k) {
+      const double x = X2[(int64_t)k * ldn + j];
+      w -= x * x;
+    }
+  }
+  q[t] = (1.0 - sc->lambda * w / s[t]) / s[t];
 }
 
 // Partial Jacobi diagonal: part[b][j] = sum_{t in [16 b, 16 b + 16), t < T}
@@ -321,6 +451,82 @@ hipError_t launch_thin_q(const double* X, int64_t ldg, int64_t T, int64_t Tp,
                      dim3(256), 0, st, X, ldg, T, part);
   hipLaunchKernelGGL(thin_q_kernel, dim3((unsigned)((Tp + 255) / 256)),
                      dim3(256), 0, st, part, nb, ldg, T, Tp, s, sc, q);
+  return hipGetLastError();
+}
+
+int64_t thin_indef_doubles(int64_t T) {
+  const int64_t l = round_up(T, 128) + 128;
+  return 5 * l * l + 2 * T;
+}
+
+hipError_t launch_thin_indef_factor(const double* G, int64_t ldg, int64_t T,
+                                    const double* s, int np_, int chol_group,
+                                    DevScalars* sc, double* ws,
+                                    hipStream_t st) {
+  const int nn = (int)T - np_;
+  if (np_ < 0 || nn < 1) return hipErrorInvalidValue;
+  const int64_t ldp = round_up(np_ > 0 ? np_ : 1, 128);
+  const int64_t ldn = round_up(nn, 128);
+  const int64_t l = round_up(T, 128) + 128;
+  double *Wpp = ws, *X1 = ws + l * l, *Mt = ws + 2 * l * l,
+         *Wnn = ws + 3 * l * l, *X2 = ws + 4 * l * l;
+  int* perm = (int*)(ws + 5 * l * l);
+  int* pos = perm + T;
+  hipLaunchKernelGGL(thin_perm_kernel, dim3(1), dim3(64), 0, st, s, T, perm,
+                     pos);
+  const int64_t big = ldp > ldn ? ldp : ldn;
+  hipLaunchKernelGGL(thin_split_kernel,
+                     dim3((unsigned)((big + 255) / 256), (unsigned)big),
+                     dim3(256), 0, st, G, ldg, s, perm, np_, nn, ldp, ldn, sc,
+                     Wpp, Mt, Wnn);
+  // the products read the inverses as full matrices
+  hipLaunchKernelGGL(fill_kernel, dim3(256), dim3(256), 0, st, X1, ldp * ldp,
+                     0.0);
+  hipLaunchKernelGGL(fill_kernel, dim3(256), dim3(256), 0, st, X2, ldn * ldn,
+                     0.0);
+  hipError_t e = hipSuccess;
+  if (np_ > 0) {
+    e = launch_potrf_trtri(Wpp, X1, ldp, &sc->fail, st, nullptr, chol_group);
+    if (e != hipSuccess) return e;
+    // M^T = X1 W_PN (ldp x ldn) into Wpp's storage, whose factor is no
+    // longer needed
+    e = launch_gemm64(X1, ldp, false, Mt, ldn, false, Wpp, ldn, ldp, ldn, ldp,
+                      1.0, 0.0, st);
+    if (e != hipSuccess) return e;
+    // -Sigma = M M^T - W_NN
+    e = launch_gemm64(Wpp, ldn, true, Wpp, ldn, false, Wnn, ldn, ldn, ldn, ldp,
+                      1.0, -1.0, st);
+    if (e != hipSuccess) return e;
+  } else {
+    // no positive bars: -Sigma = -W_NN (the identity on the padding)
+    hipLaunchKernelGGL(negate_kernel, dim3(256), dim3(256), 0, st, Wnn,
+                       ldn * ldn);
+  }
+  return launch_potrf_trtri(Wnn, X2, ldn, &sc->fail, st, nullptr, chol_group);
+}
+
+hipError_t launch_thin_indef_q(int64_t T, int64_t Tp, const double* s,
+                               int np_, const DevScalars* sc, double* ws,
+                               double* q, hipStream_t st) {
+  const int nn = (int)T - np_;
+  const int64_t ldp = round_up(np_ > 0 ? np_ : 1, 128);
+  const int64_t ldn = round_up(nn, 128);
+  const int64_t l = round_up(T, 128) + 128;
+  double *Mt = ws, *X1 = ws + l * l, *Z = ws + 2 * l * l, *X2 = ws + 4 * l * l;
+  int* pos = (int*)(ws + 5 * l * l) + T;
+  double* Y = ws + 3 * l * l;  // over -Sigma, whose factor is not needed
+  if (np_ > 0) {
+    // Z = M X1 (ldn x ldp), Y = X2 Z
+    hipError_t e = launch_gemm64(Mt, ldn, true, X1, ldp, false, Z, ldp, ldn,
+                                 ldp, ldp, 1.0, 0.0, st);
+    if (e != hipSuccess) return e;
+    e = launch_gemm64(X2, ldn, false, Z, ldp, false, Y, ldp, ldn, ldp, ldn, 1.0,
+                      0.0, st);
+    if (e != hipSuccess) return e;
+  }
+  hipLaunchKernelGGL(thin_q_indef_kernel, dim3((unsigned)((Tp + 255) / 256)),
+                     dim3(256), 0, st, X1, X2, Y, pos, np_, nn, ldp, ldn, T,
+                     Tp, s, sc, q);
   return hipGetLastError();
 }
 

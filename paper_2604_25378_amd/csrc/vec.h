@@ -31,14 +31,14 @@ struct DevScalars {
   double nfree;      // free coordinates of the current face (simplex set)
   int projected;     // this iteration took the projected trial segment
   int release;       // drop the holds at the next face evaluation
-  int ptbad;         // push-through trace not applicable (psi'' <= 0, lambda 0)
+  int ptbad;         // push-through trace not applicable (psi'' = 0, lambda 0)
   int cgdone;        // PCG: converged or broke down, later steps skipped
   int cgit;          // PCG: iterations taken
   int lsskip;        // skip the raw line search (done, or segment taken)
   int segskip;       // skip the projected-segment trial (no candidate)
   double mudseg;     // mu^T dbar of the projected segment
   int nhold0;        // holds after this iteration's face evaluation
-  int pad4;
+  int sneg;          // push-through trace: bars with psi''(z_t) < 0
 };
 
 // Face masks: mask[j] = 1 for a free coordinate of the current face of

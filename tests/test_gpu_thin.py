@@ -8,8 +8,9 @@ trace alone and not on the two preconditioners (the library's Jacobi
 preconditioner lives in ambient coordinates, the oracle's in reduced ones);
 compared to 1e-8 of |d|_inf, the direction tolerance of the dense path.
 Solve level: the PCG configuration with stall recovery on the simplex,
-the converged minimiser to 1e-7.  Fallback: where psi'' < 0 at
-some bar the identity does not apply and the dense route runs instead.
+the converged minimiser to 1e-7.  Indefinite S: where psi'' < 0 at some
+bars the identity runs on the signed factorisation of lambda S^-1 + G, with
+the dense route's escalation of lambda.
 """
 
 import numpy as np
@@ -158,30 +159,45 @@ def test_thin_reduced_storage_matches_rounded_oracle(precision):
     _close(d.cpu().numpy(), ref.d, 1e-8)
 
 
-def test_thin_falls_back_where_psi2_negative():
+def _concentrated_indefinite():
     """c = (10, 1, 10, 1): psi''(s) = 2 - 60 s + 12 s^2 is negative for
-    0.034 < s < 4.97, which the centred uniform returns reach, so the
-    identity does not apply; the dense route gives the oracle's direction."""
-    print("[case] thin fallback psi'' < 0", flush=True)
+    0.034 < s < 4.97, which the centred uniform returns reach from a
+    concentrated portfolio (|z_t| up to 0.2): S is indefinite."""
     R = synth.uniform_returns(300, 120, seed=5)
     c = np.array([10.0, 1.0, 10.0, 1.0])
     mu, A = O.center(R)
-    n = mu.size
-    x = np.full(n, 0.1 / n)
-    x[7] += 0.9                      # concentrated: |z_t| reaches 0.2
-    assert O.d2psi(c, A @ x).min() < 0.0
+    x = np.full(mu.size, 0.1 / mu.size)
+    x[7] += 0.9
+    s2 = O.d2psi(c, A @ x)
+    assert s2.min() < 0.0 < s2.max()
+    return R, c, mu, A, x, int((s2 < 0).sum())
+
+
+@pytest.mark.parametrize("reg", [1e-4, 1e-9])
+def test_thin_indefinite_matches_oracle(reg):
+    """psi'' < 0 at some bars: the push-through runs on the signed
+    factorisation of W = lambda S^-1 + G (no n x n matrix; the profile shows
+    the signed factorisation and no SYRK) and gives the oracle's direction,
+    whose explicit reduced factorisation escalates lambda on failure.  At
+    reg 1e-9 the tangent Hessian plus lambda is indefinite at first, so both
+    sides escalate; a different number of escalations would move the
+    direction by far more than the tolerance."""
+    print(f"[case] thin indefinite reg={reg}", flush=True)
+    R, c, mu, A, x, nneg = _concentrated_indefinite()
+    print(f"  {nneg} of {R.shape[0]} bars with psi'' < 0", flush=True)
     U = O.tangent_basis(O.constraints(mu, None)[0])
-    try:
-        ref = O.affine_normal(A, mu, c, x, U, solver="pcg", reg=1e-4,
-                              krylov_tol=1e-13, krylov_maxit=4000)
-    except O.Indefinite:
-        ref = None
+    ref = O.affine_normal(A, mu, c, x, U, solver="pcg", reg=reg,
+                          krylov_tol=1e-13, krylov_maxit=4000)
     ctx = yb.Context(torch.from_numpy(R).cuda())
-    opts = yb.default_opts(large=True, krylov_tol=1e-13, krylov_maxit=4000)
-    if ref is None:
-        with pytest.raises(yb.YandError):
-            ctx.affine_normal(c, x, opts=opts)
-    else:
-        d, _ = ctx.affine_normal(c, x, opts=opts)
-        _close(d.cpu().numpy(), ref.d, 1e-8)
+    ctx.profile(True)
+    opts = yb.default_opts(large=True, krylov_tol=1e-13, krylov_maxit=4000,
+                           regularization=reg)
+    d, gn = ctx.affine_normal(c, x, opts=opts)
+    prof = {k: v[1] for k, v in ctx.profile_read().items()}
     ctx.close()
+    print(f"  oracle lambda {ref.lam:.3e}; kernels {sorted(prof)}", flush=True)
+    assert "thin_indef_factor" in prof and "syrk" not in prof
+    assert gn == pytest.approx(ref.gnorm, rel=1e-12)
+    _close(d.cpu().numpy(), ref.d, 1e-8)
+    if reg == 1e-9:
+        assert prof["thin_indef_factor"] >= 2       # escalated at least once
