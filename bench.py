@@ -543,6 +543,60 @@ def line_search_bench(precision="fp64"):
     return res
 
 
+def warmstart_hard_bench(precision="fp64"):
+    """Warm start where plain solves take many iterations: the controlled
+    conditioning generator (n = 1000, T = 2000), budget set, CRRA gamma in
+    [1, 6]; the network (3 x 256, 4000 epochs) is trained on plain solutions
+    at 24 gammas and evaluated on the 23 midpoints, batched both ways.  At
+    kappa_+(AU) = 1e3 the residual test rejects every proposal (the plain
+    start is returned), which the second row shows."""
+    import torch
+
+    import synth
+    from paper_2604_25378_amd import binding as yb
+
+    res = {}
+    for kappa in (1e2, 1e3):
+        log(f"warm start, conditioned panel kappa={kappa:g}")
+        R = synth.conditioned_returns(1000, 2000, kappa, 1)
+        ctx = yb.Context(torch.from_numpy(R).cuda(), precision)
+        gtr = np.linspace(1.0, 6.0, 24)
+        Ctr = np.array([synth.crra_coefficients(g) for g in gtr])
+        Cte = np.array([synth.crra_coefficients(g)
+                        for g in 0.5 * (gtr[1:] + gtr[:-1])])
+        Wtr, _ = ctx.frontier(Ctr)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        net, loss = yb.warmstart_train(
+            ctx, Ctr, None, Wtr, yb.default_mlp_opts(hidden=256, epochs=4000))
+        torch.cuda.synchronize()
+        t_train = time.perf_counter() - t0
+        ctx.frontier(Cte[:2])                    # warm-up
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        W0, used, _ = yb.warmstart_predict(ctx, net, Cte, None)
+        _, iw = ctx.frontier(Cte, W0=W0)
+        torch.cuda.synchronize()
+        t_w = time.perf_counter() - t0
+        t0 = time.perf_counter()
+        _, ip = ctx.frontier(Cte)
+        torch.cuda.synchronize()
+        t_p = time.perf_counter() - t0
+        net.close()
+        ctx.close()
+        res[f"kappa_{kappa:g}"] = {
+            "workload": f"conditioned panel n=1000 T=2000 kappa_+(AU)={kappa:g}, "
+                        f"budget set, {len(Cte)} held-out CRRA gammas in [1, 6]",
+            "plain_iterations_mean": float(np.mean([i.iterations for i in ip])),
+            "warm_iterations_mean": float(np.mean([i.iterations for i in iw])),
+            "proposals_used": float(np.mean(used)),
+            "plain_solves_per_s": len(Cte) / t_p,
+            "warm_solves_per_s": len(Cte) / t_w,
+            "train_s": t_train, "train_loss": loss,
+            "converged": f"{_conv(iw)}/{len(Cte)}"}
+    return res
+
+
 def warmstart_bench(workload, n_train_targets=16, n_points=256, n_plain=16,
                     precision="fp64", autotune=True):
     """Frontier sweep at full scale: batched + MLP-warm-started solves vs
@@ -691,7 +745,7 @@ def main():
                     help="keep the built-in launch shapes")
     ap.add_argument("--only", default=None,
                     help="run the headline step and this one block only "
-                         "(frontier_n1000, frontier_n1000_pcg, ragged, warmstart, simplex, "
+                         "(frontier_n1000, frontier_n1000_pcg, ragged, warmstart, warmstart_hard, simplex, "
                          "conditioning, line_search, return_floor, regime, "
                          "precision, probe)")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -871,6 +925,7 @@ def main():
               "frontier_n1000_pcg": lambda: frontier_bench(
                   "n1000_T12000_frontier", 16, 8, args.precision,
                   not args.no_autotune, pcg=True),
+              "warmstart_hard": lambda: warmstart_hard_bench(args.precision),
               "ragged": lambda: ragged_bench(32, 6000, args.precision,
                                              not args.no_autotune),
               "warmstart": lambda: warmstart_bench(
@@ -895,6 +950,7 @@ def main():
                                               args.frontier_points, 16,
                                               args.precision, tune)}
         out["frontier"] = fr
+        out["warmstart_hard"] = warmstart_hard_bench(args.precision)
         out["simplex"] = simplex_bench(args.precision)
         out["conditioning"] = conditioning_bench(args.precision)
         out["line_search"] = line_search_bench(args.precision)

@@ -4,8 +4,9 @@
 // Network: in -> H (tanh) -> H (tanh) -> H (tanh) -> out (linear), weights
 // row-major W_k (fan_in x fan_out) followed by b_k, all FP32 in one buffer.
 // Loss: (1/2N) sum |out - Y|^2.  Optimiser: Adam with bias correction.
-// Every product is one tiled FP32 GEMM kernel (64 x 64 tiles, 16-deep LDS
-// slices, 4 x 4 outputs per thread) with transposition flags and a fused
+// Every product is one tiled FP32 GEMM kernel on the FP32 matrix cores
+// (64 x 64 tiles, 16-deep LDS slices, each wave a 32 x 32 block of
+// v_mfma_f32_16x16x4f32 products) with transposition flags and a fused
 // bias / tanh epilogue.
 #include <algorithm>
 #include <cmath>
@@ -18,6 +19,8 @@
 
 namespace yand {
 namespace {
+
+typedef float f32x4 __attribute__((ext_vector_type(4)));
 
 constexpr int GT = 64;    // output tile
 constexpr int GK = 16;    // k slice
@@ -33,13 +36,18 @@ gemm_f32_kernel(int M, int N, int K, const float* __restrict__ A, int lda,
                 int ldc, const float* __restrict__ bias, int act, int accum) {
   __shared__ float As[GK][GT + 4];
   __shared__ float Bs[GK][GT + 4];
-  const int tid = threadIdx.x, tx = tid & 15, ty = tid >> 4;
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   const int m0 = blockIdx.y * GT, n0 = blockIdx.x * GT;
-  float acc[4][4];
+  // wave w: rows wm .. wm + 31, columns wn .. wn + 31 of the tile, as 2 x 2
+  // blocks of 16 x 16; lane l feeds A[row l % 16][k l / 16] and
+  // B[k l / 16][col l % 16] and holds C[4 (l / 16) + r][l % 16]
+  const int wm = (w >> 1) * 32, wn = (w & 1) * 32;
+  const int lr = lane & 15, lk = lane >> 4;
+  f32x4 acc[2][2];
 #pragma unroll
-  for (int i = 0; i < 4; ++i)
+  for (int i = 0; i < 2; ++i)
 #pragma unroll
-    for (int j = 0; j < 4; ++j) acc[i][j] = 0.f;
+    for (int j = 0; j < 2; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
   for (int k0 = 0; k0 < K; k0 += GK) {
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
@@ -71,34 +79,36 @@ gemm_f32_kernel(int M, int N, int K, const float* __restrict__ A, int lda,
     }
     __syncthreads();
 #pragma unroll
-    for (int k = 0; k < GK; ++k) {
-      float a[4], b[4];
+    for (int k = 0; k < GK; k += 4) {
+      float a[2], b[2];
 #pragma unroll
-      for (int i = 0; i < 4; ++i) a[i] = As[k][ty * 4 + i];
+      for (int i = 0; i < 2; ++i) a[i] = As[k + lk][wm + 16 * i + lr];
 #pragma unroll
-      for (int j = 0; j < 4; ++j) b[j] = Bs[k][tx * 4 + j];
+      for (int j = 0; j < 2; ++j) b[j] = Bs[k + lk][wn + 16 * j + lr];
 #pragma unroll
-      for (int i = 0; i < 4; ++i)
+      for (int i = 0; i < 2; ++i)
 #pragma unroll
-        for (int j = 0; j < 4; ++j) acc[i][j] = fmaf(a[i], b[j], acc[i][j]);
+        for (int j = 0; j < 2; ++j)
+          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[i], b[j],
+                                                          acc[i][j], 0, 0, 0);
     }
     __syncthreads();
   }
 #pragma unroll
-  for (int i = 0; i < 4; ++i) {
-    const int gm = m0 + ty * 4 + i;
-    if (gm >= M) continue;
+  for (int i = 0; i < 2; ++i)
 #pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      const int gn = n0 + tx * 4 + j;
-      if (gn >= N) continue;
-      float v = acc[i][j];
-      if (bias) v += bias[gn];
-      if (act) v = tanhf(v);
-      float* c = C + (size_t)gm * ldc + gn;
-      *c = accum ? *c + v : v;
-    }
-  }
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int gm = m0 + wm + 16 * i + 4 * lk + r;
+        const int gn = n0 + wn + 16 * j + lr;
+        if (gm >= M || gn >= N) continue;
+        float v = acc[i][j][r];
+        if (bias) v += bias[gn];
+        if (act) v = tanhf(v);
+        float* c = C + (size_t)gm * ldc + gn;
+        *c = accum ? *c + v : v;
+      }
 }
 
 // delta = (out - Y) / N; per-block partial of sum (out - Y)^2.
