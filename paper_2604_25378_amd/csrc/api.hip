@@ -57,6 +57,9 @@ struct Data {
   // launch shapes chosen by yand_autotune (0: built-in defaults)
   int pass_groups[6] = {0, 0, 0, 0, 0, 0};  // per PassKind
   int chol_group = 0;
+  // XCD-aware tile order of the SYRK (device; null: plain order)
+  int* syrk_order = nullptr;
+  int64_t syrk_slots = 0;
 };
 
 struct Work {
@@ -544,7 +547,8 @@ int dir_front(const Data& D, Work& w, const double c[4], int p0,
     }));
   else
     HIPTRY(timed(w, "syrk", [&] {
-      return launch_syrk(D.precision, D.A, D.lda, Tp, w.s_t, w.B, w.st, skip);
+      return launch_syrk(D.precision, D.A, D.lda, Tp, w.s_t, w.B, w.st, skip,
+                         Lanes{}, 1, D.syrk_order, D.syrk_slots);
     }));
   return dir_front_post(D, w, p0, o, skip);
 }
@@ -1176,7 +1180,7 @@ int enqueue_group(const std::vector<LaneRef>& lanes, const DirOpts& o,
     TRY(dir_front_pre(D, w, L.c, L.p0, &w.sc->done));
   }
   HIPTRY(launch_syrk(D.precision, D.A, D.lda, Tp, G.s, G.B, st, G.skip, G.ls,
-                     G.nl));
+                     G.nl, D.syrk_order, D.syrk_slots));
   for (const auto& L : lanes) {
     Work& w = *L.w;
     TRY(dir_front_post(D, w, L.p0, o, &w.sc->done));
@@ -1697,7 +1701,8 @@ int yand_destroy(yand_ctx* ctx) {
   if (!ctx) return YAND_OK;
   flush_timed(ctx->prof, ctx->w.st);
   free_work(ctx->w);
-  void* ptrs[] = {ctx->d.A, ctx->d.At, ctx->d.mu, ctx->d.Efix, ctx->d.AEfix};
+  void* ptrs[] = {ctx->d.A,    ctx->d.At,    ctx->d.mu,
+                  ctx->d.Efix, ctx->d.AEfix, ctx->d.syrk_order};
   for (void* p : ptrs) dfree(p);
   delete ctx;
   return YAND_OK;
@@ -1753,6 +1758,19 @@ static int create_ctx(const double* R, int64_t T, int64_t n, int64_t ldr,
   if ((rc = alloc((void**)&colpart, (size_t)nchunks * n * sizeof(double))))
     return fail(rc);
   if (dense_upfront && (rc = ensure_dense(w, D))) return fail(rc);
+  // the SYRK's tile order (not in the allocation-free entry point, whose
+  // context uses the plain order)
+  if (!g_arena) {
+    const std::vector<int> ord = syrk_tile_order((int)D.nt);
+    if (!ord.empty()) {
+      if ((rc = alloc((void**)&D.syrk_order, ord.size() * sizeof(int))))
+        return fail(rc);
+      if (hipMemcpy(D.syrk_order, ord.data(), ord.size() * sizeof(int),
+                    hipMemcpyHostToDevice) != hipSuccess)
+        return fail(YAND_ERR_HIP);
+      D.syrk_slots = (int64_t)ord.size() / 2;
+    }
+  }
   if (g_arena &&
       launch_fill((double*)g_arena->base, (int64_t)(g_arena->used / 8), 0.0,
                   st) != hipSuccess)

@@ -295,7 +295,7 @@ template <typename S>
 __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2, 2)))
 syrk_kernel(const S* __restrict__ A, int64_t lda, int64_t Tp,
             const double* __restrict__ s, double* __restrict__ B,
-            const int* skip, Lanes ls) {
+            const int* skip, Lanes ls, const int* __restrict__ order) {
   const int ln = blockIdx.y;
   s += ln * ls.vec;
   B += ln * ls.mat;
@@ -303,7 +303,13 @@ syrk_kernel(const S* __restrict__ A, int64_t lda, int64_t Tp,
   if (skip && *skip) return;
   __shared__ double sA[2 * kStage], sB[2 * kStage];
   int I, J;
-  lower_tile(blockIdx.x, &I, &J);
+  if (order) {
+    I = order[2 * blockIdx.x];
+    J = order[2 * blockIdx.x + 1];
+    if (I < 0) return;
+  } else {
+    lower_tile(blockIdx.x, &I, &J);
+  }
   f64x4 acc[4][4];
   gemm_core<S, false, S, false, BM, BM, true>(
       A + (int64_t)I * BM, lda, A + (int64_t)J * BM, lda, s, 0, Tp, acc, sA, sB);
@@ -1063,23 +1069,67 @@ __global__ void symm_multi_kernel(const double* __restrict__ B, int64_t ld,
 
 // ------------------------------------------------------------ launchers --
 
+// XCD-aware SYRK order.  Workgroups go round-robin over the 8 XCDs, so XCD
+// x runs the workgroups x, x + 8, ...  The 128-column blocks of A fall into
+// 4 groups; XCD x < 6 takes the tiles of one off-diagonal pair of groups,
+// XCDs 6 and 7 the tiles of two diagonal pairs each, and the lists are then
+// evened out.  The tiles running together on one XCD then stream about half
+// of A's column blocks, which its L2 holds band by band, instead of all of
+// them.
+std::vector<int> syrk_tile_order(int nt) {
+  std::vector<int> out;
+  if (nt < 16) return out;
+  constexpr int NX = 8, NG = 4;
+  int gs[NG + 1];
+  for (int g = 0; g <= NG; ++g) gs[g] = g * nt / NG;
+  std::vector<std::vector<std::pair<int, int>>> lists(NX);
+  int x = 0;
+  for (int gi = 1; gi < NG; ++gi)
+    for (int gj = 0; gj < gi; ++gj, ++x)
+      for (int I = gs[gi]; I < gs[gi + 1]; ++I)
+        for (int J = gs[gj]; J < gs[gj + 1]; ++J) lists[x].push_back({I, J});
+  for (int g = 0; g < NG; ++g)
+    for (int I = gs[g]; I < gs[g + 1]; ++I)
+      for (int J = gs[g]; J <= I; ++J) lists[6 + g / 2].push_back({I, J});
+  for (;;) {
+    int hi = 0, lo = 0;
+    for (int k = 1; k < NX; ++k) {
+      if (lists[k].size() > lists[hi].size()) hi = k;
+      if (lists[k].size() < lists[lo].size()) lo = k;
+    }
+    if (lists[hi].size() <= lists[lo].size() + 1) break;
+    lists[lo].push_back(lists[hi].back());
+    lists[hi].pop_back();
+  }
+  size_t len = 0;
+  for (const auto& l : lists) len = std::max(len, l.size());
+  out.assign(2 * NX * len, -1);
+  for (int k = 0; k < NX; ++k)
+    for (size_t i = 0; i < lists[k].size(); ++i) {
+      out[2 * (NX * i + k)] = lists[k][i].first;
+      out[2 * (NX * i + k) + 1] = lists[k][i].second;
+    }
+  return out;
+}
+
 hipError_t launch_syrk(int precision, const void* A, int64_t lda, int64_t Tp,
                        const double* s, double* B, hipStream_t st,
-                       const int* skip, Lanes ls, int nlanes) {
+                       const int* skip, Lanes ls, int nlanes,
+                       const int* order, int64_t order_slots) {
   const int64_t nt = lda / BM, ntiles = nt * (nt + 1) / 2;
-  dim3 g((unsigned)ntiles, (unsigned)nlanes), b(NT);
+  dim3 g((unsigned)(order ? order_slots : ntiles), (unsigned)nlanes), b(NT);
   switch (precision) {
     case 0:
       hipLaunchKernelGGL(syrk_kernel<double>, g, b, 0, st, (const double*)A,
-                         lda, Tp, s, B, skip, ls);
+                         lda, Tp, s, B, skip, ls, order);
       break;
     case 1:
       hipLaunchKernelGGL(syrk_kernel<float>, g, b, 0, st, (const float*)A, lda,
-                         Tp, s, B, skip, ls);
+                         Tp, s, B, skip, ls, order);
       break;
     case 2:
       hipLaunchKernelGGL(syrk_kernel<bf16_t>, g, b, 0, st, (const bf16_t*)A,
-                         lda, Tp, s, B, skip, ls);
+                         lda, Tp, s, B, skip, ls, order);
       break;
     default:
       return hipErrorInvalidValue;

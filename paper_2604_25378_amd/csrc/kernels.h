@@ -1,6 +1,8 @@
 // Kernel launchers of libyand (internal).
 #pragma once
 
+#include <vector>
+
 #include "common.h"
 
 namespace yand {
@@ -91,10 +93,16 @@ struct Lanes {
 };
 
 // B = A^T diag(s) A (full symmetric n x n, ldb = lda), s length Tp, non-null.
+// order (device, nullable): the XCD-aware tile order of syrk_tile_order for
+// this lda / kTile, order_slots workgroups (its length / 2).
 hipError_t launch_syrk(int precision, const void* A, int64_t lda, int64_t Tp,
                        const double* s, double* B, hipStream_t st,
                        const int* skip = nullptr, Lanes ls = Lanes{},
-                       int nlanes = 1);
+                       int nlanes = 1, const int* order = nullptr,
+                       int64_t order_slots = 0);
+// (I, J) pairs of the SYRK's lower tiles per workgroup for nt x nt tiles,
+// grouped by XCD (-1 for idle slots); empty below 16 tiles (plain order).
+std::vector<int> syrk_tile_order(int nt);
 // In-place Cholesky of the lower triangle of M (np x np, np multiple of
 // kTile) and X = L^-1 (lower triangle and the diagonal blocks' upper zeros;
 // the tiles above the diagonal blocks are left untouched).  *fail != 0 on exit
