@@ -288,3 +288,65 @@ def test_frontier_rejects_probe_trace():
                      opts=yb.default_opts(large=True, trace_mode="probe"))
     assert e.value.code == -1
     ctx.close()
+
+
+@pytest.mark.parametrize("restart_max_iter", [2, 120])
+def test_frontier_pcg_simplex_restarts_match_oracle(restart_max_iter):
+    """Simplex with the boundary block in a batch (no targets, so the face
+    solver runs), PCG configuration, max_iter = 2: the instances continue
+    with the projected trial steps 0.045 and then 0.02 like the oracle's
+    solve; restarts, phase iterations, projected steps, status and iterates
+    match it per instance."""
+    print(f"[case] frontier PCG simplex restarts restart_max_iter="
+          f"{restart_max_iter}", flush=True)
+    R = synth.workload_returns("n12_T500")
+    C4 = np.array([synth.WORKLOADS["n12_T500"]["c"],
+                   synth.crra_coefficients(3.0), synth.crra_coefficients(7.0)])
+    ctx = yb.Context(torch.from_numpy(R).cuda())
+    W, infos = ctx.frontier(C4, opts=yb.default_opts(
+        large=True, feasible_set="simplex", max_iter=2,
+        restart_max_iter=restart_max_iter))
+    for b in range(len(C4)):
+        oo = O.Options.large()
+        oo.feasible_set = "simplex"
+        oo.max_iter, oo.restart_max_iter = 2, restart_max_iter
+        xr, ir = O.solve(R, C4[b], opts=oo)
+        its = [p[4] for p in ir.phases]
+        its = tuple(its + [0] * (3 - len(its)))
+        print(f"b={b}: batch {infos[b].status} restarts {infos[b].restarts} "
+              f"{infos[b].phase_iterations}; oracle {ir.status} "
+              f"{ir.restarts} {its}", flush=True)
+        assert infos[b].restarts == ir.restarts
+        assert infos[b].phase_iterations == its
+        assert infos[b].projected_steps == ir.projected_steps
+        assert infos[b].status == ir.status
+        assert np.abs(W[b].cpu().numpy() - xr).max() <= 1e-9
+    assert any(i.restarts >= 1 for i in infos)
+    ctx.close()
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16"])
+def test_frontier_pcg_reduced_storage(prec):
+    """FP32/BF16 storage: the lanes run on separate streams (their trace
+    products are on the storage precision's matrix cores) with the single
+    solve's kernels, so each instance equals its single solve, and converges
+    to a stationary point of the rounded problem judged by the oracle."""
+    from storage import round_storage
+    print(f"[case] frontier PCG {prec} n=300 T=1000", flush=True)
+    R = synth.factor_returns(300, 1000, 5, 0, 5.0, 0.0, 7)
+    mu, A = O.center(R)
+    Ar = round_storage(A, prec)
+    C4, tg = _frontier_instances(R, 2)
+    ctx = yb.Context(torch.from_numpy(R).cuda(), prec)
+    opts = yb.default_opts(large=True)
+    W, infos = ctx.frontier(C4, tg, opts=opts)
+    for b in range(len(C4)):
+        w1, i1 = ctx.solve(C4[b], target=tg[b], opts=opts)
+        wb = W[b].cpu().numpy()
+        assert infos[b].status == 0 and infos[b].iterations == i1.iterations
+        assert infos[b].cg_iters == i1.cg_iters
+        assert np.abs(wb - w1.cpu().numpy()).max() <= 1e-12
+        Cm, _ = O.constraints(mu, tg[b])
+        U = O.tangent_basis(Cm)
+        assert np.linalg.norm(U.T @ O.gradient(Ar, mu, C4[b], wb)) <= 2e-8
+    ctx.close()

@@ -201,3 +201,35 @@ def test_thin_indefinite_matches_oracle(reg):
     _close(d.cpu().numpy(), ref.d, 1e-8)
     if reg == 1e-9:
         assert prof["thin_indef_factor"] >= 2       # escalated at least once
+
+
+def test_thin_indefinite_simplex_solve():
+    """Simplex, PCG configuration, c = (10, 1, 10, 1) on the uniform n = 300,
+    T = 120 panel (2T <= n): directions with psi'' < 0 on some bars take the
+    signed factorisation.  Outside the convexity certificate the two runs
+    need not take the same path to a stationary point, so the check is the
+    outcome: the run ends without error on the push-through route only
+    (thin_traces = dense_traces), at a point of the slice whose projected
+    KKT residual and objective the oracle recomputes to the library's."""
+    print("[case] thin indefinite simplex solve n=300 T=120", flush=True)
+    R = synth.uniform_returns(300, 120, seed=5)
+    c = np.array([10.0, 1.0, 10.0, 1.0])
+    mu, A = O.center(R)
+    ctx = yb.Context(torch.from_numpy(R).cuda())
+    w, info = ctx.solve(c, opts=yb.default_opts(large=True,
+                                                feasible_set="simplex"))
+    ctx.close()
+    w = w.cpu().numpy()
+    print(f"  status {info.status} iterations {info.iterations} traces "
+          f"{info.dense_traces} thin {info.thin_traces} kkt {info.kkt:.1e}",
+          flush=True)
+    assert info.status in (0, 1, 2)
+    assert info.thin_traces == info.dense_traces > 0
+    assert abs(w.sum() - 1.0) <= 1e-12 and w.min() >= 1e-8 - 1e-15
+    g = O.gradient(A, mu, c, w)
+    kkt = float(np.linalg.norm(w - O.project_simplex(w - g, 1e-8)))
+    assert kkt == pytest.approx(info.kkt, rel=1e-6, abs=1e-14)
+    assert O.objective(A, mu, c, w) == pytest.approx(info.f, rel=1e-12)
+    # lower than the equal-weight start
+    x0 = np.full(300, 1.0 / 300)
+    assert info.f < O.objective(A, mu, c, x0)
