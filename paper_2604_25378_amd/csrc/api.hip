@@ -60,6 +60,9 @@ struct Data {
   // XCD-aware tile order of the SYRK (device; null: plain order)
   int* syrk_order = nullptr;
   int64_t syrk_slots = 0;
+  // balanced SYRK schedule over that order (device; null: not used)
+  int* syrk_plan = nullptr;
+  int syrk_wgs = 0, syrk_rounds = 0, syrk_ntile2 = 0, syrk_nslots = 0;
 };
 
 struct Work {
@@ -82,6 +85,9 @@ struct Work {
   double *tGp = nullptr, *tG = nullptr, *tC = nullptr, *tX = nullptr,
          *bdiag = nullptr, *tpart = nullptr;
   double* tW = nullptr;  // indefinite S: blocks of the signed factorisation
+  // balanced SYRK: partial tiles and arrival counters
+  double* syrk_ws = nullptr;
+  int* syrk_cnt = nullptr;
   // probe estimate of the trace: signs and block products (Tp x 64), their
   // split partials, the block PCG vectors (64 x lda each) and per-column
   // scalars and flags
@@ -230,6 +236,8 @@ void free_work(Work& w) {
                   w.pHP, w.pAP, w.pcs};
   for (double* q : pp) dfree(q);
   dfree(w.pflags);
+  dfree(w.syrk_ws);
+  dfree(w.syrk_cnt);
   if (w.sc && w.own_sc) dfree(w.sc);
   if (w.st && w.own_stream) (void)hipStreamDestroy(w.st);
   w = Work{};
@@ -343,6 +351,41 @@ int ensure_dense(Work& w, const Data& D) {
     TRY(alloc(&w.Xl, (size_t)D.lda * D.lda * 4));
   }
   return YAND_OK;
+}
+
+// Workspace of the balanced SYRK for `lanes` lanes (counters cleared once
+// here; every launch leaves them at zero).
+int alloc_syrk_ws(const Data& D, int lanes, hipStream_t st, double** ws,
+                  int** cnt) {
+  const size_t per = (size_t)std::max(D.syrk_nslots, 1) * kTile * kTile;
+  const size_t cn = ((size_t)D.syrk_ntile2 + 1) / 2 * 2;
+  TRY(alloc((void**)ws, per * lanes * sizeof(double)));
+  TRY(alloc((void**)cnt, cn * lanes * sizeof(int)));
+  HIPTRY(launch_fill((double*)*cnt, (int64_t)(cn * lanes / 2), 0.0, st));
+  return YAND_OK;
+}
+
+int ensure_syrk_ws(Work& w, const Data& D) {
+  if (!D.syrk_plan || w.syrk_ws) return YAND_OK;
+  return alloc_syrk_ws(D, 1, w.st, &w.syrk_ws, &w.syrk_cnt);
+}
+
+SyrkSplit syrk_split(const Data& D, double* ws, int* cnt, int lanes_stride) {
+  SyrkSplit p;
+  if (!D.syrk_plan || !ws) return p;
+  p.order = D.syrk_order;
+  p.plan = D.syrk_plan;
+  p.slots = D.syrk_wgs;
+  p.rounds = D.syrk_rounds;
+  p.ntile2 = D.syrk_ntile2;
+  p.nslots = D.syrk_nslots;
+  p.ws = ws;
+  p.cnt = cnt;
+  if (lanes_stride) {
+    p.ws_lane = (int64_t)std::max(D.syrk_nslots, 1) * kTile * kTile;
+    p.cnt_lane = ((int64_t)D.syrk_ntile2 + 1) / 2 * 2;
+  }
+  return p;
 }
 
 int sync_scalars(Work& w) {
@@ -545,11 +588,14 @@ int dir_front(const Data& D, Work& w, const double c[4], int p0,
       return launch_syrk_lp(D.precision, D.At, w.SAt, np, Tp, w.s_t, w.B,
                             w.st, skip);
     }));
-  else
+  else {
+    TRY(ensure_syrk_ws(w, D));
+    const SyrkSplit sp = syrk_split(D, w.syrk_ws, w.syrk_cnt, 0);
     HIPTRY(timed(w, "syrk", [&] {
       return launch_syrk(D.precision, D.A, D.lda, Tp, w.s_t, w.B, w.st, skip,
-                         Lanes{}, 1, D.syrk_order, D.syrk_slots);
+                         Lanes{}, 1, D.syrk_order, D.syrk_slots, &sp);
     }));
+  }
   return dir_front_post(D, w, p0, o, skip);
 }
 
@@ -1160,6 +1206,9 @@ struct Group {
          *Zp = nullptr, *Yp = nullptr;
   PcgLane* pl = nullptr;
   int* cgall = nullptr;
+  // balanced SYRK workspace, one per lane
+  double* syrk_ws = nullptr;
+  int* syrk_cnt = nullptr;
 };
 
 struct LaneRef {
@@ -1179,8 +1228,9 @@ int enqueue_group(const std::vector<LaneRef>& lanes, const DirOpts& o,
     TRY(stationarity(D, w, o, L.p0, eps));
     TRY(dir_front_pre(D, w, L.c, L.p0, &w.sc->done));
   }
+  const SyrkSplit sp = syrk_split(D, G.syrk_ws, G.syrk_cnt, 1);
   HIPTRY(launch_syrk(D.precision, D.A, D.lda, Tp, G.s, G.B, st, G.skip, G.ls,
-                     G.nl, D.syrk_order, D.syrk_slots));
+                     G.nl, D.syrk_order, D.syrk_slots, &sp));
   for (const auto& L : lanes) {
     Work& w = *L.w;
     TRY(dir_front_post(D, w, L.p0, o, &w.sc->done));
@@ -1701,8 +1751,9 @@ int yand_destroy(yand_ctx* ctx) {
   if (!ctx) return YAND_OK;
   flush_timed(ctx->prof, ctx->w.st);
   free_work(ctx->w);
-  void* ptrs[] = {ctx->d.A,    ctx->d.At,    ctx->d.mu,
-                  ctx->d.Efix, ctx->d.AEfix, ctx->d.syrk_order};
+  void* ptrs[] = {ctx->d.A,    ctx->d.At,         ctx->d.mu,
+                  ctx->d.Efix, ctx->d.AEfix,      ctx->d.syrk_order,
+                  ctx->d.syrk_plan};
   for (void* p : ptrs) dfree(p);
   delete ctx;
   return YAND_OK;
@@ -1757,9 +1808,8 @@ static int create_ctx(const double* R, int64_t T, int64_t n, int64_t ldr,
   const int64_t nchunks = (T + 255) / 256;
   if ((rc = alloc((void**)&colpart, (size_t)nchunks * n * sizeof(double))))
     return fail(rc);
-  if (dense_upfront && (rc = ensure_dense(w, D))) return fail(rc);
-  // the SYRK's tile order (not in the allocation-free entry point, whose
-  // context uses the plain order)
+  // the SYRK's tile order and balanced schedule (not in the allocation-free
+  // entry point, whose context uses the plain order)
   if (!g_arena) {
     const std::vector<int> ord = syrk_tile_order((int)D.nt);
     if (!ord.empty()) {
@@ -1769,8 +1819,26 @@ static int create_ctx(const double* R, int64_t T, int64_t n, int64_t ldr,
                     hipMemcpyHostToDevice) != hipSuccess)
         return fail(YAND_ERR_HIP);
       D.syrk_slots = (int64_t)ord.size() / 2;
+      SyrkPlan plan;
+      if (syrk_split_plan((int)D.nt, D.Tp / kSlice, syrk_split_slots(),
+                          &plan)) {
+        if ((rc = alloc((void**)&D.syrk_plan, plan.plan.size() * sizeof(int))))
+          return fail(rc);
+        if (hipMemcpy(D.syrk_plan, plan.plan.data(),
+                      plan.plan.size() * sizeof(int),
+                      hipMemcpyHostToDevice) != hipSuccess)
+          return fail(YAND_ERR_HIP);
+        D.syrk_wgs = plan.slots;
+        D.syrk_rounds = plan.rounds;
+        D.syrk_ntile2 = plan.ntile2;
+        D.syrk_nslots = plan.nslots;
+      }
     }
   }
+  if (dense_upfront && (rc = ensure_dense(w, D))) return fail(rc);
+  if (dense_upfront && D.precision == YAND_FP64 &&
+      (rc = ensure_syrk_ws(w, D)))
+    return fail(rc);
   if (g_arena &&
       launch_fill((double*)g_arena->base, (int64_t)(g_arena->used / 8), 0.0,
                   st) != hipSuccess)
@@ -2288,6 +2356,8 @@ static int batch_solve(int64_t B, yand_ctx* const* ctxs, const double* C4,
     grp.ls.flag = (int64_t)(sizeof(DevScalars) / sizeof(int));
     grp.skip = &dev_sc[0].done;
     grp.fail = &dev_sc[0].fail;
+    if (rc == YAND_OK && big.syrk_plan)
+      rc = alloc_syrk_ws(big, (int)nl, cs, &grp.syrk_ws, &grp.syrk_cnt);
   }
   for (int64_t i = 0; i < nl && rc == YAND_OK; ++i) {
     Work& w = works[i];
@@ -2324,6 +2394,8 @@ static int batch_solve(int64_t B, yand_ctx* const* ctxs, const double* C4,
       }
     }
     if (rc == YAND_OK) rc = ensure_dense(w, big);
+    if (rc == YAND_OK && (big.precision == YAND_FP64 || opts.dense_fp64))
+      rc = ensure_syrk_ws(w, big);
     if (rc == YAND_OK) rc = init_work(w, big);
   }
   for (int64_t start = 0; start < B && rc == YAND_OK; start += nl) {
@@ -2437,6 +2509,8 @@ static int batch_solve(int64_t B, yand_ctx* const* ctxs, const double* C4,
     rc = YAND_ERR_HIP;
   for (auto& w : works) free_work(w);
   for (double* q : gblk) dfree(q);
+  dfree(grp.syrk_ws);
+  dfree(grp.syrk_cnt);
   for (double* q : pblk) dfree(q);
   dfree(grp.pl);
   dfree(grp.cgall);

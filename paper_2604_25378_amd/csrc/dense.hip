@@ -18,7 +18,7 @@ namespace yand {
 namespace {
 
 constexpr int BM = kTile;
-constexpr int BKK = 16;
+constexpr int BKK = kSlice;
 constexpr int NT = 256;
 // Output tiles are TM x TN (128 x 128, or 64-wide for the short launches on
 // the critical path of the factorisation).
@@ -204,10 +204,11 @@ template <typename TA, bool AKC, typename TB, bool BKC, int TM = BM,
 __device__ void gemm_core(const TA* Ab, int64_t lda, const TB* Bb,
                           int64_t ldb, const double* bscale, int64_t kbeg,
                           int64_t kend, f64x4 (&acc)[TM / 32][TN / 32],
-                          double* sA, double* sB) {
+                          double* sA, double* sB,
+                          int tid = (int)threadIdx.x) {
   constexpr int MB = TM / 32, NB = TN / 32;
   constexpr int STA = stage_size<TM>(), STB = stage_size<TN>();
-  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int lane = tid & 63, w = tid >> 6;
   const int wm = (w >> 1) * (TM / 2), wn = (w & 1) * (TN / 2);
 #pragma unroll
   for (int i = 0; i < MB; ++i)
@@ -290,6 +291,18 @@ __device__ __forceinline__ void lower_tile(int64_t b, int* I, int* J) {
 }
 
 // ------------------------------------------------------------------ SYRK --
+// Tile (I, J) of B and, off the diagonal, its mirror (J, I).
+__device__ __forceinline__ void syrk_store(double* B, int64_t ld, int I, int J,
+                                           const f64x4 (&acc)[4][4]) {
+  double* Bij = B + (int64_t)I * BM * ld + (int64_t)J * BM;
+  double* Bji = B + (int64_t)J * BM * ld + (int64_t)I * BM;
+  const bool mirror = I != J;
+  for_each_acc(acc, [&](int r, int c, double v) {
+    Bij[(int64_t)r * ld + c] = v;
+    if (mirror) Bji[(int64_t)c * ld + r] = v;
+  });
+}
+
 // B = A^T diag(s) A, lower tiles computed, written to both triangles.
 template <typename S>
 __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2, 2)))
@@ -313,13 +326,107 @@ syrk_kernel(const S* __restrict__ A, int64_t lda, int64_t Tp,
   f64x4 acc[4][4];
   gemm_core<S, false, S, false, BM, BM, true>(
       A + (int64_t)I * BM, lda, A + (int64_t)J * BM, lda, s, 0, Tp, acc, sA, sB);
-  double* Bij = B + (int64_t)I * BM * lda + (int64_t)J * BM;
-  double* Bji = B + (int64_t)J * BM * lda + (int64_t)I * BM;
-  const bool mirror = I != J;
-  for_each_acc(acc, [&](int r, int c, double v) {
-    Bij[(int64_t)r * lda + c] = v;
-    if (mirror) Bji[(int64_t)c * lda + r] = v;
-  });
+  syrk_store(B, lda, I, J, acc);
+}
+
+// Balanced SYRK (stream-K).  The grid holds one workgroup per resident slot
+// (blockIdx.x = slot, slot % 8 its XCD).  Each workgroup first computes
+// `rounds` whole tiles of the XCD-aware order, then at most two pieces of the
+// tiles left on its XCD, whose K ranges are cut into one equal share per
+// workgroup of that XCD.  A tile cut into several pieces is completed by the
+// workgroup whose piece arrives last (arrival counter): every piece is
+// published to the workspace, and the last one adds them all up from there
+// in piece order (ascending K), so the sum does not depend on the order of
+// arrival, and resets the counter for the next launch.  Nothing waits on
+// another workgroup.
+template <typename S>
+__global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2, 2)))
+syrk_split_kernel(const S* __restrict__ A, int64_t lda, int64_t Tp,
+                  const double* __restrict__ s, double* __restrict__ B,
+                  const int* skip, Lanes ls, const int* __restrict__ order,
+                  int rounds, const int* __restrict__ plan, double* ws,
+                  int64_t ws_lane, int* cnt, int64_t cnt_lane) {
+  const int ln = blockIdx.y;
+  s += ln * ls.vec;
+  B += ln * ls.mat;
+  ws += ln * ws_lane;
+  cnt += ln * cnt_lane;
+  if (skip) skip += ln * ls.flag;
+  if (skip && *skip) return;
+  __shared__ double sA[2 * kStage], sB[2 * kStage];
+  __shared__ int last;
+  const int wg = blockIdx.x, slots = gridDim.x, tid = threadIdx.x;
+  const int* tiles = plan + 2 * kSplitPieceInts * slots;
+  constexpr int64_t kTileD = (int64_t)BM * BM;
+  f64x4 acc[4][4];
+  // jobs [0, rounds): whole tiles; then the two pieces of this workgroup
+  for (int job = 0; job < rounds + 2; ++job) {
+    int I, J, np = 1, t = 0;
+    int64_t kb = 0, ke = Tp;
+    const int* tt = nullptr;
+    const int* pc = nullptr;
+    if (job < rounds) {
+      I = order[2 * (job * slots + wg)];
+      J = order[2 * (job * slots + wg) + 1];
+      if (I < 0) continue;
+    } else {
+      pc = plan + (2 * wg + job - rounds) * kSplitPieceInts;
+      t = pc[0];
+      if (t < 0) continue;
+      tt = tiles + t * kSplitTileInts;
+      I = tt[0];
+      J = tt[1];
+      np = tt[2];
+      kb = (int64_t)pc[1] * BKK;
+      ke = (int64_t)pc[2] * BKK;
+    }
+    // the thread index made opaque per job, so that the products' index
+    // arithmetic is not hoisted out of the loop (it would stay live across
+    // the jobs and spill)
+    int tj = tid;
+    asm volatile("" : "+v"(tj));
+    gemm_core<S, false, S, false, BM, BM, true>(A + (int64_t)I * BM, lda,
+                                                A + (int64_t)J * BM, lda, s,
+                                                kb, ke, acc, sA, sB, tj);
+    if (np > 1) {
+      // publish this piece, thread-major (coalesced for writer and reader)
+      double* mine = ws + (int64_t)(tt[3] + pc[3]) * kTileD;
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+#pragma unroll
+          for (int r = 0; r < 4; ++r)
+            mine[(int64_t)((i * 4 + j) * 4 + r) * NT + tid] = acc[i][j][r];
+      __threadfence();
+      __syncthreads();
+      if (tid == 0) last = atomicAdd(cnt + t, 1) == np - 1;
+      __syncthreads();
+      if (!last) continue;
+      __threadfence();
+      // the tile's entries one at a time, each summed over the pieces
+      const int lane = tid & 63, w = tid >> 6;
+      const int wm = (w >> 1) * (BM / 2), wn = (w & 1) * (BM / 2);
+      double* Bij = B + (int64_t)I * BM * lda + (int64_t)J * BM;
+      double* Bji = B + (int64_t)J * BM * lda + (int64_t)I * BM;
+#pragma unroll 1
+      for (int e = 0; e < 64; ++e) {
+        double v = 0.0;
+        for (int p = 0; p < np; ++p) {
+          const double x =
+              ws[(int64_t)(tt[3] + p) * kTileD + (int64_t)e * NT + tid];
+          v = p == 0 ? x : v + x;
+        }
+        const int rr = wm + (e >> 4) * 16 + (lane >> 4) + 4 * (e & 3);
+        const int cc = wn + ((e >> 2) & 3) * 16 + (lane & 15);
+        Bij[(int64_t)rr * lda + cc] = v;
+        if (I != J) Bji[(int64_t)cc * lda + rr] = v;
+      }
+      if (tid == 0) cnt[t] = 0;
+      continue;
+    }
+    syrk_store(B, lda, I, J, acc);
+  }
 }
 
 // ------------------------------------------------------- trace row norms --
@@ -1118,10 +1225,128 @@ std::vector<int> syrk_tile_order(int nt) {
   return out;
 }
 
+bool syrk_split_plan(int nt, int64_t ns, int slots, SyrkPlan* out) {
+  constexpr int NX = 8;
+  *out = SyrkPlan{};
+  if (slots < NX || slots % NX != 0 || ns < 1) return false;
+  const std::vector<int> ord = syrk_tile_order(nt);
+  if (ord.empty()) return false;
+  const int U = slots / NX;  // workgroups per XCD
+  // list x holds its tiles at positions 0 .. len[x] - 1 (entry NX * i + x)
+  const int64_t rows = (int64_t)ord.size() / (2 * NX);
+  std::vector<int64_t> len(NX, 0);
+  for (int x = 0; x < NX; ++x)
+    for (int64_t i = 0; i < rows; ++i)
+      if (ord[2 * (NX * i + x)] >= 0) len[x] = i + 1;
+  const int64_t lmin = *std::min_element(len.begin(), len.end());
+  const int R = (int)(lmin / U);
+  std::vector<int> pieces(2 * kSplitPieceInts * slots, -1), tiles;
+  for (int x = 0; x < NX; ++x) {
+    const int64_t m = len[x] - (int64_t)R * U;  // tiles cut along K
+    if (m <= 0) continue;
+    const int64_t Q = m * ns;
+    if (Q / U < 16) return false;
+    const int t0 = (int)(tiles.size() / kSplitTileInts);
+    for (int64_t p = 0; p < m; ++p) {
+      const int64_t e = NX * (R * U + p) + x;
+      tiles.push_back(ord[2 * e]);
+      tiles.push_back(ord[2 * e + 1]);
+      tiles.push_back(0);
+      tiles.push_back(-1);
+    }
+    for (int u = 0; u < U; ++u) {
+      const int64_t lo = (int64_t)u * Q / U, hi = (int64_t)(u + 1) * Q / U;
+      const int w = NX * u + x;
+      int q = 0;
+      for (int64_t p = lo / ns; p < m && p * ns < hi; ++p) {
+        const int64_t ks = std::max(lo, p * ns) - p * ns;
+        const int64_t ke = std::min(hi, (p + 1) * ns) - p * ns;
+        if (ke <= ks) continue;
+        int* tr = &tiles[(size_t)(t0 + p) * kSplitTileInts];
+        if (q == 2) return false;
+        int* pc = &pieces[(size_t)(2 * w + q) * kSplitPieceInts];
+        pc[0] = (int)(t0 + p);
+        pc[1] = (int)ks;
+        pc[2] = (int)ke;
+        pc[3] = tr[2]++;
+        ++q;
+      }
+    }
+  }
+  // workspace slots for the pieces of the tiles cut in several; every tile
+  // covered exactly once along K, in piece order
+  const int ntile2 = (int)(tiles.size() / kSplitTileInts);
+  std::vector<int64_t> covered(ntile2, 0), next(ntile2, 0);
+  for (int w = 0; w < slots; ++w)
+    for (int q = 0; q < 2; ++q) {
+      const int* pc = &pieces[(size_t)(2 * w + q) * kSplitPieceInts];
+      if (pc[0] < 0) continue;
+      if (pc[1] != next[pc[0]]) return false;
+      next[pc[0]] = pc[2];
+      covered[pc[0]] += pc[2] - pc[1];
+    }
+  int nslots = 0;
+  for (int t = 0; t < ntile2; ++t) {
+    int* tr = &tiles[(size_t)t * kSplitTileInts];
+    if (covered[t] != ns || tr[2] < 1) return false;
+    if (tr[2] > 1) {
+      tr[3] = nslots;
+      nslots += tr[2];
+    }
+  }
+  out->order.assign(ord.begin(), ord.begin() + 2 * (size_t)R * slots);
+  out->plan = pieces;
+  out->plan.insert(out->plan.end(), tiles.begin(), tiles.end());
+  out->slots = slots;
+  out->rounds = R;
+  out->ntile2 = ntile2;
+  out->nslots = nslots;
+  return true;
+}
+
+int syrk_split_slots() {
+  int dev = 0, cus = 0, per = 0;
+  if (hipGetDevice(&dev) != hipSuccess ||
+      hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount,
+                            dev) != hipSuccess ||
+      hipOccupancyMaxActiveBlocksPerMultiprocessor(
+          &per, syrk_split_kernel<double>, NT, 0) != hipSuccess)
+    return 0;
+  return cus * per;
+}
+
 hipError_t launch_syrk(int precision, const void* A, int64_t lda, int64_t Tp,
                        const double* s, double* B, hipStream_t st,
                        const int* skip, Lanes ls, int nlanes,
-                       const int* order, int64_t order_slots) {
+                       const int* order, int64_t order_slots,
+                       const SyrkSplit* split) {
+  if (split && split->ws && split->cnt) {
+    const SyrkSplit& p = *split;
+    dim3 g((unsigned)p.slots, (unsigned)nlanes), b(NT);
+    switch (precision) {
+      case 0:
+        hipLaunchKernelGGL(syrk_split_kernel<double>, g, b, 0, st,
+                           (const double*)A, lda, Tp, s, B, skip, ls, p.order,
+                           p.rounds, p.plan, p.ws, p.ws_lane, p.cnt,
+                           p.cnt_lane);
+        break;
+      case 1:
+        hipLaunchKernelGGL(syrk_split_kernel<float>, g, b, 0, st,
+                           (const float*)A, lda, Tp, s, B, skip, ls, p.order,
+                           p.rounds, p.plan, p.ws, p.ws_lane, p.cnt,
+                           p.cnt_lane);
+        break;
+      case 2:
+        hipLaunchKernelGGL(syrk_split_kernel<bf16_t>, g, b, 0, st,
+                           (const bf16_t*)A, lda, Tp, s, B, skip, ls, p.order,
+                           p.rounds, p.plan, p.ws, p.ws_lane, p.cnt,
+                           p.cnt_lane);
+        break;
+      default:
+        return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+  }
   const int64_t nt = lda / BM, ntiles = nt * (nt + 1) / 2;
   dim3 g((unsigned)(order ? order_slots : ntiles), (unsigned)nlanes), b(NT);
   switch (precision) {

@@ -84,6 +84,7 @@ hipError_t launch_center(const double* R, int64_t T, int64_t n, int64_t ldr,
 
 // ---- dense FP64 MFMA kernels (dense.hip) ----------------------------------
 constexpr int kTile = 128;  // output tile and Cholesky block size
+constexpr int kSlice = 16;  // K depth of one pipelined slice of the products
 
 // Lanes of a grouped launch (blockIdx.y = lane): element strides between
 // the lanes' n x n matrices (B, M, X), T-vectors (s), row-norm arrays (rn)
@@ -92,17 +93,55 @@ struct Lanes {
   int64_t mat = 0, vec = 0, rn = 0, flag = 0;
 };
 
+// Balanced SYRK schedule (syrk_split_plan) and its per-lane workspace.
+// order: the first rounds x slots (I, J) pairs of syrk_tile_order; plan:
+// kSplitPieceInts ints for each of the two pieces per workgroup (tile, first
+// and end slice, piece index; tile -1: none), then kSplitTileInts ints per
+// tile cut along K (I, J, pieces, first workspace slot; its pieces take
+// consecutive slots) (device, both).  ws: nslots partial tiles of kTile x
+// kTile doubles per lane (ws_lane doubles apart); cnt: ntile2 arrival
+// counters per lane (cnt_lane ints apart), zero before the first launch and
+// left at zero by every launch.
+constexpr int kSplitPieceInts = 4;
+constexpr int kSplitTileInts = 4;
+struct SyrkSplit {
+  const int* order = nullptr;
+  const int* plan = nullptr;
+  int slots = 0, rounds = 0, ntile2 = 0, nslots = 0;
+  double* ws = nullptr;
+  int64_t ws_lane = 0;
+  int* cnt = nullptr;
+  int64_t cnt_lane = 0;
+};
+// Host tables of the balanced schedule (see syrk_split_plan).
+struct SyrkPlan {
+  std::vector<int> order, plan;
+  int slots = 0, rounds = 0, ntile2 = 0, nslots = 0;
+};
+
 // B = A^T diag(s) A (full symmetric n x n, ldb = lda), s length Tp, non-null.
 // order (device, nullable): the XCD-aware tile order of syrk_tile_order for
-// this lda / kTile, order_slots workgroups (its length / 2).
+// this lda / kTile, order_slots workgroups (its length / 2).  split
+// (nullable, with a workspace): the balanced schedule instead, on
+// split->slots workgroups per lane.
 hipError_t launch_syrk(int precision, const void* A, int64_t lda, int64_t Tp,
                        const double* s, double* B, hipStream_t st,
                        const int* skip = nullptr, Lanes ls = Lanes{},
                        int nlanes = 1, const int* order = nullptr,
-                       int64_t order_slots = 0);
+                       int64_t order_slots = 0,
+                       const SyrkSplit* split = nullptr);
 // (I, J) pairs of the SYRK's lower tiles per workgroup for nt x nt tiles,
 // grouped by XCD (-1 for idle slots); empty below 16 tiles (plain order).
 std::vector<int> syrk_tile_order(int nt);
+// Balanced schedule of the SYRK for nt x nt tiles and ns kSlice-deep
+// slices per tile on `slots` resident workgroups (a multiple of the 8 XCDs): whole
+// tiles of syrk_tile_order for as many full rounds as every XCD's list
+// fills, then each XCD's remaining tiles cut along K into one equal share
+// per workgroup of that XCD.  False when it does not apply (fewer than 16
+// tiles, shares under 16 slices).
+bool syrk_split_plan(int nt, int64_t ns, int slots, SyrkPlan* out);
+// Resident workgroups of the balanced SYRK kernel on the current device.
+int syrk_split_slots();
 // In-place Cholesky of the lower triangle of M (np x np, np multiple of
 // kTile) and X = L^-1 (lower triangle and the diagonal blocks' upper zeros;
 // the tiles above the diagonal blocks are left untouched).  *fail != 0 on exit
