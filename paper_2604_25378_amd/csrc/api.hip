@@ -62,7 +62,8 @@ struct Data {
   int64_t syrk_slots = 0;
   // balanced SYRK schedule over that order (device; null: not used)
   int* syrk_plan = nullptr;
-  int syrk_wgs = 0, syrk_rounds = 0, syrk_ntile2 = 0, syrk_nslots = 0;
+  int syrk_wgs = 0, syrk_rounds = 0, syrk_ntile2 = 0, syrk_npieces = 0,
+      syrk_nslots = 0;
 };
 
 struct Work {
@@ -378,6 +379,7 @@ SyrkSplit syrk_split(const Data& D, double* ws, int* cnt, int lanes_stride) {
   p.slots = D.syrk_wgs;
   p.rounds = D.syrk_rounds;
   p.ntile2 = D.syrk_ntile2;
+  p.npieces = D.syrk_npieces;
   p.nslots = D.syrk_nslots;
   p.ws = ws;
   p.cnt = cnt;
@@ -1831,6 +1833,7 @@ static int create_ctx(const double* R, int64_t T, int64_t n, int64_t ldr,
         D.syrk_wgs = plan.slots;
         D.syrk_rounds = plan.rounds;
         D.syrk_ntile2 = plan.ntile2;
+        D.syrk_npieces = plan.npieces;
         D.syrk_nslots = plan.nslots;
       }
     }

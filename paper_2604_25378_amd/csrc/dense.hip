@@ -10,6 +10,7 @@
 // 256 threads = 4 waves in a 2 x 2 grid, each wave 64 x 64 = 4 x 4 MFMA
 // blocks; operands are staged through LDS k-major (contiguous along m / n).
 #include <algorithm>
+#include <array>
 
 #include "common.h"
 #include "kernels.h"
@@ -331,21 +332,20 @@ syrk_kernel(const S* __restrict__ A, int64_t lda, int64_t Tp,
 
 // Balanced SYRK (stream-K).  The grid holds one workgroup per resident slot
 // (blockIdx.x = slot, slot % 8 its XCD).  Each workgroup first computes
-// `rounds` whole tiles of the XCD-aware order, then at most two pieces of the
-// tiles left on its XCD, whose K ranges are cut into one equal share per
-// workgroup of that XCD.  A tile cut into several pieces is completed by the
-// workgroup whose piece arrives last (arrival counter): every piece is
-// published to the workspace, and the last one adds them all up from there
-// in piece order (ascending K), so the sum does not depend on the order of
-// arrival, and resets the counter for the next launch.  Nothing waits on
-// another workgroup.
+// `rounds` whole tiles of the XCD-aware order, then its pieces of the tiles
+// left on its XCD (see syrk_split_plan).  A tile cut into several pieces is
+// completed by the workgroup whose piece arrives last (arrival counter):
+// every piece is published to the workspace, and the last one adds them
+// all up from there in piece order (ascending K), so the sum does not
+// depend on the order of arrival, and resets the counter for the next
+// launch.  Nothing waits on another workgroup.
 template <typename S>
 __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(2, 2)))
 syrk_split_kernel(const S* __restrict__ A, int64_t lda, int64_t Tp,
                   const double* __restrict__ s, double* __restrict__ B,
                   const int* skip, Lanes ls, const int* __restrict__ order,
-                  int rounds, const int* __restrict__ plan, double* ws,
-                  int64_t ws_lane, int* cnt, int64_t cnt_lane) {
+                  int rounds, const int* __restrict__ plan, int npieces,
+                  double* ws, int64_t ws_lane, int* cnt, int64_t cnt_lane) {
   const int ln = blockIdx.y;
   s += ln * ls.vec;
   B += ln * ls.mat;
@@ -356,11 +356,13 @@ syrk_split_kernel(const S* __restrict__ A, int64_t lda, int64_t Tp,
   __shared__ double sA[2 * kStage], sB[2 * kStage];
   __shared__ int last;
   const int wg = blockIdx.x, slots = gridDim.x, tid = threadIdx.x;
-  const int* tiles = plan + 2 * kSplitPieceInts * slots;
+  const int first = plan[2 * wg], count = plan[2 * wg + 1];
+  const int* pieces = plan + 2 * slots;
+  const int* tiles = pieces + npieces * kSplitPieceInts;
   constexpr int64_t kTileD = (int64_t)BM * BM;
   f64x4 acc[4][4];
-  // jobs [0, rounds): whole tiles; then the two pieces of this workgroup
-  for (int job = 0; job < rounds + 2; ++job) {
+  // jobs [0, rounds): whole tiles; then this workgroup's pieces
+  for (int job = 0; job < rounds + count; ++job) {
     int I, J, np = 1, t = 0;
     int64_t kb = 0, ke = Tp;
     const int* tt = nullptr;
@@ -370,9 +372,8 @@ syrk_split_kernel(const S* __restrict__ A, int64_t lda, int64_t Tp,
       J = order[2 * (job * slots + wg) + 1];
       if (I < 0) continue;
     } else {
-      pc = plan + (2 * wg + job - rounds) * kSplitPieceInts;
+      pc = pieces + (first + job - rounds) * kSplitPieceInts;
       t = pc[0];
-      if (t < 0) continue;
       tt = tiles + t * kSplitTileInts;
       I = tt[0];
       J = tt[1];
@@ -1240,66 +1241,98 @@ bool syrk_split_plan(int nt, int64_t ns, int slots, SyrkPlan* out) {
       if (ord[2 * (NX * i + x)] >= 0) len[x] = i + 1;
   const int64_t lmin = *std::min_element(len.begin(), len.end());
   const int R = (int)(lmin / U);
-  std::vector<int> pieces(2 * kSplitPieceInts * slots, -1), tiles;
+  // per workgroup its pieces (tile, first slice, end slice); per tile its
+  // block indices and pieces in K order
+  std::vector<std::vector<std::array<int, 3>>> wp(slots);
+  std::vector<int> tiles;
+  std::vector<int> npieces;
   for (int x = 0; x < NX; ++x) {
     const int64_t m = len[x] - (int64_t)R * U;  // tiles cut along K
     if (m <= 0) continue;
-    const int64_t Q = m * ns;
-    if (Q / U < 16) return false;
-    const int t0 = (int)(tiles.size() / kSplitTileInts);
+    // m <= U; every workgroup of the XCD gets an equal share Lb.  The
+    // first m take the bodies [0, Lb) of the m tiles, so that they sweep
+    // the same slices of A together; the other U - m share the remainders
+    // [Lb, ns), concatenated tile by tile.
+    const int64_t Lb = m * ns / U;
+    if (m > U || Lb < 16) return false;
+    const int t0 = (int)npieces.size();
     for (int64_t p = 0; p < m; ++p) {
       const int64_t e = NX * (R * U + p) + x;
       tiles.push_back(ord[2 * e]);
       tiles.push_back(ord[2 * e + 1]);
-      tiles.push_back(0);
-      tiles.push_back(-1);
+      npieces.push_back(0);
+      wp[NX * p + x].push_back({(int)(t0 + p), 0, (int)Lb});
     }
-    for (int u = 0; u < U; ++u) {
-      const int64_t lo = (int64_t)u * Q / U, hi = (int64_t)(u + 1) * Q / U;
-      const int w = NX * u + x;
-      int q = 0;
-      for (int64_t p = lo / ns; p < m && p * ns < hi; ++p) {
-        const int64_t ks = std::max(lo, p * ns) - p * ns;
-        const int64_t ke = std::min(hi, (p + 1) * ns) - p * ns;
-        if (ke <= ks) continue;
-        int* tr = &tiles[(size_t)(t0 + p) * kSplitTileInts];
-        if (q == 2) return false;
-        int* pc = &pieces[(size_t)(2 * w + q) * kSplitPieceInts];
-        pc[0] = (int)(t0 + p);
-        pc[1] = (int)ks;
-        pc[2] = (int)ke;
-        pc[3] = tr[2]++;
-        ++q;
+    const int64_t rw = U - m, rem = ns - Lb, Q = m * rem;
+    if (rem > 0 && rw == 0) return false;
+    for (int64_t v = 0; v < rw && rem > 0; ++v) {
+      const int64_t lo = v * Q / rw, hi = (v + 1) * Q / rw;
+      const int w = (int)(NX * (m + v) + x);
+      for (int64_t p = lo / rem; p < m && p * rem < hi; ++p) {
+        const int64_t ks = std::max(lo, p * rem) - p * rem + Lb;
+        const int64_t ke = std::min(hi, (p + 1) * rem) - p * rem + Lb;
+        if (ke > ks) wp[w].push_back({(int)(t0 + p), (int)ks, (int)ke});
       }
     }
   }
-  // workspace slots for the pieces of the tiles cut in several; every tile
-  // covered exactly once along K, in piece order
-  const int ntile2 = (int)(tiles.size() / kSplitTileInts);
-  std::vector<int64_t> covered(ntile2, 0), next(ntile2, 0);
+  // piece indices in K order per tile (bodies first, then the remainders in
+  // the order of their workgroups, which is ascending K); coverage check
+  const int ntile2 = (int)npieces.size();
+  std::vector<int64_t> next(ntile2, 0);
+  std::vector<std::vector<std::array<int, 2>>> by_tile(ntile2);  // (w, j)
   for (int w = 0; w < slots; ++w)
-    for (int q = 0; q < 2; ++q) {
-      const int* pc = &pieces[(size_t)(2 * w + q) * kSplitPieceInts];
-      if (pc[0] < 0) continue;
-      if (pc[1] != next[pc[0]]) return false;
-      next[pc[0]] = pc[2];
-      covered[pc[0]] += pc[2] - pc[1];
-    }
-  int nslots = 0;
+    for (int j = 0; j < (int)wp[w].size(); ++j) by_tile[wp[w][j][0]].push_back({w, j});
+  std::vector<std::vector<int>> pidx(slots);
+  for (int w = 0; w < slots; ++w) pidx[w].assign(wp[w].size(), -1);
   for (int t = 0; t < ntile2; ++t) {
-    int* tr = &tiles[(size_t)t * kSplitTileInts];
-    if (covered[t] != ns || tr[2] < 1) return false;
-    if (tr[2] > 1) {
-      tr[3] = nslots;
-      nslots += tr[2];
+    auto& v = by_tile[t];
+    std::sort(v.begin(), v.end(), [&](const std::array<int, 2>& a,
+                                      const std::array<int, 2>& b) {
+      return wp[a[0]][a[1]][1] < wp[b[0]][b[1]][1];
+    });
+    for (size_t k = 0; k < v.size(); ++k) {
+      const auto& pc = wp[v[k][0]][v[k][1]];
+      if (pc[1] != next[t]) return false;
+      next[t] = pc[2];
+      pidx[v[k][0]][v[k][1]] = (int)k;
     }
+    if (next[t] != ns) return false;
+    npieces[t] = (int)v.size();
+  }
+  int nslots = 0;
+  std::vector<int> base(ntile2, -1);
+  for (int t = 0; t < ntile2; ++t)
+    if (npieces[t] > 1) {
+      base[t] = nslots;
+      nslots += npieces[t];
+    }
+  // device layout: per workgroup (first piece, count); the pieces; the tiles
+  std::vector<int> plan(2 * (size_t)slots, 0);
+  int np = 0;
+  for (int w = 0; w < slots; ++w) {
+    plan[2 * w] = np;
+    plan[2 * w + 1] = (int)wp[w].size();
+    np += (int)wp[w].size();
+  }
+  for (int w = 0; w < slots; ++w)
+    for (size_t j = 0; j < wp[w].size(); ++j) {
+      plan.push_back(wp[w][j][0]);
+      plan.push_back(wp[w][j][1]);
+      plan.push_back(wp[w][j][2]);
+      plan.push_back(pidx[w][j]);
+    }
+  for (int t = 0; t < ntile2; ++t) {
+    plan.push_back(tiles[2 * t]);
+    plan.push_back(tiles[2 * t + 1]);
+    plan.push_back(npieces[t]);
+    plan.push_back(base[t]);
   }
   out->order.assign(ord.begin(), ord.begin() + 2 * (size_t)R * slots);
-  out->plan = pieces;
-  out->plan.insert(out->plan.end(), tiles.begin(), tiles.end());
+  out->plan = std::move(plan);
   out->slots = slots;
   out->rounds = R;
   out->ntile2 = ntile2;
+  out->npieces = np;
   out->nslots = nslots;
   return true;
 }
@@ -1327,20 +1360,20 @@ hipError_t launch_syrk(int precision, const void* A, int64_t lda, int64_t Tp,
       case 0:
         hipLaunchKernelGGL(syrk_split_kernel<double>, g, b, 0, st,
                            (const double*)A, lda, Tp, s, B, skip, ls, p.order,
-                           p.rounds, p.plan, p.ws, p.ws_lane, p.cnt,
-                           p.cnt_lane);
+                           p.rounds, p.plan, p.npieces, p.ws, p.ws_lane,
+                           p.cnt, p.cnt_lane);
         break;
       case 1:
         hipLaunchKernelGGL(syrk_split_kernel<float>, g, b, 0, st,
                            (const float*)A, lda, Tp, s, B, skip, ls, p.order,
-                           p.rounds, p.plan, p.ws, p.ws_lane, p.cnt,
-                           p.cnt_lane);
+                           p.rounds, p.plan, p.npieces, p.ws, p.ws_lane,
+                           p.cnt, p.cnt_lane);
         break;
       case 2:
         hipLaunchKernelGGL(syrk_split_kernel<bf16_t>, g, b, 0, st,
                            (const bf16_t*)A, lda, Tp, s, B, skip, ls, p.order,
-                           p.rounds, p.plan, p.ws, p.ws_lane, p.cnt,
-                           p.cnt_lane);
+                           p.rounds, p.plan, p.npieces, p.ws, p.ws_lane,
+                           p.cnt, p.cnt_lane);
         break;
       default:
         return hipErrorInvalidValue;

@@ -95,19 +95,19 @@ struct Lanes {
 
 // Balanced SYRK schedule (syrk_split_plan) and its per-lane workspace.
 // order: the first rounds x slots (I, J) pairs of syrk_tile_order; plan:
-// kSplitPieceInts ints for each of the two pieces per workgroup (tile, first
-// and end slice, piece index; tile -1: none), then kSplitTileInts ints per
-// tile cut along K (I, J, pieces, first workspace slot; its pieces take
-// consecutive slots) (device, both).  ws: nslots partial tiles of kTile x
-// kTile doubles per lane (ws_lane doubles apart); cnt: ntile2 arrival
-// counters per lane (cnt_lane ints apart), zero before the first launch and
-// left at zero by every launch.
+// per workgroup (first piece, piece count), then npieces pieces of
+// kSplitPieceInts ints (tile, first and end slice, index of the piece in
+// its tile), then ntile2 tiles of kSplitTileInts ints (I, J, pieces, first
+// workspace slot; a tile's pieces take consecutive slots) (device, both).
+// ws: nslots partial tiles of kTile x kTile doubles per lane (ws_lane
+// doubles apart); cnt: ntile2 arrival counters per lane (cnt_lane ints
+// apart), zero before the first launch and left at zero by every launch.
 constexpr int kSplitPieceInts = 4;
 constexpr int kSplitTileInts = 4;
 struct SyrkSplit {
   const int* order = nullptr;
   const int* plan = nullptr;
-  int slots = 0, rounds = 0, ntile2 = 0, nslots = 0;
+  int slots = 0, rounds = 0, ntile2 = 0, npieces = 0, nslots = 0;
   double* ws = nullptr;
   int64_t ws_lane = 0;
   int* cnt = nullptr;
@@ -116,7 +116,7 @@ struct SyrkSplit {
 // Host tables of the balanced schedule (see syrk_split_plan).
 struct SyrkPlan {
   std::vector<int> order, plan;
-  int slots = 0, rounds = 0, ntile2 = 0, nslots = 0;
+  int slots = 0, rounds = 0, ntile2 = 0, npieces = 0, nslots = 0;
 };
 
 // B = A^T diag(s) A (full symmetric n x n, ldb = lda), s length Tp, non-null.
@@ -134,11 +134,14 @@ hipError_t launch_syrk(int precision, const void* A, int64_t lda, int64_t Tp,
 // grouped by XCD (-1 for idle slots); empty below 16 tiles (plain order).
 std::vector<int> syrk_tile_order(int nt);
 // Balanced schedule of the SYRK for nt x nt tiles and ns kSlice-deep
-// slices per tile on `slots` resident workgroups (a multiple of the 8 XCDs): whole
-// tiles of syrk_tile_order for as many full rounds as every XCD's list
-// fills, then each XCD's remaining tiles cut along K into one equal share
-// per workgroup of that XCD.  False when it does not apply (fewer than 16
-// tiles, shares under 16 slices).
+// slices per tile on `slots` resident workgroups (a multiple of the 8
+// XCDs): whole tiles of syrk_tile_order for as many full rounds as every
+// XCD's list fills; then each XCD's m remaining tiles are shared equally by
+// its U workgroups: the first m take the tiles' leading slices (all at the
+// same K at the same time, as in a whole round), the other U - m the rest
+// of every tile, concatenated.  False when it does not apply (fewer than
+// 16 tiles, shares under 16 slices).
+
 bool syrk_split_plan(int nt, int64_t ns, int slots, SyrkPlan* out);
 // Resident workgroups of the balanced SYRK kernel on the current device.
 int syrk_split_slots();
