@@ -344,8 +344,10 @@ int yand_mvsk_solve_R(const double* R, int64_t T, int64_t n, double c1,
 
 /* For callers that cannot allocate device memory (code under HIP graph
  * capture, tight serving loops, harnesses that forbid hipMalloc): the
- * stateless solve of yand_mvsk_solve_R (same arguments, same kernels, same
- * results), with every workspace -- the centered copy of A, mu, the pass
+ * stateless solve of yand_mvsk_solve_R (same arguments, kernels and results;
+ * from 16 tile columns, n > 1920, the SYRK keeps its plain tile order instead
+ * of the balanced schedule, and results agree to rounding), with every
+ * workspace -- the centered copy of A, mu, the pass
  * partials, the n x n factor buffers -- carved from one fixed 256 MiB device
  * array that the library holds on each device it runs on until the process
  * ends.  It calls no hipMalloc, hipFree or other allocating routine and uses
