@@ -104,6 +104,9 @@ struct Work {
   // blocks (freed by the batch, not by the lane); with the PCG
   // configuration pcg_p and hv are rows of the batch's 64 x lda blocks
   bool shared_dense = false, shared_pcg = false;
+  // the context's own workspace (single solves), as opposed to a batch lane
+  // that shares the device with other lanes
+  bool solo = false;
   DevScalars hs{};
   Prof* prof = nullptr;
 };
@@ -609,7 +612,7 @@ int dir_factor(const Data& D, Work& w, int p0, const int* skip,
                         mask));
   HIPTRY(timed(w, "potrf_trtri", [&] {
     return launch_potrf_trtri(w.M, w.X, np, &w.sc->fail, w.st, skip,
-                              D.chol_group);
+                              D.chol_group, Lanes{}, 1, w.solo);
   }));
   return YAND_OK;
 }
@@ -1805,6 +1808,7 @@ static int create_ctx(const double* R, int64_t T, int64_t n, int64_t ldr,
       (rc = alloc((void**)&D.AEfix, 2 * tb)))
     return fail(rc);
   if ((rc = alloc_work(w, D, nullptr))) return fail(rc);
+  w.solo = true;
   hipStream_t st = w.st;
   double* colpart = nullptr;
   const int64_t nchunks = (T + 255) / 256;
@@ -2893,7 +2897,8 @@ int yand_autotune(yand_ctx* ctx, double* report) {
     for (int rep = 0; rep < 2; ++rep) {
       HIPTRY(launch_project(w.B, w.M, np, n, np, w.E, w.W, p0 + 1, w.sc, st));
       HIPTRY(hipEventRecord(e0, st));
-      HIPTRY(launch_potrf_trtri(w.M, w.X, np, &w.sc->fail, st, nullptr, grp));
+      HIPTRY(launch_potrf_trtri(w.M, w.X, np, &w.sc->fail, st, nullptr, grp,
+                                Lanes{}, 1, true));
       HIPTRY(hipEventRecord(e1, st));
       HIPTRY(hipEventSynchronize(e1));
       float t = 0.f;

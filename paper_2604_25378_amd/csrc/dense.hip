@@ -878,11 +878,35 @@ __device__ __forceinline__ void leaf_inv(double* S, const double* rd,
   }
 }
 
+// Work of a deferred group update carried by the diagonal-block launch:
+// sub-blocks [q0, q1) (64 x 64, see update_block) of the update from the
+// panels [kA, kB) to the columns [jlo, jhi) and inverse rows [ilo, ...).
+struct UpdFill {
+  int kA = 0, kB = 0, jlo = 0, jhi = 0, ilo = 0, nu = 0, q0 = 0, q1 = 0;
+};
+template <int TM>
+__device__ __forceinline__ void update_block(double* M, double* X, int64_t ld,
+                                             int nt, int kA, int kB, int jlo,
+                                             int jhi, int ilo, int nu, int q,
+                                             int t, double* sA, double* sB);
+constexpr int kFillTM = 64;
+static_assert(2 * 4 * (size_t)stage_size<kFillTM>() * sizeof(double) <=
+                  kDiagLds,
+              "both halves' stages fit in the diagonal block's LDS");
+
+// Workgroup 0 factors and inverts diagonal block k.  Workgroups 1, 2, ...
+// (one per CU: they take the same LDS) each compute two sub-blocks of the
+// deferred update `fill`, one per half of the workgroup: the two 64 x 64
+// halves of one 128 x 64 strip of a tile (the same reduction length, so both
+// halves pass the same barriers).  The update touches tiles disjoint from
+// block k's column and row; it only fills CUs the diagonal block leaves
+// idle.
 __global__ void __launch_bounds__(DT) diag_block_kernel(double* M, double* X,
                                                         int64_t ld, int k,
                                                         int* fail,
                                                         const int* skip,
-                                                        Lanes ls) {
+                                                        Lanes ls,
+                                                        UpdFill fill) {
   const int ln = blockIdx.y;
   M += ln * ls.mat;
   X += ln * ls.mat;
@@ -890,6 +914,17 @@ __global__ void __launch_bounds__(DT) diag_block_kernel(double* M, double* X,
   if (skip) skip += ln * ls.flag;
   if (skip && *skip) return;
   extern __shared__ double S[];  // BM x LDD, then rdiag (BM), then a zero
+  if (blockIdx.x > 0) {
+    const int q = fill.q0 + 2 * ((int)blockIdx.x - 1);
+    if (q >= fill.q1) return;  // uniform: q and q + 1 < q1 together
+    constexpr int SS = 2 * stage_size<kFillTM>();
+    const int half = (int)threadIdx.x >> 8;
+    double* sA = S + half * 2 * SS;
+    update_block<kFillTM>(M, X, ld, (int)(ld / BM), fill.kA, fill.kB,
+                          fill.jlo, fill.jhi, fill.ilo, fill.nu, q + half,
+                          (int)threadIdx.x & 255, sA, sA + SS);
+    return;
+  }
   double* rd = S + BM * LDD;
   double* zs = rd + BM;
   const int tid = threadIdx.x, lane = tid & 63;
@@ -1075,25 +1110,28 @@ __device__ __forceinline__ void sub_block(int b, int* tile, int* so, int* sc) {
 //                         stored rather than added when j >= kA (the first
 //                         contribution), so X needs no clearing beforehand.
 // The two sets touch disjoint tiles (columns J >= kB versus j < kB).
-// Occupancy: two workgroups per CU for 128-wide tiles (their LDS), three
-// for the 64-wide group-update sub-blocks and four for the 32-wide in-group
-// ones (the whole factorisation at n = 5504: 5.18 -> 4.96 -> 4.85 ms).
+// Sub-block q (see sub_block) of that trailing update, computed by the 256
+// threads t in [0, 256) of the calling workgroup with LDS stages sA, sB.
 template <int TM>
-constexpr int update_waves() { return TM == 32 ? 4 : TM == 64 ? 3 : 2; }
-template <int TM>
-__global__ void __launch_bounds__(NT)
-__attribute__((amdgpu_waves_per_eu(update_waves<TM>(), update_waves<TM>())))
-update_kernel(double* M, double* X, int64_t ld, int nt, int kA, int kB,
-              int jlo, int jhi, int ilo, int nu, const int* skip, Lanes ls) {
-  const int ln = blockIdx.y;
-  M += ln * ls.mat;
-  X += ln * ls.mat;
-  if (skip) skip += ln * ls.flag;
-  if (skip && *skip) return;
-  __shared__ double sA[2 * stage_size<TM>()], sB[2 * stage_size<TM>()];
+__device__ __forceinline__ void update_block(double* M, double* X, int64_t ld,
+                                             int nt, int kA, int kB, int jlo,
+                                             int jhi, int ilo, int nu, int q,
+                                             int t, double* sA, double* sB) {
   int b, so, sc;
-  sub_block<TM>(blockIdx.x, &b, &so, &sc);
+  sub_block<TM>(q, &b, &so, &sc);
   f64x4 acc[TM / 32][TM / 32];
+  const int lane = t & 63, w = t >> 6;
+  const int wm = (w >> 1) * (TM / 2), wn = (w & 1) * (TM / 2);
+  auto each = [&](auto f) {
+#pragma unroll
+    for (int i = 0; i < TM / 32; ++i)
+#pragma unroll
+      for (int j = 0; j < TM / 32; ++j)
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+          f(wm + i * 16 + (lane >> 4) + 4 * r, wn + j * 16 + (lane & 15),
+            acc[i][j][r]);
+  };
   if (b < nu) {
     int J = jlo;
     while (J < jhi && b >= nt - J) {   // column J holds tiles I = J .. nt-1
@@ -1105,9 +1143,9 @@ update_kernel(double* M, double* X, int64_t ld, int nt, int kA, int kB,
     const double* Lj = M + (int64_t)J * BM * ld + (int64_t)sc * ld;
     gemm_core<double, true, double, true, TM>(Li, ld, Lj, ld, nullptr,
                                               (int64_t)kA * BM,
-                                              (int64_t)kB * BM, acc, sA, sB);
+                                              (int64_t)kB * BM, acc, sA, sB, t);
     double* Mij = M + (int64_t)I * BM * ld + (int64_t)J * BM;
-    for_each_acc<TM>(acc, [&](int r, int c, double v) {
+    each([&](int r, int c, double v) {
       Mij[(int64_t)(so + r) * ld + sc + c] -= v;
     });
   } else {
@@ -1117,16 +1155,38 @@ update_kernel(double* M, double* X, int64_t ld, int nt, int kA, int kB,
     const double* Li = M + (int64_t)i * BM * ld + (int64_t)so * ld;
     gemm_core<double, true, double, false, TM>(Li, ld, X + (int64_t)j * BM + sc,
                                                ld, nullptr, (int64_t)k0 * BM,
-                                               (int64_t)kB * BM, acc, sA, sB);
+                                               (int64_t)kB * BM, acc, sA, sB, t);
     // the update whose reduction starts at k = j brings the first
     // contribution (X[k, j] = 0 for k < j): it stores, later ones add
     double* Sij = X + (int64_t)i * BM * ld + (int64_t)j * BM;
     const bool first = j >= kA;
-    for_each_acc<TM>(acc, [&](int r, int c, double v) {
+    each([&](int r, int c, double v) {
       double* p = Sij + (int64_t)(so + r) * ld + sc + c;
       *p = first ? v : *p + v;
     });
   }
+}
+
+// Occupancy: two workgroups per CU for 128-wide tiles (their LDS), three
+// for the 64-wide group-update sub-blocks and four for the 32-wide in-group
+// ones (the whole factorisation at n = 5504: 5.18 -> 4.96 -> 4.85 ms).
+template <int TM>
+constexpr int update_waves() { return TM == 32 ? 4 : TM == 64 ? 3 : 2; }
+// Sub-blocks q0 + blockIdx.x of the update.
+template <int TM>
+__global__ void __launch_bounds__(NT)
+__attribute__((amdgpu_waves_per_eu(update_waves<TM>(), update_waves<TM>())))
+update_kernel(double* M, double* X, int64_t ld, int nt, int kA, int kB,
+              int jlo, int jhi, int ilo, int nu, int q0, const int* skip,
+              Lanes ls) {
+  const int ln = blockIdx.y;
+  M += ln * ls.mat;
+  X += ln * ls.mat;
+  if (skip) skip += ln * ls.flag;
+  if (skip && *skip) return;
+  __shared__ double sA[2 * stage_size<TM>()], sB[2 * stage_size<TM>()];
+  update_block<TM>(M, X, ld, nt, kA, kB, jlo, jhi, ilo, nu,
+                   q0 + (int)blockIdx.x, (int)threadIdx.x, sA, sB);
 }
 
 // ------------------------------------------------------ matrix-vectors ----
@@ -1432,9 +1492,19 @@ constexpr int kFinBand = 32;
 constexpr int kStepTM = 32;
 constexpr int kGroupTM = 64;
 
+// CUs of the current device (0 if unknown).
+static int device_cus() {
+  int dev = 0, cus = 0;
+  if (hipGetDevice(&dev) != hipSuccess ||
+      hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount,
+                            dev) != hipSuccess)
+    return 0;
+  return cus;
+}
+
 hipError_t launch_potrf_trtri(double* M, double* X, int64_t np, int* fail,
                               hipStream_t st, const int* skip, int group,
-                              Lanes ls, int nlanes) {
+                              Lanes ls, int nlanes, bool fill) {
   const unsigned L = (unsigned)nlanes;
   const int kGroup = group > 0 ? group : kDefaultGroup;
   const int nt = (int)(np / BM);
@@ -1443,26 +1513,48 @@ hipError_t launch_potrf_trtri(double* M, double* X, int64_t np, int* fail,
   if (pe != hipSuccess) return pe;
   constexpr int QS = (BM / kStepTM) * (BM / kStepTM);  // sub-blocks per tile
   constexpr int QG = (BM / kGroupTM) * (BM / kGroupTM);
+  static_assert(kGroupTM == kFillTM, "deferred sub-blocks are group sub-blocks");
+  // workgroups a diagonal-block launch can add for the deferred update
+  // (one per CU besides its own; single lane only)
+  const int nfill = fill && nlanes == 1 ? std::max(device_cus() - 1, 0) : 0;
+  auto tiles = [&](int kB, int jlo, int jhi, int ilo, int ihi, int* nu) {
+    *nu = 0;
+    for (int J = jlo; J < jhi; ++J) *nu += nt - J;
+    return *nu + (ihi - ilo) * kB;
+  };
   auto update = [&](int kA, int kB, int jlo, int jhi, int ilo, int ihi,
                     bool small) {
-    int nu = 0;
-    for (int J = jlo; J < jhi; ++J) nu += nt - J;
-    const int ni = (ihi - ilo) * kB;
-    if (nu + ni == 0) return;
+    int nu;
+    const int n = tiles(kB, jlo, jhi, ilo, ihi, &nu);
+    if (n == 0) return;
     if (small)
-      hipLaunchKernelGGL(update_kernel<kStepTM>, dim3((nu + ni) * QS, L),
-                         dim3(NT), 0, st, M, X, np, nt, kA, kB, jlo, jhi, ilo,
-                         nu, skip, ls);
+      hipLaunchKernelGGL(update_kernel<kStepTM>, dim3(n * QS, L), dim3(NT), 0,
+                         st, M, X, np, nt, kA, kB, jlo, jhi, ilo, nu, 0, skip,
+                         ls);
     else
-      hipLaunchKernelGGL(update_kernel<kGroupTM>, dim3((nu + ni) * QG, L),
-                         dim3(NT), 0, st, M, X, np, nt, kA, kB, jlo, jhi, ilo,
-                         nu, skip, ls);
+      hipLaunchKernelGGL(update_kernel<kGroupTM>, dim3(n * QG, L), dim3(NT), 0,
+                         st, M, X, np, nt, kA, kB, jlo, jhi, ilo, nu, 0, skip,
+                         ls);
   };
+  // The group update of group g is split: the next group's columns and
+  // inverse rows at once (its steps need them), the rest (columns and
+  // inverse rows from the group after next on) deferred into the next
+  // group's diagonal-block launches, and what they do not absorb launched
+  // before the next group update.  Every tile still receives the groups'
+  // contributions in group order with the same arithmetic.
+  UpdFill pend;
   for (int g0 = 0; g0 < nt; g0 += kGroup) {
     const int g1 = g0 + kGroup < nt ? g0 + kGroup : nt;
     for (int k = g0; k < g1; ++k) {
-      hipLaunchKernelGGL(diag_block_kernel, dim3(1, L), dim3(DT), lds, st, M,
-                         X, np, k, fail, skip, ls);
+      UpdFill f = pend;
+      int extra = 0;
+      if (pend.q0 < pend.q1) {
+        extra = std::min(nfill, (pend.q1 - pend.q0) / 2);
+        f.q1 = pend.q0 + 2 * extra;
+        pend.q0 = f.q1;
+      }
+      hipLaunchKernelGGL(diag_block_kernel, dim3(1 + extra, L), dim3(DT), lds,
+                         st, M, X, np, k, fail, skip, ls, f);
       const int rem = nt - k - 1;
       if (rem + k > 0)
         hipLaunchKernelGGL(panel_finalize_kernel<kFinBand>,
@@ -1470,7 +1562,22 @@ hipError_t launch_potrf_trtri(double* M, double* X, int64_t np, int* fail,
                            st, M, X, np, k, rem, skip, ls);
       if (k + 1 < g1) update(k, k + 1, k + 1, g1, k + 1, g1, true);
     }
-    if (g1 < nt) update(g0, g1, g1, nt, g1, nt, false);
+    if (pend.q0 < pend.q1)
+      hipLaunchKernelGGL(update_kernel<kGroupTM>, dim3(pend.q1 - pend.q0, L),
+                         dim3(NT), 0, st, M, X, np, nt, pend.kA, pend.kB,
+                         pend.jlo, pend.jhi, pend.ilo, pend.nu, pend.q0, skip,
+                         ls);
+    pend = UpdFill{};
+    if (g1 >= nt) continue;
+    const int g2 = g1 + kGroup < nt ? g1 + kGroup : nt;
+    if (nfill > 0 && g2 < nt) {
+      update(g0, g1, g1, g2, g1, g2, false);
+      int nu;
+      const int n = tiles(g1, g2, nt, g2, nt, &nu);
+      pend = UpdFill{g0, g1, g2, nt, g2, nu, 0, n * QG};
+    } else {
+      update(g0, g1, g1, nt, g1, nt, false);
+    }
   }
   return hipGetLastError();
 }
