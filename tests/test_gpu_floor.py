@@ -56,7 +56,7 @@ def _compare(R, profile, q, large):
         assert abs(ret - floor) <= 1e-9 * spread
     assert ret == pytest.approx(float(mu @ w), rel=1e-12)
     assert np.abs(w - ref.x).max() <= 1e-7
-    assert abs(w.sum() - 1.0) <= 1e-12 and w.min() >= 1e-8 * (1 - 1e-9)
+    assert abs(w.sum() - 1.0) <= 1e-12 and w.min() >= 1e-8 - 1e-15
 
 
 @pytest.mark.parametrize("profile,q", [(KURT, 0.4), (KURT, 0.6), (BAL, 0.6)])

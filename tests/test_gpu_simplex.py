@@ -68,7 +68,7 @@ def test_boundary_block_iterates_match_oracle(iters):
     assert info.iterations == iters
     assert info.projected_steps == ir.projected_steps
     assert np.abs(w - xr).max() <= 1e-9
-    assert w.min() >= 1e-8 * (1 - 1e-9) and abs(w.sum() - 1.0) <= 1e-12
+    assert w.min() >= 1e-8 - 1e-15 and abs(w.sum() - 1.0) <= 1e-12
     ctx.close()
 
 
