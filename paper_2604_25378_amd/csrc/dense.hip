@@ -1191,6 +1191,46 @@ update_kernel(double* M, double* X, int64_t ld, int nt, int kA, int kB,
 
 // ------------------------------------------------------ matrix-vectors ----
 // y = X v, X lower (np x np); one wave per row, rows < n.
+// Dot products of the first len entries of one row with P vectors
+// V + a * vs (one wave; row 16-byte aligned).  Each lane reads two
+// consecutive entries of the row per load and keeps four such loads in
+// flight, so that a wave streams 4 KB of the row at a time.
+template <int P>
+__device__ __forceinline__ void row_dots(const double* __restrict__ row,
+                                         int64_t len,
+                                         const double* __restrict__ V,
+                                         int64_t vs, int lane, double (&s)[P]) {
+  constexpr int U = 4;
+  double acc[P][2];
+#pragma unroll
+  for (int a = 0; a < P; ++a) acc[a][0] = acc[a][1] = 0.0;
+  int64_t k = 2 * lane;
+  for (; k + 128 * (U - 1) + 1 < len; k += 128 * U) {
+    double2 b[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u)
+      b[u] = *reinterpret_cast<const double2*>(row + k + 128 * u);
+#pragma unroll
+    for (int u = 0; u < U; ++u)
+#pragma unroll
+      for (int a = 0; a < P; ++a) {
+        const double* e = V + a * vs + k + 128 * u;
+        acc[a][0] = fma(b[u].x, e[0], acc[a][0]);
+        acc[a][1] = fma(b[u].y, e[1], acc[a][1]);
+      }
+  }
+  for (; k < len; k += 128) {
+#pragma unroll
+    for (int a = 0; a < P; ++a) {
+      acc[a][0] = fma(row[k], V[a * vs + k], acc[a][0]);
+      if (k + 1 < len)
+        acc[a][1] = fma(row[k + 1], V[a * vs + k + 1], acc[a][1]);
+    }
+  }
+#pragma unroll
+  for (int a = 0; a < P; ++a) s[a] = wave_sum(acc[a][0] + acc[a][1]);
+}
+
 __global__ void trmv_n_kernel(const double* __restrict__ X, int64_t ld,
                               int64_t n, const double* __restrict__ v,
                               double* __restrict__ y, const int* skip) {
@@ -1198,10 +1238,9 @@ __global__ void trmv_n_kernel(const double* __restrict__ X, int64_t ld,
   const int64_t i = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
   const int lane = threadIdx.x & 63;
   if (i >= n) return;
-  double s = 0.0;
-  for (int64_t k = lane; k <= i; k += 64) s += X[i * ld + k] * v[k];
-  s = wave_sum(s);
-  if (lane == 0) y[i] = s;
+  double s[1];
+  row_dots<1>(X + i * ld, i + 1, v, 0, lane, s);
+  if (lane == 0) y[i] = s[0];
 }
 
 // part[b][j] = sum_{i in rows of block b, i >= j} X[i][j] v[i].
@@ -1219,23 +1258,20 @@ __global__ void trmv_t_kernel(const double* __restrict__ X, int64_t ld,
   part[(int64_t)blockIdx.y * n + j] = s;
 }
 
-// W[a*n + i] = sum_j B[i][j] E[a*n + j], a < p (B full symmetric).
+// W[a*n + i] = sum_j B[i][j] E[a*n + j], a < P (B full symmetric).
+template <int P>
 __global__ void symm_multi_kernel(const double* __restrict__ B, int64_t ld,
                                   int64_t n, const double* __restrict__ E,
-                                  int p, double* __restrict__ W,
-                                  const int* skip) {
+                                  double* __restrict__ W, const int* skip) {
   if (skip && *skip) return;
   const int64_t i = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
   const int lane = threadIdx.x & 63;
   if (i >= n) return;
-  double s[3] = {0.0, 0.0, 0.0};
-  for (int64_t j = lane; j < n; j += 64) {
-    double b = B[i * ld + j];
-    for (int a = 0; a < p; ++a) s[a] += b * E[a * n + j];
-  }
-  for (int a = 0; a < p; ++a) {
-    double t = wave_sum(s[a]);
-    if (lane == 0) W[a * n + i] = t;
+  double s[P];
+  row_dots<P>(B + i * ld, n, E, n, lane, s);
+  if (lane == 0) {
+#pragma unroll
+    for (int a = 0; a < P; ++a) W[a * n + i] = s[a];
   }
 }
 
@@ -1735,8 +1771,23 @@ hipError_t launch_trmv(const double* X, int64_t np, int64_t n,
 hipError_t launch_symm_multi(const double* B, int64_t ldb, int64_t n,
                              const double* E, int p, double* W,
                              hipStream_t st, const int* skip) {
-  hipLaunchKernelGGL(symm_multi_kernel, dim3((unsigned)((n + 3) / 4)),
-                     dim3(256), 0, st, B, ldb, n, E, p, W, skip);
+  const dim3 g((unsigned)((n + 3) / 4)), b(256);
+  switch (p) {
+    case 1:
+      hipLaunchKernelGGL(symm_multi_kernel<1>, g, b, 0, st, B, ldb, n, E, W,
+                         skip);
+      break;
+    case 2:
+      hipLaunchKernelGGL(symm_multi_kernel<2>, g, b, 0, st, B, ldb, n, E, W,
+                         skip);
+      break;
+    case 3:
+      hipLaunchKernelGGL(symm_multi_kernel<3>, g, b, 0, st, B, ldb, n, E, W,
+                         skip);
+      break;
+    default:
+      return hipErrorInvalidValue;
+  }
   return hipGetLastError();
 }
 

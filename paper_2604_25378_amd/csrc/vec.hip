@@ -126,40 +126,49 @@ trace_scale_kernel(const double* __restrict__ B, int64_t ld, int64_t n,
 // that block leaves K = P_S M^-1 P_S unchanged, and this one makes its share
 // a_ti^2 / M_ii of |L^-1 a_t|^2 vanish below FP64 resolution, so the exact
 // trace needs no correction for the bound coordinates.
-__global__ void project_kernel(const double* __restrict__ B, double* M,
-                               int64_t ld, int64_t n, int64_t np,
-                               const double* __restrict__ E,
-                               const double* __restrict__ W, int p,
-                               const DevScalars* __restrict__ sc,
-                               const double* __restrict__ mask) {
+// One workgroup per row i of the lower triangle; the row's own values are
+// read once and each thread walks the row's columns j <= i.
+__global__ void __launch_bounds__(256)
+project_kernel(const double* __restrict__ B, double* M, int64_t ld, int64_t n,
+               int64_t np, const double* __restrict__ E,
+               const double* __restrict__ W, int p,
+               const DevScalars* __restrict__ sc,
+               const double* __restrict__ mask) {
   if (sc->done) return;
-  const int64_t i = blockIdx.y;
-  const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (j > i || i >= np) return;
-  double v;
-  if (i < n && j < n) {
-    const double lam = sc->lambda, gam = sc->gamma;
-    double ei[3], ej[3], wi[3], wj[3];
+  const int64_t i = blockIdx.x;
+  double* Mi = M + i * ld;
+  if (i >= n) {
+    for (int64_t j = threadIdx.x; j <= i; j += blockDim.x)
+      Mi[j] = i == j ? 1.0 : 0.0;
+    return;
+  }
+  const double lam = sc->lambda, gam = sc->gamma;
+  double ei[3], wi[3], ge[9];
+  for (int a = 0; a < p; ++a) {
+    ei[a] = E[a * n + i];
+    wi[a] = W[a * n + i];
+    for (int b = 0; b < p; ++b) ge[a * 3 + b] = sc->GE[a * 3 + b];
+  }
+  const double mi = mk(mask, i);
+  const double* Bi = B + i * ld;
+  for (int64_t j = threadIdx.x; j <= i; j += blockDim.x) {
+    double ej[3], wj[3];
     for (int a = 0; a < p; ++a) {
-      ei[a] = E[a * n + i];
       ej[a] = E[a * n + j];
-      wi[a] = W[a * n + i];
       wj[a] = W[a * n + j];
     }
-    const double mi = mk(mask, i), mj = mk(mask, j);
-    v = mi * mj * B[i * ld + j];
+    const double mj = mk(mask, j);
+    double v = mi * mj * Bi[j];
     double ee = 0.0;
     for (int a = 0; a < p; ++a) {
       v -= ei[a] * (mj * wj[a]) + (mi * wi[a]) * ej[a];
       ee += ei[a] * ej[a];
-      for (int b = 0; b < p; ++b) v += ei[a] * sc->GE[a * 3 + b] * ej[b];
+      for (int b = 0; b < p; ++b) v += ei[a] * ge[a * 3 + b] * ej[b];
     }
     v += (gam - lam) * ee;
     if (i == j) v += mi != 0.0 ? lam : 1e30 * gam;
-  } else {
-    v = i == j ? 1.0 : 0.0;
+    Mi[j] = v;
   }
-  M[i * ld + j] = v;
 }
 
 // q_t = sum_J rn[J][t] - gamma^-1 sum_a (A e_a)_t^2  (a_t^T K a_t).
@@ -794,9 +803,8 @@ hipError_t launch_project(const double* B, double* M, int64_t ld, int64_t n,
                           int64_t np, const double* E, const double* W, int p,
                           const DevScalars* sc, hipStream_t st,
                           const double* mask) {
-  dim3 g((unsigned)((np + 255) / 256), (unsigned)np);
-  hipLaunchKernelGGL(project_kernel, g, dim3(256), 0, st, B, M, ld, n, np, E,
-                     W, p, sc, mask);
+  hipLaunchKernelGGL(project_kernel, dim3((unsigned)np), dim3(256), 0, st, B,
+                     M, ld, n, np, E, W, p, sc, mask);
   return hipGetLastError();
 }
 hipError_t launch_trace_weight(const double* rn, int nt, int64_t Tp,
