@@ -10,7 +10,10 @@ the direction and the solve it feeds (exact-trace, direct configuration):
     solve matching the oracle's iterates to 1e-9 (every iteration launches
     the SYRK again on the counters the previous launch left at zero);
   - grouped lanes (one launch for all lanes, a workspace per lane) equal
-    lanes on separate streams bit for bit at n = 2048.
+    lanes on separate streams bit for bit at n = 2048;
+  - FP32 and BF16 storage with the exact trace's products in FP64
+    (dense_fp64 = 1, the same schedule reading the stored type): direction
+    against the oracle's on the rounded matrix to 1e-8 at n = 2048.
 """
 
 import numpy as np
@@ -18,6 +21,7 @@ import pytest
 
 import oracle as O
 import synth
+from storage import round_storage
 
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
@@ -66,4 +70,25 @@ def test_balanced_syrk_grouped_lanes_match_separate_streams():
                            grouped=True)
     for b in range(2):
         assert np.array_equal(Wg[b].cpu().numpy(), Ws[b].cpu().numpy())
+    ctx.close()
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16"])
+def test_balanced_syrk_reduced_storage_fp64_products(prec):
+    print(f"[case] balanced SYRK {prec} storage, FP64 products, n=2048",
+          flush=True)
+    R = synth.factor_returns(2048, 3000, 8, 4, 5.0, 0.01, 23)
+    c = np.array([1.0, 5.0, 2.0, 10.0])
+    mu, A = O.center(R)
+    Ar = round_storage(A, prec)
+    Cm, b = O.constraints(mu)
+    U = O.tangent_basis(Cm)
+    x = O.feasible_start(Cm, b)
+    ref = O.affine_normal(Ar, mu, c, x, U)
+    ctx = yb.Context(torch.from_numpy(R).cuda(), prec)
+    d, gn = ctx.affine_normal(c, x, opts=yb.default_opts(dense_fp64=1))
+    err = _rel(d.cpu().numpy(), ref.d)
+    print(f"  direction relative error {err:.2e}", flush=True)
+    assert gn == pytest.approx(ref.gnorm, rel=1e-11)
+    assert err <= 1e-8
     ctx.close()
