@@ -13,7 +13,11 @@ the direction and the solve it feeds (exact-trace, direct configuration):
     lanes on separate streams bit for bit at n = 2048;
   - FP32 and BF16 storage with the exact trace's products in FP64
     (dense_fp64 = 1, the same schedule reading the stored type): direction
-    against the oracle's on the rounded matrix to 1e-8 at n = 2048.
+    against the oracle's on the rounded matrix to 1e-8 at n = 2048;
+  - the deferred group update of single solves (carried by the diagonal-
+    block launches) leaves every result unchanged: single solves equal
+    batch lanes on separate streams, which factor without it, bit for bit
+    at n = 2048 (16 tile columns: three groups defer work).
 """
 
 import numpy as np
@@ -91,4 +95,20 @@ def test_balanced_syrk_reduced_storage_fp64_products(prec):
     print(f"  direction relative error {err:.2e}", flush=True)
     assert gn == pytest.approx(ref.gnorm, rel=1e-11)
     assert err <= 1e-8
+    ctx.close()
+
+
+def test_deferred_group_update_is_bit_identical():
+    print("[case] deferred group update, single solves vs batch lanes, "
+          "n=2048", flush=True)
+    R = synth.factor_returns(2048, 3000, 8, 4, 5.0, 0.01, 24)
+    C4 = np.array([synth.crra_coefficients(g) for g in (2.0, 6.0)])
+    ctx = yb.Context(torch.from_numpy(R).cuda())
+    opts = yb.default_opts(max_iter=3, eps=0.0)
+    Wb, ib = yb.batch_solve([ctx] * 2, C4, opts=opts, grouped=False,
+                            use_graph=False)
+    for b in range(2):
+        w, info = ctx.solve(C4[b], opts=opts)
+        assert info.iterations == ib[b].iterations == 3
+        assert np.array_equal(w.cpu().numpy(), Wb[b].cpu().numpy())
     ctx.close()
