@@ -237,12 +237,14 @@ hipError_t launch_lane_scale(const double* Z, const double* s, int64_t vec,
 // q_t = k^-1 sum_j Xi_tj Q_tj (zero for t >= T).
 hipError_t launch_probe_q(const double* Xi, const double* Q, int64_t T,
                           int64_t Tp, int k, double* q, hipStream_t st);
-// y = X v (lower), y = X^T v (transposed); X is np x np.  part holds
+// y = X v (lower), y = X^T v (transposed); X is np x np, 16-byte aligned
+// with np even (rows are read two entries at a time).  part holds
 // ceil(n/64) * n doubles of partial sums for the transposed product.
 hipError_t launch_trmv(const double* X, int64_t np, int64_t n,
                        const double* v, double* y, double* part, bool trans,
                        hipStream_t st, const int* skip = nullptr);
-// W[:, a] = B E[:, a] for a < p (E is n x p column-major with ld n).
+// W[:, a] = B E[:, a] for a < p <= 3 (E is n x p column-major with ld n;
+// B 16-byte aligned with ldb even).
 hipError_t launch_symm_multi(const double* B, int64_t ldb, int64_t n,
                              const double* E, int p, double* W,
                              hipStream_t st, const int* skip = nullptr);
