@@ -11,7 +11,7 @@ are compared, not samples:
   - affine-normal direction and one full outer iteration from equal weights:
     relative 1e-9 of |d|_inf (observed ~2e-11; the bound leaves room for the
     condition of the tangent Hessian times FP64 rounding);
-  - a complete solve and four frontier instances: stationarity judged by the
+  - a complete solve and twelve frontier instances: stationarity judged by the
     oracle, |U^T grad f(w)| <= 2e-8 with the oracle's own tangent basis, and
     the constraints to rounding.
 """
@@ -125,10 +125,14 @@ def test_fullscale_solve_objective_matches_oracle_solve(full):
 
 
 def test_fullscale_frontier_certified_by_oracle(full):
+    """Twelve frontier instances in lockstep (four return targets x CRRA
+    gamma 3, 5, 8): each stationary by the oracle's reduced gradient, on
+    its budget and return constraints."""
     R, A, mu, ctx = full["R"], full["A"], full["mu"], full["ctx"]
-    targets = synth.frontier_targets(R, 5)[1:4:2]
-    C4 = np.array([synth.crra_coefficients(g) for g in (3.0, 8.0) for _ in targets])
-    tg = np.tile(targets, 2)
+    targets = synth.frontier_targets(R, 6)[1:5]
+    gammas = (3.0, 5.0, 8.0)
+    C4 = np.array([synth.crra_coefficients(g) for g in gammas for _ in targets])
+    tg = np.tile(targets, len(gammas))
     W, infos = ctx.frontier(C4, tg)
     W = W.cpu().numpy()
     for b in range(len(tg)):
