@@ -1243,7 +1243,7 @@ int enqueue_group(const std::vector<LaneRef>& lanes, const DirOpts& o,
                           w.st, face_mask(w, o)));
   }
   HIPTRY(launch_potrf_trtri(G.M, G.X, np, G.fail, st, G.skip, D.chol_group,
-                            G.ls, G.nl));
+                            G.ls, G.nl, true));
   HIPTRY(launch_trace_gemm(D.precision, D.A, D.lda, Tp, G.X, np, G.rn, st,
                            G.skip, G.ls, G.nl));
   for (const auto& L : lanes) {

@@ -894,8 +894,9 @@ static_assert(2 * 4 * (size_t)stage_size<kFillTM>() * sizeof(double) <=
                   kDiagLds,
               "both halves' stages fit in the diagonal block's LDS");
 
-// Workgroup 0 factors and inverts diagonal block k.  Workgroups 1, 2, ...
-// (one per CU: they take the same LDS) each compute two sub-blocks of the
+// Per lane (blockIdx.y), workgroup 0 factors and inverts diagonal block k.
+// Workgroups 1, 2, ... (one per CU: they take the same LDS) each compute
+// two sub-blocks of the
 // deferred update `fill`, one per half of the workgroup: the two 64 x 64
 // halves of one 128 x 64 strip of a tile (the same reduction length, so both
 // halves pass the same barriers).  The update touches tiles disjoint from
@@ -1550,9 +1551,16 @@ hipError_t launch_potrf_trtri(double* M, double* X, int64_t np, int* fail,
   constexpr int QS = (BM / kStepTM) * (BM / kStepTM);  // sub-blocks per tile
   constexpr int QG = (BM / kGroupTM) * (BM / kGroupTM);
   static_assert(kGroupTM == kFillTM, "deferred sub-blocks are group sub-blocks");
-  // workgroups a diagonal-block launch can add for the deferred update
-  // (one per CU besides its own; single lane only)
-  const int nfill = fill && nlanes == 1 ? std::max(device_cus() - 1, 0) : 0;
+  // workgroups a diagonal-block launch can add per lane for the deferred
+  // update: the CUs the lanes' own diagonal blocks leave, shared equally,
+  // so that every lane's diagonal block starts at once (none if that leaves
+  // fewer than 8 per lane)
+  int nfill = 0;
+  if (fill) {
+    const int cus = device_cus();
+    nfill = cus > nlanes ? (cus - nlanes) / nlanes : 0;
+    if (nfill < 8) nfill = 0;
+  }
   auto tiles = [&](int kB, int jlo, int jhi, int ilo, int ihi, int* nu) {
     *nu = 0;
     for (int J = jlo; J < jhi; ++J) *nu += nt - J;

@@ -148,10 +148,10 @@ int syrk_split_slots();
 // In-place Cholesky of the lower triangle of M (np x np, np multiple of
 // kTile) and X = L^-1 (lower triangle and the diagonal blocks' upper zeros;
 // the tiles above the diagonal blocks are left untouched).  *fail != 0 on exit
-// when a pivot was not positive.  fill (single lane): the diagonal-block
-// launches also carry most of the previous group update on the CUs they
-// leave idle (the same results; meant for a stream that has the device to
-// itself, since those launches then take every CU).
+// when a pivot was not positive.  fill: the diagonal-block launches also
+// carry most of the previous group update on the CUs they leave idle, shared
+// equally among the lanes (the same results; meant for a stream that has the
+// device to itself, since those launches then take every CU).
 hipError_t launch_potrf_trtri(double* M, double* X, int64_t np, int* fail,
                               hipStream_t st, const int* skip = nullptr,
                               int group = 0, Lanes ls = Lanes{},
