@@ -4,7 +4,8 @@ the direction and the solve it feeds (exact-trace, direct configuration):
 
   - n = 2048, T = 3000 (16 x 16 tiles: no whole round, every tile cut into
     3 to 5 pieces) and n = 4224, T = 6000 (33 tiles: one whole round, then
-    the 49 tiles left in up to 12 pieces each); T > n, so that the tangent
+    the 49 tiles left in up to 12 pieces each), and n = 2500, T = 3001 (ragged
+    padding of both dimensions, 20 tile columns); T > n, so that the tangent
     Hessian has full rank:
     affine-normal direction relative 1e-9 of |d|_inf and a three-iteration
     solve matching the oracle's iterates to 1e-9 (every iteration launches
@@ -37,7 +38,7 @@ def _rel(got, ref):
     return np.abs(got - ref).max() / np.abs(ref).max()
 
 
-@pytest.mark.parametrize("n,T", [(2048, 3000), (4224, 6000)])
+@pytest.mark.parametrize("n,T", [(2048, 3000), (2500, 3001), (4224, 6000)])
 def test_balanced_syrk_direction_and_iterates_match_oracle(n, T):
     print(f"[case] balanced SYRK n={n} T={T}", flush=True)
     R = synth.factor_returns(n, T, 8, 4, 5.0, 0.01, 21)
