@@ -591,7 +591,7 @@ int dir_front(const Data& D, Work& w, const double c[4], int p0,
   if (D.precision != YAND_FP64 && !o.dense64)
     HIPTRY(timed(w, "syrk", [&] {
       return launch_syrk_lp(D.precision, D.At, w.SAt, np, Tp, w.s_t, w.B,
-                            w.st, skip);
+                            w.st, skip, D.syrk_order, D.syrk_slots);
     }));
   else {
     TRY(ensure_syrk_ws(w, D));

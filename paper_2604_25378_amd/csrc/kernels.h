@@ -170,10 +170,13 @@ hipError_t launch_transpose_lp(int precision, const void* A, int64_t lda,
                                int64_t Tp, void* At, hipStream_t st);
 // B = A^T diag(s) A from At: SAt (np x Tp x 4 bytes scratch) = s-scaled At
 // (BF16: high and low parts), then FP32-accumulated products; B (np x np,
-// FP64) exactly symmetric.
+// FP64) exactly symmetric.  order (device, nullable): the XCD-aware tile
+// order of syrk_tile_order, order_slots workgroups.
 hipError_t launch_syrk_lp(int precision, const void* At, void* SAt,
                           int64_t np, int64_t Tp, const double* s, double* B,
-                          hipStream_t st, const int* skip = nullptr);
+                          hipStream_t st, const int* skip = nullptr,
+                          const int* order = nullptr,
+                          int64_t order_slots = 0);
 // rn as launch_trace_gemm from X rounded into Xl (np x np x 4 bytes
 // scratch; BF16: high and low parts).
 hipError_t launch_trace_lp(int precision, const void* A, int64_t lda,

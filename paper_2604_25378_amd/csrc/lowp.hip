@@ -194,17 +194,26 @@ __device__ __forceinline__ void lp_lower_tile(int64_t b, int* I, int* J) {
 }
 
 // B = At SAt^T (n x n, FP64 out): lower tiles, mirrored.  A diagonal tile
-// writes its lower half and mirrors it, so B is exactly symmetric.
+// writes its lower half and mirrors it, so B is exactly symmetric.  order
+// (nullable): the tile (I, J) of each workgroup, -1 for an idle one (the
+// XCD-aware order of the FP64 SYRK).
 template <typename S>
 __global__ void __launch_bounds__(LNT) __attribute__((amdgpu_waves_per_eu(2, 2)))
 syrk_lp_kernel(const S* __restrict__ At, const S* __restrict__ SAt,
                int64_t ldt, int64_t K, int64_t qsplit,
-               double* __restrict__ B, int64_t ldb, const int* skip) {
+               double* __restrict__ B, int64_t ldb, const int* skip,
+               const int* __restrict__ order) {
   if (skip && *skip) return;
   __shared__ __align__(16) S sP[2 * lp_stage_elems<S>()];
   __shared__ __align__(16) S sQ[2 * lp_stage_elems<S>()];
   int I, J;
-  lp_lower_tile(blockIdx.x, &I, &J);
+  if (order) {
+    I = order[2 * blockIdx.x];
+    J = order[2 * blockIdx.x + 1];
+    if (I < 0) return;
+  } else {
+    lp_lower_tile(blockIdx.x, &I, &J);
+  }
   f32x4 acc[4][4];
   lp_core<S>(At + (int64_t)I * LT * ldt, ldt, SAt + (int64_t)J * LT * ldt,
              ldt, K, acc, sP, sQ);
@@ -377,14 +386,15 @@ xconv_kernel(const double* __restrict__ X, int64_t np, S* __restrict__ Xl,
 template <typename S>
 hipError_t syrk_lp(const S* At, S* SAt, int64_t np, int64_t Tp,
                    const double* s, double* B, hipStream_t st,
-                   const int* skip) {
+                   const int* skip, const int* order, int64_t order_slots) {
   const int64_t chunks = np * (Tp / Lp<S>::E);
   const unsigned g = (unsigned)std::min<int64_t>((chunks + 255) / 256, 8192);
   hipLaunchKernelGGL(scale_cols_kernel<S>, dim3(g), dim3(256), 0, st, At, np,
                      Tp, s, SAt, skip);
   const int64_t nt = np / LT;
-  hipLaunchKernelGGL(syrk_lp_kernel<S>, dim3((unsigned)(nt * (nt + 1) / 2)),
-                     dim3(LNT), 0, st, At, SAt, Tp, Tp, np * Tp, B, np, skip);
+  const int64_t nwg = order ? order_slots : nt * (nt + 1) / 2;
+  hipLaunchKernelGGL(syrk_lp_kernel<S>, dim3((unsigned)nwg), dim3(LNT), 0, st,
+                     At, SAt, Tp, Tp, np * Tp, B, np, skip, order);
   return hipGetLastError();
 }
 
@@ -419,13 +429,14 @@ hipError_t launch_transpose_lp(int precision, const void* A, int64_t lda,
 
 hipError_t launch_syrk_lp(int precision, const void* At, void* SAt,
                           int64_t np, int64_t Tp, const double* s, double* B,
-                          hipStream_t st, const int* skip) {
+                          hipStream_t st, const int* skip, const int* order,
+                          int64_t order_slots) {
   if (precision == 1)
     return syrk_lp<float>((const float*)At, (float*)SAt, np, Tp, s, B, st,
-                          skip);
+                          skip, order, order_slots);
   if (precision == 2)
     return syrk_lp<bf16_t>((const bf16_t*)At, (bf16_t*)SAt, np, Tp, s, B, st,
-                           skip);
+                           skip, order, order_slots);
   return hipErrorInvalidValue;
 }
 

@@ -12,9 +12,11 @@ the direction and the solve it feeds (exact-trace, direct configuration):
     the SYRK again on the counters the previous launch left at zero);
   - grouped lanes (one launch for all lanes, a workspace per lane) equal
     lanes on separate streams bit for bit at n = 2048;
-  - FP32 and BF16 storage with the exact trace's products in FP64
-    (dense_fp64 = 1, the same schedule reading the stored type): direction
-    against the oracle's on the rounded matrix to 1e-8 at n = 2048;
+  - FP32 and BF16 storage at n = 2048: with the exact trace's products in
+    FP64 (dense_fp64 = 1, the same schedule reading the stored type) the
+    direction matches the oracle's on the rounded matrix to 1e-8; with the
+    FP32-accumulated matrix-core products (in the XCD-aware tile order) to
+    1e-2, five times the measured error;
   - the deferred group update of single solves (carried by the diagonal-
     block launches) leaves every result unchanged: single solves equal
     batch lanes on separate streams, which factor without it, bit for bit
@@ -78,10 +80,19 @@ def test_balanced_syrk_grouped_lanes_match_separate_streams():
     ctx.close()
 
 
+# direction error of the FP32-accumulated matrix-core products, relative to
+# |d|_inf: measured 1.7e-3 (FP32) and 1.0e-3 (BF16) on this instance, whose
+# tangent Hessian (T = 1.5 n) amplifies the products' FP32 accumulation more
+# than the n = 300, T = 1000 instance of the storage-precision tests; a tile
+# computed for the wrong (I, J) would move the direction by O(1)
+D_BOUND = {"fp32": 1e-2, "bf16": 1e-2}
+
+
+@pytest.mark.parametrize("dense_fp64", [1, 0])
 @pytest.mark.parametrize("prec", ["fp32", "bf16"])
-def test_balanced_syrk_reduced_storage_fp64_products(prec):
-    print(f"[case] balanced SYRK {prec} storage, FP64 products, n=2048",
-          flush=True)
+def test_balanced_syrk_reduced_storage_fp64_products(prec, dense_fp64):
+    print(f"[case] {prec} storage, dense_fp64={dense_fp64}, n=2048 (XCD-aware "
+          f"tile order of the products)", flush=True)
     R = synth.factor_returns(2048, 3000, 8, 4, 5.0, 0.01, 23)
     c = np.array([1.0, 5.0, 2.0, 10.0])
     mu, A = O.center(R)
@@ -91,11 +102,11 @@ def test_balanced_syrk_reduced_storage_fp64_products(prec):
     x = O.feasible_start(Cm, b)
     ref = O.affine_normal(Ar, mu, c, x, U)
     ctx = yb.Context(torch.from_numpy(R).cuda(), prec)
-    d, gn = ctx.affine_normal(c, x, opts=yb.default_opts(dense_fp64=1))
+    d, gn = ctx.affine_normal(c, x, opts=yb.default_opts(dense_fp64=dense_fp64))
     err = _rel(d.cpu().numpy(), ref.d)
     print(f"  direction relative error {err:.2e}", flush=True)
     assert gn == pytest.approx(ref.gnorm, rel=1e-11)
-    assert err <= 1e-8
+    assert err <= (1e-8 if dense_fp64 else D_BOUND[prec])
     ctx.close()
 
 
