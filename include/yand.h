@@ -319,21 +319,36 @@ int yand_profile_enable(yand_ctx* ctx, int enable);
 int yand_profile_read(yand_ctx* ctx, int index, char* name, int name_len,
                       double* total_ms, int64_t* count);
 
+/* A launch-shape record (yand_tuning, yand_autotune) holds
+ * YAND_TUNING_INTS ints, 0 selecting the built-in default in every slot:
+ *   [0..5]   workgroups per streaming pass, for the oracle, value, HVP,
+ *            line-search, dot and third-order passes (rows per workgroup);
+ *   [6]      128-column blocks per group of the two-level Cholesky;
+ *   [7..12]  rows per block of the same six passes (1, 2 or 4; a height
+ *            above the pass's register budget takes that budget's);
+ *   [13]     sub-block width of the Cholesky's in-group updates (32 or 64);
+ *   [14]     band width of its panel step (32 or 64).
+ * Results change only in rounding order: the workgroup count and block
+ * height regroup the FP64 sums of a pass; the widths leave the factor and
+ * its inverse bit for bit the same. */
+#define YAND_TUNING_INTS 15
+/* Doubles of an autotune report: the chosen record, then the best mean
+ * times in ms of the six passes and of the factorisation with inverse. */
+#define YAND_AUTOTUNE_REPORT (YAND_TUNING_INTS + 7)
+
 /* Launch-shape autotuner (an extension for serving).  Times candidate
  * launch shapes on this context's own A at equal weights with c = (1,5,2,10):
- * workgroups per streaming pass (256, 384, 512, 768 or 1024, i.e. rows per
- * workgroup) for each pass kind, and the number of 128-column blocks per
- * group of the two-level Cholesky (2, 4 or 8).  The fastest are kept in the
- * context and used by every later call on it (and by batched solves over
- * it).  Results change only in rounding order.  report (host, nullable, 14
- * doubles): chosen workgroups for the oracle, value, HVP, line-search, dot
- * and third-order passes, the chosen group size, then the best mean times
- * in ms in the same order.  Overwrites the context's scratch state. */
+ * for each pass kind the workgroup count (256, 384, 512, 768 or 1024), then
+ * the block height at that count; the group size of the Cholesky (2, 4 or
+ * 8), then the in-group sub-block and panel band widths at that size.  The
+ * fastest are kept in the context and used by every later call on it (and
+ * by batched solves over it).  report (host, nullable, YAND_AUTOTUNE_REPORT
+ * doubles): see above.  Overwrites the context's scratch state. */
 int yand_autotune(yand_ctx* ctx, double* report);
 
-/* Read (get, host, 7 ints, nullable) and/or set (set, host, 7 ints,
- * nullable) the launch shapes: six workgroup counts in the order above and
- * the group size; 0 selects the built-in default. */
+/* Read (get, host, YAND_TUNING_INTS ints, nullable) and/or set (set, host,
+ * YAND_TUNING_INTS ints, nullable) the launch-shape record.  A value outside
+ * the sets above gives YAND_ERR_ARG and changes nothing. */
 int yand_tuning(yand_ctx* ctx, const int* set, int* get);
 
 /* Stateless wrapper: returns R (device, T x n contiguous) -> w_out (device),

@@ -417,23 +417,38 @@ class Context:
 
     PASS_KINDS = ("oracle", "value", "hvp", "line", "dot", "third")
 
+    TUNING_INTS = 15  # YAND_TUNING_INTS
+
     def autotune(self):
         """Time candidate launch shapes on this context and keep the fastest.
 
         Returns {"pass_groups": {kind: workgroups}, "chol_group": blocks,
-        "ms": {kind or "potrf_trtri": best mean ms}}."""
-        rep = (C.c_double * 14)()
+        "pass_rows": {kind: rows per block}, "chol_step_tm": width,
+        "chol_band": width, "ms": {kind or "potrf_trtri": best mean ms}}
+        (0 = the built-in default)."""
+        nt = self.TUNING_INTS
+        rep = (C.c_double * (nt + 7))()
         _check(self._lib.yand_autotune(self._h, rep), "yand_autotune")
         r = list(rep)
         return {"pass_groups": {k: int(r[i]) for i, k in enumerate(self.PASS_KINDS)},
                 "chol_group": int(r[6]),
-                "ms": {**{k: r[7 + i] for i, k in enumerate(self.PASS_KINDS)},
-                       "potrf_trtri": r[13]}}
+                "pass_rows": {k: int(r[7 + i]) for i, k in enumerate(self.PASS_KINDS)},
+                "chol_step_tm": int(r[13]),
+                "chol_band": int(r[14]),
+                "ms": {**{k: r[nt + i] for i, k in enumerate(self.PASS_KINDS)},
+                       "potrf_trtri": r[nt + 6]}}
 
     def tuning(self, set=None):
-        """Current launch shapes (7 ints; 0 = default); optionally set them."""
-        get = (C.c_int * 7)()
-        sv = (C.c_int * 7)(*[int(v) for v in set]) if set is not None else None
+        """Current launch-shape record (TUNING_INTS ints; 0 = default);
+        optionally set it first."""
+        nt = self.TUNING_INTS
+        get = (C.c_int * nt)()
+        if set is not None:
+            if len(set) != nt:
+                raise ValueError(f"a launch-shape record has {nt} entries")
+            sv = (C.c_int * nt)(*[int(v) for v in set])
+        else:
+            sv = None
         _check(self._lib.yand_tuning(self._h, sv, get), "yand_tuning")
         return list(get)
 

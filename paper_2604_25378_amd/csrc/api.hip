@@ -56,7 +56,10 @@ struct Data {
   double mbar = 0.0, mnorm = 0.0;  // mean of mu and |mu - mbar|
   // launch shapes chosen by yand_autotune (0: built-in defaults)
   int pass_groups[6] = {0, 0, 0, 0, 0, 0};  // per PassKind
+  int pass_rows[6] = {0, 0, 0, 0, 0, 0};    // rows per block, per PassKind
   int chol_group = 0;
+  int chol_step_tm = 0;  // sub-block width of the in-group updates
+  int chol_band = 0;     // band width of the panel step
   // XCD-aware tile order of the SYRK (device; null: plain order)
   int* syrk_order = nullptr;
   int64_t syrk_slots = 0;
@@ -420,6 +423,7 @@ int run_pass(const Data& D, Work& w, PassKind kind, const PassArgs& a,
              int* nwg, const char* name) {
   PassArgs b = a;
   b.groups = D.pass_groups[(int)kind];
+  b.rows = D.pass_rows[(int)kind];
   HIPTRY(timed(w, name, [&] {
     return launch_pass(D.precision, kind, b, w.st, nwg);
   }));
@@ -612,7 +616,8 @@ int dir_factor(const Data& D, Work& w, int p0, const int* skip,
                         mask));
   HIPTRY(timed(w, "potrf_trtri", [&] {
     return launch_potrf_trtri(w.M, w.X, np, &w.sc->fail, w.st, skip,
-                              D.chol_group, Lanes{}, 1, w.solo);
+                              D.chol_group, Lanes{}, 1, w.solo,
+                              D.chol_step_tm, D.chol_band);
   }));
   return YAND_OK;
 }
@@ -1243,7 +1248,7 @@ int enqueue_group(const std::vector<LaneRef>& lanes, const DirOpts& o,
                           w.st, face_mask(w, o)));
   }
   HIPTRY(launch_potrf_trtri(G.M, G.X, np, G.fail, st, G.skip, D.chol_group,
-                            G.ls, G.nl, true));
+                            G.ls, G.nl, true, D.chol_step_tm, D.chol_band));
   HIPTRY(launch_trace_gemm(D.precision, D.A, D.lda, Tp, G.X, np, G.rn, st,
                            G.skip, G.ls, G.nl));
   for (const auto& L : lanes) {
@@ -2856,8 +2861,11 @@ int yand_autotune(yand_ctx* ctx, double* report) {
     return YAND_OK;
   };
   // workgroups per pass: a band of rows per workgroup; more groups hide
-  // more latency, fewer write fewer partial rows
+  // more latency, fewer write fewer partial rows.  Then the rows per block
+  // at that count: taller blocks share one reduction, shorter ones hold
+  // fewer registers.
   static const int kCands[] = {256, 384, 512, 768, 1024};
+  static const int kRows[] = {1, 2, 4};
   static const PassKind kKinds[6] = {PassKind::Oracle, PassKind::Value,
                                      PassKind::Hvp,    PassKind::Line,
                                      PassKind::Dot,    PassKind::Third};
@@ -2874,6 +2882,7 @@ int yand_autotune(yand_ctx* ctx, double* report) {
       case PassKind::Third: a.zc = w.z; a.q = w.q; break;
     }
     best_ms[k] = 1e30;
+    D.pass_rows[k] = 0;
     for (int g : kCands) {
       a.groups = g;
       int nwg = 0;
@@ -2885,36 +2894,69 @@ int yand_autotune(yand_ctx* ctx, double* report) {
         D.pass_groups[k] = g;
       }
     }
+    a.groups = D.pass_groups[k];
+    for (int r : kRows) {
+      a.rows = r;
+      int nwg = 0;
+      double ms = 0.0;
+      TRY(time_ms([&] { return launch_pass(D.precision, kKinds[k], a, st, &nwg); },
+                  5, &ms));
+      if (ms < best_ms[k]) {
+        best_ms[k] = ms;
+        D.pass_rows[k] = r;
+      }
+    }
   }
   // blocks per group of the two-level Cholesky: deeper group updates touch
-  // the trailing matrix less often, shallower groups shorten the steps
+  // the trailing matrix less often, shallower groups shorten the steps; then
+  // the widths of the in-group update sub-blocks and the panel bands at that
+  // group size (narrower pieces spread a short step over more CUs)
   DirOpts o;
   TRY(dir_front(D, w, c, p0, o, nullptr));
   const int64_t n = D.n, np = D.lda;
-  best_ms[6] = 1e30;
-  for (int grp : {2, 4, 8}) {
+  auto time_factor = [&](int grp, int tm, int band, double* ms) -> int {
     double total = 0.0;
     for (int rep = 0; rep < 2; ++rep) {
       HIPTRY(launch_project(w.B, w.M, np, n, np, w.E, w.W, p0 + 1, w.sc, st));
       HIPTRY(hipEventRecord(e0, st));
       HIPTRY(launch_potrf_trtri(w.M, w.X, np, &w.sc->fail, st, nullptr, grp,
-                                Lanes{}, 1, true));
+                                Lanes{}, 1, true, tm, band));
       HIPTRY(hipEventRecord(e1, st));
       HIPTRY(hipEventSynchronize(e1));
       float t = 0.f;
       HIPTRY(hipEventElapsedTime(&t, e0, e1));
       if (rep > 0) total += t;
     }
-    if (total < best_ms[6]) {
-      best_ms[6] = total;
+    *ms = total;
+    return YAND_OK;
+  };
+  best_ms[6] = 1e30;
+  D.chol_step_tm = 0;
+  D.chol_band = 0;
+  for (int grp : {2, 4, 8}) {
+    double ms = 0.0;
+    TRY(time_factor(grp, 0, 0, &ms));
+    if (ms < best_ms[6]) {
+      best_ms[6] = ms;
       D.chol_group = grp;
     }
   }
+  for (int tm : {32, 64})
+    for (int band : {32, 64}) {
+      double ms = 0.0;
+      TRY(time_factor(D.chol_group, tm, band, &ms));
+      if (ms < best_ms[6]) {
+        best_ms[6] = ms;
+        D.chol_step_tm = tm;
+        D.chol_band = band;
+      }
+    }
   HIPTRY(hipStreamSynchronize(st));
   if (report) {
-    for (int k = 0; k < 6; ++k) report[k] = D.pass_groups[k];
-    report[6] = D.chol_group;
-    for (int k = 0; k < 7; ++k) report[7 + k] = best_ms[k];
+    int rec[YAND_TUNING_INTS];
+    TRY(yand_tuning(ctx, nullptr, rec));
+    for (int k = 0; k < YAND_TUNING_INTS; ++k) report[k] = rec[k];
+    for (int k = 0; k < 7; ++k) report[YAND_TUNING_INTS + k] = best_ms[k];
   }
   return YAND_OK;
 }
@@ -2923,15 +2965,30 @@ int yand_tuning(yand_ctx* ctx, const int* set, int* get) {
   if (!ctx) return YAND_ERR_ARG;
   Data& D = ctx->d;
   if (set) {
-    for (int k = 0; k < 6; ++k)
+    for (int k = 0; k < 6; ++k) {
       if (set[k] < 0 || set[k] > kMaxPassGroups) return YAND_ERR_ARG;
+      const int r = set[7 + k];
+      if (r != 0 && r != 1 && r != 2 && r != 4) return YAND_ERR_ARG;
+    }
     if (set[6] < 0 || set[6] > 64) return YAND_ERR_ARG;
-    for (int k = 0; k < 6; ++k) D.pass_groups[k] = set[k];
+    for (int k = 13; k < 15; ++k)
+      if (set[k] != 0 && set[k] != 32 && set[k] != 64) return YAND_ERR_ARG;
+    for (int k = 0; k < 6; ++k) {
+      D.pass_groups[k] = set[k];
+      D.pass_rows[k] = set[7 + k];
+    }
     D.chol_group = set[6];
+    D.chol_step_tm = set[13];
+    D.chol_band = set[14];
   }
   if (get) {
-    for (int k = 0; k < 6; ++k) get[k] = D.pass_groups[k];
+    for (int k = 0; k < 6; ++k) {
+      get[k] = D.pass_groups[k];
+      get[7 + k] = D.pass_rows[k];
+    }
     get[6] = D.chol_group;
+    get[13] = D.chol_step_tm;
+    get[14] = D.chol_band;
   }
   return YAND_OK;
 }

@@ -1524,7 +1524,8 @@ constexpr int kDefaultGroup = 4;
 // so narrower pieces on more workgroups shorten each launch.  The group
 // updates run in 64 x 64 sub-blocks: their tile counts (126 to 936 tiles of
 // 128 x 128 at n = 5440) leave whole rounds of 512 slots part-empty, which
-// four times as many pieces even out.
+// four times as many pieces even out.  The defaults below; a caller may ask
+// for 64 for either of the first two (the launcher's step_tm, fin_band).
 constexpr int kFinBand = 32;
 constexpr int kStepTM = 32;
 constexpr int kGroupTM = 64;
@@ -1541,7 +1542,8 @@ static int device_cus() {
 
 hipError_t launch_potrf_trtri(double* M, double* X, int64_t np, int* fail,
                               hipStream_t st, const int* skip, int group,
-                              Lanes ls, int nlanes, bool fill) {
+                              Lanes ls, int nlanes, bool fill, int step_tm,
+                              int fin_band) {
   const unsigned L = (unsigned)nlanes;
   const int kGroup = group > 0 ? group : kDefaultGroup;
   const int nt = (int)(np / BM);
@@ -1571,7 +1573,10 @@ hipError_t launch_potrf_trtri(double* M, double* X, int64_t np, int* fail,
     int nu;
     const int n = tiles(kB, jlo, jhi, ilo, ihi, &nu);
     if (n == 0) return;
-    if (small)
+    if (small && step_tm == 64)
+      hipLaunchKernelGGL(update_kernel<64>, dim3(n * QG, L), dim3(NT), 0, st,
+                         M, X, np, nt, kA, kB, jlo, jhi, ilo, nu, 0, skip, ls);
+    else if (small)
       hipLaunchKernelGGL(update_kernel<kStepTM>, dim3(n * QS, L), dim3(NT), 0,
                          st, M, X, np, nt, kA, kB, jlo, jhi, ilo, nu, 0, skip,
                          ls);
@@ -1600,7 +1605,11 @@ hipError_t launch_potrf_trtri(double* M, double* X, int64_t np, int* fail,
       hipLaunchKernelGGL(diag_block_kernel, dim3(1 + extra, L), dim3(DT), lds,
                          st, M, X, np, k, fail, skip, ls, f);
       const int rem = nt - k - 1;
-      if (rem + k > 0)
+      if (rem + k > 0 && fin_band == 64)
+        hipLaunchKernelGGL(panel_finalize_kernel<64>,
+                           dim3((rem + k) * (BM / 64), L), dim3(NT), 0, st, M,
+                           X, np, k, rem, skip, ls);
+      else if (rem + k > 0)
         hipLaunchKernelGGL(panel_finalize_kernel<kFinBand>,
                            dim3((rem + k) * (BM / kFinBand), L), dim3(NT), 0,
                            st, M, X, np, k, rem, skip, ls);

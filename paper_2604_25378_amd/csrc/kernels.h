@@ -64,6 +64,8 @@ struct PassArgs {
   double invT;
   const int* skip;      // nonzero: every workgroup returns at once
   int groups;           // workgroups to launch (0: the shape's default)
+  int rows;             // rows per block: 1, 2 or 4, capped at the shape's
+                        // register budget (0: the shape's default)
 };
 
 int pass_groups(int64_t Tp, int R, int groups, int64_t* rows_per_wg);
@@ -151,11 +153,15 @@ int syrk_split_slots();
 // when a pivot was not positive.  fill: the diagonal-block launches also
 // carry most of the previous group update on the CUs they leave idle, shared
 // equally among the lanes (the same results; meant for a stream that has the
-// device to itself, since those launches then take every CU).
+// device to itself, since those launches then take every CU).  step_tm: sub-
+// block width of the in-group updates, fin_band: band width of the panel
+// step (32 or 64 each, 0: 32); every choice gives bit-identical L and X,
+// since each entry is the same product over the same reduction order.
 hipError_t launch_potrf_trtri(double* M, double* X, int64_t np, int* fail,
                               hipStream_t st, const int* skip = nullptr,
                               int group = 0, Lanes ls = Lanes{},
-                              int nlanes = 1, bool fill = false);
+                              int nlanes = 1, bool fill = false,
+                              int step_tm = 0, int fin_band = 0);
 // Sets the LDS attribute of the diagonal-block kernel (call before capture).
 hipError_t prepare_dense_kernels();
 // rn[J][t] = sum_{j in tile J} (sum_k A[t][k] X[j][k])^2  (X lower)

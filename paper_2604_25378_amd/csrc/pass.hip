@@ -402,15 +402,30 @@ constexpr int rows_for(int nch) {
   return r;
 }
 
+// One instance per block height up to the shape's budget; a requested
+// height above it (or 0) takes the budget's.
+template <typename S, int K, class Op>
+static void launch_rows(int rows, PassArgs a, dim3 g, dim3 b, hipStream_t st) {
+  constexpr int TPB = PassShape<S>::TPB, RMAX = rows_for<S>(K);
+  if (RMAX >= 4 && (rows == 0 || rows >= 4)) {
+    hipLaunchKernelGGL((pass_kernel<S, TPB, K, (RMAX >= 4 ? 4 : 1), Op>), g,
+                       b, 0, st, a);
+  } else if (RMAX >= 2 && (rows == 0 || rows >= 2)) {
+    hipLaunchKernelGGL((pass_kernel<S, TPB, K, (RMAX >= 2 ? 2 : 1), Op>), g,
+                       b, 0, st, a);
+  } else {
+    hipLaunchKernelGGL((pass_kernel<S, TPB, K, 1, Op>), g, b, 0, st, a);
+  }
+}
+
 template <typename S, class Op>
 static hipError_t launch_nch(int nch, PassArgs a, int nwg, hipStream_t st) {
   constexpr int TPB = PassShape<S>::TPB;
   dim3 g(nwg), b(TPB);
   switch (nch) {
-#define YAND_NCH_CASE(K)                                                  \
-  case K:                                                               \
-    hipLaunchKernelGGL((pass_kernel<S, TPB, K, rows_for<S>(K), Op>), g, b, \
-                       0, st, a);                                       \
+#define YAND_NCH_CASE(K)                           \
+  case K:                                          \
+    launch_rows<S, K, Op>(a.rows, a, g, b, st);    \
     break;
     YAND_NCH_CASE(1)
     YAND_NCH_CASE(2)

@@ -1,7 +1,8 @@
 """The launch-shape autotuner: chosen shapes come from the candidate sets,
 results under any shape agree with the default shapes to rounding order
-(1e-13 relative; only the grouping of the FP64 sums changes), and solves
-after tuning still reach the oracle's unique minimiser."""
+(1e-13 relative; workgroup counts and block heights only regroup the FP64
+sums), the Cholesky's sub-block and band widths change no bit of a solve,
+and solves after tuning still reach the oracle's unique minimiser."""
 
 import numpy as np
 import pytest
@@ -21,7 +22,7 @@ def test_autotune_shapes_and_results():
     c = np.array([1.0, 5.0, 2.0, 10.0])
     mu, A = O.center(R)
     ctx = yb.Context(torch.from_numpy(R).cuda())
-    assert ctx.tuning() == [0] * 7
+    assert ctx.tuning() == [0] * 15
     x = np.full(300, 1.0 / 300) + 1e-3 * np.random.default_rng(1).normal(size=300)
     x -= (x.sum() - 1.0) / 300
     v = np.random.default_rng(2).normal(size=300)
@@ -30,9 +31,16 @@ def test_autotune_shapes_and_results():
     rep = ctx.autotune()
     assert set(rep["pass_groups"].values()) <= {256, 384, 512, 768, 1024}
     assert rep["chol_group"] in (2, 4, 8)
+    assert set(rep["pass_rows"].values()) <= {0, 1, 2, 4}
+    assert rep["chol_step_tm"] in (0, 32, 64) and rep["chol_band"] in (0, 32, 64)
     assert all(t > 0 for t in rep["ms"].values())
-    assert ctx.tuning() == [*rep["pass_groups"].values(), rep["chol_group"]]
-    for shape in ([1024] * 6 + [2], [256] * 6 + [8], None):
+    assert ctx.tuning() == [*rep["pass_groups"].values(), rep["chol_group"],
+                            *rep["pass_rows"].values(), rep["chol_step_tm"],
+                            rep["chol_band"]]
+    print(f"tuned {ctx.tuning()}", flush=True)
+    for shape in ([1024] * 6 + [2] + [1] * 6 + [64, 64],
+                  [256] * 6 + [8] + [4] * 6 + [32, 64],
+                  [384] * 6 + [4] + [2] * 6 + [64, 32], None):
         if shape is not None:
             ctx.tuning(shape)
         f, g, _ = ctx.eval(c, x)
@@ -48,6 +56,34 @@ def test_autotune_shapes_and_results():
         assert np.linalg.norm(U.T @ O.gradient(A, mu, c, w.cpu().numpy())) <= 2e-8
         Hr = U.T @ (A.T @ (O.d2psi(c, A @ xr)[:, None] * A) / A.shape[0]) @ U
         assert np.abs(w.cpu().numpy() - xr).max() <= 10 * 1e-8 / np.linalg.eigvalsh(Hr)[0]
-    with pytest.raises(yb.YandError):
-        ctx.tuning([-1, 0, 0, 0, 0, 0, 0])
+    for bad in ([-1] + [0] * 14, [0] * 7 + [3] + [0] * 7, [0] * 13 + [48, 0],
+                [0] * 14 + [128]):
+        with pytest.raises(yb.YandError):
+            ctx.tuning(bad)
+    with pytest.raises(ValueError):
+        ctx.tuning([0] * 7)
+    ctx.close()
+
+
+@pytest.mark.parametrize("grp", [2, 4])
+def test_cholesky_widths_change_no_bit(grp):
+    """Every entry of the factor and its inverse is the same product over the
+    same reduction whatever the sub-block and band widths, so three
+    iterations of a solve (n = 1000: eight tile columns, in-group updates
+    and group updates) end on the same weights bit for bit."""
+    print(f"[case] cholesky widths n=1000 T=3000 group {grp}", flush=True)
+    R = synth.factor_returns(1000, 3000, 5, 3, 5.0, 0.0, 11)
+    c = [1.0, 5.0, 2.0, 10.0]
+    ctx = yb.Context(torch.from_numpy(R).cuda())
+    opts = yb.default_opts(max_iter=3, eps=0.0)
+    ref = None
+    for tm, band in ((0, 0), (64, 32), (32, 64), (64, 64)):
+        ctx.tuning([0] * 6 + [grp] + [0] * 6 + [tm, band])
+        w, info = ctx.solve(c, opts=opts)
+        assert info.iterations == 3
+        w = w.cpu().numpy()
+        if ref is None:
+            ref = w
+        else:
+            assert np.array_equal(w, ref), (tm, band)
     ctx.close()
