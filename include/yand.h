@@ -339,10 +339,10 @@ int yand_profile_read(yand_ctx* ctx, int index, char* name, int name_len,
 /* Launch-shape autotuner (an extension for serving).  Times candidate
  * launch shapes on this context's own A at equal weights with c = (1,5,2,10):
  * for each pass kind the workgroup count (256, 384, 512, 768 or 1024), then
- * the block height at that count; the group size of the Cholesky (2, 4 or
- * 8), then the in-group sub-block and panel band widths at that size.  The
- * fastest are kept in the context and used by every later call on it (and
- * by batched solves over it).  report (host, nullable, YAND_AUTOTUNE_REPORT
+ * the block height at that count; the group size of the Cholesky (2, 3, 4,
+ * 5, 6 or 8), then the in-group sub-block and panel band widths at that
+ * size.  The fastest are kept in the context and used by every later call
+ * on it (and by batched solves over it).  report (host, nullable, YAND_AUTOTUNE_REPORT
  * doubles): see above.  Overwrites the context's scratch state. */
 int yand_autotune(yand_ctx* ctx, double* report);
 

@@ -2895,7 +2895,9 @@ int yand_autotune(yand_ctx* ctx, double* report) {
       }
     }
     a.groups = D.pass_groups[k];
+    const int cap = pass_rows_cap(D.precision, D.lda);
     for (int r : kRows) {
+      if (r > cap) break;
       a.rows = r;
       int nwg = 0;
       double ms = 0.0;
@@ -2933,7 +2935,7 @@ int yand_autotune(yand_ctx* ctx, double* report) {
   best_ms[6] = 1e30;
   D.chol_step_tm = 0;
   D.chol_band = 0;
-  for (int grp : {2, 4, 8}) {
+  for (int grp : {2, 3, 4, 5, 6, 8}) {
     double ms = 0.0;
     TRY(time_factor(grp, 0, 0, &ms));
     if (ms < best_ms[6]) {

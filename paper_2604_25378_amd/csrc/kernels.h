@@ -70,6 +70,9 @@ struct PassArgs {
 
 int pass_groups(int64_t Tp, int R, int groups, int64_t* rows_per_wg);
 int64_t max_pass_columns(int precision);
+// Largest block height a pass over rows of lda entries runs at (its
+// register budget); a larger request runs at this one.
+int pass_rows_cap(int precision, int64_t lda);
 hipError_t launch_pass(int precision, PassKind kind, const PassArgs& a,
                        hipStream_t st, int* nwg);
 hipError_t launch_reduce_partials(const double* part, int nwg, int64_t lda,
