@@ -16,8 +16,14 @@ of each function:
 
 * centering, objective, moments, gradient, HVP, third-order action,
   line-search coefficients, step selection, feasibility cap, reduced basis,
-  affine-normal direction, solve loop, simplex projection, projected-KKT
-  residual, boundary block: pinned (tests/test_oracle_*.py).
+  affine-normal direction, solve loop: pinned (tests/test_oracle_pins.py).
+* simplex projection, projected-KKT residual, boundary block with its face
+  solver, Armijo rule: pinned (tests/test_oracle_simplex.py).
+* stall test and the stall-recovery restarts: pinned
+  (tests/test_oracle_stall.py).
+* probe estimate of the trace (counter-based signs, block PCG): pinned
+  (tests/test_oracle_probe.py).
+* return-floor protocol: pinned (tests/test_oracle_floor.py).
 * PCG inner iterates: parity unpinned per iteration (the paper does not name
   its preconditioner); pinned only at solve level through uniqueness of the
   minimiser under the convexity certificate.

@@ -87,3 +87,35 @@ def test_cholesky_widths_change_no_bit(grp):
         else:
             assert np.array_equal(w, ref), (tm, band)
     ctx.close()
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32", "bf16"])
+def test_block_heights_regroup_sums_only(precision):
+    """Every block height of every pass (1, 2 and 4 rows, each capped by
+    the storage type's register budget) gives the default shape's value,
+    gradient and Hessian-vector product to rounding order (1e-13)."""
+    print(f"[case] block heights n=300 T=2000 {precision}", flush=True)
+    R = synth.factor_returns(300, 2000, 5, 0, 5.0, 0.0, 7)
+    c = np.array([1.0, 5.0, 2.0, 10.0])
+    ctx = yb.Context(torch.from_numpy(R).cuda(), precision)
+    x = np.full(300, 1.0 / 300) + 1e-3 * np.random.default_rng(3).normal(size=300)
+    x -= (x.sum() - 1.0) / 300
+    v = np.random.default_rng(4).normal(size=300)
+    f0, g0, _ = ctx.eval(c, x)
+    g0 = g0.cpu().numpy()
+    h0 = ctx.hvp(c, x, v).cpu().numpy()
+    # two iterations run the value, line-search and third-order passes too
+    opts = yb.default_opts(max_iter=2, eps=0.0)
+    w0, _ = ctx.solve(c, opts=opts)
+    w0 = w0.cpu().numpy()
+    for rows in (1, 2, 4):
+        ctx.tuning([0] * 7 + [rows] * 6 + [0, 0])
+        f, g, _ = ctx.eval(c, x)
+        h = ctx.hvp(c, x, v).cpu().numpy()
+        assert f == pytest.approx(f0, rel=1e-13)
+        assert np.abs(g.cpu().numpy() - g0).max() <= 1e-13 * np.abs(g0).max()
+        assert np.abs(h - h0).max() <= 1e-13 * np.abs(h0).max()
+        w, info = ctx.solve(c, opts=opts)
+        assert info.iterations == 2
+        assert np.abs(w.cpu().numpy() - w0).max() <= 1e-10
+    ctx.close()
