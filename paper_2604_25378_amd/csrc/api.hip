@@ -194,8 +194,11 @@ template <class F>
 hipError_t timed(Work& w, const char* name, F fn) {
   if (!w.prof || !w.prof->on) return fn();
   TimedLaunch t{name, nullptr, nullptr};
-  if (hipEventCreate(&t.a) != hipSuccess || hipEventCreate(&t.b) != hipSuccess)
+  if (hipEventCreate(&t.a) != hipSuccess) return hipErrorOutOfMemory;
+  if (hipEventCreate(&t.b) != hipSuccess) {
+    (void)hipEventDestroy(t.a);
     return hipErrorOutOfMemory;
+  }
   hipEventRecord(t.a, w.st);
   hipError_t e = fn();
   hipEventRecord(t.b, w.st);
@@ -2838,16 +2841,16 @@ int yand_autotune(yand_ctx* ctx, double* report) {
   TRY(setup_lane(D, w, nullptr, nullptr, &p0));
   TRY(oracle_at(D, w, c, w.x, true));
   HIPTRY(launch_grad_project(w.g, w.E, p0, D.n, w.sc, st, -1.0));
-  hipEvent_t e0 = nullptr, e1 = nullptr;
-  HIPTRY(hipEventCreate(&e0));
-  HIPTRY(hipEventCreate(&e1));
   struct Ev {
-    hipEvent_t a, b;
+    hipEvent_t a = nullptr, b = nullptr;
     ~Ev() {
-      (void)hipEventDestroy(a);
-      (void)hipEventDestroy(b);
+      if (a) (void)hipEventDestroy(a);
+      if (b) (void)hipEventDestroy(b);
     }
-  } guard{e0, e1};
+  } guard;
+  HIPTRY(hipEventCreate(&guard.a));
+  HIPTRY(hipEventCreate(&guard.b));
+  const hipEvent_t e0 = guard.a, e1 = guard.b;
   // mean milliseconds of reps calls of fn on st, after one warm-up call
   auto time_ms = [&](auto&& fn, int reps, double* ms) -> int {
     HIPTRY(fn());
