@@ -215,7 +215,7 @@ def probe_bench(workload="n5440_T12000", probes=64, seed=0):
                       "outcome": OUTCOME.get(info.status, str(info.status)),
                       "gnorm": info.gnorm, "f": f}
     ctx.close()
-    return {"workload": f"{workload}: n={n} T={T}, c={tuple(c)}, budget set, "
+    return {"workload": f"{workload}: n={n} T={T}, c={tuple(float(v) for v in c)}, budget set, "
                         f"PCG configuration, {probes} probes",
             **rows,
             "objective_rel_gap": abs(res["probe"] - res["exact"]) / abs(res["exact"]),
@@ -279,7 +279,7 @@ def precision_bench(reps=3):
         ctx64.close()
         del Rd
         out[f"{wl}_{solver}"] = {
-            "workload": f"{wl}: n={n} T={T}, c={tuple(c)}, budget set, "
+            "workload": f"{wl}: n={n} T={T}, c={tuple(float(v) for v in c)}, budget set, "
                         f"{'PCG with stall recovery' if solver == 'pcg' else 'direct'}",
             **rows}
     return out
@@ -914,7 +914,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": f"{args.workload}: n={n} T={T} factor model "
                                f"K={wl['K']} S={wl['S']} nu={wl['nu']} "
-                               f"jumps={wl['p_jump']}, c={tuple(wl['c'])}, "
+                               f"jumps={wl['p_jump']}, c={tuple(float(v) for v in wl['c'])}, "
                                "budget set, direct exact-trace solve",
                    "precision": args.precision},
         "roofline": roof,
