@@ -405,23 +405,37 @@ syrk_split_kernel(const S* __restrict__ A, int64_t lda, int64_t Tp,
       __syncthreads();
       if (!last) continue;
       __threadfence();
-      // the tile's entries one at a time, each summed over the pieces
+      // the tile's entries, each summed over the pieces in piece order;
+      // EB entries at a time so that their loads are in flight together
+      // (a wait for loads also waits for the stores issued before them)
       const int lane = tid & 63, w = tid >> 6;
       const int wm = (w >> 1) * (BM / 2), wn = (w & 1) * (BM / 2);
       double* Bij = B + (int64_t)I * BM * lda + (int64_t)J * BM;
       double* Bji = B + (int64_t)J * BM * lda + (int64_t)I * BM;
+      const double* w0 = ws + (int64_t)tt[3] * kTileD + tid;
+      constexpr int EB = 16;
 #pragma unroll 1
-      for (int e = 0; e < 64; ++e) {
-        double v = 0.0;
-        for (int p = 0; p < np; ++p) {
-          const double x =
-              ws[(int64_t)(tt[3] + p) * kTileD + (int64_t)e * NT + tid];
-          v = p == 0 ? x : v + x;
+      for (int e0 = 0; e0 < 64; e0 += EB) {
+        double v[EB];
+#pragma unroll
+        for (int u = 0; u < EB; ++u) v[u] = w0[(int64_t)(e0 + u) * NT];
+#pragma unroll 1
+        for (int p = 1; p < np; ++p) {
+          const double* wp = w0 + (int64_t)p * kTileD;
+          double x[EB];
+#pragma unroll
+          for (int u = 0; u < EB; ++u) x[u] = wp[(int64_t)(e0 + u) * NT];
+#pragma unroll
+          for (int u = 0; u < EB; ++u) v[u] += x[u];
         }
-        const int rr = wm + (e >> 4) * 16 + (lane >> 4) + 4 * (e & 3);
-        const int cc = wn + ((e >> 2) & 3) * 16 + (lane & 15);
-        Bij[(int64_t)rr * lda + cc] = v;
-        if (I != J) Bji[(int64_t)cc * lda + rr] = v;
+#pragma unroll
+        for (int u = 0; u < EB; ++u) {
+          const int e = e0 + u;
+          const int rr = wm + (e >> 4) * 16 + (lane >> 4) + 4 * (e & 3);
+          const int cc = wn + ((e >> 2) & 3) * 16 + (lane & 15);
+          Bij[(int64_t)rr * lda + cc] = v[u];
+          if (I != J) Bji[(int64_t)cc * lda + rr] = v[u];
+        }
       }
       if (tid == 0) cnt[t] = 0;
       continue;
@@ -1323,6 +1337,12 @@ std::vector<int> syrk_tile_order(int nt) {
   return out;
 }
 
+// Cost of one piece of the balanced SYRK beyond its slices (pipeline fill,
+// drain, publish and arrival), in slices: at n = 5440, T = 12000 (752
+// slices) bodies longer by 0, 8, 16 and 24 slices gave 5.71, 5.65, 5.68 and
+// 5.72 ms per launch, and 8 is this cost times m / U there.
+constexpr int64_t kPieceSlices = 10;
+
 bool syrk_split_plan(int nt, int64_t ns, int slots, SyrkPlan* out) {
   constexpr int NX = 8;
   *out = SyrkPlan{};
@@ -1346,11 +1366,15 @@ bool syrk_split_plan(int nt, int64_t ns, int slots, SyrkPlan* out) {
   for (int x = 0; x < NX; ++x) {
     const int64_t m = len[x] - (int64_t)R * U;  // tiles cut along K
     if (m <= 0) continue;
-    // m <= U; every workgroup of the XCD gets an equal share Lb.  The
-    // first m take the bodies [0, Lb) of the m tiles, so that they sweep
-    // the same slices of A together; the other U - m share the remainders
-    // [Lb, ns), concatenated tile by tile.
-    const int64_t Lb = m * ns / U;
+    // m <= U; every workgroup of the XCD gets an equal share.  The first m
+    // take the bodies [0, Lb) of the m tiles, so that they sweep the same
+    // slices of A together; the other U - m share the remainders [Lb, ns),
+    // concatenated tile by tile.  A remainder workgroup runs about m /
+    // (U - m) + 1 pieces, each with its own pipeline fill, drain and
+    // publish, where a body runs one; equal times then need the bodies
+    // longer by the piece cost times m / U.
+    const int64_t Lb =
+        std::min<int64_t>(ns, m * ns / U + kPieceSlices * m / U);
     if (m > U || Lb < 16) return false;
     const int t0 = (int)npieces.size();
     for (int64_t p = 0; p < m; ++p) {
