@@ -1598,8 +1598,9 @@ hipError_t launch_potrf_trtri(double* M, double* X, int64_t np, int* fail,
     const int n = tiles(kB, jlo, jhi, ilo, ihi, &nu);
     if (n == 0) return;
     if (small && step_tm == 64)
-      hipLaunchKernelGGL(update_kernel<64>, dim3(n * QG, L), dim3(NT), 0, st,
-                         M, X, np, nt, kA, kB, jlo, jhi, ilo, nu, 0, skip, ls);
+      hipLaunchKernelGGL(update_kernel<64>, dim3(n * (BM / 64) * (BM / 64), L),
+                         dim3(NT), 0, st, M, X, np, nt, kA, kB, jlo, jhi, ilo,
+                         nu, 0, skip, ls);
     else if (small)
       hipLaunchKernelGGL(update_kernel<kStepTM>, dim3(n * QS, L), dim3(NT), 0,
                          st, M, X, np, nt, kA, kB, jlo, jhi, ilo, nu, 0, skip,

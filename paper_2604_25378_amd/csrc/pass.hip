@@ -482,21 +482,7 @@ static int rows_cap_t(int64_t lda) {
   constexpr int TPB = PassShape<S>::TPB;
   constexpr int VEC = Vec16<S>::N;
   const int nch = (int)((lda / VEC + TPB - 1) / TPB);
-  switch (nch < 1 ? 1 : nch) {
-#define YAND_NCH_CASE(K) \
-  case K:                \
-    return rows_for<S>(K);
-    YAND_NCH_CASE(1)
-    YAND_NCH_CASE(2)
-    YAND_NCH_CASE(3)
-    YAND_NCH_CASE(4)
-    YAND_NCH_CASE(5)
-    YAND_NCH_CASE(6)
-    YAND_NCH_CASE(7)
-    YAND_NCH_CASE(8)
-#undef YAND_NCH_CASE
-  }
-  return 1;
+  return rows_for<S>(nch < 1 ? 1 : nch);
 }
 
 int pass_rows_cap(int precision, int64_t lda) {
