@@ -1135,6 +1135,7 @@ __device__ __forceinline__ void update_block(double* M, double* X, int64_t ld,
   int b, so, sc;
   sub_block<TM>(q, &b, &so, &sc);
   f64x4 acc[TM / 32][TM / 32];
+  constexpr int kEntries = (TM / 32) * (TM / 32) * 4;  // per thread
   const int lane = t & 63, w = t >> 6;
   const int wm = (w >> 1) * (TM / 2), wn = (w & 1) * (TM / 2);
   auto each = [&](auto f) {
@@ -1159,9 +1160,18 @@ __device__ __forceinline__ void update_block(double* M, double* X, int64_t ld,
     gemm_core<double, true, double, true, TM>(Li, ld, Lj, ld, nullptr,
                                               (int64_t)kA * BM,
                                               (int64_t)kB * BM, acc, sA, sB, t);
+    // read-modify-write with every read issued first: a wait for a load
+    // also waits for the stores before it, so alternating them would make
+    // one memory round trip per entry
     double* Mij = M + (int64_t)I * BM * ld + (int64_t)J * BM;
+    double old[kEntries];
+    int e = 0;
+    each([&](int r, int c, double) {
+      old[e++] = Mij[(int64_t)(so + r) * ld + sc + c];
+    });
+    e = 0;
     each([&](int r, int c, double v) {
-      Mij[(int64_t)(so + r) * ld + sc + c] -= v;
+      Mij[(int64_t)(so + r) * ld + sc + c] = old[e++] - v;
     });
   } else {
     b -= nu;
@@ -1174,11 +1184,21 @@ __device__ __forceinline__ void update_block(double* M, double* X, int64_t ld,
     // the update whose reduction starts at k = j brings the first
     // contribution (X[k, j] = 0 for k < j): it stores, later ones add
     double* Sij = X + (int64_t)i * BM * ld + (int64_t)j * BM;
-    const bool first = j >= kA;
-    each([&](int r, int c, double v) {
-      double* p = Sij + (int64_t)(so + r) * ld + sc + c;
-      *p = first ? v : *p + v;
-    });
+    if (j >= kA) {
+      each([&](int r, int c, double v) {
+        Sij[(int64_t)(so + r) * ld + sc + c] = v;
+      });
+    } else {
+      double old[kEntries];
+      int e = 0;
+      each([&](int r, int c, double) {
+        old[e++] = Sij[(int64_t)(so + r) * ld + sc + c];
+      });
+      e = 0;
+      each([&](int r, int c, double v) {
+        Sij[(int64_t)(so + r) * ld + sc + c] = old[e++] + v;
+      });
+    }
   }
 }
 
