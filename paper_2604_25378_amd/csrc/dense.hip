@@ -572,10 +572,32 @@ gemm64_kernel(const double* __restrict__ A, int64_t lda,
   f64x4 acc[BM / 32][BM / 32];
   gemm_core<double, AKC, double, BKC, BM, BM>(Ab, lda, Bb, ldb, nullptr, 0, K,
                                               acc, sA, sB);
-  for_each_acc<BM, BM>(acc, [&](int r, int c, double v) {
-    double* p = C + (m0 + r) * ldc + n0 + c;
-    *p = beta != 0.0 ? alpha * v + beta * *p : alpha * v;
-  });
+  if (beta == 0.0) {
+    for_each_acc<BM, BM>(acc, [&](int r, int c, double v) {
+      C[(m0 + r) * ldc + n0 + c] = alpha * v;
+    });
+    return;
+  }
+  // with beta: each 16-row block's reads before its writes (a wait for a
+  // load also waits for the stores before it)
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int wm = (w >> 1) * (BM / 2), wn = (w & 1) * (BM / 2);
+#pragma unroll
+  for (int i = 0; i < BM / 32; ++i) {
+    double old[BM / 32][4];
+#pragma unroll
+    for (int j = 0; j < BM / 32; ++j)
+#pragma unroll
+      for (int r = 0; r < 4; ++r)
+        old[j][r] = C[(m0 + wm + i * 16 + (lane >> 4) + 4 * r) * ldc + n0 +
+                      wn + j * 16 + (lane & 15)];
+#pragma unroll
+    for (int j = 0; j < BM / 32; ++j)
+#pragma unroll
+      for (int r = 0; r < 4; ++r)
+        C[(m0 + wm + i * 16 + (lane >> 4) + 4 * r) * ldc + n0 + wn + j * 16 +
+          (lane & 15)] = alpha * acc[i][j][r] + beta * old[j][r];
+  }
 }
 
 // ZS[t][l] = Z[t][l] s_l[t] for lanes l < nl (s_l at s + l * vec), 0 for
