@@ -127,11 +127,14 @@ trace_scale_kernel(const double* __restrict__ B, int64_t ld, int64_t n,
 // a_ti^2 / M_ii of |L^-1 a_t|^2 vanish below FP64 resolution, so the exact
 // trace needs no correction for the bound coordinates.
 // One workgroup per row i of the lower triangle; the row's own values are
-// read once and each thread walks the row's columns j <= i.
+// read once and each thread walks the row's columns j <= i, PU columns at a
+// time with all their reads issued before the first write (a wait for a
+// load also waits for the stores before it).  P = p, the frame's width.
+template <int P>
 __global__ void __launch_bounds__(256)
 project_kernel(const double* __restrict__ B, double* M, int64_t ld, int64_t n,
                int64_t np, const double* __restrict__ E,
-               const double* __restrict__ W, int p,
+               const double* __restrict__ W,
                const DevScalars* __restrict__ sc,
                const double* __restrict__ mask) {
   if (sc->done) return;
@@ -143,31 +146,49 @@ project_kernel(const double* __restrict__ B, double* M, int64_t ld, int64_t n,
     return;
   }
   const double lam = sc->lambda, gam = sc->gamma;
-  double ei[3], wi[3], ge[9];
-  for (int a = 0; a < p; ++a) {
+  double ei[P], wi[P], ge[P][P];
+#pragma unroll
+  for (int a = 0; a < P; ++a) {
     ei[a] = E[a * n + i];
     wi[a] = W[a * n + i];
-    for (int b = 0; b < p; ++b) ge[a * 3 + b] = sc->GE[a * 3 + b];
+#pragma unroll
+    for (int b = 0; b < P; ++b) ge[a][b] = sc->GE[a * 3 + b];
   }
   const double mi = mk(mask, i);
   const double* Bi = B + i * ld;
-  for (int64_t j = threadIdx.x; j <= i; j += blockDim.x) {
-    double ej[3], wj[3];
-    for (int a = 0; a < p; ++a) {
-      ej[a] = E[a * n + j];
-      wj[a] = W[a * n + j];
+  constexpr int PU = 4;
+  const int64_t stride = blockDim.x;
+  for (int64_t j0 = threadIdx.x; j0 <= i; j0 += PU * stride) {
+    double ej[PU][P], wj[PU][P], mj[PU], bj[PU];
+#pragma unroll
+    for (int u = 0; u < PU; ++u) {
+      // columns past the row read column i (in bounds) and are not written
+      const int64_t j = j0 + u * stride <= i ? j0 + u * stride : i;
+#pragma unroll
+      for (int a = 0; a < P; ++a) {
+        ej[u][a] = E[a * n + j];
+        wj[u][a] = W[a * n + j];
+      }
+      mj[u] = mk(mask, j);
+      bj[u] = Bi[j];
     }
-    const double mj = mk(mask, j);
-    double v = mi * mj * Bi[j];
-    double ee = 0.0;
-    for (int a = 0; a < p; ++a) {
-      v -= ei[a] * (mj * wj[a]) + (mi * wi[a]) * ej[a];
-      ee += ei[a] * ej[a];
-      for (int b = 0; b < p; ++b) v += ei[a] * ge[a * 3 + b] * ej[b];
+#pragma unroll
+    for (int u = 0; u < PU; ++u) {
+      const int64_t j = j0 + u * stride;
+      if (j > i) break;
+      double v = mi * mj[u] * bj[u];
+      double ee = 0.0;
+#pragma unroll
+      for (int a = 0; a < P; ++a) {
+        v -= ei[a] * (mj[u] * wj[u][a]) + (mi * wi[a]) * ej[u][a];
+        ee += ei[a] * ej[u][a];
+#pragma unroll
+        for (int b = 0; b < P; ++b) v += ei[a] * ge[a][b] * ej[u][b];
+      }
+      v += (gam - lam) * ee;
+      if (i == j) v += mi != 0.0 ? lam : 1e30 * gam;
+      Mi[j] = v;
     }
-    v += (gam - lam) * ee;
-    if (i == j) v += mi != 0.0 ? lam : 1e30 * gam;
-    Mi[j] = v;
   }
 }
 
@@ -803,8 +824,23 @@ hipError_t launch_project(const double* B, double* M, int64_t ld, int64_t n,
                           int64_t np, const double* E, const double* W, int p,
                           const DevScalars* sc, hipStream_t st,
                           const double* mask) {
-  hipLaunchKernelGGL(project_kernel, dim3((unsigned)np), dim3(256), 0, st, B,
-                     M, ld, n, np, E, W, p, sc, mask);
+  const dim3 g((unsigned)np), b(256);
+  switch (p) {
+    case 1:
+      hipLaunchKernelGGL(project_kernel<1>, g, b, 0, st, B, M, ld, n, np, E, W,
+                         sc, mask);
+      break;
+    case 2:
+      hipLaunchKernelGGL(project_kernel<2>, g, b, 0, st, B, M, ld, n, np, E, W,
+                         sc, mask);
+      break;
+    case 3:
+      hipLaunchKernelGGL(project_kernel<3>, g, b, 0, st, B, M, ld, n, np, E, W,
+                         sc, mask);
+      break;
+    default:
+      return hipErrorInvalidValue;
+  }
   return hipGetLastError();
 }
 hipError_t launch_trace_weight(const double* rn, int nt, int64_t Tp,
